@@ -1,0 +1,146 @@
+/*
+ * ezeta.h -- C ABI of libezeta, the MI355X (gfx950) implementation of the
+ * Epstein zeta method for many-body lattice sums (Buchheit & Busse,
+ * arXiv 2504.11989).
+ *
+ * Conventions shared by every entry point
+ *  - d in {1, 2, 3}.  A lattice is given by its generator matrix A, d x d,
+ *    row-major, whose COLUMNS are the basis vectors: Lambda = A Z^d,
+ *    Lambda* = A^{-T} Z^d, V = |det A| (paper, Sec. 2, Definition (Lattices)).
+ *  - Pointers named *_dev are device pointers (HBM of the current HIP device);
+ *    pointers named *_host are host pointers.  The caller owns every buffer it
+ *    passes.  The library owns its cached workspace, rule tables and plans,
+ *    keyed by device, and frees them in ez_finalize().
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every entry point
+ *    only enqueues work on `stream` and returns; results are valid once the
+ *    stream has been synchronised.  Host arguments are consumed before return.
+ *  - Argument errors are detected on the host before any launch and returned
+ *    as ez_status; per-lattice problems found on the device (singular or
+ *    too-skewed lattice, non-finite result) set bits in status_dev[i] and
+ *    write NaN to that lattice's results without failing the batch.
+ *  - Calls that overlap on one device are serialised by the caller's stream
+ *    order; the library workspace is shared per device, so concurrent calls
+ *    from different host threads on one device must use one stream.
+ */
+#ifndef EZETA_H
+#define EZETA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EZ_OK = 0,
+    EZ_ERR_INVALID_ARG = 1,      /* bad d, sizes, null pointer, bad spec          */
+    EZ_ERR_SINGULAR_LATTICE = 2, /* reserved for host-side lattice checks         */
+    EZ_ERR_POLE = 3,             /* exponent on a pole of the requested function  */
+    EZ_ERR_UNSUPPORTED = 4,      /* Hadamard exponent mu + 2k = 0 (paper, Sec. 3)  */
+    EZ_ERR_NOMEM = 5,            /* device allocation failed                      */
+    EZ_ERR_HIP = 6               /* a HIP runtime call failed                     */
+} ez_status;
+
+/* bits of status_dev[i] */
+#define EZ_FLAG_SINGULAR 0x1u   /* A not finite or |det A| <= 1e-300               */
+#define EZ_FLAG_CAPACITY 0x2u   /* lattice too skewed for the point-table capacity */
+#define EZ_FLAG_NONFINITE 0x4u  /* a result came out NaN or Inf                    */
+#define EZ_FLAG_HADAMARD 0x8u   /* a Hadamard exponent mu + 2k hit 0 on the device  */
+#define EZ_FLAG_POLE 0x10u      /* ez_epstein_zeta: nu = d at y in Lambda*          */
+
+#define EZ_PREC_FP64 0
+#define EZ_PREC_MIXED 1
+
+/* Quadrature plan of the Epstein representation (paper, Sec. 3):
+ * v in [0,1]^{d-1}: n_q-point Gauss-Legendre per dimension (paper: n_q = 14);
+ * u in (0, eps): Taylor expansion of Z^reg to order 2*ell and Hadamard
+ *   integrals (paper: eps = 1e-2, ell = 4);
+ * u in (eps, 1/2]: n_panels geometric panels eps*r^i (r = (1/(2 eps))^{1/n_panels}),
+ *   n_g Gauss-Legendre points each.
+ * lam: Ewald split parameter in units of V^{1/d} (0 selects 1.0);
+ * a_cut: terms whose incomplete-gamma argument exceeds a_cut are dropped
+ *   (0 selects 36, a truncation below 1e-15 relative for nu <= 12 at lam = 1). */
+typedef struct ez_quad_spec {
+    int32_t n_q;
+    int32_t n_panels;
+    int32_t n_g;
+    int32_t ell;
+    double eps;
+    double lam;
+    double a_cut;
+    int32_t precision; /* EZ_PREC_FP64 */
+    int32_t flags;     /* 0 */
+} ez_quad_spec;
+
+/* Epstein zeta Z_{Lambda,nu}(x, y) = sum'_{z in Lambda} e^{-2 pi i y.z} |z - x|^{-nu},
+ * meromorphically continued in nu (paper, Sec. 2, Definition (Epstein zeta
+ * function)), evaluated by the incomplete-gamma split into a real-space and a
+ * reciprocal-space sum.  The primed sum omits z = x.
+ *   A_dev   : d*d doubles (one lattice)
+ *   nu_host : n_nu exponents
+ *   x_dev, y_dev : n_pts points each, row-major (n_pts x d)
+ *   lam, a_cut   : as in ez_quad_spec (0 selects the defaults)
+ *   out_dev : n_nu x n_pts x 2 doubles, (re, im) of Z(nu_j; x_i, y_i) at
+ *             out_dev[2*(j*n_pts + i) + {0,1}]
+ *   status_dev : 1 uint32 (lattice flags), may be NULL
+ * y on Lambda* (within 1e-12 in fractional coordinates) takes the value of the
+ * continuation in nu at that y; x within 1e-12 of a lattice point is taken on it.
+ * Errors: EZ_ERR_INVALID_ARG (d, n_nu < 1, n_pts < 0, null pointers, non-finite nu),
+ *         EZ_ERR_POLE (nu == d: pole at y in Lambda*). */
+ez_status ez_epstein_zeta(int d, const double *A_dev, int n_nu, const double *nu_host,
+                          int64_t n_pts, const double *x_dev, const double *y_dev,
+                          double lam, double a_cut, double *out_dev, uint32_t *status_dev,
+                          void *stream);
+
+/* n-body zeta zeta^(n)_Lambda(nu) (paper, Sec. 2, Definition (Many-body zeta
+ * function)) by the Epstein representation V int_BZ prod_i Z_{Lambda,nu_i}(k) dk
+ * (Sec. 2, Theorem) with the Duffy transform and the Hadamard continuation
+ * (Sec. 3), for a batch of lattices.
+ *   A_dev   : batch*d*d doubles
+ *   n, nu_host : number of bodies and their n exponents (integers, |nu| <= 64)
+ *   spec    : host pointer to one plan used for every lattice
+ *   out_dev : batch doubles
+ *   status_dev : batch uint32 (may be NULL)
+ * Errors: EZ_ERR_INVALID_ARG, EZ_ERR_UNSUPPORTED (a Hadamard exponent mu+2k = 0). */
+ez_status ez_nbody_lattice_sum(int batch, int d, const double *A_dev, int n, const double *nu_host,
+                               const ez_quad_spec *spec, double *out_dev, uint32_t *status_dev,
+                               void *stream);
+
+/* Axilrod-Teller-Muto cohesive energy per particle (paper, Sec. 2, Definition
+ * (ATM potential)) via E = 1/24 zeta(3,3,3) - 3/16 zeta(-1,5,5) + 3/8 zeta(1,3,5)
+ * (Sec. 2, Proposition), the three integrands fused at one node set.
+ *   A_dev   : batch*d*d doubles;  E_dev : batch doubles
+ *   dEdA_dev: batch*d*d doubles of dE/dA (row-major like A), or NULL
+ *   status_dev : batch uint32 (may be NULL) */
+ez_status ez_atm_energy(int batch, int d, const double *A_dev, const ez_quad_spec *spec,
+                        double *E_dev, double *dEdA_dev, uint32_t *status_dev, void *stream);
+
+/* General form behind the two entry points above: several results per lattice,
+ * each a linear combination of products of Epstein zeta functions integrated
+ * over the Brillouin zone,
+ *   result_r = sum_{t : term_result[t] = r} term_coef[t] * V int_BZ prod_f Z_{nu[fac]}^{mult} dk.
+ *   nu_host  : n_nu distinct integer exponents (n_nu <= 8)
+ *   term_*   : n_terms terms (n_terms <= 8); term t has term_nfac[t] (<= 4) distinct
+ *              factors; its factors are term_fac[4*t + f] (index into nu_host) with
+ *              multiplicity term_mult[4*t + f] (>= 1, total degree <= 64)
+ *   specs    : n_specs == 1 (shared plan) or n_specs == batch (one plan per lattice)
+ *   out_dev  : batch x n_results doubles (n_results <= 8) */
+ez_status ez_lattice_sums(int batch, int d, const double *A_dev, int n_nu, const double *nu_host,
+                          int n_terms, const int *term_result, const double *term_coef,
+                          const int *term_nfac, const int *term_fac, const int *term_mult,
+                          int n_results, const ez_quad_spec *specs, int n_specs, double *out_dev,
+                          uint32_t *status_dev, void *stream);
+
+/* Text of the last error on the calling host thread (never NULL). */
+const char *ez_last_error(void);
+
+/* Frees the library's cached device workspace and plans on every device. */
+ez_status ez_finalize(void);
+
+/* Library version string. */
+const char *ez_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EZETA_H */

@@ -1,0 +1,162 @@
+"""MI355X (gfx950) implementation of the Epstein zeta method for many-body
+lattice sums (Buchheit & Busse, arXiv 2504.11989).
+
+Thin Python layer over libezeta.so (see include/ezeta.h): torch tensors on the
+GPU are passed to the C ABI as device pointers on torch's current stream.
+
+    epstein_zeta(A, nu, x, y)        Z_{A Z^d, nu}(x, y), complex
+    nbody_lattice_sum(A, nu, spec)   zeta^(n)_Lambda(nu) for a batch of lattices
+    atm_energy(A, spec)              ATM cohesive energy per particle
+    lattice_sums(A, nu, terms, ...)  several product integrals per lattice
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Iterable, Sequence
+
+from ._native import (FLAG_CAPACITY, FLAG_HADAMARD, FLAG_NONFINITE, FLAG_POLE, FLAG_SINGULAR,
+                      PREC_FP64, PREC_MIXED, EzError, QuadSpec, check, lib)
+
+__all__ = ["epstein_zeta", "nbody_lattice_sum", "atm_energy", "lattice_sums", "QuadSpec", "EzError",
+           "DEFAULT_SPEC", "FLAG_SINGULAR", "FLAG_CAPACITY", "FLAG_NONFINITE", "FLAG_HADAMARD",
+           "FLAG_POLE", "version", "finalize"]
+
+# paper: n_q = 14, eps = 1e-2, ell = 4;  7 x 16 u-nodes on (eps, 1/2]
+DEFAULT_SPEC = dict(n_q=14, n_panels=7, n_g=16, ell=4, eps=1e-2, lam=1.0, a_cut=36.0, precision=PREC_FP64)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_f64(t, device=None):
+    torch = _torch()
+    t = torch.as_tensor(t, dtype=torch.float64, device=device if device is not None else "cuda")
+    return t.contiguous()
+
+
+def _host_f64(seq):
+    vals = [float(v) for v in seq]
+    return (ctypes.c_double * max(1, len(vals)))(*vals), len(vals)
+
+
+def _spec(spec) -> QuadSpec:
+    if spec is None:
+        return QuadSpec.from_dict(DEFAULT_SPEC)
+    if isinstance(spec, QuadSpec):
+        return spec
+    s = dict(DEFAULT_SPEC)
+    s.update(spec)
+    return QuadSpec.from_dict(s)
+
+
+def _lattices(A):
+    """A: (d, d) or (batch, d, d) tensor/array -> contiguous float64 CUDA tensor (batch, d, d)."""
+    torch = _torch()
+    A = _dev_f64(A)
+    if A.dim() == 2:
+        A = A.unsqueeze(0)
+    if A.dim() != 3 or A.shape[1] != A.shape[2] or A.shape[1] not in (1, 2, 3):
+        raise ValueError("A must have shape (d, d) or (batch, d, d), d in {1,2,3}")
+    return A.contiguous(), int(A.shape[0]), int(A.shape[1])
+
+
+def epstein_zeta(A, nu: Sequence[float], x, y, lam: float = 0.0, a_cut: float = 0.0, with_status=False):
+    """Z_{A Z^d, nu_j}(x_i, y_i) for all j, i: complex128 tensor (len(nu), n_pts)."""
+    torch = _torch()
+    A, b, d = _lattices(A)
+    if b != 1:
+        raise ValueError("epstein_zeta takes one lattice")
+    x = _dev_f64(x, A.device).reshape(-1, d).contiguous()
+    y = _dev_f64(y, A.device).reshape(-1, d).contiguous()
+    if x.shape != y.shape:
+        raise ValueError("x and y must have the same number of points")
+    n = x.shape[0]
+    nu_h, n_nu = _host_f64(nu)
+    out = torch.empty((n_nu, n, 2), dtype=torch.float64, device=A.device)
+    st = torch.zeros(1, dtype=torch.int32, device=A.device)
+    check(lib().ez_epstein_zeta(d, _dptr(A), n_nu, nu_h, n, _dptr(x), _dptr(y), float(lam), float(a_cut),
+                                _dptr(out), _dptr(st), _stream_ptr(A.device)))
+    z = torch.view_as_complex(out)
+    return (z, st) if with_status else z
+
+
+def nbody_lattice_sum(A, nu: Sequence[float], spec=None, with_status=False):
+    """zeta^(n)_Lambda(nu) for each lattice of the batch: float64 tensor (batch,)."""
+    torch = _torch()
+    A, b, d = _lattices(A)
+    nu_h, n = _host_f64(nu)
+    sp = _spec(spec)
+    out = torch.empty(b, dtype=torch.float64, device=A.device)
+    st = torch.zeros(b, dtype=torch.int32, device=A.device)
+    check(lib().ez_nbody_lattice_sum(b, d, _dptr(A), n, nu_h, ctypes.byref(sp), _dptr(out), _dptr(st),
+                                     _stream_ptr(A.device)))
+    return (out, st) if with_status else out
+
+
+def atm_energy(A, spec=None, with_status=False):
+    """ATM cohesive energy per particle for each lattice of the batch: float64 (batch,)."""
+    torch = _torch()
+    A, b, d = _lattices(A)
+    sp = _spec(spec)
+    out = torch.empty(b, dtype=torch.float64, device=A.device)
+    st = torch.zeros(b, dtype=torch.int32, device=A.device)
+    check(lib().ez_atm_energy(b, d, _dptr(A), ctypes.byref(sp), _dptr(out), None, _dptr(st),
+                              _stream_ptr(A.device)))
+    return (out, st) if with_status else out
+
+
+def lattice_sums(A, nu: Sequence[float], terms: Iterable, n_results: int, specs=None, with_status=False):
+    """Several results per lattice, result_r = sum of coef * V int_BZ prod Z_nu^mult dk.
+
+    terms: iterable of (result_index, coef, [(nu_index, multiplicity), ...]).
+    specs: None, one spec, or a list with one spec per lattice.
+    Returns float64 tensor (batch, n_results)."""
+    torch = _torch()
+    A, b, d = _lattices(A)
+    nu_h, n_nu = _host_f64(nu)
+    terms = list(terms)
+    nt = len(terms)
+    res = (ctypes.c_int * max(1, nt))()
+    coef = (ctypes.c_double * max(1, nt))()
+    nfac = (ctypes.c_int * max(1, nt))()
+    fac = (ctypes.c_int * max(4, 4 * nt))()
+    mult = (ctypes.c_int * max(4, 4 * nt))()
+    for t, (r, c, fl) in enumerate(terms):
+        res[t] = int(r)
+        coef[t] = float(c)
+        fl = list(fl)
+        nfac[t] = len(fl)
+        if len(fl) > 4:
+            raise ValueError("at most 4 distinct factors per term")
+        for f, (i, m) in enumerate(fl):
+            fac[4 * t + f] = int(i)
+            mult[4 * t + f] = int(m)
+    if specs is None or isinstance(specs, (dict, QuadSpec)):
+        sp_list = [_spec(specs)]
+    else:
+        sp_list = [_spec(s) for s in specs]
+    sp_arr = (QuadSpec * len(sp_list))(*sp_list)
+    out = torch.empty((b, n_results), dtype=torch.float64, device=A.device)
+    st = torch.zeros(b, dtype=torch.int32, device=A.device)
+    check(lib().ez_lattice_sums(b, d, _dptr(A), n_nu, nu_h, nt, res, coef, nfac, fac, mult, int(n_results),
+                                sp_arr, len(sp_list), _dptr(out), _dptr(st), _stream_ptr(A.device)))
+    return (out, st) if with_status else out
+
+
+def version() -> str:
+    return lib().ez_version().decode()
+
+
+def finalize():
+    check(lib().ez_finalize())

@@ -1,0 +1,81 @@
+"""ctypes binding of libezeta.so (argument marshalling only).
+
+Every numerical step runs in the HIP kernels of the library.  PyTorch is used
+for device memory and streams: tensors are passed as raw device pointers and
+the call is enqueued on torch's current HIP stream.  There is no CPU fallback:
+if the library is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libezeta.so")
+
+EZ_OK = 0
+STATUS_NAMES = {0: "EZ_OK", 1: "EZ_ERR_INVALID_ARG", 2: "EZ_ERR_SINGULAR_LATTICE", 3: "EZ_ERR_POLE",
+                4: "EZ_ERR_UNSUPPORTED", 5: "EZ_ERR_NOMEM", 6: "EZ_ERR_HIP"}
+FLAG_SINGULAR, FLAG_CAPACITY, FLAG_NONFINITE, FLAG_HADAMARD, FLAG_POLE = 0x1, 0x2, 0x4, 0x8, 0x10
+PREC_FP64, PREC_MIXED = 0, 1
+
+# every symbol declared in include/ezeta.h
+EXPORTED = ("ez_epstein_zeta", "ez_nbody_lattice_sum", "ez_atm_energy", "ez_lattice_sums",
+            "ez_last_error", "ez_finalize", "ez_version")
+
+
+class EzError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class QuadSpec(ctypes.Structure):
+    """Mirror of ez_quad_spec (include/ezeta.h)."""
+    _fields_ = [("n_q", ctypes.c_int32), ("n_panels", ctypes.c_int32), ("n_g", ctypes.c_int32),
+                ("ell", ctypes.c_int32), ("eps", ctypes.c_double), ("lam", ctypes.c_double),
+                ("a_cut", ctypes.c_double), ("precision", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+    @classmethod
+    def from_dict(cls, s: dict) -> "QuadSpec":
+        return cls(int(s.get("n_q", 14)), int(s.get("n_panels", 7)), int(s.get("n_g", 16)),
+                   int(s.get("ell", 4)), float(s.get("eps", 1e-2)), float(s.get("lam", 1.0)),
+                   float(s.get("a_cut", 36.0)), int(s.get("precision", PREC_FP64)), 0)
+
+
+_lib = None
+
+
+def lib():
+    """Load libezeta.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    I, D, P, VP = ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p
+    I64 = ctypes.c_int64
+    L.ez_epstein_zeta.restype = I
+    L.ez_epstein_zeta.argtypes = [I, VP, I, P, I64, VP, VP, D, D, VP, VP, VP]
+    L.ez_nbody_lattice_sum.restype = I
+    L.ez_nbody_lattice_sum.argtypes = [I, I, VP, I, P, ctypes.POINTER(QuadSpec), VP, VP, VP]
+    L.ez_atm_energy.restype = I
+    L.ez_atm_energy.argtypes = [I, I, VP, ctypes.POINTER(QuadSpec), VP, VP, VP, VP]
+    IP = ctypes.POINTER(ctypes.c_int)
+    L.ez_lattice_sums.restype = I
+    L.ez_lattice_sums.argtypes = [I, I, VP, I, P, I, IP, P, IP, IP, IP, I, ctypes.POINTER(QuadSpec), I,
+                                  VP, VP, VP]
+    L.ez_last_error.restype = ctypes.c_char_p
+    L.ez_last_error.argtypes = []
+    L.ez_finalize.restype = I
+    L.ez_finalize.argtypes = []
+    L.ez_version.restype = ctypes.c_char_p
+    L.ez_version.argtypes = []
+    _lib = L
+    return L
+
+
+def check(code: int):
+    if code != EZ_OK:
+        raise EzError(code, lib().ez_last_error().decode())

@@ -1,0 +1,564 @@
+// ez_api.hip -- C ABI of libezeta: argument validation, programs (which
+// products are integrated), quadrature plans and rule tables, the per-device
+// workspace, and the launch sequence  setup -> nodes -> hadamard -> finalize.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ezeta.h"
+#include "ez_internal.h"
+#include "ez_kernels.h"
+
+namespace {
+
+thread_local std::string g_err = "";
+
+ez_status fail(ez_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define EZ_HIP_TRY(call)                                                             \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess)                                                        \
+            return fail(EZ_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Gauss-Legendre nodes on [lo, hi]: Newton's method on P_n (three-term
+// recurrence), started from Tricomi's asymptotic root estimate.
+void gauss_legendre(int n, double lo, double hi, double *x, double *w) {
+    for (int k = 1; k <= n; ++k) {
+        double th = M_PI * (4.0 * k - 1.0) / (4.0 * n + 2.0);
+        double t = (1.0 - (n - 1.0) / (8.0 * n * n * n)) * std::cos(th);
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p_prev = 1.0, p = t;
+            for (int j = 1; j < n; ++j) {
+                double p_next = ((2.0 * j + 1.0) * t * p - j * p_prev) / (j + 1.0);
+                p_prev = p;
+                p = p_next;
+            }
+            if (n == 1) { p = t; p_prev = 1.0; }
+            dp = n * (p_prev - t * p) / (1.0 - t * t);
+            double dt = p / dp;
+            t -= dt;
+            if (std::fabs(dt) <= 1e-16) {
+                // refresh dp at the final t
+                p_prev = 1.0; p = t;
+                for (int j = 1; j < n; ++j) {
+                    double p_next = ((2.0 * j + 1.0) * t * p - j * p_prev) / (j + 1.0);
+                    p_prev = p;
+                    p = p_next;
+                }
+                if (n == 1) { p = t; p_prev = 1.0; }
+                dp = n * (p_prev - t * p) / (1.0 - t * t);
+                break;
+            }
+        }
+        // roots come out in decreasing t; store ascending
+        int idx = n - k;
+        x[idx] = 0.5 * (lo + hi) + 0.5 * (hi - lo) * t;
+        w[idx] = (hi - lo) / ((1.0 - t * t) * dp * dp);
+    }
+}
+
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+ez_status grow(DevBuf &b, size_t bytes) {
+    if (bytes <= b.bytes && b.p) return EZ_OK;
+    if (b.p) {
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = std::max<size_t>(bytes, 256);
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        b.p = nullptr;
+        return fail(EZ_ERR_NOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+    }
+    b.bytes = want;
+    return EZ_OK;
+}
+
+// A plan depends only on (d, batch, specs): rule tables, per-lattice plans, prefixes.
+struct DevPlan {
+    DevBuf rules, plans, tile_begin, dir_begin;
+    int n_tiles = 0, n_dirs = 0;
+    std::vector<EzInstPlan> host_plans;
+};
+
+struct DeviceState {
+    std::map<std::string, DevPlan *> plans;
+    std::vector<std::string> plan_order;
+    DevBuf meta, real, rec, tile_part, dir_part, dir_flag;
+    DevBuf gmeta, greal, grec;   // general-x Epstein tables
+};
+
+std::mutex g_mu;
+std::map<int, DeviceState *> g_dev;
+
+DeviceState *device_state(int dev) {
+    auto it = g_dev.find(dev);
+    if (it != g_dev.end()) return it->second;
+    DeviceState *s = new DeviceState();
+    g_dev[dev] = s;
+    return s;
+}
+
+void free_buf(DevBuf &b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+void free_plan(DevPlan *p) {
+    free_buf(p->rules); free_buf(p->plans); free_buf(p->tile_begin); free_buf(p->dir_begin);
+    delete p;
+}
+
+// ---------------------------------------------------------------------------
+ez_status check_spec(const ez_quad_spec &s) {
+    if (s.n_q < 1 || s.n_q > 64) return fail(EZ_ERR_INVALID_ARG, "spec.n_q must be in [1, 64]");
+    if (s.n_panels < 1 || s.n_panels > 256) return fail(EZ_ERR_INVALID_ARG, "spec.n_panels must be in [1, 256]");
+    if (s.n_g < 1 || s.n_g > 128) return fail(EZ_ERR_INVALID_ARG, "spec.n_g must be in [1, 128]");
+    if (s.ell < 0 || s.ell > EZ_ELL_MAX) return fail(EZ_ERR_INVALID_ARG, "spec.ell must be in [0, 8]");
+    if (!(s.eps > 0.0 && s.eps < 0.5)) return fail(EZ_ERR_INVALID_ARG, "spec.eps must be in (0, 1/2)");
+    if (!(s.lam >= 0.0 && s.lam <= 8.0)) return fail(EZ_ERR_INVALID_ARG, "spec.lam must be in [0, 8]");
+    if (!(s.a_cut >= 0.0 && s.a_cut <= 200.0)) return fail(EZ_ERR_INVALID_ARG, "spec.a_cut must be in [0, 200]");
+    if (s.precision != EZ_PREC_FP64) return fail(EZ_ERR_UNSUPPORTED, "spec.precision: only EZ_PREC_FP64 here");
+    return EZ_OK;
+}
+
+double spec_lam(const ez_quad_spec &s) { return s.lam > 0.0 ? s.lam : 1.0; }
+double spec_acut(const ez_quad_spec &s) { return s.a_cut > 0.0 ? s.a_cut : 36.0; }
+
+struct Term {
+    int res;
+    double coef;
+    std::vector<std::pair<int, int>> fac;   // (nu index, multiplicity)
+};
+
+ez_status build_program(int d, const std::vector<double> &nu, const std::vector<Term> &terms, int n_res,
+                        int ell_max, EzProgram &P) {
+    std::memset(&P, 0, sizeof(P));
+    if ((int)nu.size() < 1 || (int)nu.size() > EZ_NU_MAX) return fail(EZ_ERR_INVALID_ARG, "1 <= n_nu <= 8");
+    if ((int)terms.size() < 1 || (int)terms.size() > EZ_TERM_MAX) return fail(EZ_ERR_INVALID_ARG, "1 <= n_terms <= 8");
+    if (n_res < 1 || n_res > EZ_RES_MAX) return fail(EZ_ERR_INVALID_ARG, "1 <= n_results <= 8");
+    P.d = d;
+    P.n_nu = (int)nu.size();
+    P.n_res = n_res;
+    P.n_terms = (int)terms.size();
+    for (int i = 0; i < P.n_nu; ++i) {
+        double v = nu[i];
+        if (!std::isfinite(v) || v != std::floor(v) || std::fabs(v) > 64.0)
+            return fail(EZ_ERR_INVALID_ARG, "quadrature exponents must be integers with |nu| <= 64");
+        P.nu[i] = v;
+        P.p2[i] = (int)v - d + 2;
+        int em = (int)v - d;
+        P.logm[i] = (em >= 0 && em % 2 == 0) ? em / 2 : -1;
+        P.e[i] = v - d;
+        if ((P.p2[i] & 1) == 0 && P.p2[i] / 2 >= 1) P.need_e1 = 1;
+        if (P.p2[i] & 1) P.need_half = 1;
+    }
+    for (int t = 0; t < P.n_terms; ++t) {
+        const Term &T = terms[t];
+        if (T.res < 0 || T.res >= n_res) return fail(EZ_ERR_INVALID_ARG, "term_result out of range");
+        if (T.fac.empty() || (int)T.fac.size() > EZ_FAC_MAX) return fail(EZ_ERR_INVALID_ARG, "1 <= term_nfac <= 4");
+        P.term_res[t] = T.res;
+        P.term_coef[t] = T.coef;
+        P.term_nfac[t] = (int)T.fac.size();
+        int deg = 0;
+        for (size_t f = 0; f < T.fac.size(); ++f) {
+            int fi = T.fac[f].first, m = T.fac[f].second;
+            if (fi < 0 || fi >= P.n_nu) return fail(EZ_ERR_INVALID_ARG, "term_fac out of range");
+            if (m < 1) return fail(EZ_ERR_INVALID_ARG, "term_mult must be >= 1");
+            P.term_fac[t][f] = fi;
+            P.term_mult[t][f] = m;
+            deg += m;
+        }
+        if (deg > EZ_MULT_MAX) return fail(EZ_ERR_INVALID_ARG, "total degree of a term must be <= 64");
+        // Hadamard exponents mu = d + sum_f j_f (nu_f - d) + 2J must avoid 0 (paper, Sec. 3)
+        std::vector<int> jj(T.fac.size(), 0);
+        while (true) {
+            int E = 0, rest = 0;
+            for (size_t f = 0; f < T.fac.size(); ++f) {
+                E += jj[f] * ((int)P.nu[T.fac[f].first] - d);
+                rest += T.fac[f].second - jj[f];
+            }
+            int Jmax = std::min(rest * ell_max, 32);
+            for (int J = 0; J <= Jmax; ++J)
+                if (d + E + 2 * J == 0)
+                    return fail(EZ_ERR_UNSUPPORTED, "Hadamard exponent mu + 2k = 0 (logarithmic correction not implemented)");
+            size_t f = 0;
+            while (f < T.fac.size()) {
+                if (++jj[f] <= T.fac[f].second) break;
+                jj[f] = 0;
+                ++f;
+            }
+            if (f == T.fac.size()) break;
+        }
+    }
+    return EZ_OK;
+}
+
+std::string plan_key(int d, int batch, const ez_quad_spec *specs, int n_specs) {
+    std::string k(reinterpret_cast<const char *>(&d), sizeof(d));
+    k.append(reinterpret_cast<const char *>(&batch), sizeof(batch));
+    k.append(reinterpret_cast<const char *>(&n_specs), sizeof(n_specs));
+    k.append(reinterpret_cast<const char *>(specs), sizeof(ez_quad_spec) * (size_t)n_specs);
+    return k;
+}
+
+ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, int n_specs, DevPlan **out) {
+    std::string key = plan_key(d, batch, specs, n_specs);
+    auto it = S->plans.find(key);
+    if (it != S->plans.end()) { *out = it->second; return EZ_OK; }
+    // rule tables: one v-rule per distinct n_q, one u-rule per distinct (n_panels, n_g, eps)
+    std::vector<double> rules;
+    std::map<int, int> vrule_of;
+    std::map<std::string, int> urule_of;
+    DevPlan *P = new DevPlan();
+    P->host_plans.resize(batch);
+    std::vector<int> tb(batch + 1, 0), db(batch + 1, 0);
+    long long tiles = 0, dirs = 0;
+    for (int b = 0; b < batch; ++b) {
+        const ez_quad_spec &s = specs[n_specs == 1 ? 0 : b];
+        EzInstPlan &ip = P->host_plans[b];
+        std::memset(&ip, 0, sizeof(ip));
+        ip.n_q = s.n_q;
+        ip.ell = s.ell;
+        ip.eps = s.eps;
+        ip.lam_rel = spec_lam(s);
+        int nq = (d == 1) ? 1 : s.n_q;
+        if (!vrule_of.count(nq)) {
+            vrule_of[nq] = (int)rules.size();
+            std::vector<double> x(nq), w(nq);
+            gauss_legendre(nq, 0.0, 1.0, x.data(), w.data());
+            if (d == 1) { x[0] = 0.0; w[0] = 1.0; }
+            rules.insert(rules.end(), x.begin(), x.end());
+            rules.insert(rules.end(), w.begin(), w.end());
+        }
+        ip.vrule = vrule_of[nq];
+        if (d == 1) ip.n_q = 1;
+        std::string uk(reinterpret_cast<const char *>(&s.n_panels), sizeof(int));
+        uk.append(reinterpret_cast<const char *>(&s.n_g), sizeof(int));
+        uk.append(reinterpret_cast<const char *>(&s.eps), sizeof(double));
+        const int n_u = s.n_panels * s.n_g;
+        if (!urule_of.count(uk)) {
+            urule_of[uk] = (int)rules.size();
+            std::vector<double> ux(n_u), uw(n_u), gx(s.n_g), gw(s.n_g);
+            const double r = std::pow(0.5 / s.eps, 1.0 / s.n_panels);
+            for (int p = 0; p < s.n_panels; ++p) {
+                double lo = s.eps * std::pow(r, (double)p);
+                double hi = (p == s.n_panels - 1) ? 0.5 : s.eps * std::pow(r, (double)(p + 1));
+                gauss_legendre(s.n_g, lo, hi, gx.data(), gw.data());
+                for (int g = 0; g < s.n_g; ++g) { ux[p * s.n_g + g] = gx[g]; uw[p * s.n_g + g] = gw[g]; }
+            }
+            rules.insert(rules.end(), ux.begin(), ux.end());
+            rules.insert(rules.end(), uw.begin(), uw.end());
+        }
+        ip.urule = urule_of[uk];
+        ip.n_u = n_u;
+        long long nd = (long long)d * (1ll << (d - 1));
+        for (int i = 0; i < d - 1; ++i) nd *= s.n_q;
+        ip.n_dir = (int)nd;
+        long long nn = nd * n_u;
+        ip.tile_begin = (int)tiles;
+        ip.dir_begin = (int)dirs;
+        tb[b] = (int)tiles;
+        db[b] = (int)dirs;
+        tiles += (nn + EZ_TILE - 1) / EZ_TILE;
+        dirs += nd;
+        if (tiles > (1ll << 30) || dirs > (1ll << 30)) {
+            delete P;
+            return fail(EZ_ERR_INVALID_ARG, "quadrature too large for one call");
+        }
+    }
+    tb[batch] = (int)tiles;
+    db[batch] = (int)dirs;
+    P->n_tiles = (int)tiles;
+    P->n_dirs = (int)dirs;
+    ez_status st;
+    if ((st = grow(P->rules, rules.size() * sizeof(double))) ||
+        (st = grow(P->plans, sizeof(EzInstPlan) * batch)) ||
+        (st = grow(P->tile_begin, sizeof(int) * (batch + 1))) ||
+        (st = grow(P->dir_begin, sizeof(int) * (batch + 1)))) {
+        free_plan(P);
+        return st;
+    }
+    // one-time synchronous uploads (plans are cached and reused)
+    if (hipMemcpy(P->rules.p, rules.data(), rules.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(P->plans.p, P->host_plans.data(), sizeof(EzInstPlan) * batch, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(P->tile_begin.p, tb.data(), sizeof(int) * (batch + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(P->dir_begin.p, db.data(), sizeof(int) * (batch + 1), hipMemcpyHostToDevice) != hipSuccess) {
+        free_plan(P);
+        return fail(EZ_ERR_HIP, "upload of the quadrature plan failed");
+    }
+    if (S->plans.size() >= 32) {                 // bounded cache, oldest out
+        std::string old = S->plan_order.front();
+        S->plan_order.erase(S->plan_order.begin());
+        free_plan(S->plans[old]);
+        S->plans.erase(old);
+    }
+    S->plans[key] = P;
+    S->plan_order.push_back(key);
+    *out = P;
+    return EZ_OK;
+}
+
+const double kOmega[4] = {0.0, 2.0, M_PI, 4.0 * M_PI / 3.0};
+const double kSkew = 2.5;   // bound on (1/2) sum |a_i| / V^{1/d} assumed for table capacity
+
+int real_capacity(int d, double lam, double acut, bool general) {
+    double R = lam * std::sqrt(acut / M_PI) + (general ? kSkew : 0.0);
+    double n = kOmega[d] * std::pow(R + kSkew, d);
+    return (int)std::ceil(general ? n : 0.5 * n) + 16;
+}
+int rec_capacity(int d, double lam, double acut) {
+    double R = std::sqrt(acut / M_PI) / lam + kSkew;
+    return (int)std::ceil(kOmega[d] * std::pow(R + kSkew, d)) + 16;
+}
+
+ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog, const ez_quad_spec *specs,
+                   int n_specs, double *out_dev, uint32_t *status_dev, hipStream_t stream) {
+    int dev = 0;
+    EZ_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_mu);
+    DeviceState *S = device_state(dev);
+    DevPlan *P = nullptr;
+    ez_status st = get_plan(S, d, batch, specs, n_specs, &P);
+    if (st) return st;
+    double lam_min = 1e300, lam_max = 0.0, acut = spec_acut(specs[0]);
+    for (int i = 0; i < n_specs; ++i) {
+        lam_min = std::min(lam_min, spec_lam(specs[i]));
+        lam_max = std::max(lam_max, spec_lam(specs[i]));
+        if (spec_acut(specs[i]) != acut) return fail(EZ_ERR_INVALID_ARG, "all specs of one call must share a_cut");
+    }
+    EzTables tab;
+    tab.real_cap = real_capacity(d, lam_max, acut, false);
+    tab.rec_cap = rec_capacity(d, lam_min, acut);
+    tab.rstride = 4 * ((3 + prog.n_nu + 3) / 4);
+    if ((st = grow(S->meta, sizeof(EzLatMeta) * batch)) ||
+        (st = grow(S->real, sizeof(double) * (size_t)batch * tab.real_cap * tab.rstride)) ||
+        (st = grow(S->rec, sizeof(double) * (size_t)batch * tab.rec_cap * 4)) ||
+        (st = grow(S->tile_part, sizeof(double) * 2 * (size_t)P->n_tiles * prog.n_res)) ||
+        (st = grow(S->dir_part, sizeof(double) * (size_t)P->n_dirs * prog.n_res)) ||
+        (st = grow(S->dir_flag, sizeof(uint32_t) * (size_t)P->n_dirs)))
+        return st;
+    tab.real = (double *)S->real.p;
+    tab.rec = (double *)S->rec.p;
+
+    EzSetupArgs sa;
+    sa.prog = prog;
+    sa.A = A_dev;
+    sa.plans = (const EzInstPlan *)P->plans.p;
+    sa.meta = (EzLatMeta *)S->meta.p;
+    sa.tab = tab;
+    sa.a_cut = acut;
+    sa.general_x = 0;
+    sa.status_out = nullptr;
+    EZ_HIP_TRY(ez_launch_setup(sa, batch, stream));
+
+    EzQuadArgs qa;
+    qa.prog = prog;
+    qa.batch = batch;
+    qa.plans = (const EzInstPlan *)P->plans.p;
+    qa.tile_begin = (const int *)P->tile_begin.p;
+    qa.dir_begin = (const int *)P->dir_begin.p;
+    qa.meta = (const EzLatMeta *)S->meta.p;
+    qa.tab = tab;
+    qa.rules = (const double *)P->rules.p;
+    qa.tile_part = (double *)S->tile_part.p;
+    qa.dir_part = (double *)S->dir_part.p;
+    qa.dir_flag = (uint32_t *)S->dir_flag.p;
+    qa.out = out_dev;
+    qa.status = status_dev;
+    EZ_HIP_TRY(ez_launch_nodes(qa, P->n_tiles, stream));
+    EZ_HIP_TRY(ez_launch_hadamard(qa, P->n_dirs, stream));
+    EZ_HIP_TRY(ez_launch_finalize(qa, stream));
+    return EZ_OK;
+}
+
+ez_status check_common(int batch, int d, const double *A_dev, const ez_quad_spec *spec, const void *out) {
+    if (d < 1 || d > 3) return fail(EZ_ERR_INVALID_ARG, "d must be 1, 2 or 3");
+    if (batch < 1) return fail(EZ_ERR_INVALID_ARG, "batch must be >= 1");
+    if (!A_dev || !spec || !out) return fail(EZ_ERR_INVALID_ARG, "null pointer argument");
+    return EZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ez_last_error(void) { return g_err.c_str(); }
+
+const char *ez_version(void) { return "libezeta 0.1 (gfx950, FP64)"; }
+
+ez_status ez_finalize(void) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &kv : g_dev) {
+        (void)hipSetDevice(kv.first);
+        DeviceState *S = kv.second;
+        for (auto &p : S->plans) free_plan(p.second);
+        free_buf(S->meta); free_buf(S->real); free_buf(S->rec);
+        free_buf(S->tile_part); free_buf(S->dir_part); free_buf(S->dir_flag);
+        free_buf(S->gmeta); free_buf(S->greal); free_buf(S->grec);
+        delete S;
+    }
+    g_dev.clear();
+    (void)hipSetDevice(cur);
+    return EZ_OK;
+}
+
+ez_status ez_lattice_sums(int batch, int d, const double *A_dev, int n_nu, const double *nu_host, int n_terms,
+                          const int *term_result, const double *term_coef, const int *term_nfac,
+                          const int *term_fac, const int *term_mult, int n_results, const ez_quad_spec *specs,
+                          int n_specs, double *out_dev, uint32_t *status_dev, void *stream) {
+    ez_status st = check_common(batch, d, A_dev, specs, out_dev);
+    if (st) return st;
+    if (!nu_host || !term_result || !term_coef || !term_nfac || !term_fac || !term_mult)
+        return fail(EZ_ERR_INVALID_ARG, "null pointer argument");
+    if (n_specs != 1 && n_specs != batch) return fail(EZ_ERR_INVALID_ARG, "n_specs must be 1 or batch");
+    if (n_nu < 1 || n_nu > EZ_NU_MAX || n_terms < 1 || n_terms > EZ_TERM_MAX)
+        return fail(EZ_ERR_INVALID_ARG, "n_nu and n_terms must be in [1, 8]");
+    int ell_max = 0;
+    for (int i = 0; i < n_specs; ++i) {
+        if ((st = check_spec(specs[i]))) return st;
+        ell_max = std::max(ell_max, specs[i].ell);
+    }
+    std::vector<double> nu(nu_host, nu_host + n_nu);
+    std::vector<Term> terms(n_terms);
+    for (int t = 0; t < n_terms; ++t) {
+        terms[t].res = term_result[t];
+        terms[t].coef = term_coef[t];
+        if (term_nfac[t] < 1 || term_nfac[t] > EZ_FAC_MAX) return fail(EZ_ERR_INVALID_ARG, "term_nfac must be in [1, 4]");
+        for (int f = 0; f < term_nfac[t]; ++f)
+            terms[t].fac.push_back({term_fac[EZ_FAC_MAX * t + f], term_mult[EZ_FAC_MAX * t + f]});
+    }
+    EzProgram prog;
+    if ((st = build_program(d, nu, terms, n_results, ell_max, prog))) return st;
+    return run_sums(batch, d, A_dev, prog, specs, n_specs, out_dev, status_dev, (hipStream_t)stream);
+}
+
+ez_status ez_nbody_lattice_sum(int batch, int d, const double *A_dev, int n, const double *nu_host,
+                               const ez_quad_spec *spec, double *out_dev, uint32_t *status_dev, void *stream) {
+    ez_status st = check_common(batch, d, A_dev, spec, out_dev);
+    if (st) return st;
+    if (!nu_host || n < 1 || n > EZ_MULT_MAX) return fail(EZ_ERR_INVALID_ARG, "need 1 <= n <= 64 exponents");
+    if ((st = check_spec(*spec))) return st;
+    std::vector<double> distinct;
+    std::vector<int> mult;
+    for (int i = 0; i < n; ++i) {
+        auto it = std::find(distinct.begin(), distinct.end(), nu_host[i]);
+        if (it == distinct.end()) { distinct.push_back(nu_host[i]); mult.push_back(1); }
+        else mult[it - distinct.begin()]++;
+    }
+    if ((int)distinct.size() > EZ_FAC_MAX)
+        return fail(EZ_ERR_INVALID_ARG, "at most 4 distinct exponents per n-body sum");
+    Term T;
+    T.res = 0;
+    T.coef = 1.0;
+    for (size_t i = 0; i < distinct.size(); ++i) T.fac.push_back({(int)i, mult[i]});
+    EzProgram prog;
+    if ((st = build_program(d, distinct, {T}, 1, spec->ell, prog))) return st;
+    return run_sums(batch, d, A_dev, prog, spec, 1, out_dev, status_dev, (hipStream_t)stream);
+}
+
+ez_status ez_atm_energy(int batch, int d, const double *A_dev, const ez_quad_spec *spec, double *E_dev,
+                        double *dEdA_dev, uint32_t *status_dev, void *stream) {
+    ez_status st = check_common(batch, d, A_dev, spec, E_dev);
+    if (st) return st;
+    if ((st = check_spec(*spec))) return st;
+    if (dEdA_dev) return fail(EZ_ERR_UNSUPPORTED, "dE/dA is not available in this build");
+    // nu set {-1, 1, 3, 5};  E = 1/24 Z3^3 - 3/16 Z-1 Z5^2 + 3/8 Z1 Z3 Z5
+    std::vector<double> nu = {-1.0, 1.0, 3.0, 5.0};
+    Term t0{0, 1.0 / 24.0, {{2, 3}}};
+    Term t1{0, -3.0 / 16.0, {{0, 1}, {3, 2}}};
+    Term t2{0, 3.0 / 8.0, {{1, 1}, {2, 1}, {3, 1}}};
+    EzProgram prog;
+    if ((st = build_program(d, nu, {t0, t1, t2}, 1, spec->ell, prog))) return st;
+    return run_sums(batch, d, A_dev, prog, spec, 1, E_dev, status_dev, (hipStream_t)stream);
+}
+
+ez_status ez_epstein_zeta(int d, const double *A_dev, int n_nu, const double *nu_host, int64_t n_pts,
+                          const double *x_dev, const double *y_dev, double lam, double a_cut, double *out_dev,
+                          uint32_t *status_dev, void *stream) {
+    if (d < 1 || d > 3) return fail(EZ_ERR_INVALID_ARG, "d must be 1, 2 or 3");
+    if (!A_dev || !nu_host || (n_pts > 0 && (!x_dev || !y_dev || !out_dev)))
+        return fail(EZ_ERR_INVALID_ARG, "null pointer argument");
+    if (n_nu < 1 || n_nu > EZ_NU_MAX) return fail(EZ_ERR_INVALID_ARG, "n_nu must be in [1, 8]");
+    if (n_pts < 0) return fail(EZ_ERR_INVALID_ARG, "n_pts must be >= 0");
+    if (!(lam >= 0.0 && lam <= 8.0) || !(a_cut >= 0.0 && a_cut <= 200.0))
+        return fail(EZ_ERR_INVALID_ARG, "lam in [0, 8], a_cut in [0, 200]");
+    for (int i = 0; i < n_nu; ++i)
+        if (!std::isfinite(nu_host[i]) || std::fabs(nu_host[i]) > 64.0)
+            return fail(EZ_ERR_INVALID_ARG, "nu must be finite, |nu| <= 64");
+    if (lam == 0.0) lam = 1.0;
+    if (a_cut == 0.0) a_cut = 36.0;
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    EZ_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_mu);
+    DeviceState *S = device_state(dev);
+    EzProgram prog;
+    std::memset(&prog, 0, sizeof(prog));
+    prog.d = d;
+    prog.n_nu = 0;   // general-x tables carry no weights
+    EzTables tab;
+    tab.real_cap = real_capacity(d, lam, a_cut, true);
+    tab.rec_cap = rec_capacity(d, lam, a_cut);
+    tab.rstride = 4;
+    ez_status st;
+    if ((st = grow(S->gmeta, sizeof(EzLatMeta))) ||
+        (st = grow(S->greal, sizeof(double) * (size_t)tab.real_cap * tab.rstride)) ||
+        (st = grow(S->grec, sizeof(double) * (size_t)tab.rec_cap * 4)))
+        return st;
+    tab.real = (double *)S->greal.p;
+    tab.rec = (double *)S->grec.p;
+    // a one-lattice plan carrying lam
+    ez_quad_spec sp;
+    std::memset(&sp, 0, sizeof(sp));
+    sp.n_q = 1; sp.n_panels = 1; sp.n_g = 1; sp.ell = 0; sp.eps = 0.01; sp.lam = lam; sp.a_cut = a_cut;
+    DevPlan *P = nullptr;
+    if ((st = get_plan(S, d, 1, &sp, 1, &P))) return st;
+    EzSetupArgs sa;
+    sa.prog = prog;
+    sa.A = A_dev;
+    sa.plans = (const EzInstPlan *)P->plans.p;
+    sa.meta = (EzLatMeta *)S->gmeta.p;
+    sa.tab = tab;
+    sa.a_cut = a_cut;
+    sa.general_x = 1;
+    sa.status_out = status_dev;
+    EZ_HIP_TRY(ez_launch_setup(sa, 1, s));
+    EzEpsteinArgs ea;
+    std::memset(&ea, 0, sizeof(ea));
+    ea.d = d;
+    ea.n_nu = n_nu;
+    for (int i = 0; i < n_nu; ++i) ea.nu[i] = nu_host[i];
+    ea.n_pts = n_pts;
+    ea.x = x_dev;
+    ea.y = y_dev;
+    ea.meta = (const EzLatMeta *)S->gmeta.p;
+    ea.tab = tab;
+    ea.out = out_dev;
+    ea.status = status_dev;
+    EZ_HIP_TRY(ez_launch_epstein(ea, s));
+    return EZ_OK;
+}
+
+}  // extern "C"

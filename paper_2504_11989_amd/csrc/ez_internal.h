@@ -1,0 +1,64 @@
+// ez_internal.h -- structures shared by the host and the kernels of libezeta.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define EZ_NU_MAX 8      // distinct exponents per call
+#define EZ_TERM_MAX 8    // product terms per call
+#define EZ_FAC_MAX 4     // distinct factors per term
+#define EZ_RES_MAX 8     // results per lattice
+#define EZ_ELL_MAX 8     // Taylor cutoff
+#define EZ_MULT_MAX 64   // total degree of a product term
+#define EZ_TILE 256      // quadrature nodes per workgroup of the node kernel
+
+// Which lattice sums one call computes (host-built, passed by value).
+// Exponent nu_i enters the reciprocal sum through E_{p_i}(a), p_i = (nu_i - d + 2)/2
+// (E_p the generalised exponential integral), so 2 p_i = nu_i - d + 2 is an integer.
+struct EzProgram {
+    int d, n_nu, n_res, n_terms;
+    double nu[EZ_NU_MAX];
+    int p2[EZ_NU_MAX];      // 2 p_i
+    int logm[EZ_NU_MAX];    // m if nu_i = d + 2m (logarithmic singular part), else -1
+    double e[EZ_NU_MAX];    // nu_i - d, exponent of the singular part
+    int term_res[EZ_TERM_MAX];
+    double term_coef[EZ_TERM_MAX];
+    int term_nfac[EZ_TERM_MAX];
+    int term_fac[EZ_TERM_MAX][EZ_FAC_MAX];
+    int term_mult[EZ_TERM_MAX][EZ_FAC_MAX];
+    int need_e1;            // some p_i is an integer >= 1
+    int need_half;          // some p_i is a half-integer
+};
+
+// Per-lattice constants written by the setup kernel.
+struct EzLatMeta {
+    double A[9], B[9];      // row-major; B = A^{-T}
+    double V, lam, alpha;   // |det A|, Ewald parameter, pi lam^2
+    double a_cut;
+    double K[EZ_NU_MAX];    // pi^{nu-d/2} / (Gamma(nu/2) V) * alpha^{(d-nu)/2}
+    double self_[EZ_NU_MAX];// (pi/lam^2)^{nu/2} / Gamma(nu/2 + 1)
+    double sig[EZ_NU_MAX];  // s_hat(k)/V = sig |k|^{nu-d} [ * log(pi |k|^2) ]
+    int n_real;             // real-space entries (pairs +-z stored once)
+    int n_rec;              // reciprocal entries (all m*, m* = 0 first)
+    uint32_t status;
+    int pad_;
+};
+
+// Per-lattice quadrature plan (host-built).
+struct EzInstPlan {
+    int n_q, n_u, n_dir, ell;
+    int tile_begin;         // first node tile of this lattice
+    int dir_begin;          // first direction of this lattice (Hadamard output)
+    int vrule;              // offset of the n_q-point Gauss rule on [0,1] (nodes, then weights)
+    int urule;              // offset of the n_u u-nodes on (eps,1/2] (nodes, then weights)
+    double eps;
+    double lam_rel;         // Ewald parameter in units of V^{1/d}
+};
+
+struct EzTables {
+    int real_cap, rec_cap, rstride;   // capacity per lattice, doubles per real entry
+    double *real;                     // [batch][real_cap][rstride]: z (3), 2 W_nu(z) (n_nu)
+    double *rec;                      // [batch][rec_cap][4]: m* (3), |m*|^2
+};
+
+#define EZ_PI 3.141592653589793238462643383279502884
+#define EZ_EULER 0.577215664901532860606512090082402431

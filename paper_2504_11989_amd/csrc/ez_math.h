@@ -1,0 +1,163 @@
+// ez_math.h -- FP64 device special functions for the Epstein zeta kernels.
+//
+// E_p(a) = int_1^inf e^{-a t} t^{-p} dt (generalised exponential integral) carries
+// every incomplete gamma of the method: a^{-s} Gamma(s, a) = E_{1-s}(a).
+//  * E_1: a < 1 power series (DLMF 6.6.2); a >= 1 the rational fit of
+//    x e^x E1(x) in t = 1/x from e1_rational.h (Sanathanan-Koerner least squares).
+//  * E_{1/2}(a) = sqrt(pi/a) erfc(sqrt a).
+//  * other p by the recurrence p E_{p+1} = e^{-a} - a E_p (DLMF 8.19.12), upward
+//    from E_1 / E_{1/2} for p >= 1, downward from E_0 = e^{-a}/a / E_{1/2} below.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "e1_rational.h"
+#include "ez_internal.h"
+
+__device__ __forceinline__ double ez_rcp(double x) { return 1.0 / x; }
+
+// E1(a) for 0 < a < 1: -gamma - ln a + sum_{k>=1} (-1)^{k+1} a^k / (k k!)
+__device__ __forceinline__ double ez_e1_series(double a) {
+    // Ein(a) = sum_{k=1}^{19} (-1)^{k+1} a^k/(k k!), Horner in a; terms beyond k = 19 < 1e-19
+    double s = 0.0;
+#pragma unroll
+    for (int k = 19; k >= 1; --k) {
+        double fk = 1.0;
+        for (int j = 2; j <= k; ++j) fk *= (double)j;          // folded at compile time
+        double c = ((k & 1) ? 1.0 : -1.0) / ((double)k * fk);
+        s = fma(s, a, c);
+    }
+    s *= a;
+    return -EZ_EULER - log(a) + s;
+}
+
+// e^a E1(a) for a >= 1 from the rational fit (relative error < 1e-15)
+__device__ __forceinline__ double ez_e1_scaled_large(double a, double inv_a) {
+    const double t = inv_a;
+    double P = ez_e1r_p[EZ_E1R_DEG], Q = ez_e1r_q[EZ_E1R_DEG];
+#pragma unroll
+    for (int j = EZ_E1R_DEG - 1; j >= 0; --j) {
+        P = fma(P, t, ez_e1r_p[j]);
+        Q = fma(Q, t, ez_e1r_q[j]);
+    }
+    return t * P / Q;
+}
+
+// E1(a), a > 0, given e = e^{-a} and inv_a = 1/a
+__device__ __forceinline__ double ez_e1(double a, double e, double inv_a) {
+    if (a < 1.0) return ez_e1_series(a);
+    return e * ez_e1_scaled_large(a, inv_a);
+}
+
+// E_{p}(a) for 2p = p2 (integer), from the bases E1 / E_{1/2}
+__device__ __forceinline__ double ez_ep_from(int p2, double a, double e, double inv_a, double E1, double Eh) {
+    if ((p2 & 1) == 0) {
+        int p = p2 / 2;
+        if (p >= 1) {
+            double E = E1;
+            for (int q = 1; q < p; ++q) E = (e - a * E) * (1.0 / (double)q);
+            return E;
+        }
+        double E = e * inv_a;                      // E_0
+        for (int q = -1; q >= p; --q) E = (e - (double)q * E) * inv_a;
+        return E;
+    }
+    // half-integer p = p2/2
+    double E = Eh;                                 // E_{1/2}
+    if (p2 >= 1) {
+        for (int q2 = 1; q2 < p2; q2 += 2) E = (e - a * E) * (2.0 / (double)q2);
+        return E;
+    }
+    for (int q2 = -1; q2 >= p2; q2 -= 2) E = (e - 0.5 * (double)q2 * E) * inv_a;
+    return E;
+}
+
+__device__ __forceinline__ double ez_ehalf(double a) {
+    double r = sqrt(a);
+    return 1.7724538509055160272981674833411452 * erfc(r) / r;   // sqrt(pi) erfc(sqrt a)/sqrt a
+}
+
+// 1/Gamma(x), zero at the poles
+__device__ __forceinline__ double ez_rgamma(double x) {
+    if (x <= 0.0 && x == floor(x)) return 0.0;
+    return 1.0 / tgamma(x);
+}
+
+// Upper incomplete gamma Gamma(s, a), a > 0, any real s (used off the hot path).
+//  2s integer: Gamma(s,a) = a^s E_{1-s}(a) through the E_p recurrences;
+//  otherwise:  a < max(2, s + 1): Gamma(s) - a^s e^{-a} sum_k a^k / (s)_{k+1} (DLMF 8.7.1),
+//              else the continued fraction of DLMF 8.9.2 (even part), Lentz's method,
+//              for s < 0 after the downward recurrence Gamma(s,a) = (Gamma(s+1,a) - a^s e^{-a})/s.
+__device__ inline double ez_gamma_upper(double s, double a) {
+    const double s2 = 2.0 * s;
+    if (s2 == floor(s2) && fabs(s) <= 64.0) {
+        int p2 = 2 - (int)s2;                      // 2 (1 - s)
+        double e = exp(-a), inv = 1.0 / a;
+        double E1 = ((p2 & 1) == 0 && p2 >= 2) ? ez_e1(a, e, inv) : 0.0;
+        double Eh = (p2 & 1) ? ez_ehalf(a) : 0.0;
+        return pow(a, s) * ez_ep_from(p2, a, e, inv, E1, Eh);
+    }
+    if (a < 2.0 || a < s + 1.0) {
+        double term = 1.0 / s, sum = term;
+        for (int k = 1; k < 500; ++k) {
+            term *= a / (s + (double)k);
+            sum += term;
+            if (fabs(term) < 1e-17 * fabs(sum)) break;
+        }
+        return tgamma(s) - exp(s * log(a) - a) * sum;
+    }
+    // shift s up to s' > 0 if needed, then continued fraction at s'
+    int nshift = 0;
+    double sp = s;
+    while (sp <= 0.0) { sp += 1.0; ++nshift; }
+    double f;
+    {
+        const double tiny = 1e-300;
+        double F = tiny, C = F, D = 0.0;
+        for (int j = 1; j < 2000; ++j) {
+            double aj = (j == 1) ? 1.0 : -(double)(j - 1) * ((double)(j - 1) - sp);
+            double bj = a + 2.0 * j - 1.0 - sp;
+            D = bj + aj * D; if (D == 0.0) D = tiny;
+            C = bj + aj / C; if (C == 0.0) C = tiny;
+            D = 1.0 / D;
+            double dl = C * D;
+            F *= dl;
+            if (fabs(dl - 1.0) < 1e-16) break;
+        }
+        f = exp(sp * log(a) - a) * F;
+    }
+    for (int i = 0; i < nshift; ++i) {
+        sp -= 1.0;
+        f = (f - exp(sp * log(a) - a)) / sp;
+    }
+    return f;
+}
+
+// cos(2 pi t) with the argument reduced exactly modulo 1
+__device__ __forceinline__ double ez_cos2pi(double t) { return cospi(2.0 * (t - rint(t))); }
+__device__ __forceinline__ void ez_sincos2pi(double t, double *s, double *c) {
+    double r = 2.0 * (t - rint(t));
+    *s = sinpi(r);
+    *c = cospi(r);
+}
+
+// ---- double-double accumulation (error-free sums, fixed order) ----
+struct ez_dd { double hi, lo; };
+__device__ __forceinline__ ez_dd ez_dd_add(ez_dd a, ez_dd b) {
+    double s = a.hi + b.hi;
+    double bb = s - a.hi;
+    double err = (a.hi - (s - bb)) + (b.hi - bb);
+    err += a.lo + b.lo;
+    double hi = s + err;
+    double lo = err - (hi - s);
+    return {hi, lo};
+}
+__device__ __forceinline__ ez_dd ez_dd_add_d(ez_dd a, double b) { return ez_dd_add(a, ez_dd{b, 0.0}); }
+
+__device__ __forceinline__ ez_dd ez_dd_shfl_xor(ez_dd v, int m) {
+    return {__shfl_xor(v.hi, m, 64), __shfl_xor(v.lo, m, 64)};
+}
+// wave64 butterfly: every lane ends with the same, order-independent-of-timing sum
+__device__ __forceinline__ ez_dd ez_dd_wave_sum(ez_dd v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = ez_dd_add(v, ez_dd_shfl_xor(v, m));
+    return v;
+}

@@ -1,0 +1,466 @@
+// ez_quad.hip -- quadrature of products of Epstein zeta functions over the
+// Brillouin zone (paper, Sec. 2, Theorem (Epstein representation); Sec. 3,
+// Corollary (Duffy transformation) and the meromorphic continuation).
+//
+//   zeta = 2 sum_{p,j} int_0^{1/2} u^{d-1} int_{[0,1]^{d-1}} f(u w(v)) dv du,
+//   w(v) = A^{-T} sigma^j (p1 v1, ..., p_{d-1} v_{d-1}, 1).
+//
+// ez_node_kernel   : u in (eps, 1/2].  One thread per node k = u w: Z_nu(k) for
+//                    the exponent set by the split (real-space table + reciprocal
+//                    table), the products of the terms, weight, then a
+//                    double-double reduction to one partial per 256-node tile.
+// ez_hadamard_kernel: u in (0, eps).  One thread per direction w: Taylor
+//                    coefficients of Z^reg_nu(u w) in u, expansion of the products
+//                    of (singular + Taylor) factors and closed-form Hadamard integrals.
+// ez_finalize_kernel: fixed-order double-double sum of tiles and directions.
+//
+// Direction numbering: dir = block * n_q^{d-1} + iv, block = j 2^{d-1} + ip,
+// bit b of ip set <=> p_{b+1} = -1, iv = sum_b iv_b n_q^b; node = dir * n_u + iu.
+#include "ez_internal.h"
+#include "ez_math.h"
+#include "ez_kernels.h"
+
+namespace {
+
+constexpr int EZ_PDEG = 33;   // coefficients kept in the Taylor product polynomials (in u^2)
+
+__device__ __forceinline__ int find_segment(const int *begin, int n, int x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (begin[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int D>
+__device__ __forceinline__ void ez_direction(const EzInstPlan &P, const double *rules, const double *B,
+                                             int dir, double *w, double *wv) {
+    int nv = 1;
+#pragma unroll
+    for (int i = 0; i < D - 1; ++i) nv *= P.n_q;
+    const int np = 1 << (D - 1);
+    const int block = dir / nv;
+    int iv = dir - block * nv;
+    const int j = block / np, ip = block - j * np;
+    double x[3] = {0.0, 0.0, 0.0};
+    double weight = 1.0;
+#pragma unroll
+    for (int b = 0; b < D - 1; ++b) {
+        int ib = iv % P.n_q;
+        iv /= P.n_q;
+        double v = rules[P.vrule + ib];
+        weight *= rules[P.vrule + P.n_q + ib];
+        x[b] = ((ip >> b) & 1) ? -v : v;
+    }
+    x[D - 1] = 1.0;
+    double wh[3];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        int src = i - j;
+        if (src < 0) src += D;
+        wh[i] = (src == 0) ? x[0] : (src == 1 ? x[1] : x[2]);
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) s = fma(B[i * D + c], wh[c], s);
+        w[i] = s;
+    }
+    *wv = weight;
+}
+
+template <int D, int NNU>
+__global__ __launch_bounds__(EZ_TILE) void ez_node_kernel(EzQuadArgs args) {
+    const int tile = blockIdx.x;
+    const int inst = find_segment(args.tile_begin, args.batch, tile);
+    const EzInstPlan P = args.plans[inst];
+    const EzLatMeta *M = args.meta + inst;
+    const int n_res = args.prog.n_res;
+    const int node = (tile - args.tile_begin[inst]) * EZ_TILE + threadIdx.x;
+    const int n_nodes = P.n_dir * P.n_u;
+
+    double res[EZ_RES_MAX];
+#pragma unroll
+    for (int r = 0; r < EZ_RES_MAX; ++r) res[r] = 0.0;
+
+    if (M->status == 0 && node < n_nodes) {
+        const int dir = node / P.n_u;
+        const int iu = node - dir * P.n_u;
+        double B[D * D];
+#pragma unroll
+        for (int i = 0; i < D * D; ++i) B[i] = M->B[i];
+        double w[3] = {0.0, 0.0, 0.0}, wv;
+        ez_direction<D>(P, args.rules, B, dir, w, &wv);
+        const double u = args.rules[P.urule + iu];
+        const double wu = args.rules[P.urule + P.n_u + iu];
+        double k[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < D; ++i) k[i] = u * w[i];
+        double W = 2.0 * wv * wu;
+#pragma unroll
+        for (int i = 0; i < D - 1; ++i) W *= u;
+
+        double accr[NNU], acck[NNU];
+#pragma unroll
+        for (int i = 0; i < NNU; ++i) { accr[i] = 0.0; acck[i] = 0.0; }
+
+        // real space: sum over pairs of 2 W_nu(z) cos(2 pi k.z)
+        const int rs = args.tab.rstride;
+        const double *rt = args.tab.real + (size_t)inst * args.tab.real_cap * rs;
+        const int n_real = M->n_real;
+        for (int p = 0; p < n_real; ++p) {
+            const double *e = rt + (size_t)p * rs;
+            double t = k[0] * e[0];
+            if (D > 1) t = fma(k[1], e[1], t);
+            if (D > 2) t = fma(k[2], e[2], t);
+            const double c = ez_cos2pi(t);
+#pragma unroll
+            for (int i = 0; i < NNU; ++i) accr[i] = fma(e[3 + i], c, accr[i]);
+        }
+
+        // reciprocal space: sum over m* of E_{p_nu}(pi lam^2 |m* + k|^2)
+        const double *kt = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
+        const int n_rec = M->n_rec;
+        const double alpha = M->alpha, acut = M->a_cut;
+        const bool need_e1 = args.prog.need_e1 != 0, need_half = args.prog.need_half != 0;
+        for (int q = 0; q < n_rec; ++q) {
+            const double *e = kt + (size_t)q * 4;
+            double qx = e[0] + k[0];
+            double rho = qx * qx;
+            if (D > 1) { double qy = e[1] + k[1]; rho = fma(qy, qy, rho); }
+            if (D > 2) { double qz = e[2] + k[2]; rho = fma(qz, qz, rho); }
+            const double a = alpha * rho;
+            if (a <= acut) {
+                const double ex = exp(-a);
+                const double inv = 1.0 / a;
+                const double E1 = need_e1 ? ez_e1(a, ex, inv) : 0.0;
+                const double Eh = need_half ? ez_ehalf(a) : 0.0;
+#pragma unroll
+                for (int i = 0; i < NNU; ++i)
+                    acck[i] += ez_ep_from(args.prog.p2[i], a, ex, inv, E1, Eh);
+            }
+        }
+
+        double Z[NNU];
+#pragma unroll
+        for (int i = 0; i < NNU; ++i) Z[i] = accr[i] + M->K[i] * acck[i] - M->self_[i];
+
+        for (int t = 0; t < args.prog.n_terms; ++t) {
+            double prod = args.prog.term_coef[t];
+            for (int f = 0; f < args.prog.term_nfac[t]; ++f) {
+                const int fi = args.prog.term_fac[t][f];
+                double z = Z[0];
+#pragma unroll
+                for (int i = 1; i < NNU; ++i) z = (fi == i) ? Z[i] : z;
+                for (int m = 0; m < args.prog.term_mult[t][f]; ++m) prod *= z;
+            }
+            const int rr = args.prog.term_res[t];
+#pragma unroll
+            for (int r = 0; r < EZ_RES_MAX; ++r)
+                if (rr == r) res[r] += prod;
+        }
+#pragma unroll
+        for (int r = 0; r < EZ_RES_MAX; ++r) res[r] *= W;
+    }
+
+    // tile reduction: wave butterflies, then the four waves in fixed order
+    __shared__ double red[EZ_RES_MAX][EZ_TILE / 64][2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int r = 0; r < EZ_RES_MAX; ++r) {
+        if (r < n_res) {
+            ez_dd v = ez_dd_wave_sum(ez_dd{res[r], 0.0});
+            if (lane == 0) { red[r][wave][0] = v.hi; red[r][wave][1] = v.lo; }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < n_res) {
+        const int r = threadIdx.x;
+        ez_dd s{red[r][0][0], red[r][0][1]};
+        for (int wv = 1; wv < EZ_TILE / 64; ++wv) s = ez_dd_add(s, ez_dd{red[r][wv][0], red[r][wv][1]});
+        args.tile_part[((size_t)tile * n_res + r) * 2 + 0] = s.hi;
+        args.tile_part[((size_t)tile * n_res + r) * 2 + 1] = s.lo;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Hadamard part on (0, eps)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double binom(int n, int k) {
+    if (k < 0 || k > n) return 0.0;
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
+    return r;
+}
+
+__device__ __forceinline__ double fact(int n) {
+    double r = 1.0;
+    for (int i = 2; i <= n; ++i) r *= (double)i;
+    return r;
+}
+
+// fp int_0^eps u^{mu-1} L(u)^q du, L(u) = log(pi u^2 |w|^2); Leps = L(eps)
+__device__ double had_I(double mu, int q, double eps, double Leps, bool *bad) {
+    if (mu == 0.0) { *bad = true; return 0.0; }
+    const double em = pow(eps, mu);
+    const double rmu = 1.0 / mu;
+    double I = em * rmu;
+    double Lp = 1.0;
+    for (int j = 1; j <= q; ++j) {
+        Lp *= Leps;
+        I = (em * Lp - 2.0 * (double)j * I) * rmu;
+    }
+    return I;
+}
+
+template <int D>
+__global__ __launch_bounds__(64) void ez_hadamard_kernel(EzQuadArgs args, int n_dirs) {
+    const int gd = blockIdx.x * 64 + threadIdx.x;
+    if (gd >= n_dirs) return;
+    const int inst = find_segment(args.dir_begin, args.batch, gd);
+    const EzInstPlan P = args.plans[inst];
+    const EzLatMeta *M = args.meta + inst;
+    const EzProgram &prog = args.prog;
+    const int n_res = prog.n_res, n_nu = prog.n_nu;
+    if (M->status != 0) {
+        for (int r = 0; r < n_res; ++r) args.dir_part[(size_t)gd * n_res + r] = 0.0;
+        args.dir_flag[gd] = 0;
+        return;
+    }
+    const int ell = P.ell;
+    double B[D * D];
+    for (int i = 0; i < D * D; ++i) B[i] = M->B[i];
+    double w[3] = {0.0, 0.0, 0.0}, wv;
+    ez_direction<D>(P, args.rules, B, gd - args.dir_begin[inst], w, &wv);
+    double w2 = 0.0;
+    for (int i = 0; i < D; ++i) w2 += w[i] * w[i];
+    const double alpha = M->alpha;
+
+    // C[i][k]: coefficient of u^{2k} in Z^reg_{nu_i}(u w)
+    double C[EZ_NU_MAX][EZ_ELL_MAX + 1];
+    for (int i = 0; i < EZ_NU_MAX; ++i)
+        for (int k = 0; k <= EZ_ELL_MAX; ++k) C[i][k] = 0.0;
+    for (int i = 0; i < n_nu; ++i) C[i][0] -= M->self_[i];
+
+    // real space: 2 W cos(2 pi u w.z) = 2 W sum_k (-1)^k (2 pi w.z)^{2k} u^{2k} / (2k)!
+    {
+        const int rs = args.tab.rstride;
+        const double *rt = args.tab.real + (size_t)inst * args.tab.real_cap * rs;
+        for (int p = 0; p < M->n_real; ++p) {
+            const double *e = rt + (size_t)p * rs;
+            double t = 0.0;
+            for (int i = 0; i < D; ++i) t += w[i] * e[i];
+            const double x = (2.0 * EZ_PI * t) * (2.0 * EZ_PI * t);
+            double term = 1.0;
+            for (int k = 0; k <= ell; ++k) {
+                for (int i = 0; i < n_nu; ++i) C[i][k] += e[3 + i] * term;
+                term *= -x / ((2.0 * k + 1.0) * (2.0 * k + 2.0));
+            }
+        }
+    }
+    // reciprocal space, m* != 0: F(rho) = K E_p(alpha rho) at rho(u) = |m*|^2 + 2 u w.m* + u^2 |w|^2;
+    // F^(n) = K (-alpha)^n E_{p-n}; u^{2k} collects F^(n)/n! C(n, 2k-n) (2b)^{2n-2k} w2^{2k-n}
+    {
+        const double *kt = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
+        for (int q = 1; q < M->n_rec; ++q) {
+            const double *e = kt + (size_t)q * 4;
+            double b = 0.0;
+            for (int i = 0; i < D; ++i) b += w[i] * e[i];
+            const double a0 = alpha * e[3];
+            const double ex = exp(-a0), inv = 1.0 / a0;
+            const double E1 = ez_e1(a0, ex, inv);
+            const double Eh = ez_ehalf(a0);
+            const double b4 = 4.0 * b * b;
+            for (int i = 0; i < n_nu; ++i) {
+                double Fn[2 * EZ_ELL_MAX + 1];
+                int p2 = prog.p2[i];
+                double E = ez_ep_from(p2, a0, ex, inv, E1, Eh);     // E_p
+                double sc = M->K[i];
+                for (int n = 0; n <= 2 * ell; ++n) {
+                    Fn[n] = sc * E / fact(n);
+                    // E_{p-n-1} = (e^{-a} - (p-n-1) E_{p-n}) / a
+                    double pnm1 = 0.5 * (double)p2 - (double)n - 1.0;
+                    E = (ex - pnm1 * E) * inv;
+                    sc *= -alpha;
+                }
+                for (int k = 0; k <= ell; ++k) {
+                    double s = 0.0;
+                    for (int n = k; n <= 2 * k; ++n)
+                        s += Fn[n] * binom(n, 2 * k - n) * pow(b4, (double)(n - k)) * pow(w2, (double)(2 * k - n));
+                    C[i][k] += s;
+                }
+            }
+        }
+    }
+    // m* = 0: regular part of K E_p(alpha |k|^2) as a series in a = alpha w2 u^2
+    for (int i = 0; i < n_nu; ++i) {
+        const double s = 0.5 * ((double)D - prog.nu[i]);
+        const double aw = alpha * w2;
+        const int m = prog.logm[i];
+        if (m < 0) {
+            for (int j = 0; j <= ell; ++j)
+                C[i][j] += -M->K[i] * (((j & 1) ? -1.0 : 1.0) / (fact(j) * (s + (double)j))) * pow(aw, (double)j);
+        } else {
+            // K [ (-1)^{m+1}/m! a^m ln lam^2 + (-1)^m/m! ( a^m (-gamma - sum_{j>=1} (-a)^j/(j j!))
+            //     - e^{-a} sum_{i<m} (-1)^i i! a^{m-i-1} ) ]
+            const double sm = (m & 1) ? -1.0 : 1.0, mf = fact(m);
+            double cJ[EZ_ELL_MAX + 1];
+            for (int J = 0; J <= ell; ++J) cJ[J] = 0.0;
+            if (m <= ell) cJ[m] += -sm / mf * log(M->lam * M->lam) + sm / mf * (-EZ_EULER);
+            for (int j = 1; m + j <= ell; ++j) cJ[m + j] += -sm / mf * (((j & 1) ? -1.0 : 1.0) / ((double)j * fact(j)));
+            for (int ii = 0; ii < m; ++ii)
+                for (int r = 0; m - ii - 1 + r <= ell; ++r)
+                    cJ[m - ii - 1 + r] += -sm / mf * (((ii & 1) ? -1.0 : 1.0) * fact(ii)) * (((r & 1) ? -1.0 : 1.0) / fact(r));
+            for (int J = 0; J <= ell; ++J) C[i][J] += M->K[i] * cJ[J] * pow(aw, (double)J);
+        }
+    }
+
+    // products of (sigma u^e L^delta + sum_k C_k u^{2k}) and their Hadamard integrals
+    const double eps = P.eps;
+    const double Leps = log(EZ_PI * eps * eps * w2);
+    bool bad = false;
+    double H[EZ_RES_MAX];
+    for (int r = 0; r < EZ_RES_MAX; ++r) H[r] = 0.0;
+    for (int t = 0; t < prog.n_terms; ++t) {
+        const int nf = prog.term_nfac[t];
+        int mult[EZ_FAC_MAX], fac[EZ_FAC_MAX], jj[EZ_FAC_MAX];
+        double sig[EZ_FAC_MAX];
+        for (int f = 0; f < nf; ++f) {
+            fac[f] = prog.term_fac[t][f];
+            mult[f] = prog.term_mult[t][f];
+            jj[f] = 0;
+            sig[f] = M->sig[fac[f]] * pow(w2, 0.5 * prog.e[fac[f]]);
+        }
+        double tsum = 0.0;
+        while (true) {
+            double c = prog.term_coef[t];
+            double E = 0.0;
+            int Q = 0;
+            double poly[EZ_PDEG];
+            for (int J = 0; J < EZ_PDEG; ++J) poly[J] = 0.0;
+            poly[0] = 1.0;
+            int deg = 0;
+            for (int f = 0; f < nf; ++f) {
+                const int i = fac[f];
+                c *= binom(mult[f], jj[f]) * pow(sig[f], (double)jj[f]);
+                E += (double)jj[f] * prog.e[i];
+                Q += jj[f] * (prog.logm[i] >= 0 ? 1 : 0);
+                for (int rep = 0; rep < mult[f] - jj[f]; ++rep) {
+                    int nd = min(deg + ell, EZ_PDEG - 1);
+                    for (int J = nd; J >= 0; --J) {
+                        double s = 0.0;
+                        for (int kk = 0; kk <= ell && kk <= J; ++kk)
+                            if (J - kk <= deg) s += poly[J - kk] * C[i][kk];
+                        poly[J] = s;
+                    }
+                    deg = nd;
+                }
+            }
+            double acc = 0.0;
+            for (int J = 0; J <= deg; ++J)
+                if (poly[J] != 0.0) acc += poly[J] * had_I((double)D + E + 2.0 * J, Q, eps, Leps, &bad);
+            tsum += c * acc;
+            // next multi-index
+            int f = 0;
+            while (f < nf) {
+                if (++jj[f] <= mult[f]) break;
+                jj[f] = 0;
+                ++f;
+            }
+            if (f == nf) break;
+        }
+        const int rr = prog.term_res[t];
+        for (int r = 0; r < EZ_RES_MAX; ++r)
+            if (r == rr) H[r] += tsum;
+    }
+    for (int r = 0; r < n_res; ++r) args.dir_part[(size_t)gd * n_res + r] = 2.0 * wv * H[r];
+    args.dir_flag[gd] = bad ? 1u : 0u;
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void ez_finalize_kernel(EzQuadArgs args) {
+    const int inst = blockIdx.x;
+    const int n_res = args.prog.n_res;
+    const int tb = args.tile_begin[inst], te = args.tile_begin[inst + 1];
+    const int db = args.dir_begin[inst], de = args.dir_begin[inst + 1];
+    __shared__ double red[256 / 64][2];
+    __shared__ uint32_t flag_sh;
+    if (threadIdx.x == 0) flag_sh = 0;
+    __syncthreads();
+    uint32_t fl = 0;
+    for (int g = db + (int)threadIdx.x; g < de; g += 256) fl |= args.dir_flag[g];
+    if (fl) atomicOr(&flag_sh, 1u);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int r = 0; r < n_res; ++r) {
+        ez_dd s{0.0, 0.0};
+        for (int t = tb + (int)threadIdx.x; t < te; t += 256)
+            s = ez_dd_add(s, ez_dd{args.tile_part[((size_t)t * n_res + r) * 2], args.tile_part[((size_t)t * n_res + r) * 2 + 1]});
+        for (int g = db + (int)threadIdx.x; g < de; g += 256)
+            s = ez_dd_add_d(s, args.dir_part[(size_t)g * n_res + r]);
+        s = ez_dd_wave_sum(s);
+        __syncthreads();
+        if (lane == 0) { red[wave][0] = s.hi; red[wave][1] = s.lo; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            ez_dd tot{red[0][0], red[0][1]};
+            for (int w = 1; w < 256 / 64; ++w) tot = ez_dd_add(tot, ez_dd{red[w][0], red[w][1]});
+            double v = tot.hi + tot.lo;
+            uint32_t st = args.meta[inst].status;
+            if (flag_sh) st |= 0x8u;
+            if (st) v = __longlong_as_double(0x7ff8000000000000ll);
+            else if (!isfinite(v)) st |= 0x4u;
+            args.out[(size_t)inst * n_res + r] = v;
+            if (args.status && r == 0) args.status[inst] = st;
+        }
+    }
+}
+
+template <int D, int NNU>
+hipError_t launch_nodes_t(const EzQuadArgs &args, int n_tiles, hipStream_t stream) {
+    hipLaunchKernelGGL((ez_node_kernel<D, NNU>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
+    return hipGetLastError();
+}
+
+template <int D>
+hipError_t launch_nodes_d(const EzQuadArgs &args, int n_tiles, hipStream_t stream) {
+    switch (args.prog.n_nu) {
+        case 1: return launch_nodes_t<D, 1>(args, n_tiles, stream);
+        case 2: return launch_nodes_t<D, 2>(args, n_tiles, stream);
+        case 3: return launch_nodes_t<D, 3>(args, n_tiles, stream);
+        case 4: return launch_nodes_t<D, 4>(args, n_tiles, stream);
+        case 5: return launch_nodes_t<D, 5>(args, n_tiles, stream);
+        case 6: return launch_nodes_t<D, 6>(args, n_tiles, stream);
+        case 7: return launch_nodes_t<D, 7>(args, n_tiles, stream);
+        case 8: return launch_nodes_t<D, 8>(args, n_tiles, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t ez_launch_nodes(const EzQuadArgs &args, int n_tiles, hipStream_t stream) {
+    switch (args.prog.d) {
+        case 1: return launch_nodes_d<1>(args, n_tiles, stream);
+        case 2: return launch_nodes_d<2>(args, n_tiles, stream);
+        case 3: return launch_nodes_d<3>(args, n_tiles, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t ez_launch_hadamard(const EzQuadArgs &args, int n_dirs, hipStream_t stream) {
+    const int blocks = (n_dirs + 63) / 64;
+    switch (args.prog.d) {
+        case 1: hipLaunchKernelGGL(ez_hadamard_kernel<1>, dim3(blocks), dim3(64), 0, stream, args, n_dirs); break;
+        case 2: hipLaunchKernelGGL(ez_hadamard_kernel<2>, dim3(blocks), dim3(64), 0, stream, args, n_dirs); break;
+        case 3: hipLaunchKernelGGL(ez_hadamard_kernel<3>, dim3(blocks), dim3(64), 0, stream, args, n_dirs); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t ez_launch_finalize(const EzQuadArgs &args, hipStream_t stream) {
+    hipLaunchKernelGGL(ez_finalize_kernel, dim3(args.batch), dim3(256), 0, stream, args);
+    return hipGetLastError();
+}

@@ -1,0 +1,138 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle on the same
+seeded inputs and the same quadrature plans.  FP64 bar: 1e-12 relative."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ez():
+    import paper_2504_11989_amd as ez
+    ez.version()                     # raises if the HIP library is missing
+    return ez
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+# ---------------------------------------------------------------- Epstein zeta at points
+def test_c1_spot_values(ez):
+    nus, xs, ys = W.c1_spot_values()
+    z = ez.epstein_zeta(np.eye(1), [1.5, 2.0, 3.0, 4.5], xs, ys).cpu().numpy()
+    col = {1.5: 0, 2.0: 1, 3.0: 2, 4.5: 3}
+    for i, (nu, x, y) in enumerate(zip(nus, xs, ys)):
+        ref = O.epstein(np.eye(1), nu, [x], [y])
+        assert abs(z[col[nu], i] - ref) <= TOL * abs(ref), (i, nu, x, y)
+
+
+def test_epstein_origin_and_lattice_points(ez):
+    # Z(0,0) (y on Lambda*: continuation), x on the lattice, y on the reciprocal lattice
+    for A in [np.eye(1), np.eye(2), W.A_HEX, W.sc(), W.fcc(), W.bcc()]:
+        d = A.shape[0]
+        B = np.linalg.inv(A).T
+        pts_x = np.stack([np.zeros(d), A @ np.ones(d), np.full(d, 0.3)])
+        pts_y = np.stack([np.zeros(d), np.full(d, 0.17), B @ np.ones(d)])
+        nus = [-1.0, 1.5, 4.0, 6.0] if d != 1 else [-1.0, 0.5, 3.0, 4.0]
+        z = ez.epstein_zeta(A, nus, pts_x, pts_y).cpu().numpy()
+        for j, nu in enumerate(nus):
+            for i in range(3):
+                ref = O.epstein(A, nu, pts_x[i], pts_y[i])
+                assert abs(z[j, i] - ref) <= TOL * max(abs(ref), 1.0), (d, nu, i)
+
+
+def test_epstein_random_points_3d(ez):
+    rng = np.random.default_rng(11)
+    A = W.bct(1.23)
+    x = rng.uniform(-2, 2, size=(37, 3))
+    y = rng.uniform(-2, 2, size=(37, 3))
+    nus = [-1.0, 1.0, 2.5, 5.0, 9.0]
+    z = ez.epstein_zeta(A, nus, x, y).cpu().numpy()
+    for j, nu in enumerate(nus):
+        for i in range(0, 37, 6):
+            ref = O.epstein(A, nu, x[i], y[i])
+            assert abs(z[j, i] - ref) <= TOL * max(abs(ref), 1.0), (nu, i)
+
+
+def test_epstein_empty_batch(ez):
+    z = ez.epstein_zeta(np.eye(3), [3.0], np.zeros((0, 3)), np.zeros((0, 3)))
+    assert z.shape == (1, 0)
+
+
+# ---------------------------------------------------------------- quadrature: n-body sums
+def test_c1_three_body_1d(ez):
+    v = ez.nbody_lattice_sum(np.eye(1), [3, 3, 3], W.SPEC_1D).item()
+    ref = O.nbody(np.eye(1), [3, 3, 3], W.SPEC_1D)
+    assert rel(v, ref) <= TOL
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_atm_small_plans(ez, d):
+    lats = {1: [np.eye(1)], 2: [np.eye(2), W.A_HEX], 3: [W.sc(), W.fcc(), W.bcc()]}[d]
+    spec = {1: W.SPEC_1D, 2: dict(W.SPEC_2D, n_q=9, n_panels=3, n_g=11), 3: W.SPEC_SMALL_3D}[d]
+    A = np.stack(lats)
+    got = ez.atm_energy(A, spec).cpu().numpy()
+    for i, Ai in enumerate(lats):
+        assert rel(got[i], O.atm(Ai, spec)) <= TOL, (d, i)
+
+
+@pytest.mark.parametrize("nus", [(3, 3), (-1, 5), (1, 3), (6, 6, 6), (3, 5, 7, 9)])
+def test_nbody_3d_small_plan(ez, nus):
+    spec = dict(W.SPEC_SMALL_3D, n_q=5, n_panels=2, n_g=7)     # 12*25*14 = 4200 nodes: ragged tile
+    A = np.stack([W.fcc(), W.bct(0.9)])
+    got = ez.nbody_lattice_sum(A, nus, spec).cpu().numpy()
+    for i in range(2):
+        assert rel(got[i], O.nbody(A[i], nus, spec)) <= TOL, (nus, i)
+
+
+def test_lattice_sums_multi_result(ez):
+    # C3-style program: zeta(nu,nu,nu) for nu in {3,6,9,12} plus ATM, one node pass
+    nu = [-1.0, 1.0, 3.0, 5.0, 6.0, 9.0, 12.0]
+    terms = [(0, 1.0, [(2, 3)]), (1, 1.0, [(4, 3)]), (2, 1.0, [(5, 3)]), (3, 1.0, [(6, 3)]),
+             (4, 1.0 / 24.0, [(2, 3)]), (4, -3.0 / 16.0, [(0, 1), (3, 2)]), (4, 3.0 / 8.0, [(1, 1), (2, 1), (3, 1)])]
+    ca = [0.85, 1.0, 1.3]
+    A = np.stack([W.bct(c) for c in ca])
+    specs = [W.c3_spec(n) for n in (16, 20, 24)]
+    got = ez.lattice_sums(A, nu, terms, 5, specs).cpu().numpy()
+    for i in range(3):
+        for r, nus in enumerate([(3, 3, 3), (6, 6, 6), (9, 9, 9), (12, 12, 12)]):
+            assert rel(got[i, r], O.nbody(A[i], nus, specs[i])) <= TOL, (i, r)
+        assert rel(got[i, 4], O.atm(A[i], specs[i])) <= TOL, i
+
+
+def test_bad_lattice_flags_without_failing_batch(ez):
+    A = np.stack([W.sc(), np.zeros((3, 3)), W.fcc()])
+    out, st = ez.atm_energy(A, W.SPEC_SMALL_3D, with_status=True)
+    out = out.cpu().numpy()
+    st = st.cpu().numpy()
+    assert st[0] == 0 and st[2] == 0 and (st[1] & ez.FLAG_SINGULAR)
+    assert np.isnan(out[1]) and np.isfinite(out[0]) and np.isfinite(out[2])
+    assert rel(out[2], O.atm(W.fcc(), W.SPEC_SMALL_3D)) <= TOL
+
+
+def test_determinism(ez):
+    A = np.stack([W.sc(), W.bcc()])
+    a = ez.atm_energy(A, W.SPEC_SMALL_3D).cpu().numpy()
+    b = ez.atm_energy(A, W.SPEC_SMALL_3D).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------- full-size C2 (bench config)
+def test_c2_full_size_vs_stored_oracle(ez):
+    g = json.load(open(os.path.join(GOLD, "oracle_c2_full.json")))
+    names = ["sc", "fcc", "bcc"]
+    A = np.stack([W.c2_lattices()[n] for n in names])
+    got = ez.atm_energy(A, g["spec"]).cpu().numpy()
+    for i, n in enumerate(names):
+        assert rel(got[i], g["atm"][n]) <= TOL, n
