@@ -1,0 +1,164 @@
+#!/usr/bin/env python3
+"""Benchmark of the Epstein-zeta hot path on one MI355X.
+
+Workload (one step): the ATM cohesive energy per particle of the sc, fcc and
+bcc lattices at unit density, d = 3, FP64, each on a 263424-node plan
+(12 Duffy blocks x 14^2 Gauss-Legendre v-nodes x 112 u-nodes on 7 geometric
+panels toward k = 0, plus the Taylor/Hadamard part on (0, 1e-2)).  One step
+is one ez_atm_energy call on the batch of three generator matrices already
+resident in HBM: lattice tables, nodes, reciprocal and real-space sums,
+singular split, products, Hadamard part and fixed-order reduction.
+
+Prints one JSON line.  `value` = ATM lattice sums per second.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_VALU_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+METRIC = "ATM lattice sums/s and Epstein-zeta evals/s at 1e-12 rel err, FP64 vs mixed"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nodes_c2.json")
+KERNEL_SOURCES = ["ez_quad.hip", "ez_math.h", "ez_internal.h", "e1_rational.h"]
+
+
+def node_kernel_flops_per_node(lam_rel: float, a_cut: float, n_nu: int, d: int = 3) -> float:
+    """Algorithmic FP64 flops of one quadrature node (unit-density lattice):
+    N_rec reciprocal terms x (8 for |m*+k|^2, 70 for exp + E1, 30 for the E_p ladder
+    and accumulation of 4 exponents) + N_real real-space pairs x (5 dot + 20 cos +
+    2 per exponent), with N_rec = |ball of radius sqrt(a_cut/pi)/lam| and
+    N_real = |ball of radius lam sqrt(a_cut/pi)| / 2 (lattice and reciprocal lattice
+    of unit covolume)."""
+    import math
+    r = math.sqrt(a_cut / math.pi)
+    ball = {1: 2.0, 2: math.pi, 3: 4.0 * math.pi / 3.0}[d]
+    n_rec = ball * (r / lam_rel) ** d
+    n_real = 0.5 * ball * (r * lam_rel) ** d
+    rec_term = 8.0 + 70.0 + 7.5 * n_nu
+    real_term = (2 * d - 1) + 20.0 + 2.0 * n_nu
+    return n_rec * rec_term + n_real * real_term
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2504_11989_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(spec) -> dict:
+    """The oracle (oracle/ezo.c, OpenMP over directions) on one of the three
+    lattices (sc) at the full plan."""
+    import oracle
+    import workloads as W
+    t0 = time.perf_counter()
+    oracle.atm(W.sc(), spec)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "ATM lattice sums/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "one lattice (sc) of the three, full 263424-node plan, %.1f s" % dt}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the lattice sums shard trivially "
+              "by lattice or node tile; no multi-GPU path is built)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2504_11989_amd as ez
+    from paper_2504_11989_amd import _native as nat
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    spec = dict(W.SPEC_FULL_3D)
+    names = ["sc", "fcc", "bcc"]
+    A = torch.tensor(np.stack([W.c2_lattices()[n] for n in names]), dtype=torch.float64, device=dev)
+    nodes = W.n_nodes(3, spec)
+    n_nu = 4
+
+    out = ez.atm_energy(A, spec)
+    for _ in range(args.warmup):
+        out = ez.atm_energy(A, spec)
+    torch.cuda.synchronize()
+
+    # accuracy against the oracle on the identical plan (stored by tests/golden/make_oracle_golden.py)
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_c2_full.json")))
+    got = out.cpu().numpy()
+    max_rel = max(abs(got[i] - gold["atm"][n]) / abs(gold["atm"][n]) for i, n in enumerate(names))
+
+    nat.timing_reset()
+    nat.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = ez.atm_energy(A, spec)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nat.timing_enable(False)
+    kt = {k: nat.timing_read(i) for k, i in [("setup", nat.KERNEL_SETUP), ("nodes", nat.KERNEL_NODES),
+                                              ("hadamard", nat.KERNEL_HADAMARD),
+                                              ("finalize", nat.KERNEL_FINALIZE)]}
+    elapsed = t1 - t0
+    ms_step = 1e3 * elapsed / args.steps
+    sums_per_s = len(names) * args.steps / elapsed
+    evals_per_s = len(names) * nodes * n_nu * args.steps / elapsed
+
+    node_ms = kt["nodes"][0] / max(1, kt["nodes"][1])
+    flops_launch = node_kernel_flops_per_node(spec["lam"], spec["a_cut"], n_nu) * nodes * len(names)
+    achieved = flops_launch / (node_ms * 1e-3) / 1e12
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("kernel_source_sha") == kernel_source_sha():
+            traffic = tr["bytes_per_launch"]
+    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP64_VALU_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_VALU_TFLOPS, 5), "traffic": traffic,
+                "kernel": "ez_node_kernel<3,4>", "kernel_ms": round(node_ms, 5),
+                "flops_per_launch": flops_launch}
+
+    line = {
+        "metric": METRIC,
+        "value": sums_per_s,
+        "unit": "ATM lattice sums/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "d=3 ATM cohesive energy per particle, sc/fcc/bcc at unit density, "
+                               "263424 nodes per lattice (12 Duffy blocks x 14^2 v x 112 graded u) + Hadamard part, FP64",
+                   "lattices": len(names), "nodes_per_lattice": nodes, "spec": spec},
+        "epstein_evals_per_s": evals_per_s,
+        "max_rel_err_vs_oracle": max_rel,
+        "kernel_ms": {k: round(v[0] / max(1, v[1]), 5) for k, v in kt.items()},
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(spec)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -131,6 +131,20 @@ ez_status ez_lattice_sums(int batch, int d, const double *A_dev, int n_nu, const
                           int n_results, const ez_quad_spec *specs, int n_specs, double *out_dev,
                           uint32_t *status_dev, void *stream);
 
+/* Kernel timing (tracing aid).  When enabled, every kernel the library launches
+ * is bracketed by a pair of HIP events recorded on the launch stream; reading
+ * synchronises the recorded events and returns the accumulated elapsed time and
+ * launch count of one kernel kind.  Costs two event records per launch. */
+#define EZ_KERNEL_SETUP 0      /* per-lattice tables                    */
+#define EZ_KERNEL_NODES 1      /* quadrature nodes on (eps, 1/2]         */
+#define EZ_KERNEL_HADAMARD 2   /* Taylor / Hadamard part on (0, eps)     */
+#define EZ_KERNEL_FINALIZE 3   /* fixed-order reduction                  */
+#define EZ_KERNEL_EPSTEIN 4    /* Z(x, y) at arbitrary points            */
+#define EZ_KERNEL_COUNT 5
+ez_status ez_timing_enable(int enable);
+ez_status ez_timing_reset(void);
+ez_status ez_timing_read(int kernel, double *total_ms, int64_t *launches);
+
 /* Text of the last error on the calling host thread (never NULL). */
 const char *ez_last_error(void);
 

@@ -21,7 +21,9 @@ PREC_FP64, PREC_MIXED = 0, 1
 
 # every symbol declared in include/ezeta.h
 EXPORTED = ("ez_epstein_zeta", "ez_nbody_lattice_sum", "ez_atm_energy", "ez_lattice_sums",
+            "ez_timing_enable", "ez_timing_reset", "ez_timing_read",
             "ez_last_error", "ez_finalize", "ez_version")
+KERNEL_SETUP, KERNEL_NODES, KERNEL_HADAMARD, KERNEL_FINALIZE, KERNEL_EPSTEIN = 0, 1, 2, 3, 4
 
 
 class EzError(RuntimeError):
@@ -72,6 +74,12 @@ def lib():
     L.ez_finalize.argtypes = []
     L.ez_version.restype = ctypes.c_char_p
     L.ez_version.argtypes = []
+    L.ez_timing_enable.restype = I
+    L.ez_timing_enable.argtypes = [I]
+    L.ez_timing_reset.restype = I
+    L.ez_timing_reset.argtypes = []
+    L.ez_timing_read.restype = I
+    L.ez_timing_read.argtypes = [I, P, ctypes.POINTER(I64)]
     _lib = L
     return L
 
@@ -79,3 +87,19 @@ def lib():
 def check(code: int):
     if code != EZ_OK:
         raise EzError(code, lib().ez_last_error().decode())
+
+
+def timing_enable(on: bool = True):
+    check(lib().ez_timing_enable(1 if on else 0))
+
+
+def timing_reset():
+    check(lib().ez_timing_reset())
+
+
+def timing_read(kernel: int):
+    """(total milliseconds, launches) recorded for one kernel kind."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    check(lib().ez_timing_read(int(kernel), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value

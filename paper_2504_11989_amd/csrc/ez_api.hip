@@ -94,8 +94,8 @@ ez_status grow(DevBuf &b, size_t bytes) {
 
 // A plan depends only on (d, batch, specs): rule tables, per-lattice plans, prefixes.
 struct DevPlan {
-    DevBuf rules, plans, tile_begin, dir_begin;
-    int n_tiles = 0, n_dirs = 0;
+    DevBuf rules, plans, tile_begin, dir_begin, htile_begin;
+    int n_tiles = 0, n_dirs = 0, n_htiles = 0;
     std::vector<EzInstPlan> host_plans;
 };
 
@@ -108,6 +108,42 @@ struct DeviceState {
 
 std::mutex g_mu;
 std::map<int, DeviceState *> g_dev;
+
+// ---- optional per-kernel timing with HIP events on the launch stream ----
+struct TimedLaunch { hipEvent_t a, b; int kernel; };
+bool g_timing = false;
+std::vector<TimedLaunch> g_pending;
+double g_ms[EZ_KERNEL_COUNT] = {0};
+long long g_calls[EZ_KERNEL_COUNT] = {0};
+
+void timing_flush() {
+    for (auto &t : g_pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(t.b) == hipSuccess && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+            g_ms[t.kernel] += ms;
+            g_calls[t.kernel] += 1;
+        }
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    g_pending.clear();
+}
+
+// records an event pair around `launch` when timing is on
+template <class F>
+hipError_t timed(int kernel, hipStream_t s, F launch) {
+    if (!g_timing) return launch();
+    if (g_pending.size() >= 4096) timing_flush();
+    TimedLaunch t;
+    t.kernel = kernel;
+    if (hipEventCreate(&t.a) != hipSuccess) return launch();
+    if (hipEventCreate(&t.b) != hipSuccess) { (void)hipEventDestroy(t.a); return launch(); }
+    (void)hipEventRecord(t.a, s);
+    hipError_t e = launch();
+    (void)hipEventRecord(t.b, s);
+    g_pending.push_back(t);
+    return e;
+}
 
 DeviceState *device_state(int dev) {
     auto it = g_dev.find(dev);
@@ -125,6 +161,7 @@ void free_buf(DevBuf &b) {
 
 void free_plan(DevPlan *p) {
     free_buf(p->rules); free_buf(p->plans); free_buf(p->tile_begin); free_buf(p->dir_begin);
+    free_buf(p->htile_begin);
     delete p;
 }
 
@@ -231,8 +268,8 @@ ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, 
     std::map<std::string, int> urule_of;
     DevPlan *P = new DevPlan();
     P->host_plans.resize(batch);
-    std::vector<int> tb(batch + 1, 0), db(batch + 1, 0);
-    long long tiles = 0, dirs = 0;
+    std::vector<int> tb(batch + 1, 0), db(batch + 1, 0), hb(batch + 1, 0);
+    long long tiles = 0, dirs = 0, htiles = 0;
     for (int b = 0; b < batch; ++b) {
         const ez_quad_spec &s = specs[n_specs == 1 ? 0 : b];
         EzInstPlan &ip = P->host_plans[b];
@@ -279,8 +316,10 @@ ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, 
         ip.dir_begin = (int)dirs;
         tb[b] = (int)tiles;
         db[b] = (int)dirs;
+        hb[b] = (int)htiles;
         tiles += (nn + EZ_TILE - 1) / EZ_TILE;
         dirs += nd;
+        htiles += (nd + 63) / 64;
         if (tiles > (1ll << 30) || dirs > (1ll << 30)) {
             delete P;
             return fail(EZ_ERR_INVALID_ARG, "quadrature too large for one call");
@@ -288,13 +327,16 @@ ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, 
     }
     tb[batch] = (int)tiles;
     db[batch] = (int)dirs;
+    hb[batch] = (int)htiles;
     P->n_tiles = (int)tiles;
     P->n_dirs = (int)dirs;
+    P->n_htiles = (int)htiles;
     ez_status st;
     if ((st = grow(P->rules, rules.size() * sizeof(double))) ||
         (st = grow(P->plans, sizeof(EzInstPlan) * batch)) ||
         (st = grow(P->tile_begin, sizeof(int) * (batch + 1))) ||
-        (st = grow(P->dir_begin, sizeof(int) * (batch + 1)))) {
+        (st = grow(P->dir_begin, sizeof(int) * (batch + 1))) ||
+        (st = grow(P->htile_begin, sizeof(int) * (batch + 1)))) {
         free_plan(P);
         return st;
     }
@@ -302,7 +344,8 @@ ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, 
     if (hipMemcpy(P->rules.p, rules.data(), rules.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(P->plans.p, P->host_plans.data(), sizeof(EzInstPlan) * batch, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(P->tile_begin.p, tb.data(), sizeof(int) * (batch + 1), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(P->dir_begin.p, db.data(), sizeof(int) * (batch + 1), hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(P->dir_begin.p, db.data(), sizeof(int) * (batch + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(P->htile_begin.p, hb.data(), sizeof(int) * (batch + 1), hipMemcpyHostToDevice) != hipSuccess) {
         free_plan(P);
         return fail(EZ_ERR_HIP, "upload of the quadrature plan failed");
     }
@@ -369,7 +412,7 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     sa.a_cut = acut;
     sa.general_x = 0;
     sa.status_out = nullptr;
-    EZ_HIP_TRY(ez_launch_setup(sa, batch, stream));
+    EZ_HIP_TRY(timed(EZ_KERNEL_SETUP, stream, [&] { return ez_launch_setup(sa, batch, stream); }));
 
     EzQuadArgs qa;
     qa.prog = prog;
@@ -377,6 +420,7 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     qa.plans = (const EzInstPlan *)P->plans.p;
     qa.tile_begin = (const int *)P->tile_begin.p;
     qa.dir_begin = (const int *)P->dir_begin.p;
+    qa.htile_begin = (const int *)P->htile_begin.p;
     qa.meta = (const EzLatMeta *)S->meta.p;
     qa.tab = tab;
     qa.rules = (const double *)P->rules.p;
@@ -385,9 +429,9 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     qa.dir_flag = (uint32_t *)S->dir_flag.p;
     qa.out = out_dev;
     qa.status = status_dev;
-    EZ_HIP_TRY(ez_launch_nodes(qa, P->n_tiles, stream));
-    EZ_HIP_TRY(ez_launch_hadamard(qa, P->n_dirs, stream));
-    EZ_HIP_TRY(ez_launch_finalize(qa, stream));
+    EZ_HIP_TRY(timed(EZ_KERNEL_NODES, stream, [&] { return ez_launch_nodes(qa, P->n_tiles, stream); }));
+    EZ_HIP_TRY(timed(EZ_KERNEL_HADAMARD, stream, [&] { return ez_launch_hadamard(qa, P->n_htiles, stream); }));
+    EZ_HIP_TRY(timed(EZ_KERNEL_FINALIZE, stream, [&] { return ez_launch_finalize(qa, stream); }));
     return EZ_OK;
 }
 
@@ -408,6 +452,7 @@ const char *ez_version(void) { return "libezeta 0.1 (gfx950, FP64)"; }
 
 ez_status ez_finalize(void) {
     std::lock_guard<std::mutex> lock(g_mu);
+    timing_flush();
     int cur = 0;
     (void)hipGetDevice(&cur);
     for (auto &kv : g_dev) {
@@ -544,7 +589,7 @@ ez_status ez_epstein_zeta(int d, const double *A_dev, int n_nu, const double *nu
     sa.a_cut = a_cut;
     sa.general_x = 1;
     sa.status_out = status_dev;
-    EZ_HIP_TRY(ez_launch_setup(sa, 1, s));
+    EZ_HIP_TRY(timed(EZ_KERNEL_SETUP, s, [&] { return ez_launch_setup(sa, 1, s); }));
     EzEpsteinArgs ea;
     std::memset(&ea, 0, sizeof(ea));
     ea.d = d;
@@ -557,7 +602,30 @@ ez_status ez_epstein_zeta(int d, const double *A_dev, int n_nu, const double *nu
     ea.tab = tab;
     ea.out = out_dev;
     ea.status = status_dev;
-    EZ_HIP_TRY(ez_launch_epstein(ea, s));
+    EZ_HIP_TRY(timed(EZ_KERNEL_EPSTEIN, s, [&] { return ez_launch_epstein(ea, s); }));
+    return EZ_OK;
+}
+
+ez_status ez_timing_enable(int enable) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_timing = enable != 0;
+    return EZ_OK;
+}
+
+ez_status ez_timing_reset(void) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    timing_flush();
+    for (int i = 0; i < EZ_KERNEL_COUNT; ++i) { g_ms[i] = 0.0; g_calls[i] = 0; }
+    return EZ_OK;
+}
+
+ez_status ez_timing_read(int kernel, double *total_ms, int64_t *launches) {
+    if (kernel < 0 || kernel >= EZ_KERNEL_COUNT || !total_ms || !launches)
+        return fail(EZ_ERR_INVALID_ARG, "kernel id out of range or null pointer");
+    std::lock_guard<std::mutex> lock(g_mu);
+    timing_flush();
+    *total_ms = g_ms[kernel];
+    *launches = g_calls[kernel];
     return EZ_OK;
 }
 

@@ -19,6 +19,7 @@ struct EzQuadArgs {
     const EzInstPlan *plans;
     const int *tile_begin;     // batch + 1 prefix of node tiles
     const int *dir_begin;      // batch + 1 prefix of directions
+    const int *htile_begin;    // batch + 1 prefix of 64-direction Hadamard tiles
     const EzLatMeta *meta;
     EzTables tab;
     const double *rules;       // Gauss rules (v on [0,1], u on (eps,1/2])
@@ -42,6 +43,6 @@ struct EzEpsteinArgs {
 
 hipError_t ez_launch_setup(const EzSetupArgs &args, int batch, hipStream_t stream);
 hipError_t ez_launch_nodes(const EzQuadArgs &args, int n_tiles, hipStream_t stream);
-hipError_t ez_launch_hadamard(const EzQuadArgs &args, int n_dirs, hipStream_t stream);
+hipError_t ez_launch_hadamard(const EzQuadArgs &args, int n_htiles, hipStream_t stream);
 hipError_t ez_launch_finalize(const EzQuadArgs &args, hipStream_t stream);
 hipError_t ez_launch_epstein(const EzEpsteinArgs &args, hipStream_t stream);

@@ -9,7 +9,7 @@
 //                    the exponent set by the split (real-space table + reciprocal
 //                    table), the products of the terms, weight, then a
 //                    double-double reduction to one partial per 256-node tile.
-// ez_hadamard_kernel: u in (0, eps).  One thread per direction w: Taylor
+// ez_hadamard_kernel: u in (0, eps).  One thread per direction w (64 per workgroup): Taylor
 //                    coefficients of Z^reg_nu(u w) in u, expansion of the products
 //                    of (singular + Taylor) factors and closed-form Hadamard integrals.
 // ez_finalize_kernel: fixed-order double-double sum of tiles and directions.
@@ -215,123 +215,226 @@ __device__ double had_I(double mu, int q, double eps, double Leps, bool *bad) {
     return I;
 }
 
-template <int D>
-__global__ __launch_bounds__(64) void ez_hadamard_kernel(EzQuadArgs args, int n_dirs) {
-    const int gd = blockIdx.x * 64 + threadIdx.x;
-    if (gd >= n_dirs) return;
-    const int inst = find_segment(args.dir_begin, args.batch, gd);
+constexpr int EZ_HCH = 32;                      // m* per LDS chunk in the Hadamard kernel
+constexpr int EZ_NF = 2 * EZ_ELL_MAX + 1;       // derivative orders 0..2 ell
+
+// binomial coefficient as a compile-time constant after unrolling
+__host__ __device__ constexpr double cbinom(int n, int k) {
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
+    return (k < 0 || k > n) ? 0.0 : r;
+}
+
+// One thread per direction w, 64 directions of one lattice per workgroup.
+template <int D, int NNU>
+__global__ __launch_bounds__(64) void ez_hadamard_kernel(EzQuadArgs args) {
+    __shared__ double fsh[EZ_HCH][NNU][EZ_NF];
+    const int blk = blockIdx.x;
+    const int inst = find_segment(args.htile_begin, args.batch, blk);
     const EzInstPlan P = args.plans[inst];
     const EzLatMeta *M = args.meta + inst;
     const EzProgram &prog = args.prog;
-    const int n_res = prog.n_res, n_nu = prog.n_nu;
-    if (M->status != 0) {
-        for (int r = 0; r < n_res; ++r) args.dir_part[(size_t)gd * n_res + r] = 0.0;
-        args.dir_flag[gd] = 0;
+    const int n_res = prog.n_res;
+    const int dloc = (blk - args.htile_begin[inst]) * 64 + (int)threadIdx.x;
+    const bool valid = dloc < P.n_dir;
+    const int gd = P.dir_begin + dloc;
+    if (M->status != 0) {                      // uniform over the workgroup
+        if (valid) {
+            for (int r = 0; r < n_res; ++r) args.dir_part[(size_t)gd * n_res + r] = 0.0;
+            args.dir_flag[gd] = 0;
+        }
         return;
     }
     const int ell = P.ell;
     double B[D * D];
+#pragma unroll
     for (int i = 0; i < D * D; ++i) B[i] = M->B[i];
-    double w[3] = {0.0, 0.0, 0.0}, wv;
-    ez_direction<D>(P, args.rules, B, gd - args.dir_begin[inst], w, &wv);
+    double w[3] = {0.0, 0.0, 0.0}, wv = 0.0;
+    ez_direction<D>(P, args.rules, B, valid ? dloc : 0, w, &wv);
     double w2 = 0.0;
-    for (int i = 0; i < D; ++i) w2 += w[i] * w[i];
+#pragma unroll
+    for (int i = 0; i < D; ++i) w2 = fma(w[i], w[i], w2);
     const double alpha = M->alpha;
+    double pw2[EZ_ELL_MAX + 1];
+    pw2[0] = 1.0;
+#pragma unroll
+    for (int j = 1; j <= EZ_ELL_MAX; ++j) pw2[j] = pw2[j - 1] * w2;
 
     // C[i][k]: coefficient of u^{2k} in Z^reg_{nu_i}(u w)
-    double C[EZ_NU_MAX][EZ_ELL_MAX + 1];
-    for (int i = 0; i < EZ_NU_MAX; ++i)
+    double C[NNU][EZ_ELL_MAX + 1];
+#pragma unroll
+    for (int i = 0; i < NNU; ++i) {
+#pragma unroll
         for (int k = 0; k <= EZ_ELL_MAX; ++k) C[i][k] = 0.0;
-    for (int i = 0; i < n_nu; ++i) C[i][0] -= M->self_[i];
+        C[i][0] = -M->self_[i];
+    }
 
     // real space: 2 W cos(2 pi u w.z) = 2 W sum_k (-1)^k (2 pi w.z)^{2k} u^{2k} / (2k)!
     {
         const int rs = args.tab.rstride;
         const double *rt = args.tab.real + (size_t)inst * args.tab.real_cap * rs;
-        for (int p = 0; p < M->n_real; ++p) {
+        const int n_real = M->n_real;
+        for (int p = 0; p < n_real; ++p) {
             const double *e = rt + (size_t)p * rs;
             double t = 0.0;
-            for (int i = 0; i < D; ++i) t += w[i] * e[i];
+#pragma unroll
+            for (int i = 0; i < D; ++i) t = fma(w[i], e[i], t);
             const double x = (2.0 * EZ_PI * t) * (2.0 * EZ_PI * t);
             double term = 1.0;
-            for (int k = 0; k <= ell; ++k) {
-                for (int i = 0; i < n_nu; ++i) C[i][k] += e[3 + i] * term;
-                term *= -x / ((2.0 * k + 1.0) * (2.0 * k + 2.0));
-            }
-        }
-    }
-    // reciprocal space, m* != 0: F(rho) = K E_p(alpha rho) at rho(u) = |m*|^2 + 2 u w.m* + u^2 |w|^2;
-    // F^(n) = K (-alpha)^n E_{p-n}; u^{2k} collects F^(n)/n! C(n, 2k-n) (2b)^{2n-2k} w2^{2k-n}
-    {
-        const double *kt = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
-        for (int q = 1; q < M->n_rec; ++q) {
-            const double *e = kt + (size_t)q * 4;
-            double b = 0.0;
-            for (int i = 0; i < D; ++i) b += w[i] * e[i];
-            const double a0 = alpha * e[3];
-            const double ex = exp(-a0), inv = 1.0 / a0;
-            const double E1 = ez_e1(a0, ex, inv);
-            const double Eh = ez_ehalf(a0);
-            const double b4 = 4.0 * b * b;
-            for (int i = 0; i < n_nu; ++i) {
-                double Fn[2 * EZ_ELL_MAX + 1];
-                int p2 = prog.p2[i];
-                double E = ez_ep_from(p2, a0, ex, inv, E1, Eh);     // E_p
-                double sc = M->K[i];
-                for (int n = 0; n <= 2 * ell; ++n) {
-                    Fn[n] = sc * E / fact(n);
-                    // E_{p-n-1} = (e^{-a} - (p-n-1) E_{p-n}) / a
-                    double pnm1 = 0.5 * (double)p2 - (double)n - 1.0;
-                    E = (ex - pnm1 * E) * inv;
-                    sc *= -alpha;
-                }
-                for (int k = 0; k <= ell; ++k) {
-                    double s = 0.0;
-                    for (int n = k; n <= 2 * k; ++n)
-                        s += Fn[n] * binom(n, 2 * k - n) * pow(b4, (double)(n - k)) * pow(w2, (double)(2 * k - n));
-                    C[i][k] += s;
+#pragma unroll
+            for (int k = 0; k <= EZ_ELL_MAX; ++k) {
+                if (k <= ell) {
+#pragma unroll
+                    for (int i = 0; i < NNU; ++i) C[i][k] = fma(e[3 + i], term, C[i][k]);
+                    term *= -x / ((2.0 * k + 1.0) * (2.0 * k + 2.0));
                 }
             }
-        }
-    }
-    // m* = 0: regular part of K E_p(alpha |k|^2) as a series in a = alpha w2 u^2
-    for (int i = 0; i < n_nu; ++i) {
-        const double s = 0.5 * ((double)D - prog.nu[i]);
-        const double aw = alpha * w2;
-        const int m = prog.logm[i];
-        if (m < 0) {
-            for (int j = 0; j <= ell; ++j)
-                C[i][j] += -M->K[i] * (((j & 1) ? -1.0 : 1.0) / (fact(j) * (s + (double)j))) * pow(aw, (double)j);
-        } else {
-            // K [ (-1)^{m+1}/m! a^m ln lam^2 + (-1)^m/m! ( a^m (-gamma - sum_{j>=1} (-a)^j/(j j!))
-            //     - e^{-a} sum_{i<m} (-1)^i i! a^{m-i-1} ) ]
-            const double sm = (m & 1) ? -1.0 : 1.0, mf = fact(m);
-            double cJ[EZ_ELL_MAX + 1];
-            for (int J = 0; J <= ell; ++J) cJ[J] = 0.0;
-            if (m <= ell) cJ[m] += -sm / mf * log(M->lam * M->lam) + sm / mf * (-EZ_EULER);
-            for (int j = 1; m + j <= ell; ++j) cJ[m + j] += -sm / mf * (((j & 1) ? -1.0 : 1.0) / ((double)j * fact(j)));
-            for (int ii = 0; ii < m; ++ii)
-                for (int r = 0; m - ii - 1 + r <= ell; ++r)
-                    cJ[m - ii - 1 + r] += -sm / mf * (((ii & 1) ? -1.0 : 1.0) * fact(ii)) * (((r & 1) ? -1.0 : 1.0) / fact(r));
-            for (int J = 0; J <= ell; ++J) C[i][J] += M->K[i] * cJ[J] * pow(aw, (double)J);
         }
     }
 
+    // reciprocal space, m* != 0: F(rho) = K E_p(alpha rho), rho(u) = |m*|^2 + 2 u b + u^2 w2, b = w.m*.
+    // With F_n = F^(n)(|m*|^2)/n! = K (-alpha)^n E_{p-n}(alpha |m*|^2)/n!, the u^{2k} coefficient is
+    //   sum_{n=k}^{2k} F_n C(n, 2k-n) (4 b^2)^{n-k} w2^{2k-n}.
+    {
+        const double *kt = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
+        const int n_rec = M->n_rec;
+        for (int base = 1; base < n_rec; base += EZ_HCH) {
+            __syncthreads();
+            if ((int)threadIdx.x < EZ_HCH) {
+                const int q = base + (int)threadIdx.x;
+                if (q < n_rec) {
+                    const double a0 = alpha * kt[(size_t)q * 4 + 3];
+                    const double ex = exp(-a0), inv = 1.0 / a0;
+                    const double E1 = ez_e1(a0, ex, inv);
+                    const double Eh = ez_ehalf(a0);
+#pragma unroll
+                    for (int i = 0; i < NNU; ++i) {
+                        const int p2 = prog.p2[i];
+                        double E = ez_ep_from(p2, a0, ex, inv, E1, Eh);
+                        double sc = M->K[i];
+                        double rf = 1.0;
+                        for (int n = 0; n <= 2 * ell; ++n) {
+                            fsh[threadIdx.x][i][n] = sc * E * rf;
+                            const double pnm1 = 0.5 * (double)p2 - (double)n - 1.0;
+                            E = (ex - pnm1 * E) * inv;          // E_{p-n-1}
+                            sc *= -alpha;
+                            rf /= (double)(n + 1);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            const int cnt = min(EZ_HCH, n_rec - base);
+            for (int t = 0; t < cnt; ++t) {
+                const double *e = kt + (size_t)(base + t) * 4;
+                double b = 0.0;
+#pragma unroll
+                for (int i = 0; i < D; ++i) b = fma(w[i], e[i], b);
+                const double b4 = 4.0 * b * b;
+                double pb[EZ_ELL_MAX + 1];
+                pb[0] = 1.0;
+#pragma unroll
+                for (int j = 1; j <= EZ_ELL_MAX; ++j) pb[j] = pb[j - 1] * b4;
+#pragma unroll
+                for (int k = 0; k <= EZ_ELL_MAX; ++k) {
+                    if (k <= ell) {
+#pragma unroll
+                        for (int n = k; n <= 2 * k; ++n) {
+                            const double H = cbinom(n, 2 * k - n) * pb[n - k] * pw2[2 * k - n];
+#pragma unroll
+                            for (int i = 0; i < NNU; ++i) C[i][k] = fma(fsh[t][i][n], H, C[i][k]);
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    // m* = 0: regular part of K E_p(alpha |k|^2) as a series in a = alpha w2 u^2
+    const double aw = alpha * w2;
+#pragma unroll
+    for (int i = 0; i < NNU; ++i) {
+        const double s = 0.5 * ((double)D - prog.nu[i]);
+        const int m = prog.logm[i];
+        const double K = M->K[i];
+        if (m < 0) {
+            double awj = 1.0, jf = 1.0;
+#pragma unroll
+            for (int j = 0; j <= EZ_ELL_MAX; ++j) {
+                if (j <= ell) {
+                    if (j > 0) { awj *= aw; jf *= (double)j; }
+                    C[i][j] += -K * (((j & 1) ? -awj : awj) / (jf * (s + (double)j)));
+                }
+            }
+        } else {
+            // K [ (-1)^{m+1}/m! a^m ln lam^2 + (-1)^m/m! ( a^m (-gamma - sum_{j>=1} (-a)^j/(j j!))
+            //     - e^{-a} sum_{i<m} (-1)^i i! a^{m-i-1} ) ]  as a power series in a
+            const double sm = (m & 1) ? -1.0 : 1.0;
+            double mf = 1.0;
+            for (int j = 2; j <= m; ++j) mf *= (double)j;
+            double cJ[EZ_ELL_MAX + 1];
+#pragma unroll
+            for (int J = 0; J <= EZ_ELL_MAX; ++J) cJ[J] = 0.0;
+            const double lnl2 = log(M->lam * M->lam);
+#pragma unroll
+            for (int J = 0; J <= EZ_ELL_MAX; ++J) {
+                if (J > ell) continue;
+                double c = 0.0;
+                if (J == m) c += -sm / mf * lnl2 + sm / mf * (-EZ_EULER);
+                if (J > m) {
+                    const int j = J - m;
+                    double jf = 1.0;
+                    for (int q = 2; q <= j; ++q) jf *= (double)q;
+                    c += -sm / mf * (((j & 1) ? -1.0 : 1.0) / ((double)j * jf));
+                }
+                // e^{-a} sum_{ii<m} (-1)^ii ii! a^{m-ii-1}: a^J with r = J - (m - ii - 1) >= 0
+                double iif = 1.0;
+                for (int ii = 0; ii < m; ++ii) {
+                    if (ii > 0) iif *= (double)ii;
+                    const int r = J - (m - ii - 1);
+                    if (r >= 0) {
+                        double rf = 1.0;
+                        for (int q = 2; q <= r; ++q) rf *= (double)q;
+                        c += -sm / mf * (((ii & 1) ? -iif : iif)) * (((r & 1) ? -1.0 : 1.0) / rf);
+                    }
+                }
+                cJ[J] = c;
+            }
+            double awj = 1.0;
+#pragma unroll
+            for (int J = 0; J <= EZ_ELL_MAX; ++J) {
+                if (J <= ell) {
+                    C[i][J] += K * cJ[J] * awj;
+                    awj *= aw;
+                }
+            }
+        }
+    }
+    if (!valid) return;
+
     // products of (sigma u^e L^delta + sum_k C_k u^{2k}) and their Hadamard integrals
-    const double eps = P.eps;
-    const double Leps = log(EZ_PI * eps * eps * w2);
+    // fp int_0^eps u^{mu-1} L^q du:  I_0 = eps^mu/mu,  I_q = (eps^mu L(eps)^q - 2q I_{q-1})/mu
+    const double eps = P.eps, eps2 = eps * eps, leps = log(eps);
+    const double Leps = log(EZ_PI * eps2 * w2);
+    double sigw[NNU];
+#pragma unroll
+    for (int i = 0; i < NNU; ++i) sigw[i] = M->sig[i] * pow(w2, 0.5 * prog.e[i]);
     bool bad = false;
     double H[EZ_RES_MAX];
+#pragma unroll
     for (int r = 0; r < EZ_RES_MAX; ++r) H[r] = 0.0;
     for (int t = 0; t < prog.n_terms; ++t) {
         const int nf = prog.term_nfac[t];
         int mult[EZ_FAC_MAX], fac[EZ_FAC_MAX], jj[EZ_FAC_MAX];
-        double sig[EZ_FAC_MAX];
+        double sg[EZ_FAC_MAX];
+        for (int f = 0; f < EZ_FAC_MAX; ++f) { mult[f] = 0; fac[f] = 0; jj[f] = 0; sg[f] = 0.0; }
         for (int f = 0; f < nf; ++f) {
             fac[f] = prog.term_fac[t][f];
             mult[f] = prog.term_mult[t][f];
-            jj[f] = 0;
-            sig[f] = M->sig[fac[f]] * pow(w2, 0.5 * prog.e[fac[f]]);
+            double sv = sigw[0];
+#pragma unroll
+            for (int i = 1; i < NNU; ++i) sv = (fac[f] == i) ? sigw[i] : sv;
+            sg[f] = sv;
         }
         double tsum = 0.0;
         while (true) {
@@ -344,25 +447,45 @@ __global__ __launch_bounds__(64) void ez_hadamard_kernel(EzQuadArgs args, int n_
             int deg = 0;
             for (int f = 0; f < nf; ++f) {
                 const int i = fac[f];
-                c *= binom(mult[f], jj[f]) * pow(sig[f], (double)jj[f]);
+                double bn = 1.0;                          // C(mult, jj) sigma^jj
+                for (int q = 1; q <= jj[f]; ++q) bn = bn * (double)(mult[f] - jj[f] + q) / (double)q * sg[f];
+                c *= bn;
                 E += (double)jj[f] * prog.e[i];
                 Q += jj[f] * (prog.logm[i] >= 0 ? 1 : 0);
+                double Ci[EZ_ELL_MAX + 1];
+#pragma unroll
+                for (int k = 0; k <= EZ_ELL_MAX; ++k) {
+                    double v = C[0][k];
+#pragma unroll
+                    for (int ii = 1; ii < NNU; ++ii) v = (i == ii) ? C[ii][k] : v;
+                    Ci[k] = v;
+                }
                 for (int rep = 0; rep < mult[f] - jj[f]; ++rep) {
-                    int nd = min(deg + ell, EZ_PDEG - 1);
+                    const int nd = min(deg + ell, EZ_PDEG - 1);
                     for (int J = nd; J >= 0; --J) {
-                        double s = 0.0;
+                        double sacc = 0.0;
                         for (int kk = 0; kk <= ell && kk <= J; ++kk)
-                            if (J - kk <= deg) s += poly[J - kk] * C[i][kk];
-                        poly[J] = s;
+                            if (J - kk <= deg) sacc = fma(poly[J - kk], Ci[kk], sacc);
+                        poly[J] = sacc;
                     }
                     deg = nd;
                 }
             }
             double acc = 0.0;
-            for (int J = 0; J <= deg; ++J)
-                if (poly[J] != 0.0) acc += poly[J] * had_I((double)D + E + 2.0 * J, Q, eps, Leps, &bad);
-            tsum += c * acc;
-            // next multi-index
+            double mu = (double)D + E;
+            double em = exp(mu * leps);                  // eps^mu
+            for (int J = 0; J <= deg; ++J, mu += 2.0, em *= eps2) {
+                if (poly[J] == 0.0) continue;
+                if (mu == 0.0) { bad = true; continue; }
+                const double rmu = 1.0 / mu;
+                double I = em * rmu, Lp = 1.0;
+                for (int j = 1; j <= Q; ++j) {
+                    Lp *= Leps;
+                    I = (em * Lp - 2.0 * (double)j * I) * rmu;
+                }
+                acc = fma(poly[J], I, acc);
+            }
+            tsum = fma(c, acc, tsum);
             int f = 0;
             while (f < nf) {
                 if (++jj[f] <= mult[f]) break;
@@ -372,6 +495,7 @@ __global__ __launch_bounds__(64) void ez_hadamard_kernel(EzQuadArgs args, int n_
             if (f == nf) break;
         }
         const int rr = prog.term_res[t];
+#pragma unroll
         for (int r = 0; r < EZ_RES_MAX; ++r)
             if (r == rr) H[r] += tsum;
     }
@@ -438,9 +562,7 @@ hipError_t launch_nodes_d(const EzQuadArgs &args, int n_tiles, hipStream_t strea
     }
 }
 
-}  // namespace
-
-hipError_t ez_launch_nodes(const EzQuadArgs &args, int n_tiles, hipStream_t stream) {
+hipError_t ez_launch_nodes_impl(const EzQuadArgs &args, int n_tiles, hipStream_t stream) {
     switch (args.prog.d) {
         case 1: return launch_nodes_d<1>(args, n_tiles, stream);
         case 2: return launch_nodes_d<2>(args, n_tiles, stream);
@@ -449,15 +571,40 @@ hipError_t ez_launch_nodes(const EzQuadArgs &args, int n_tiles, hipStream_t stre
     }
 }
 
-hipError_t ez_launch_hadamard(const EzQuadArgs &args, int n_dirs, hipStream_t stream) {
-    const int blocks = (n_dirs + 63) / 64;
-    switch (args.prog.d) {
-        case 1: hipLaunchKernelGGL(ez_hadamard_kernel<1>, dim3(blocks), dim3(64), 0, stream, args, n_dirs); break;
-        case 2: hipLaunchKernelGGL(ez_hadamard_kernel<2>, dim3(blocks), dim3(64), 0, stream, args, n_dirs); break;
-        case 3: hipLaunchKernelGGL(ez_hadamard_kernel<3>, dim3(blocks), dim3(64), 0, stream, args, n_dirs); break;
+template <int D, int NNU>
+hipError_t launch_had_t(const EzQuadArgs &args, int n_htiles, hipStream_t stream) {
+    hipLaunchKernelGGL((ez_hadamard_kernel<D, NNU>), dim3(n_htiles), dim3(64), 0, stream, args);
+    return hipGetLastError();
+}
+
+template <int D>
+hipError_t launch_had_d(const EzQuadArgs &args, int n_htiles, hipStream_t stream) {
+    switch (args.prog.n_nu) {
+        case 1: return launch_had_t<D, 1>(args, n_htiles, stream);
+        case 2: return launch_had_t<D, 2>(args, n_htiles, stream);
+        case 3: return launch_had_t<D, 3>(args, n_htiles, stream);
+        case 4: return launch_had_t<D, 4>(args, n_htiles, stream);
+        case 5: return launch_had_t<D, 5>(args, n_htiles, stream);
+        case 6: return launch_had_t<D, 6>(args, n_htiles, stream);
+        case 7: return launch_had_t<D, 7>(args, n_htiles, stream);
+        case 8: return launch_had_t<D, 8>(args, n_htiles, stream);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t ez_launch_nodes(const EzQuadArgs &args, int n_tiles, hipStream_t stream) {
+    return ez_launch_nodes_impl(args, n_tiles, stream);
+}
+
+hipError_t ez_launch_hadamard(const EzQuadArgs &args, int n_htiles, hipStream_t stream) {
+    switch (args.prog.d) {
+        case 1: return launch_had_d<1>(args, n_htiles, stream);
+        case 2: return launch_had_d<2>(args, n_htiles, stream);
+        case 3: return launch_had_d<3>(args, n_htiles, stream);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t ez_launch_finalize(const EzQuadArgs &args, hipStream_t stream) {
