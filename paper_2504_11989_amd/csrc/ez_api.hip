@@ -102,7 +102,7 @@ struct DevPlan {
 struct DeviceState {
     std::map<std::string, DevPlan *> plans;
     std::vector<std::string> plan_order;
-    DevBuf meta, real, rec, tile_part, dir_part, dir_flag;
+    DevBuf meta, real, rn, rows, rec, tile_part, dir_part, dir_flag;
     DevBuf gmeta, greal, grec;   // general-x Epstein tables
 };
 
@@ -208,6 +208,14 @@ ez_status build_program(int d, const std::vector<double> &nu, const std::vector<
         P.e[i] = v - d;
         if ((P.p2[i] & 1) == 0 && P.p2[i] / 2 >= 1) P.need_e1 = 1;
         if (P.p2[i] & 1) P.need_half = 1;
+    }
+    P.pset = 0;
+    for (int id = 1; id < EZ_NPSETS; ++id) {
+        EzPSet ps = ez_pset(id);
+        if (ps.n != P.n_nu) continue;
+        bool same = true;
+        for (int i = 0; i < ps.n; ++i) same = same && ps.p2[i] == P.p2[i];
+        if (same) { P.pset = id; break; }
     }
     for (int t = 0; t < P.n_terms; ++t) {
         const Term &T = terms[t];
@@ -393,14 +401,19 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     tab.real_cap = real_capacity(d, lam_max, acut, false);
     tab.rec_cap = rec_capacity(d, lam_min, acut);
     tab.rstride = 4 * ((3 + prog.n_nu + 3) / 4);
+    tab.row_cap = tab.real_cap;
     if ((st = grow(S->meta, sizeof(EzLatMeta) * batch)) ||
         (st = grow(S->real, sizeof(double) * (size_t)batch * tab.real_cap * tab.rstride)) ||
+        (st = grow(S->rn, sizeof(int) * 4 * (size_t)batch * tab.real_cap)) ||
+        (st = grow(S->rows, sizeof(int) * 8 * (size_t)batch * tab.row_cap)) ||
         (st = grow(S->rec, sizeof(double) * (size_t)batch * tab.rec_cap * 4)) ||
         (st = grow(S->tile_part, sizeof(double) * 2 * (size_t)P->n_tiles * prog.n_res)) ||
         (st = grow(S->dir_part, sizeof(double) * (size_t)P->n_dirs * prog.n_res)) ||
         (st = grow(S->dir_flag, sizeof(uint32_t) * (size_t)P->n_dirs)))
         return st;
     tab.real = (double *)S->real.p;
+    tab.rn = (int *)S->rn.p;
+    tab.rows = (int *)S->rows.p;
     tab.rec = (double *)S->rec.p;
 
     EzSetupArgs sa;
@@ -459,7 +472,7 @@ ez_status ez_finalize(void) {
         (void)hipSetDevice(kv.first);
         DeviceState *S = kv.second;
         for (auto &p : S->plans) free_plan(p.second);
-        free_buf(S->meta); free_buf(S->real); free_buf(S->rec);
+        free_buf(S->meta); free_buf(S->real); free_buf(S->rec); free_buf(S->rn); free_buf(S->rows);
         free_buf(S->tile_part); free_buf(S->dir_part); free_buf(S->dir_flag);
         free_buf(S->gmeta); free_buf(S->greal); free_buf(S->grec);
         delete S;
@@ -567,6 +580,9 @@ ez_status ez_epstein_zeta(int d, const double *A_dev, int n_nu, const double *nu
     tab.real_cap = real_capacity(d, lam, a_cut, true);
     tab.rec_cap = rec_capacity(d, lam, a_cut);
     tab.rstride = 4;
+    tab.row_cap = 0;
+    tab.rn = nullptr;
+    tab.rows = nullptr;
     ez_status st;
     if ((st = grow(S->gmeta, sizeof(EzLatMeta))) ||
         (st = grow(S->greal, sizeof(double) * (size_t)tab.real_cap * tab.rstride)) ||

@@ -27,7 +27,20 @@ struct EzProgram {
     int term_mult[EZ_TERM_MAX][EZ_FAC_MAX];
     int need_e1;            // some p_i is an integer >= 1
     int need_half;          // some p_i is a half-integer
+    int pset;               // id of a compile-time exponent set matching p2, or 0
 };
+
+// Exponent sets with kernels specialised at compile time (2 p_i = nu_i - d + 2);
+// set 0 reads the exponents at run time.
+struct EzPSet { int n; int p2[EZ_NU_MAX]; };
+#define EZ_NPSETS 5
+__host__ __device__ constexpr EzPSet ez_pset(int id) {
+    return id == 1 ? EzPSet{4, {-2, 0, 2, 4}}                 // d = 3, nu = -1, 1, 3, 5 (ATM)
+         : id == 2 ? EzPSet{4, {-1, 1, 3, 5}}                 // d = 2, ATM
+         : id == 3 ? EzPSet{4, {0, 2, 4, 6}}                  // d = 1, ATM
+         : id == 4 ? EzPSet{7, {-2, 0, 2, 4, 5, 8, 11}}       // d = 3, ATM and nu = 6, 9, 12
+                   : EzPSet{0, {0}};
+}
 
 // Per-lattice constants written by the setup kernel.
 struct EzLatMeta {
@@ -40,6 +53,8 @@ struct EzLatMeta {
     int n_real;             // real-space entries (pairs +-z stored once)
     int n_rec;              // reciprocal entries (all m*, m* = 0 first)
     uint32_t status;
+    int n_rows;             // rows of the real-space table (pairs mode)
+    int n_inner;            // reciprocal entries [0, n_inner) may have a < 1; the rest have a >= 1
     int pad_;
 };
 
@@ -54,9 +69,15 @@ struct EzInstPlan {
     double lam_rel;         // Ewald parameter in units of V^{1/d}
 };
 
+// Real-space table (pairs mode): points ordered by (n3, n2, n1), so that each
+// row (n2, n3 fixed) is a run of consecutive n1.  A row record holds
+// {first point, count, n1 of the first point, n2, n3, starts a new plane,
+//  n1 shift from the previous row's first point, n2 step from the previous row}.
 struct EzTables {
-    int real_cap, rec_cap, rstride;   // capacity per lattice, doubles per real entry
+    int real_cap, rec_cap, rstride, row_cap;  // capacities per lattice, doubles per real entry
     double *real;                     // [batch][real_cap][rstride]: z (3), 2 W_nu(z) (n_nu)
+    int *rn;                          // [batch][real_cap][4]: integer coordinates of each point
+    int *rows;                        // [batch][row_cap][8]: row records
     double *rec;                      // [batch][rec_cap][4]: m* (3), |m*|^2
 };
 

@@ -12,7 +12,48 @@
 #include "e1_rational.h"
 #include "ez_internal.h"
 
-__device__ __forceinline__ double ez_rcp(double x) { return 1.0 / x; }
+// a*b + c as one three-operand v_fma_f64: the addend (a table constant) is read in
+// place instead of being copied into the destination register first
+__device__ __forceinline__ double ez_fma3(double a, double b, double c) {
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// e^{-a} for 0 <= a <= 700.  a = n ln2 + r, n = rint(a / ln2), with ln2 split as
+// LN2_HI + LN2_LO (LN2_HI has a 32-bit significand, so n LN2_HI is exact: Cody and
+// Waite's argument reduction); e^{-r}, |r| <= ln2/2, by its Taylor series through
+// r^13 (truncation < 4e-18); then scaled by 2^{-n}.
+__device__ __forceinline__ double ez_expm(double a) {
+    const double n = rint(a * 1.4426950408889634);
+    double r = fma(-n, 0.6931471803691238, a);
+    r = fma(-n, 1.9082149292705877e-10, r);
+    const double x = -r;
+    double p = 1.0 / 6227020800.0;                       // 1/13!
+    p = ez_fma3(p, x, 1.0 / 479001600.0);
+    p = ez_fma3(p, x, 1.0 / 39916800.0);
+    p = ez_fma3(p, x, 1.0 / 3628800.0);
+    p = ez_fma3(p, x, 1.0 / 362880.0);
+    p = ez_fma3(p, x, 1.0 / 40320.0);
+    p = ez_fma3(p, x, 1.0 / 5040.0);
+    p = ez_fma3(p, x, 1.0 / 720.0);
+    p = ez_fma3(p, x, 1.0 / 120.0);
+    p = ez_fma3(p, x, 1.0 / 24.0);
+    p = ez_fma3(p, x, 1.0 / 6.0);
+    p = fma(p, x, 0.5);
+    p = fma(p, x, 1.0);
+    p = fma(p, x, 1.0);
+    return ldexp(p, -(int)n);
+}
+
+// 1/x: hardware reciprocal estimate refined by two Newton steps (x normal, finite)
+__device__ __forceinline__ double ez_rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
 
 // E1(a) for 0 < a < 1: -gamma - ln a + sum_{k>=1} (-1)^{k+1} a^k / (k k!)
 __device__ __forceinline__ double ez_e1_series(double a) {
@@ -38,8 +79,23 @@ __device__ __forceinline__ double ez_e1_scaled_large(double a, double inv_a) {
         P = fma(P, t, ez_e1r_p[j]);
         Q = fma(Q, t, ez_e1r_q[j]);
     }
-    return t * P / Q;
+    return t * P * ez_rcp(Q);
 }
+
+// e^a E1(a) for a >= 1/4 from the wide rational fit, given t = 1/a
+__device__ __forceinline__ double ez_e1w_scaled(double t) {
+    double P = ez_e1w_p[EZ_E1W_DEG], Q = ez_e1w_q[EZ_E1W_DEG];
+#pragma unroll
+    for (int j = EZ_E1W_DEG - 1; j >= 0; --j) {
+        P = ez_fma3(P, t, ez_e1w_p[j]);
+        Q = ez_fma3(Q, t, ez_e1w_q[j]);
+    }
+    return t * P * ez_rcp(Q);
+}
+
+// E1(a) for 0 < a < 1/4 by the series; kept out of line so that its constants
+// do not occupy registers in the loops that call it only for a few lanes
+__device__ __attribute__((noinline, const)) double ez_e1_small(double a) { return ez_e1_series(a); }
 
 // E1(a), a > 0, given e = e^{-a} and inv_a = 1/a
 __device__ __forceinline__ double ez_e1(double a, double e, double inv_a) {
@@ -137,6 +193,13 @@ __device__ __forceinline__ void ez_sincos2pi(double t, double *s, double *c) {
     double r = 2.0 * (t - rint(t));
     *s = sinpi(r);
     *c = cospi(r);
+}
+
+// out of line, reads and writes no memory (so loads around its call stay scalar)
+__device__ __attribute__((noinline, const)) double2 ez_sincos2pi_ool(double t) {
+    double s, c;
+    ez_sincos2pi(t, &s, &c);
+    return make_double2(s, c);
 }
 
 // ---- double-double accumulation (error-free sums, fixed order) ----

@@ -9,7 +9,8 @@
 //                    the exponent set by the split (real-space table + reciprocal
 //                    table), the products of the terms, weight, then a
 //                    double-double reduction to one partial per 256-node tile.
-// ez_hadamard_kernel: u in (0, eps).  One thread per direction w (64 per workgroup): Taylor
+// ez_hadamard_kernel: u in (0, eps).  One lane per direction w (64 per workgroup, the
+//                    tables split over 4 waves): Taylor
 //                    coefficients of Z^reg_nu(u w) in u, expansion of the products
 //                    of (singular + Taylor) factors and closed-form Hadamard integrals.
 // ez_finalize_kernel: fixed-order double-double sum of tiles and directions.
@@ -35,7 +36,7 @@ __device__ __forceinline__ int find_segment(const int *begin, int n, int x) {
 
 template <int D>
 __device__ __forceinline__ void ez_direction(const EzInstPlan &P, const double *rules, const double *B,
-                                             int dir, double *w, double *wv) {
+                                             int dir, double *w, double *wv, double *what = nullptr) {
     int nv = 1;
 #pragma unroll
     for (int i = 0; i < D - 1; ++i) nv *= P.n_q;
@@ -67,11 +68,40 @@ __device__ __forceinline__ void ez_direction(const EzInstPlan &P, const double *
 #pragma unroll
         for (int c = 0; c < D; ++c) s = fma(B[i * D + c], wh[c], s);
         w[i] = s;
+        if (what) what[i] = wh[i];
     }
     *wv = weight;
 }
 
-template <int D, int NNU>
+// complex multiply (a r + i a i)(b r + i b i)
+__device__ __forceinline__ void cmul(double &ar, double &ai, double br, double bi) {
+    const double r = fma(ar, br, -ai * bi);
+    const double i = fma(ar, bi, ai * br);
+    ar = r;
+    ai = i;
+}
+
+template <int SET>
+__device__ __forceinline__ int pset_p2(const EzProgram &prog, int i) {
+    if constexpr (SET == 0) return prog.p2[i];
+    else return ez_pset(SET).p2[i];
+}
+template <int SET, int NNU>
+__device__ __forceinline__ bool pset_need_e1(const EzProgram &prog) {
+    if constexpr (SET == 0) return prog.need_e1 != 0;
+    bool r = false;
+    for (int i = 0; i < NNU; ++i) r = r || ((ez_pset(SET).p2[i] & 1) == 0 && ez_pset(SET).p2[i] >= 2);
+    return r;
+}
+template <int SET, int NNU>
+__device__ __forceinline__ bool pset_need_half(const EzProgram &prog) {
+    if constexpr (SET == 0) return prog.need_half != 0;
+    bool r = false;
+    for (int i = 0; i < NNU; ++i) r = r || (ez_pset(SET).p2[i] & 1);
+    return r;
+}
+
+template <int D, int NNU, int SET>
 __global__ __launch_bounds__(EZ_TILE) void ez_node_kernel(EzQuadArgs args) {
     const int tile = blockIdx.x;
     const int inst = find_segment(args.tile_begin, args.batch, tile);
@@ -91,8 +121,8 @@ __global__ __launch_bounds__(EZ_TILE) void ez_node_kernel(EzQuadArgs args) {
         double B[D * D];
 #pragma unroll
         for (int i = 0; i < D * D; ++i) B[i] = M->B[i];
-        double w[3] = {0.0, 0.0, 0.0}, wv;
-        ez_direction<D>(P, args.rules, B, dir, w, &wv);
+        double w[3] = {0.0, 0.0, 0.0}, wh[3] = {0.0, 0.0, 0.0}, wv;
+        ez_direction<D>(P, args.rules, B, dir, w, &wv, wh);
         const double u = args.rules[P.urule + iu];
         const double wu = args.rules[P.urule + P.n_u + iu];
         double k[3] = {0.0, 0.0, 0.0};
@@ -106,26 +136,73 @@ __global__ __launch_bounds__(EZ_TILE) void ez_node_kernel(EzQuadArgs args) {
 #pragma unroll
         for (int i = 0; i < NNU; ++i) { accr[i] = 0.0; acck[i] = 0.0; }
 
-        // real space: sum over pairs of 2 W_nu(z) cos(2 pi k.z)
-        const int rs = args.tab.rstride;
-        const double *rt = args.tab.real + (size_t)inst * args.tab.real_cap * rs;
-        const int n_real = M->n_real;
-        for (int p = 0; p < n_real; ++p) {
-            const double *e = rt + (size_t)p * rs;
-            double t = k[0] * e[0];
-            if (D > 1) t = fma(k[1], e[1], t);
-            if (D > 2) t = fma(k[2], e[2], t);
-            const double c = ez_cos2pi(t);
+        // real space: sum over pairs of 2 W_nu(z) Re e^{2 pi i k.z}, k.z = theta.n with
+        // theta = A^T k = u w_hat.  Row by row (n2, n3 fixed, consecutive n1) the phase
+        // advances by c1 = e^{2 pi i theta_1}; from row to row within a plane by
+        // c2^{dn2} c1^{dn1}; each plane starts from one sincos.
+        {
+            const int rs = args.tab.rstride;
+            const double *rt = args.tab.real + (size_t)inst * args.tab.real_cap * rs;
+            const int *rows = args.tab.rows + (size_t)inst * args.tab.row_cap * 8;
+            const int n_rows = M->n_rows;
+            double th[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-            for (int i = 0; i < NNU; ++i) accr[i] = fma(e[3 + i], c, accr[i]);
+            for (int i = 0; i < D; ++i) th[i] = u * wh[i];
+            double c1r, c1i, c2r = 1.0, c2i = 0.0;
+            ez_sincos2pi(th[0], &c1i, &c1r);
+            if (D > 1) ez_sincos2pi(th[1], &c2i, &c2r);
+            double br = 1.0, bi = 0.0;
+            for (int r = 0; r < n_rows; ++r) {
+                const int *R = rows + (size_t)r * 8;
+                const int first = R[0], cnt = R[1];
+                if (R[5]) {
+                    double ph = th[0] * (double)R[2];
+                    if (D > 1) ph = fma(th[1], (double)R[3], ph);
+                    if (D > 2) ph = fma(th[2], (double)R[4], ph);
+                    const double2 sc = ez_sincos2pi_ool(ph);
+                    bi = sc.x;
+                    br = sc.y;
+                } else {
+                    for (int j = 0; j < R[7]; ++j) cmul(br, bi, c2r, c2i);
+                    const int dl = R[6];
+                    if (dl > 0) for (int j = 0; j < dl; ++j) cmul(br, bi, c1r, c1i);
+                    else for (int j = 0; j < -dl; ++j) cmul(br, bi, c1r, -c1i);
+                }
+                double pr = br, pi = bi;
+                const double *e = rt + (size_t)first * rs;
+                for (int j = 0; j < cnt; ++j, e += rs) {
+#pragma unroll
+                    for (int i = 0; i < NNU; ++i) accr[i] = fma(e[3 + i], pr, accr[i]);
+                    cmul(pr, pi, c1r, c1i);
+                }
+            }
         }
 
-        // reciprocal space: sum over m* of E_{p_nu}(pi lam^2 |m* + k|^2)
+        // reciprocal space: sum over m* of E_{p_nu}(pi lam^2 |m* + k|^2).  Entry 0 is
+        // m* = 0, where a = alpha |k|^2 can be small (series of E1); every other entry
+        // has a >= alpha / (4 |A|_F^2) >= 1/4 (the setup raises lam to ensure it), so the
+        // main loop is one branch-free formula with E1 from the wide rational.
         const double *kt = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
         const int n_rec = M->n_rec;
         const double alpha = M->alpha, acut = M->a_cut;
-        const bool need_e1 = args.prog.need_e1 != 0, need_half = args.prog.need_half != 0;
-        for (int q = 0; q < n_rec; ++q) {
+        const bool need_e1 = pset_need_e1<SET, NNU>(args.prog), need_half = pset_need_half<SET, NNU>(args.prog);
+        {
+            double rho = k[0] * k[0];
+            if (D > 1) rho = fma(k[1], k[1], rho);
+            if (D > 2) rho = fma(k[2], k[2], rho);
+            const double a = alpha * rho;
+            if (a <= acut) {
+                const double ex = ez_expm(a);
+                const double inv = ez_rcp(a);
+                double E1 = 0.0;
+                if (need_e1) E1 = (a < 0.25) ? ez_e1_series(a) : ex * ez_e1w_scaled(inv);
+                const double Eh = need_half ? ez_ehalf(a) : 0.0;
+#pragma unroll
+                for (int i = 0; i < NNU; ++i)
+                    acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
+            }
+        }
+        for (int q = 1; q < n_rec; ++q) {
             const double *e = kt + (size_t)q * 4;
             double qx = e[0] + k[0];
             double rho = qx * qx;
@@ -133,13 +210,13 @@ __global__ __launch_bounds__(EZ_TILE) void ez_node_kernel(EzQuadArgs args) {
             if (D > 2) { double qz = e[2] + k[2]; rho = fma(qz, qz, rho); }
             const double a = alpha * rho;
             if (a <= acut) {
-                const double ex = exp(-a);
-                const double inv = 1.0 / a;
-                const double E1 = need_e1 ? ez_e1(a, ex, inv) : 0.0;
+                const double ex = ez_expm(a);
+                const double inv = ez_rcp(a);
+                const double E1 = need_e1 ? ex * ez_e1w_scaled(inv) : 0.0;
                 const double Eh = need_half ? ez_ehalf(a) : 0.0;
 #pragma unroll
                 for (int i = 0; i < NNU; ++i)
-                    acck[i] += ez_ep_from(args.prog.p2[i], a, ex, inv, E1, Eh);
+                    acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
             }
         }
 
@@ -225,21 +302,29 @@ __host__ __device__ constexpr double cbinom(int n, int k) {
     return (k < 0 || k > n) ? 0.0 : r;
 }
 
-// One thread per direction w, 64 directions of one lattice per workgroup.
+// 64 directions of one lattice per workgroup, 4 waves: lane = direction, wave =
+// quarter of the real-space and reciprocal tables; the four partial Taylor
+// coefficient sets are summed in LDS in fixed order, then wave 0 finishes.
+constexpr int EZ_HW = 4;                        // waves per Hadamard workgroup
+
 template <int D, int NNU>
-__global__ __launch_bounds__(64) void ez_hadamard_kernel(EzQuadArgs args) {
-    __shared__ double fsh[EZ_HCH][NNU][EZ_NF];
+__global__ __launch_bounds__(64 * EZ_HW) void ez_hadamard_kernel(EzQuadArgs args) {
+    constexpr int FSZ = EZ_HCH * NNU * EZ_NF;
+    constexpr int CSZ = 64 * NNU * (EZ_ELL_MAX + 1);
+    __shared__ double lds[FSZ > CSZ ? FSZ : CSZ];
+    double (*fsh)[NNU][EZ_NF] = reinterpret_cast<double (*)[NNU][EZ_NF]>(lds);
     const int blk = blockIdx.x;
     const int inst = find_segment(args.htile_begin, args.batch, blk);
     const EzInstPlan P = args.plans[inst];
     const EzLatMeta *M = args.meta + inst;
     const EzProgram &prog = args.prog;
     const int n_res = prog.n_res;
-    const int dloc = (blk - args.htile_begin[inst]) * 64 + (int)threadIdx.x;
+    const int lane = (int)threadIdx.x & 63, part = (int)threadIdx.x >> 6;
+    const int dloc = (blk - args.htile_begin[inst]) * 64 + lane;
     const bool valid = dloc < P.n_dir;
     const int gd = P.dir_begin + dloc;
     if (M->status != 0) {                      // uniform over the workgroup
-        if (valid) {
+        if (valid && part == 0) {
             for (int r = 0; r < n_res; ++r) args.dir_part[(size_t)gd * n_res + r] = 0.0;
             args.dir_flag[gd] = 0;
         }
@@ -260,13 +345,13 @@ __global__ __launch_bounds__(64) void ez_hadamard_kernel(EzQuadArgs args) {
 #pragma unroll
     for (int j = 1; j <= EZ_ELL_MAX; ++j) pw2[j] = pw2[j - 1] * w2;
 
-    // C[i][k]: coefficient of u^{2k} in Z^reg_{nu_i}(u w)
+    // C[i][k]: this wave's share of the coefficient of u^{2k} in Z^reg_{nu_i}(u w)
     double C[NNU][EZ_ELL_MAX + 1];
 #pragma unroll
     for (int i = 0; i < NNU; ++i) {
 #pragma unroll
         for (int k = 0; k <= EZ_ELL_MAX; ++k) C[i][k] = 0.0;
-        C[i][0] = -M->self_[i];
+        if (part == 0) C[i][0] = -M->self_[i];
     }
 
     // real space: 2 W cos(2 pi u w.z) = 2 W sum_k (-1)^k (2 pi w.z)^{2k} u^{2k} / (2k)!
@@ -274,7 +359,7 @@ __global__ __launch_bounds__(64) void ez_hadamard_kernel(EzQuadArgs args) {
         const int rs = args.tab.rstride;
         const double *rt = args.tab.real + (size_t)inst * args.tab.real_cap * rs;
         const int n_real = M->n_real;
-        for (int p = 0; p < n_real; ++p) {
+        for (int p = part; p < n_real; p += EZ_HW) {
             const double *e = rt + (size_t)p * rs;
             double t = 0.0;
 #pragma unroll
@@ -325,7 +410,7 @@ __global__ __launch_bounds__(64) void ez_hadamard_kernel(EzQuadArgs args) {
             }
             __syncthreads();
             const int cnt = min(EZ_HCH, n_rec - base);
-            for (int t = 0; t < cnt; ++t) {
+            for (int t = part; t < cnt; t += EZ_HW) {
                 const double *e = kt + (size_t)(base + t) * 4;
                 double b = 0.0;
 #pragma unroll
@@ -349,6 +434,27 @@ __global__ __launch_bounds__(64) void ez_hadamard_kernel(EzQuadArgs args) {
             }
         }
     }
+
+    // fixed-order sum of the four waves' coefficients into wave 0 (LDS reused)
+    for (int src = 1; src < EZ_HW; ++src) {
+        __syncthreads();
+        if (part == src) {
+#pragma unroll
+            for (int i = 0; i < NNU; ++i)
+#pragma unroll
+                for (int k = 0; k <= EZ_ELL_MAX; ++k)
+                    if (k <= ell) lds[(i * (EZ_ELL_MAX + 1) + k) * 64 + lane] = C[i][k];
+        }
+        __syncthreads();
+        if (part == 0) {
+#pragma unroll
+            for (int i = 0; i < NNU; ++i)
+#pragma unroll
+                for (int k = 0; k <= EZ_ELL_MAX; ++k)
+                    if (k <= ell) C[i][k] += lds[(i * (EZ_ELL_MAX + 1) + k) * 64 + lane];
+        }
+    }
+    if (part != 0) return;
 
     // m* = 0: regular part of K E_p(alpha |k|^2) as a series in a = alpha w2 u^2
     const double aw = alpha * w2;
@@ -541,14 +647,18 @@ __global__ __launch_bounds__(256) void ez_finalize_kernel(EzQuadArgs args) {
     }
 }
 
-template <int D, int NNU>
+template <int D, int NNU, int SET = 0>
 hipError_t launch_nodes_t(const EzQuadArgs &args, int n_tiles, hipStream_t stream) {
-    hipLaunchKernelGGL((ez_node_kernel<D, NNU>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
+    hipLaunchKernelGGL((ez_node_kernel<D, NNU, SET>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
     return hipGetLastError();
 }
 
 template <int D>
 hipError_t launch_nodes_d(const EzQuadArgs &args, int n_tiles, hipStream_t stream) {
+    if (D == 3 && args.prog.pset == 1) return launch_nodes_t<D, 4, 1>(args, n_tiles, stream);
+    if (D == 2 && args.prog.pset == 2) return launch_nodes_t<D, 4, 2>(args, n_tiles, stream);
+    if (D == 1 && args.prog.pset == 3) return launch_nodes_t<D, 4, 3>(args, n_tiles, stream);
+    if (D == 3 && args.prog.pset == 4) return launch_nodes_t<D, 7, 4>(args, n_tiles, stream);
     switch (args.prog.n_nu) {
         case 1: return launch_nodes_t<D, 1>(args, n_tiles, stream);
         case 2: return launch_nodes_t<D, 2>(args, n_tiles, stream);
@@ -573,7 +683,7 @@ hipError_t ez_launch_nodes_impl(const EzQuadArgs &args, int n_tiles, hipStream_t
 
 template <int D, int NNU>
 hipError_t launch_had_t(const EzQuadArgs &args, int n_htiles, hipStream_t stream) {
-    hipLaunchKernelGGL((ez_hadamard_kernel<D, NNU>), dim3(n_htiles), dim3(64), 0, stream, args);
+    hipLaunchKernelGGL((ez_hadamard_kernel<D, NNU>), dim3(n_htiles), dim3(64 * EZ_HW), 0, stream, args);
     return hipGetLastError();
 }
 

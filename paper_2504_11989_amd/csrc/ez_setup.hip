@@ -120,6 +120,14 @@ __global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
                 for (int j = 0; j < d; ++j) sh.B[i * d + j] = sh.Ai[j * d + i];
             sh.V = fabs(det);
             sh.lam = lam_rel * pow(sh.V, 1.0 / d);
+            // every m* != 0 then has pi lam^2 |m* + k|^2 >= 1/4 for the quadrature nodes
+            // k in B[-1/2,1/2]^d (|m* + k| >= sigma_min(B)/2 >= 1/(2 |A|_F)); the node
+            // kernel's rational E1 is fitted for arguments >= 1/4
+            if (!args.general_x) {
+                double fro2 = 0.0;
+                for (int i = 0; i < d * d; ++i) fro2 += sh.A[i] * sh.A[i];
+                sh.lam = fmax(sh.lam, sqrt(fro2 / EZ_PI) * (1.0 + 1e-12));
+            }
             sh.alpha = EZ_PI * sh.lam * sh.lam;
             sh.Rr = sh.lam * sqrt(a_cut / EZ_PI);
             sh.Rk = sqrt(a_cut / EZ_PI) / sh.lam;
@@ -157,8 +165,8 @@ __global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
         long long idx = base + threadIdx.x;
         bool keep = false;
         double z[3] = {0.0, 0.0, 0.0};
+        int n[3] = {0, 0, 0};
         if (idx < sh.nbox) {
-            int n[3];
             box_index(idx, sh.lo, sh.hi, d, n);
             bool nonzero = (n[0] | n[1] | n[2]) != 0;
             // pairs mode: keep the representative whose last nonzero coordinate is > 0
@@ -181,6 +189,10 @@ __global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
             if (slot < args.tab.real_cap) {
                 double *e = rtab + (size_t)slot * rs;
                 e[0] = z[0]; e[1] = z[1]; e[2] = z[2];
+                if (!args.general_x) {
+                    int *ni = args.tab.rn + ((size_t)inst * args.tab.real_cap + slot) * 4;
+                    ni[0] = n[0]; ni[1] = n[1]; ni[2] = n[2]; ni[3] = 0;
+                }
             } else {
                 atomicOr(&sh.status, 0x2u);
             }
@@ -201,6 +213,44 @@ __global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
             }
             for (int i = 3 + args.prog.n_nu; i < rs; ++i) e[i] = 0.0;
         }
+    }
+    __syncthreads();
+    // rows of the real-space table (pairs mode)
+    if (!args.general_x) {
+        const int *rn = args.tab.rn + (size_t)inst * args.tab.real_cap * 4;
+        int *rows = args.tab.rows + (size_t)inst * args.tab.row_cap * 8;
+        if (threadIdx.x == 0) sh.count = 0;
+        __syncthreads();
+        for (int base = 0; base < n_real; base += SB) {
+            const int t = base + (int)threadIdx.x;
+            bool start = false;
+            if (t < n_real) {
+                start = (t == 0) || rn[4 * t + 1] != rn[4 * (t - 1) + 1] || rn[4 * t + 2] != rn[4 * (t - 1) + 2];
+            }
+            int slot = compact_slot(start, &sh);
+            if (start && slot < args.tab.row_cap) {
+                int cnt = 1;
+                while (t + cnt < n_real && rn[4 * (t + cnt) + 1] == rn[4 * t + 1] && rn[4 * (t + cnt) + 2] == rn[4 * t + 2]) ++cnt;
+                int *R = rows + (size_t)slot * 8;
+                R[0] = t; R[1] = cnt; R[2] = rn[4 * t]; R[3] = rn[4 * t + 1]; R[4] = rn[4 * t + 2];
+            } else if (start) {
+                atomicOr(&sh.status, 0x2u);
+            }
+        }
+        __syncthreads();
+        const int n_rows = min(sh.count, args.tab.row_cap);
+        for (int r = threadIdx.x; r < n_rows; r += SB) {
+            int *R = rows + (size_t)r * 8;
+            const int *Rp = rows + (size_t)(r > 0 ? r - 1 : 0) * 8;
+            const bool np = (r == 0) || R[4] != Rp[4];
+            R[5] = np ? 1 : 0;
+            R[6] = np ? 0 : R[2] - Rp[2];
+            R[7] = np ? 0 : R[3] - Rp[3];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) meta->n_rows = n_rows;
+    } else if (threadIdx.x == 0) {
+        meta->n_rows = 0;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -227,7 +277,13 @@ __global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
     __syncthreads();
     double *ktab = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
     const double Rk2 = sh.Rk * sh.Rk;
-    if (!(sh.status & 0x2u)) {
+    // inner: entries that can reach a = alpha |m* + k|^2 < 1 for a node k in B[-1/2,1/2]^d.
+    // |m* + k| >= sigma_min(B) (|m|_inf - 1/2) and sigma_min(B) >= 1/|A|_F give the test.
+    double fro2 = 0.0;
+    for (int i = 0; i < d * d; ++i) fro2 += sh.A[i] * sh.A[i];
+    int n_inner = 1;
+    for (int pass = 0; pass < 2; ++pass) {
+        if (sh.status & 0x2u) break;
         for (long long base = 0; base < sh.nbox; base += SB) {
             long long idx = base + threadIdx.x;
             bool keep = false;
@@ -241,7 +297,10 @@ __global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
                     m[i] = s;
                 }
                 double r2 = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
-                keep = ((n[0] | n[1] | n[2]) != 0) && r2 <= Rk2;
+                int ninf = max(abs(n[0]), max(abs(n[1]), abs(n[2])));
+                double g = (double)ninf - 0.5;
+                bool inner = sh.alpha * g * g < fro2;
+                keep = ((n[0] | n[1] | n[2]) != 0) && r2 <= Rk2 && (pass == 0 ? inner : !inner);
             }
             int slot = compact_slot(keep, &sh);
             if (keep) {
@@ -254,6 +313,8 @@ __global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
                 }
             }
         }
+        if (pass == 0) n_inner = sh.count;
+        __syncthreads();
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -282,6 +343,7 @@ __global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
         }
         meta->n_real = n_real;
         meta->n_rec = min(sh.count, args.tab.rec_cap);
+        meta->n_inner = min(n_inner, meta->n_rec);
         uint32_t st = sh.status;
         if (sh.count > args.tab.rec_cap) st |= 0x2u;
         meta->status = st;
