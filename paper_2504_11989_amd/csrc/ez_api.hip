@@ -71,6 +71,46 @@ void gauss_legendre(int n, double lo, double hi, double *x, double *w) {
 }
 
 // ---------------------------------------------------------------------------
+// Least squares: pinv (n x P, row-major) with pinv M = I for M (P x n, row-major,
+// full column rank), by modified Gram-Schmidt QR (two passes) and back substitution.
+void lstsq_pinv(int P, int n, const std::vector<double> &M, std::vector<double> &pinv) {
+    std::vector<double> Q(M), R((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        for (int pass = 0; pass < 2; ++pass)
+            for (int i = 0; i < j; ++i) {
+                double r = 0.0;
+                for (int p = 0; p < P; ++p) r += Q[(size_t)p * n + i] * Q[(size_t)p * n + j];
+                for (int p = 0; p < P; ++p) Q[(size_t)p * n + j] -= r * Q[(size_t)p * n + i];
+                R[(size_t)i * n + j] += r;
+            }
+        double nr = 0.0;
+        for (int p = 0; p < P; ++p) nr += Q[(size_t)p * n + j] * Q[(size_t)p * n + j];
+        nr = std::sqrt(nr);
+        R[(size_t)j * n + j] = nr;
+        for (int p = 0; p < P; ++p) Q[(size_t)p * n + j] /= nr;
+    }
+    // pinv = R^{-1} Q^T
+    pinv.assign((size_t)n * P, 0.0);
+    for (int p = 0; p < P; ++p)
+        for (int i = n - 1; i >= 0; --i) {
+            double v = Q[(size_t)p * n + i];
+            for (int j = i + 1; j < n; ++j) v -= R[(size_t)i * n + j] * pinv[(size_t)j * P + p];
+            pinv[(size_t)i * P + p] = v / R[(size_t)i * n + i];
+        }
+}
+
+int n_mono(int d, int g) { return d == 1 ? 1 : (d == 2 ? g + 1 : (g + 1) * (g + 2) / 2); }
+
+// monomials of degree g of x (order: a0 descending, then a1 descending)
+void monomials(int d, int g, const double *x, std::vector<double> &out) {
+    out.clear();
+    if (d == 1) { out.push_back(std::pow(x[0], g)); return; }
+    if (d == 2) { for (int a = g; a >= 0; --a) out.push_back(std::pow(x[0], a) * std::pow(x[1], g - a)); return; }
+    for (int a = g; a >= 0; --a)
+        for (int b = g - a; b >= 0; --b) out.push_back(std::pow(x[0], a) * std::pow(x[1], b) * std::pow(x[2], g - a - b));
+}
+
+// ---------------------------------------------------------------------------
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -96,13 +136,15 @@ ez_status grow(DevBuf &b, size_t bytes) {
 struct DevPlan {
     DevBuf rules, plans, tile_begin, dir_begin, htile_begin;
     int n_tiles = 0, n_dirs = 0, n_htiles = 0;
+    int n_probe = 0, ell_probe = 0, probe_off = 0;
+    int pinv_off[EZ_ELL_MAX + 1] = {0};
     std::vector<EzInstPlan> host_plans;
 };
 
 struct DeviceState {
     std::map<std::string, DevPlan *> plans;
     std::vector<std::string> plan_order;
-    DevBuf meta, real, rn, rows, rec, tile_part, dir_part, dir_flag;
+    DevBuf meta, real, rn, rows, rec, tile_part, dir_part, dir_flag, probe_val, tensor;
     DevBuf gmeta, greal, grec;   // general-x Epstein tables
 };
 
@@ -188,7 +230,8 @@ struct Term {
 };
 
 ez_status build_program(int d, const std::vector<double> &nu, const std::vector<Term> &terms, int n_res,
-                        int ell_max, EzProgram &P) {
+                        int ell_max, EzProgram &P, std::vector<EzCombo> &combos) {
+    combos.clear();
     std::memset(&P, 0, sizeof(P));
     if ((int)nu.size() < 1 || (int)nu.size() > EZ_NU_MAX) return fail(EZ_ERR_INVALID_ARG, "1 <= n_nu <= 8");
     if ((int)terms.size() < 1 || (int)terms.size() > EZ_TERM_MAX) return fail(EZ_ERR_INVALID_ARG, "1 <= n_terms <= 8");
@@ -234,14 +277,31 @@ ez_status build_program(int d, const std::vector<double> &nu, const std::vector<
             deg += m;
         }
         if (deg > EZ_MULT_MAX) return fail(EZ_ERR_INVALID_ARG, "total degree of a term must be <= 64");
+        // expansion of the product of (singular + Taylor) factors into combinations;
         // Hadamard exponents mu = d + sum_f j_f (nu_f - d) + 2J must avoid 0 (paper, Sec. 3)
         std::vector<int> jj(T.fac.size(), 0);
         while (true) {
-            int E = 0, rest = 0;
+            int E = 0, rest = 0, Q = 0;
+            double coef = T.coef;
             for (size_t f = 0; f < T.fac.size(); ++f) {
                 E += jj[f] * ((int)P.nu[T.fac[f].first] - d);
+                Q += jj[f] * (P.logm[T.fac[f].first] >= 0 ? 1 : 0);
                 rest += T.fac[f].second - jj[f];
+                double bn = 1.0;
+                for (int q = 1; q <= jj[f]; ++q) bn = bn * (double)(T.fac[f].second - jj[f] + q) / (double)q;
+                coef *= bn;
             }
+            if ((int)combos.size() >= EZ_COMBO_MAX)
+                return fail(EZ_ERR_UNSUPPORTED, "more than 64 expansion terms on (0, eps)");
+            EzCombo cb;
+            std::memset(&cb, 0, sizeof(cb));
+            cb.coef = coef;
+            cb.E = E;
+            cb.Q = Q;
+            cb.t = (signed char)t;
+            cb.res = (signed char)T.res;
+            for (size_t f = 0; f < T.fac.size(); ++f) cb.j[f] = (signed char)jj[f];
+            combos.push_back(cb);
             int Jmax = std::min(rest * ell_max, 32);
             for (int J = 0; J <= Jmax; ++J)
                 if (d + E + 2 * J == 0)
@@ -258,16 +318,18 @@ ez_status build_program(int d, const std::vector<double> &nu, const std::vector<
     return EZ_OK;
 }
 
-std::string plan_key(int d, int batch, const ez_quad_spec *specs, int n_specs) {
+std::string plan_key(int d, int batch, const ez_quad_spec *specs, int n_specs, int ndb) {
     std::string k(reinterpret_cast<const char *>(&d), sizeof(d));
+    k.append(reinterpret_cast<const char *>(&ndb), sizeof(ndb));
     k.append(reinterpret_cast<const char *>(&batch), sizeof(batch));
     k.append(reinterpret_cast<const char *>(&n_specs), sizeof(n_specs));
     k.append(reinterpret_cast<const char *>(specs), sizeof(ez_quad_spec) * (size_t)n_specs);
     return k;
 }
 
-ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, int n_specs, DevPlan **out) {
-    std::string key = plan_key(d, batch, specs, n_specs);
+// ndb: directions per workgroup of the Hadamard direction kernel
+ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, int n_specs, int ndb, DevPlan **out) {
+    std::string key = plan_key(d, batch, specs, n_specs, ndb);
     auto it = S->plans.find(key);
     if (it != S->plans.end()) { *out = it->second; return EZ_OK; }
     // rule tables: one v-rule per distinct n_q, one u-rule per distinct (n_panels, n_g, eps)
@@ -327,7 +389,7 @@ ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, 
         hb[b] = (int)htiles;
         tiles += (nn + EZ_TILE - 1) / EZ_TILE;
         dirs += nd;
-        htiles += (nd + 63) / 64;
+        htiles += (nd + ndb - 1) / ndb;
         if (tiles > (1ll << 30) || dirs > (1ll << 30)) {
             delete P;
             return fail(EZ_ERR_INVALID_ARG, "quadrature too large for one call");
@@ -336,6 +398,44 @@ ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, 
     tb[batch] = (int)tiles;
     db[batch] = (int)dirs;
     hb[batch] = (int)htiles;
+    // probe directions and least-squares inverses for the Taylor coefficients
+    {
+        int lp = 0;
+        for (int b = 0; b < batch; ++b) lp = std::max(lp, P->host_plans[b].ell);
+        const int np = (d == 1) ? 1 : (d == 2 ? n_mono(2, 2 * lp) + 8 : n_mono(3, 2 * lp) + 32);
+        std::vector<double> probes((size_t)np * d);
+        for (int p = 0; p < np; ++p) {
+            if (d == 1) {
+                probes[p] = 1.0;
+            } else if (d == 2) {
+                const double th = M_PI * (p + 0.5) / np;
+                probes[2 * p] = std::cos(th);
+                probes[2 * p + 1] = std::sin(th);
+            } else {          // Fibonacci points on the unit sphere
+                const double z = 1.0 - 2.0 * (p + 0.5) / np, r = std::sqrt(1.0 - z * z);
+                const double th = M_PI * (1.0 + std::sqrt(5.0)) * (p + 0.5);
+                probes[3 * p] = r * std::cos(th);
+                probes[3 * p + 1] = r * std::sin(th);
+                probes[3 * p + 2] = z;
+            }
+        }
+        P->n_probe = np;
+        P->ell_probe = lp;
+        P->probe_off = (int)rules.size();
+        rules.insert(rules.end(), probes.begin(), probes.end());
+        std::vector<double> mono, Mk, pinv;
+        for (int k = 0; k <= lp; ++k) {
+            const int nm = n_mono(d, 2 * k);
+            Mk.assign((size_t)np * nm, 0.0);
+            for (int p = 0; p < np; ++p) {
+                monomials(d, 2 * k, &probes[(size_t)p * d], mono);
+                for (int a = 0; a < nm; ++a) Mk[(size_t)p * nm + a] = mono[a];
+            }
+            lstsq_pinv(np, nm, Mk, pinv);
+            P->pinv_off[k] = (int)rules.size();
+            rules.insert(rules.end(), pinv.begin(), pinv.end());
+        }
+    }
     P->n_tiles = (int)tiles;
     P->n_dirs = (int)dirs;
     P->n_htiles = (int)htiles;
@@ -382,14 +482,16 @@ int rec_capacity(int d, double lam, double acut) {
     return (int)std::ceil(kOmega[d] * std::pow(R + kSkew, d)) + 16;
 }
 
-ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog, const ez_quad_spec *specs,
-                   int n_specs, double *out_dev, uint32_t *status_dev, hipStream_t stream) {
+ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog, const std::vector<EzCombo> &combos,
+                   const ez_quad_spec *specs, int n_specs, double *out_dev, uint32_t *status_dev, hipStream_t stream) {
     int dev = 0;
     EZ_HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lock(g_mu);
     DeviceState *S = device_state(dev);
     DevPlan *P = nullptr;
-    ez_status st = get_plan(S, d, batch, specs, n_specs, &P);
+    if (combos.size() < 2) return fail(EZ_ERR_INVALID_ARG, "internal: expansion with fewer than 2 terms");
+    const int ndb = 256 / (int)combos.size();
+    ez_status st = get_plan(S, d, batch, specs, n_specs, ndb, &P);
     if (st) return st;
     double lam_min = 1e300, lam_max = 0.0, acut = spec_acut(specs[0]);
     for (int i = 0; i < n_specs; ++i) {
@@ -409,7 +511,9 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
         (st = grow(S->rec, sizeof(double) * (size_t)batch * tab.rec_cap * 4)) ||
         (st = grow(S->tile_part, sizeof(double) * 2 * (size_t)P->n_tiles * prog.n_res)) ||
         (st = grow(S->dir_part, sizeof(double) * (size_t)P->n_dirs * prog.n_res)) ||
-        (st = grow(S->dir_flag, sizeof(uint32_t) * (size_t)P->n_dirs)))
+        (st = grow(S->dir_flag, sizeof(uint32_t) * (size_t)P->n_dirs)) ||
+        (st = grow(S->probe_val, sizeof(double) * (size_t)batch * P->n_probe * prog.n_nu * (EZ_ELL_MAX + 1))) ||
+        (st = grow(S->tensor, sizeof(double) * (size_t)batch * prog.n_nu * EZ_TDIM)))
         return st;
     tab.real = (double *)S->real.p;
     tab.rn = (int *)S->rn.p;
@@ -434,6 +538,14 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     qa.tile_begin = (const int *)P->tile_begin.p;
     qa.dir_begin = (const int *)P->dir_begin.p;
     qa.htile_begin = (const int *)P->htile_begin.p;
+    qa.n_probe = P->n_probe;
+    qa.ell_probe = P->ell_probe;
+    qa.probe_off = P->probe_off;
+    for (int k = 0; k <= EZ_ELL_MAX; ++k) qa.pinv_off[k] = P->pinv_off[k];
+    qa.probe_val = (double *)S->probe_val.p;
+    qa.tensor = (double *)S->tensor.p;
+    qa.n_combo = (int)combos.size();
+    for (size_t c = 0; c < combos.size(); ++c) qa.combo[c] = combos[c];
     qa.meta = (const EzLatMeta *)S->meta.p;
     qa.tab = tab;
     qa.rules = (const double *)P->rules.p;
@@ -473,7 +585,7 @@ ez_status ez_finalize(void) {
         DeviceState *S = kv.second;
         for (auto &p : S->plans) free_plan(p.second);
         free_buf(S->meta); free_buf(S->real); free_buf(S->rec); free_buf(S->rn); free_buf(S->rows);
-        free_buf(S->tile_part); free_buf(S->dir_part); free_buf(S->dir_flag);
+        free_buf(S->tile_part); free_buf(S->dir_part); free_buf(S->dir_flag); free_buf(S->probe_val); free_buf(S->tensor);
         free_buf(S->gmeta); free_buf(S->greal); free_buf(S->grec);
         delete S;
     }
@@ -508,8 +620,9 @@ ez_status ez_lattice_sums(int batch, int d, const double *A_dev, int n_nu, const
             terms[t].fac.push_back({term_fac[EZ_FAC_MAX * t + f], term_mult[EZ_FAC_MAX * t + f]});
     }
     EzProgram prog;
-    if ((st = build_program(d, nu, terms, n_results, ell_max, prog))) return st;
-    return run_sums(batch, d, A_dev, prog, specs, n_specs, out_dev, status_dev, (hipStream_t)stream);
+    std::vector<EzCombo> combos;
+    if ((st = build_program(d, nu, terms, n_results, ell_max, prog, combos))) return st;
+    return run_sums(batch, d, A_dev, prog, combos, specs, n_specs, out_dev, status_dev, (hipStream_t)stream);
 }
 
 ez_status ez_nbody_lattice_sum(int batch, int d, const double *A_dev, int n, const double *nu_host,
@@ -532,8 +645,9 @@ ez_status ez_nbody_lattice_sum(int batch, int d, const double *A_dev, int n, con
     T.coef = 1.0;
     for (size_t i = 0; i < distinct.size(); ++i) T.fac.push_back({(int)i, mult[i]});
     EzProgram prog;
-    if ((st = build_program(d, distinct, {T}, 1, spec->ell, prog))) return st;
-    return run_sums(batch, d, A_dev, prog, spec, 1, out_dev, status_dev, (hipStream_t)stream);
+    std::vector<EzCombo> combos;
+    if ((st = build_program(d, distinct, {T}, 1, spec->ell, prog, combos))) return st;
+    return run_sums(batch, d, A_dev, prog, combos, spec, 1, out_dev, status_dev, (hipStream_t)stream);
 }
 
 ez_status ez_atm_energy(int batch, int d, const double *A_dev, const ez_quad_spec *spec, double *E_dev,
@@ -548,8 +662,9 @@ ez_status ez_atm_energy(int batch, int d, const double *A_dev, const ez_quad_spe
     Term t1{0, -3.0 / 16.0, {{0, 1}, {3, 2}}};
     Term t2{0, 3.0 / 8.0, {{1, 1}, {2, 1}, {3, 1}}};
     EzProgram prog;
-    if ((st = build_program(d, nu, {t0, t1, t2}, 1, spec->ell, prog))) return st;
-    return run_sums(batch, d, A_dev, prog, spec, 1, E_dev, status_dev, (hipStream_t)stream);
+    std::vector<EzCombo> combos;
+    if ((st = build_program(d, nu, {t0, t1, t2}, 1, spec->ell, prog, combos))) return st;
+    return run_sums(batch, d, A_dev, prog, combos, spec, 1, E_dev, status_dev, (hipStream_t)stream);
 }
 
 ez_status ez_epstein_zeta(int d, const double *A_dev, int n_nu, const double *nu_host, int64_t n_pts,
@@ -595,7 +710,7 @@ ez_status ez_epstein_zeta(int d, const double *A_dev, int n_nu, const double *nu
     std::memset(&sp, 0, sizeof(sp));
     sp.n_q = 1; sp.n_panels = 1; sp.n_g = 1; sp.ell = 0; sp.eps = 0.01; sp.lam = lam; sp.a_cut = a_cut;
     DevPlan *P = nullptr;
-    if ((st = get_plan(S, d, 1, &sp, 1, &P))) return st;
+    if ((st = get_plan(S, d, 1, &sp, 1, 256, &P))) return st;
     EzSetupArgs sa;
     sa.prog = prog;
     sa.A = A_dev;

@@ -13,13 +13,32 @@ struct EzSetupArgs {
     uint32_t *status_out;      // general-x mode: receives the lattice flags (may be NULL)
 };
 
+// One term of the (0, eps) expansion: term t with factor slot f taking its singular
+// part j[f] times and its Taylor part mult - j[f] times; coef holds the term
+// coefficient times the binomials; the integrand is u^{d-1+E} L^Q times a
+// polynomial in u^2.
+#define EZ_COMBO_MAX 64
+struct EzCombo {
+    double coef;
+    int E, Q;
+    signed char t, res, j[EZ_FAC_MAX];
+    short pad_;
+};
+
 struct EzQuadArgs {
     EzProgram prog;
     int batch;
     const EzInstPlan *plans;
     const int *tile_begin;     // batch + 1 prefix of node tiles
     const int *dir_begin;      // batch + 1 prefix of directions
-    const int *htile_begin;    // batch + 1 prefix of 64-direction Hadamard tiles
+    const int *htile_begin;    // batch + 1 prefix of 256-direction Hadamard tiles
+    int n_probe, ell_probe;    // probe directions per lattice, Taylor order they carry
+    int probe_off;             // offset of the probe directions (n_probe x d) in rules
+    int pinv_off[EZ_ELL_MAX + 1];  // offsets of the least-squares inverses (nmono x n_probe) in rules
+    double *probe_val;         // [batch][n_probe][n_nu][EZ_ELL_MAX + 1]
+    double *tensor;            // [batch][n_nu][EZ_TDIM] coefficients of C_k in w_hat monomials
+    int n_combo;
+    EzCombo combo[EZ_COMBO_MAX];
     const EzLatMeta *meta;
     EzTables tab;
     const double *rules;       // Gauss rules (v on [0,1], u on (eps,1/2])
