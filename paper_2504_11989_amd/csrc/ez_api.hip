@@ -490,9 +490,21 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     DeviceState *S = device_state(dev);
     DevPlan *P = nullptr;
     if (combos.size() < 2) return fail(EZ_ERR_INVALID_ARG, "internal: expansion with fewer than 2 terms");
-    const int ndb = 256 / (int)combos.size();
+    const int ndb = std::min(EZ_HDIR, 256 / (int)combos.size());
+    int ell_max = 0;
+    for (int i = 0; i < n_specs; ++i) ell_max = std::max(ell_max, specs[i].ell);
+    int maxdeg = 0;          // highest power of u^2 in the (0, eps) product polynomials
+    for (const EzCombo &cb : combos) {
+        int rest = 0;
+        for (int f = 0; f < prog.term_nfac[cb.t]; ++f) rest += prog.term_mult[cb.t][f] - cb.j[f];
+        maxdeg = std::max(maxdeg, rest * ell_max);
+    }
+    if (maxdeg > 32)
+        return fail(EZ_ERR_UNSUPPORTED, "Taylor product of degree > 32 in u^2 on (0, eps): lower ell or the multiplicity");
     ez_status st = get_plan(S, d, batch, specs, n_specs, ndb, &P);
     if (st) return st;
+    const int n_pblk = (P->n_probe + 63) / 64;
+    const int n_slice = std::max(1, std::min(EZ_SLICE_MAX, 512 / std::max(1, batch * n_pblk)));
     double lam_min = 1e300, lam_max = 0.0, acut = spec_acut(specs[0]);
     for (int i = 0; i < n_specs; ++i) {
         lam_min = std::min(lam_min, spec_lam(specs[i]));
@@ -512,7 +524,7 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
         (st = grow(S->tile_part, sizeof(double) * 2 * (size_t)P->n_tiles * prog.n_res)) ||
         (st = grow(S->dir_part, sizeof(double) * (size_t)P->n_dirs * prog.n_res)) ||
         (st = grow(S->dir_flag, sizeof(uint32_t) * (size_t)P->n_dirs)) ||
-        (st = grow(S->probe_val, sizeof(double) * (size_t)batch * P->n_probe * prog.n_nu * (EZ_ELL_MAX + 1))) ||
+        (st = grow(S->probe_val, sizeof(double) * (size_t)batch * n_slice * P->n_probe * prog.n_nu * (EZ_ELL_MAX + 1))) ||
         (st = grow(S->tensor, sizeof(double) * (size_t)batch * prog.n_nu * EZ_TDIM)))
         return st;
     tab.real = (double *)S->real.p;
@@ -538,6 +550,9 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     qa.tile_begin = (const int *)P->tile_begin.p;
     qa.dir_begin = (const int *)P->dir_begin.p;
     qa.htile_begin = (const int *)P->htile_begin.p;
+    qa.n_dir_blk = ndb;
+    qa.poly_deg = maxdeg <= 12 ? 13 : 33;
+    qa.n_slice = n_slice;
     qa.n_probe = P->n_probe;
     qa.ell_probe = P->ell_probe;
     qa.probe_off = P->probe_off;

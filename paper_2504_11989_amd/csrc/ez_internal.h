@@ -11,6 +11,8 @@
 #define EZ_MULT_MAX 64   // total degree of a product term
 #define EZ_TILE 256      // quadrature nodes per workgroup of the node kernel
 #define EZ_TDIM 525      // monomials of even degree <= 2 EZ_ELL_MAX in 3 variables
+#define EZ_HDIR 64       // quadrature directions per workgroup of the Hadamard direction kernel
+#define EZ_SLICE_MAX 8   // table slices of the probe kernel
 
 // Which lattice sums one call computes (host-built, passed by value).
 // Exponent nu_i enters the reciprocal sum through E_{p_i}(a), p_i = (nu_i - d + 2)/2

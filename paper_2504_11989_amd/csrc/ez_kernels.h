@@ -31,11 +31,14 @@ struct EzQuadArgs {
     const EzInstPlan *plans;
     const int *tile_begin;     // batch + 1 prefix of node tiles
     const int *dir_begin;      // batch + 1 prefix of directions
-    const int *htile_begin;    // batch + 1 prefix of 256-direction Hadamard tiles
+    const int *htile_begin;    // batch + 1 prefix of Hadamard direction tiles
+    int n_dir_blk;             // directions per Hadamard direction workgroup (<= EZ_HDIR)
+    int poly_deg;              // 13 or 33: coefficients kept in the (0, eps) product polynomials
     int n_probe, ell_probe;    // probe directions per lattice, Taylor order they carry
+    int n_slice;               // table slices per probe set (workgroups that split the sums)
     int probe_off;             // offset of the probe directions (n_probe x d) in rules
     int pinv_off[EZ_ELL_MAX + 1];  // offsets of the least-squares inverses (nmono x n_probe) in rules
-    double *probe_val;         // [batch][n_probe][n_nu][EZ_ELL_MAX + 1]
+    double *probe_val;         // [batch][n_slice][n_probe][n_nu][EZ_ELL_MAX + 1] partial sums
     double *tensor;            // [batch][n_nu][EZ_TDIM] coefficients of C_k in w_hat monomials
     int n_combo;
     EzCombo combo[EZ_COMBO_MAX];

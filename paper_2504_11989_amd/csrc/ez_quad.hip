@@ -313,14 +313,13 @@ __host__ __device__ constexpr double cbinom(int n, int k) {
 // ---------------------------------------------------------------------------
 constexpr int EZ_HW = 4;                        // waves per probe workgroup
 
-// C[i][k] at direction w: real-space, reciprocal (m* != 0), m* = 0 and self parts.
-// Lane = direction, the tables split over EZ_HW waves, summed in LDS in fixed
-// order; on return wave 0 holds the full coefficients.
+// Partial C[i][k] at direction w over one slice of the tables: real-space pairs,
+// reciprocal m* != 0, and (slice 0 only) the self term and the m* = 0 series.
+// Lane = direction, the slice's entries split over EZ_HW waves, summed in LDS in
+// fixed order; on return wave 0 holds the slice's coefficients.
 template <int D, int NNU>
 __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta *M, int ell, const double *w,
-                              double (&C)[NNU][EZ_ELL_MAX + 1], double *lds) {
-    constexpr int FSZ = EZ_HCH * NNU * EZ_NF;
-    (void)FSZ;
+                              double (&C)[NNU][EZ_ELL_MAX + 1], double *lds, int slice, int n_slice) {
     double (*fsh)[NNU][EZ_NF] = reinterpret_cast<double (*)[NNU][EZ_NF]>(lds);
     const EzProgram &prog = args.prog;
     const int lane = (int)threadIdx.x & 63, part = (int)threadIdx.x >> 6;
@@ -336,14 +335,14 @@ __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta 
     for (int i = 0; i < NNU; ++i) {
 #pragma unroll
         for (int k = 0; k <= EZ_ELL_MAX; ++k) C[i][k] = 0.0;
-        if (part == 0) C[i][0] = -M->self_[i];
+        if (part == 0 && slice == 0) C[i][0] = -M->self_[i];
     }
     // real space: 2 W cos(2 pi u w.z) = 2 W sum_k (-1)^k (2 pi w.z)^{2k} u^{2k} / (2k)!
     {
         const int rs = args.tab.rstride;
         const double *rt = args.tab.real + (size_t)inst * args.tab.real_cap * rs;
         const int n_real = M->n_real;
-        for (int p = part; p < n_real; p += EZ_HW) {
+        for (int p = slice * EZ_HW + part; p < n_real; p += EZ_HW * n_slice) {
             const double *e = rt + (size_t)p * rs;
             double t = 0.0;
 #pragma unroll
@@ -355,7 +354,7 @@ __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta 
                 if (k <= ell) {
 #pragma unroll
                     for (int i = 0; i < NNU; ++i) C[i][k] = fma(e[3 + i], term, C[i][k]);
-                    term *= -x / ((2.0 * k + 1.0) * (2.0 * k + 2.0));
+                    term *= -x * (1.0 / ((2.0 * k + 1.0) * (2.0 * k + 2.0)));
                 }
             }
         }
@@ -366,27 +365,27 @@ __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta 
     {
         const double *kt = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
         const int n_rec = M->n_rec;
-        for (int base = 1; base < n_rec; base += EZ_HCH) {
+        for (int base = 1 + slice * EZ_HCH; base < n_rec; base += EZ_HCH * n_slice) {
             __syncthreads();
-            if ((int)threadIdx.x < EZ_HCH) {
-                const int q = base + (int)threadIdx.x;
+            // F_n for (entry, nu) pairs, one per thread
+            for (int task = (int)threadIdx.x; task < EZ_HCH * NNU; task += 64 * EZ_HW) {
+                const int te = task / NNU, i = task - te * NNU;
+                const int q = base + te;
                 if (q < n_rec) {
                     const double a0 = alpha * kt[(size_t)q * 4 + 3];
-                    const double ex = exp(-a0), inv = 1.0 / a0;
-                    const double E1 = ez_e1(a0, ex, inv);
-                    const double Eh = ez_ehalf(a0);
+                    const double ex = exp(-a0), inv = ez_rcp(a0);
+                    const int p2 = prog.p2[i];
+                    const double E1 = ((p2 & 1) == 0) ? ez_e1(a0, ex, inv) : 0.0;
+                    const double Eh = (p2 & 1) ? ez_ehalf(a0) : 0.0;
+                    double E = ez_ep_from(p2, a0, ex, inv, E1, Eh);
+                    double sc = M->K[i];
 #pragma unroll
-                    for (int i = 0; i < NNU; ++i) {
-                        const int p2 = prog.p2[i];
-                        double E = ez_ep_from(p2, a0, ex, inv, E1, Eh);
-                        double sc = M->K[i];
-                        double rf = 1.0;
-                        for (int n = 0; n <= 2 * ell; ++n) {
-                            fsh[threadIdx.x][i][n] = sc * E * rf;
+                    for (int n = 0; n < EZ_NF; ++n) {
+                        if (n <= 2 * ell) {
+                            fsh[te][i][n] = sc * E;
                             const double pnm1 = 0.5 * (double)p2 - (double)n - 1.0;
                             E = (ex - pnm1 * E) * inv;          // E_{p-n-1}
-                            sc *= -alpha;
-                            rf /= (double)(n + 1);
+                            sc *= -alpha * (1.0 / (double)(n + 1));
                         }
                     }
                 }
@@ -437,7 +436,7 @@ __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta 
         }
     }
     // m* = 0: regular part of K E_p(alpha |k|^2) as a series in a = alpha w2 u^2
-    if (part != 0) return;
+    if (part != 0 || slice != 0) return;
     const double aw = alpha * w2;
 #pragma unroll
     for (int i = 0; i < NNU; ++i) {
@@ -489,21 +488,25 @@ __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta 
     }
 }
 
-// Probe kernel: C_k(B w_hat_p) for the probe directions, 64 per workgroup.
+// Probe kernel: partial C_k(B w_hat_p) over one table slice for 64 probe directions.
+// Grid: batch x probe blocks x slices.
 template <int D, int NNU>
 __global__ __launch_bounds__(64 * EZ_HW) void ez_probe_kernel(EzQuadArgs args) {
     constexpr int FSZ = EZ_HCH * NNU * EZ_NF;
     constexpr int CSZ = 64 * NNU * (EZ_ELL_MAX + 1);
     __shared__ double lds[FSZ > CSZ ? FSZ : CSZ];
     const int nblk = (args.n_probe + 63) / 64;
-    const int inst = (int)blockIdx.x / nblk;
-    const int pb = (int)blockIdx.x - inst * nblk;
+    const int S = args.n_slice;
+    const int inst = (int)blockIdx.x / (nblk * S);
+    const int rem = (int)blockIdx.x - inst * nblk * S;
+    const int pb = rem / S, slice = rem - pb * S;
     const EzLatMeta *M = args.meta + inst;
     const int lane = (int)threadIdx.x & 63, part = (int)threadIdx.x >> 6;
     const int p = pb * 64 + lane;
     const bool valid = p < args.n_probe;
     const int ell = args.ell_probe;
-    double *out = args.probe_val + ((size_t)inst * args.n_probe + (valid ? p : 0)) * NNU * (EZ_ELL_MAX + 1);
+    double *out = args.probe_val +
+                  (((size_t)inst * S + slice) * args.n_probe + (valid ? p : 0)) * NNU * (EZ_ELL_MAX + 1);
     if (M->status != 0) return;               // uniform; the direction kernel skips the lattice
     double wh[3] = {0.0, 0.0, 0.0}, w[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -516,7 +519,7 @@ __global__ __launch_bounds__(64 * EZ_HW) void ez_probe_kernel(EzQuadArgs args) {
         w[i] = s;
     }
     double C[NNU][EZ_ELL_MAX + 1];
-    taylor_coeffs<D, NNU>(args, inst, M, ell, w, C, lds);
+    taylor_coeffs<D, NNU>(args, inst, M, ell, w, C, lds, slice, S);
     if (part != 0 || !valid) return;
 #pragma unroll
     for (int i = 0; i < NNU; ++i)
@@ -528,61 +531,89 @@ __global__ __launch_bounds__(64 * EZ_HW) void ez_probe_kernel(EzQuadArgs args) {
 // number of monomials of degree g in D variables
 __host__ __device__ constexpr int nmono(int D, int g) { return D == 1 ? 1 : (D == 2 ? g + 1 : (g + 1) * (g + 2) / 2); }
 
-// Tensor kernel: T[i][off_k + a] = sum_p pinv_k[a][p] C_k(probe p), one workgroup per lattice.
+constexpr int EZ_TOUT = 16;                     // tensor coefficients per workgroup
+
+// Tensor kernel: T[i][off_k + a] = sum_p pinv_k[a][p] C_k(probe p), the probe values
+// first summed over the table slices in fixed order.  Grid: batch x n_nu x groups of
+// EZ_TOUT coefficients; thread = (coefficient, probe residue mod 16).
 template <int D, int NNU>
 __global__ __launch_bounds__(256) void ez_tensor_kernel(EzQuadArgs args) {
-    const int inst = blockIdx.x;
-    if (args.meta[inst].status != 0) return;
-    const int lp = args.ell_probe;
-    const double *pv = args.probe_val + (size_t)inst * args.n_probe * NNU * (EZ_ELL_MAX + 1);
-    double *T = args.tensor + (size_t)inst * NNU * EZ_TDIM;
+    __shared__ double part[EZ_TOUT][17];
+    const int lp = args.ell_probe, S = args.n_slice, np = args.n_probe;
     int tdim = 0;
     for (int k = 0; k <= lp; ++k) tdim += nmono(D, 2 * k);
-    for (int idx = threadIdx.x; idx < NNU * tdim; idx += 256) {
-        const int i = idx / tdim;
-        int a = idx - i * tdim, k = 0;
+    const int ngrp = (tdim + EZ_TOUT - 1) / EZ_TOUT;
+    const int inst = (int)blockIdx.x / (NNU * ngrp);
+    const int rem = (int)blockIdx.x - inst * NNU * ngrp;
+    const int i = rem / ngrp, grp = rem - i * ngrp;
+    if (args.meta[inst].status != 0) return;  // uniform over the workgroup
+    const int o = (int)threadIdx.x >> 4, pp = (int)threadIdx.x & 15;
+    const int aa = grp * EZ_TOUT + o;
+    double s = 0.0;
+    if (aa < tdim) {
+        int a = aa, k = 0;
         while (a >= nmono(D, 2 * k)) { a -= nmono(D, 2 * k); ++k; }
-        const double *pinv = args.rules + args.pinv_off[k] + (size_t)a * args.n_probe;
-        double s = 0.0;
-        for (int p = 0; p < args.n_probe; ++p)
-            s = fma(pinv[p], pv[((size_t)p * NNU + i) * (EZ_ELL_MAX + 1) + k], s);
-        T[(size_t)i * EZ_TDIM + (idx - i * tdim)] = s;
+        const double *pinv = args.rules + args.pinv_off[k] + (size_t)a * np;
+        const double *pv = args.probe_val + (size_t)inst * S * np * NNU * (EZ_ELL_MAX + 1) +
+                           (size_t)i * (EZ_ELL_MAX + 1) + k;
+        for (int p = pp; p < np; p += 16) {
+            double v = 0.0;
+            for (int sl = 0; sl < S; ++sl) v += pv[((size_t)sl * np + p) * NNU * (EZ_ELL_MAX + 1)];
+            s = fma(pinv[p], v, s);
+        }
+    }
+    part[o][pp] = s;
+    __syncthreads();
+    if (pp == 0 && aa < tdim) {
+        double t = 0.0;
+        for (int q = 0; q < 16; ++q) t += part[o][q];
+        args.tensor[((size_t)inst * NNU + i) * EZ_TDIM + aa] = t;
     }
 }
 
-// Direction kernel: a workgroup takes ndb = 256 / n_combo directions of one lattice.
-// Phase 1: one thread per direction contracts the tensors with the monomials of
-// w_hat (C_k), and the singular coefficients; phase 2: one thread per (direction,
-// combination) builds the product polynomial and its Hadamard integrals; phase 3:
-// per direction, the combinations are summed in fixed order.
-template <int D, int NNU>
+// Direction kernel: a workgroup takes ndb = min(EZ_HDIR, 256 / n_combo) directions
+// of one lattice.  Phase 0: direction geometry and the tensors into LDS; phase 1:
+// one thread per (direction, order k) contracts the tensor with the monomials of
+// w_hat of degree 2k (C_k); phase 2: one thread per (direction, combination) builds
+// the product polynomial (PD coefficients, in registers) and its Hadamard
+// integrals; phase 3: per direction, the combinations are summed in fixed order.
+template <int D, int NNU, int PD>
 __global__ __launch_bounds__(256) void ez_hadamard_kernel(EzQuadArgs args) {
-    // every term has at least two combinations (singular part used 0 or >= 1 times),
-    // so a workgroup holds at most 128 directions
-    __shared__ double Csh[128][NNU][EZ_ELL_MAX + 1];
-    __shared__ double ssh[128][NNU];     // sigma_i |w|^{nu_i - d}
-    __shared__ double dsh[128][3];       // 2 w_v, log(pi eps^2 |w|^2), validity
-    __shared__ double vsh[256];          // value of each (direction, combination)
-    __shared__ uint32_t fsh_bad[128];    // a Hadamard exponent mu = 0 was met
+    __shared__ double Tsh[NNU * EZ_TDIM];
+    __shared__ double Csh[EZ_HDIR][NNU][EZ_ELL_MAX + 1];
+    __shared__ double ssh[EZ_HDIR][NNU];   // sigma_i |w|^{nu_i - d}
+    __shared__ double dsh[EZ_HDIR][6];     // 2 w_v, log(pi eps^2 |w|^2), validity, w_hat
+    __shared__ double vsh[256];            // value of each (direction, combination)
+    __shared__ uint32_t fsh_bad[EZ_HDIR];  // a Hadamard exponent mu = 0 was met
     const int blk = blockIdx.x;
     const int inst = find_segment(args.htile_begin, args.batch, blk);
     const EzInstPlan P = args.plans[inst];
     const EzLatMeta *M = args.meta + inst;
     const EzProgram &prog = args.prog;
     const int n_res = prog.n_res, nc = args.n_combo;
-    const int ndb = 256 / nc;                       // directions per workgroup
+    const int ndb = args.n_dir_blk;
     const int d0 = (blk - args.htile_begin[inst]) * ndb;
     const int ell = P.ell;
+    const int tid = (int)threadIdx.x;
     if (M->status != 0) {                           // uniform over the workgroup
-        const int dl = d0 + (int)threadIdx.x;
-        if ((int)threadIdx.x < ndb && dl < P.n_dir) {
+        const int dl = d0 + tid;
+        if (tid < ndb && dl < P.n_dir) {
             for (int r = 0; r < n_res; ++r) args.dir_part[(size_t)(P.dir_begin + dl) * n_res + r] = 0.0;
             args.dir_flag[P.dir_begin + dl] = 0;
         }
         return;
     }
-    if ((int)threadIdx.x < ndb) {
-        const int dl = d0 + (int)threadIdx.x;
+    int tdim = 0;
+    for (int k = 0; k <= ell; ++k) tdim += nmono(D, 2 * k);
+    {
+        const double *T = args.tensor + (size_t)inst * NNU * EZ_TDIM;
+        for (int idx = tid; idx < NNU * tdim; idx += 256) {
+            const int i = idx / tdim;
+            Tsh[idx] = T[(size_t)i * EZ_TDIM + (idx - i * tdim)];
+        }
+    }
+    if (tid < ndb) {
+        const int dl = d0 + tid;
         const bool valid = dl < P.n_dir;
         double B[D * D];
 #pragma unroll
@@ -592,86 +623,90 @@ __global__ __launch_bounds__(256) void ez_hadamard_kernel(EzQuadArgs args) {
         double w2 = 0.0;
 #pragma unroll
         for (int i = 0; i < D; ++i) w2 = fma(w[i], w[i], w2);
-        const double *T = args.tensor + (size_t)inst * NNU * EZ_TDIM;
+#pragma unroll
+        for (int i = 0; i < NNU; ++i) ssh[tid][i] = M->sig[i] * pow(w2, 0.5 * prog.e[i]);
+        dsh[tid][0] = 2.0 * wv;
+        dsh[tid][1] = log(EZ_PI * P.eps * P.eps * w2);
+        dsh[tid][2] = valid ? 1.0 : 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) dsh[tid][3 + i] = wh[i];
+        fsh_bad[tid] = 0u;
+    }
+    __syncthreads();
+
+    // phase 1: C_k(w) = sum over monomials of degree 2k of w_hat (order: a0 desc, a1 desc)
+    for (int idx = tid; idx < ndb * (ell + 1); idx += 256) {
+        const int dd = idx / (ell + 1), k = idx - dd * (ell + 1);
+        const int g = 2 * k;
         int off = 0;
-        for (int k = 0; k <= ell; ++k) {
-            const int g = 2 * k;
-            double acc[NNU];
+        for (int kk = 0; kk < k; ++kk) off += nmono(D, 2 * kk);
+        const double x0 = dsh[dd][3], x1 = dsh[dd][4], x2 = dsh[dd][5];
+        double acc[NNU];
 #pragma unroll
-            for (int i = 0; i < NNU; ++i) acc[i] = 0.0;
-            if (D == 1) {
+        for (int i = 0; i < NNU; ++i) acc[i] = 0.0;
+        if (D == 1) {
+            double mono = 1.0;
+            for (int q = 0; q < g; ++q) mono *= x0;
 #pragma unroll
-                for (int i = 0; i < NNU; ++i) acc[i] = T[(size_t)i * EZ_TDIM + off] * pow(wh[0], (double)g);
-            } else if (D == 2) {
-                int a_idx = 0;
-                for (int a = g; a >= 0; --a, ++a_idx) {
-                    double mono = 1.0;
-                    for (int q = 0; q < a; ++q) mono *= wh[0];
-                    for (int q = 0; q < g - a; ++q) mono *= wh[1];
+            for (int i = 0; i < NNU; ++i) acc[i] = Tsh[i * tdim + off] * mono;
+        } else if (D == 2) {
+            int a_idx = 0;
+            for (int a = g; a >= 0; --a, ++a_idx) {
+                double mono = 1.0;
+                for (int q = 0; q < a; ++q) mono *= x0;
+                for (int q = 0; q < g - a; ++q) mono *= x1;
 #pragma unroll
-                    for (int i = 0; i < NNU; ++i) acc[i] = fma(T[(size_t)i * EZ_TDIM + off + a_idx], mono, acc[i]);
-                }
-            } else {
-                int a_idx = 0;
-                double pa = 1.0;
-                for (int q = 0; q < g; ++q) pa *= wh[0];
-                const double rx = (wh[0] != 0.0) ? 1.0 / wh[0] : 0.0;
-                for (int a = g; a >= 0; --a) {
-                    // x0^a: from x0^g by division while x0 != 0, directly otherwise
-                    double p0 = pa;
-                    if (wh[0] == 0.0) p0 = (a == 0) ? 1.0 : 0.0;
-                    double pb = 1.0;
-                    for (int q = 0; q < g - a; ++q) pb *= wh[1];
-                    const double ry = (wh[1] != 0.0) ? 1.0 / wh[1] : 0.0;
-                    for (int b = g - a; b >= 0; --b, ++a_idx) {
-                        double p1 = pb;
-                        if (wh[1] == 0.0) p1 = (b == 0) ? 1.0 : 0.0;
-                        double p2 = 1.0;
-                        for (int q = 0; q < g - a - b; ++q) p2 *= wh[2];
-                        const double mono = p0 * p1 * p2;
+                for (int i = 0; i < NNU; ++i) acc[i] = fma(Tsh[i * tdim + off + a_idx], mono, acc[i]);
+            }
+        } else {
+            int a_idx = 0;
+            for (int a = g; a >= 0; --a) {
+                double p0 = 1.0;
+                for (int q = 0; q < a; ++q) p0 *= x0;
+                for (int b = g - a; b >= 0; --b, ++a_idx) {
+                    double mono = p0;
+                    for (int q = 0; q < b; ++q) mono *= x1;
+                    for (int q = 0; q < g - a - b; ++q) mono *= x2;
 #pragma unroll
-                        for (int i = 0; i < NNU; ++i) acc[i] = fma(T[(size_t)i * EZ_TDIM + off + a_idx], mono, acc[i]);
-                        pb *= ry;
-                    }
-                    pa *= rx;
+                    for (int i = 0; i < NNU; ++i) acc[i] = fma(Tsh[i * tdim + off + a_idx], mono, acc[i]);
                 }
             }
-#pragma unroll
-            for (int i = 0; i < NNU; ++i) Csh[threadIdx.x][i][k] = acc[i];
-            off += nmono(D, g);
         }
 #pragma unroll
-        for (int i = 0; i < NNU; ++i) ssh[threadIdx.x][i] = M->sig[i] * pow(w2, 0.5 * prog.e[i]);
-        dsh[threadIdx.x][0] = 2.0 * wv;
-        dsh[threadIdx.x][1] = log(EZ_PI * P.eps * P.eps * w2);
-        dsh[threadIdx.x][2] = valid ? 1.0 : 0.0;
-        fsh_bad[threadIdx.x] = 0u;
+        for (int i = 0; i < NNU; ++i) Csh[dd][i][k] = acc[i];
     }
     __syncthreads();
 
     // phase 2: one (direction, combination) per thread
-    const int myd = (int)threadIdx.x / nc, myc = (int)threadIdx.x - myd * nc;
+    const int myd = tid / nc, myc = tid - myd * nc;
     bool bad = false;
     if (myd < ndb) {
         const EzCombo &cb = args.combo[myc];
         const int t = cb.t;
         const int nf = prog.term_nfac[t];
         double c = cb.coef;
-        double poly[EZ_PDEG];
+        double poly[PD];
         poly[0] = 1.0;
+#pragma unroll
+        for (int J = 1; J < PD; ++J) poly[J] = 0.0;
         int deg = 0;
         for (int f = 0; f < nf; ++f) {
             const int i = prog.term_fac[t][f];
             for (int q = 0; q < cb.j[f]; ++q) c *= ssh[myd][i];
+            double Ck[EZ_ELL_MAX + 1];
+#pragma unroll
+            for (int kk = 0; kk <= EZ_ELL_MAX; ++kk) Ck[kk] = (kk <= ell) ? Csh[myd][i][kk] : 0.0;
             for (int rep = 0; rep < prog.term_mult[t][f] - cb.j[f]; ++rep) {
-                const int nd = min(deg + ell, EZ_PDEG - 1);
-                for (int J = nd; J >= 0; --J) {
+                // poly <- poly * sum_k C_k u^{2k}, truncated to PD coefficients
+#pragma unroll
+                for (int J = PD - 1; J >= 0; --J) {
                     double sacc = 0.0;
-                    const int kmin = max(0, J - deg), kmax = min(ell, J);
-                    for (int kk = kmin; kk <= kmax; ++kk) sacc = fma(poly[J - kk], Csh[myd][i][kk], sacc);
+#pragma unroll
+                    for (int kk = 0; kk <= EZ_ELL_MAX; ++kk)
+                        if (kk <= J) sacc = fma(poly[J - kk], Ck[kk], sacc);
                     poly[J] = sacc;
                 }
-                deg = nd;
+                deg = min(deg + ell, PD - 1);
             }
         }
         // fp int_0^eps u^{mu-1} L^Q du, mu = d + E + 2J:
@@ -681,33 +716,41 @@ __global__ __launch_bounds__(256) void ez_hadamard_kernel(EzQuadArgs args) {
         double mu = (double)(D + cb.E);
         double em = pow(eps, mu);
         double acc = 0.0;
-        for (int J = 0; J <= deg; ++J, mu += 2.0, em *= eps2) {
-            if (mu == 0.0) { bad = true; continue; }
-            const double rmu = ez_rcp(mu);
-            double I = em * rmu, Lp = 1.0;
-            for (int j = 1; j <= cb.Q; ++j) {
-                Lp *= Leps;
-                I = (em * Lp - 2.0 * (double)j * I) * rmu;
+#pragma unroll
+        for (int J = 0; J < PD; ++J) {
+            if (J <= deg) {
+                if (mu == 0.0) {
+                    bad = true;
+                } else {
+                    const double rmu = ez_rcp(mu);
+                    double I = em * rmu, Lp = 1.0;
+                    for (int j = 1; j <= cb.Q; ++j) {
+                        Lp *= Leps;
+                        I = (em * Lp - 2.0 * (double)j * I) * rmu;
+                    }
+                    acc = fma(poly[J], I, acc);
+                }
             }
-            acc = fma(poly[J], I, acc);
+            mu += 2.0;
+            em *= eps2;
         }
-        vsh[threadIdx.x] = c * acc;
+        vsh[tid] = c * acc;
         if (bad) atomicOr(&fsh_bad[myd], 1u);
     }
     __syncthreads();
     // phase 3: per direction, fixed-order sum over the combinations
-    if ((int)threadIdx.x < ndb) {
-        const int dl = d0 + (int)threadIdx.x;
+    if (tid < ndb) {
+        const int dl = d0 + tid;
         if (dl < P.n_dir) {
             const int gd = P.dir_begin + dl;
             for (int r = 0; r < n_res; ++r) {
                 double h = 0.0;
                 for (int c = 0; c < nc; ++c)
-                    if (args.combo[c].res == r) h += vsh[threadIdx.x * nc + c];
-                args.dir_part[(size_t)gd * n_res + r] = dsh[threadIdx.x][0] * h;
+                    if (args.combo[c].res == r) h += vsh[tid * nc + c];
+                args.dir_part[(size_t)gd * n_res + r] = dsh[tid][0] * h;
             }
             // device-side guard for a Hadamard exponent mu = 0 (the host rejects such programs)
-            args.dir_flag[gd] = fsh_bad[threadIdx.x];
+            args.dir_flag[gd] = fsh_bad[tid];
         }
     }
 }
@@ -784,29 +827,40 @@ hipError_t ez_launch_nodes_impl(const EzQuadArgs &args, int n_tiles, hipStream_t
     }
 }
 
-template <int D, int NNU>
+template <int D, int NNU, int PD>
 hipError_t launch_had_t(const EzQuadArgs &args, int n_htiles, hipStream_t stream) {
     const int nblk = (args.n_probe + 63) / 64;
-    hipLaunchKernelGGL((ez_probe_kernel<D, NNU>), dim3(args.batch * nblk), dim3(64 * EZ_HW), 0, stream, args);
+    hipLaunchKernelGGL((ez_probe_kernel<D, NNU>), dim3(args.batch * nblk * args.n_slice), dim3(64 * EZ_HW), 0,
+                       stream, args);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((ez_tensor_kernel<D, NNU>), dim3(args.batch), dim3(256), 0, stream, args);
+    int tdim = 0;
+    for (int k = 0; k <= args.ell_probe; ++k) tdim += nmono(D, 2 * k);
+    const int ngrp = (tdim + EZ_TOUT - 1) / EZ_TOUT;
+    hipLaunchKernelGGL((ez_tensor_kernel<D, NNU>), dim3(args.batch * NNU * ngrp), dim3(256), 0, stream, args);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL((ez_hadamard_kernel<D, NNU>), dim3(n_htiles), dim3(256), 0, stream, args);
+    hipLaunchKernelGGL((ez_hadamard_kernel<D, NNU, PD>), dim3(n_htiles), dim3(256), 0, stream, args);
     return hipGetLastError();
+}
+
+template <int D, int NNU>
+hipError_t launch_had_p(const EzQuadArgs &args, int n_htiles, hipStream_t stream) {
+    if (args.poly_deg == 13) return launch_had_t<D, NNU, 13>(args, n_htiles, stream);
+    if (args.poly_deg == 33) return launch_had_t<D, NNU, 33>(args, n_htiles, stream);
+    return hipErrorInvalidValue;
 }
 
 template <int D>
 hipError_t launch_had_d(const EzQuadArgs &args, int n_htiles, hipStream_t stream) {
     switch (args.prog.n_nu) {
-        case 1: return launch_had_t<D, 1>(args, n_htiles, stream);
-        case 2: return launch_had_t<D, 2>(args, n_htiles, stream);
-        case 3: return launch_had_t<D, 3>(args, n_htiles, stream);
-        case 4: return launch_had_t<D, 4>(args, n_htiles, stream);
-        case 5: return launch_had_t<D, 5>(args, n_htiles, stream);
-        case 6: return launch_had_t<D, 6>(args, n_htiles, stream);
-        case 7: return launch_had_t<D, 7>(args, n_htiles, stream);
-        case 8: return launch_had_t<D, 8>(args, n_htiles, stream);
+        case 1: return launch_had_p<D, 1>(args, n_htiles, stream);
+        case 2: return launch_had_p<D, 2>(args, n_htiles, stream);
+        case 3: return launch_had_p<D, 3>(args, n_htiles, stream);
+        case 4: return launch_had_p<D, 4>(args, n_htiles, stream);
+        case 5: return launch_had_p<D, 5>(args, n_htiles, stream);
+        case 6: return launch_had_p<D, 6>(args, n_htiles, stream);
+        case 7: return launch_had_p<D, 7>(args, n_htiles, stream);
+        case 8: return launch_had_p<D, 8>(args, n_htiles, stream);
         default: return hipErrorInvalidValue;
     }
 }
