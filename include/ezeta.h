@@ -110,7 +110,10 @@ ez_status ez_nbody_lattice_sum(int batch, int d, const double *A_dev, int n, con
  * (ATM potential)) via E = 1/24 zeta(3,3,3) - 3/16 zeta(-1,5,5) + 3/8 zeta(1,3,5)
  * (Sec. 2, Proposition), the three integrands fused at one node set.
  *   A_dev   : batch*d*d doubles;  E_dev : batch doubles
- *   dEdA_dev: batch*d*d doubles of dE/dA (row-major like A), or NULL
+ *   dEdA_dev: batch*d*d doubles of dE/dA (row-major like A), or NULL.  The
+ *             derivative is that of the quadrature value on the given plan (the
+ *             nodes are fixed in fractional coordinates, lam is held fixed); it
+ *             comes from the adjoint kernels, at about twice the cost of E alone.
  *   status_dev : batch uint32 (may be NULL) */
 ez_status ez_atm_energy(int batch, int d, const double *A_dev, const ez_quad_spec *spec,
                         double *E_dev, double *dEdA_dev, uint32_t *status_dev, void *stream);
@@ -131,6 +134,19 @@ ez_status ez_lattice_sums(int batch, int d, const double *A_dev, int n_nu, const
                           int n_results, const ez_quad_spec *specs, int n_specs, double *out_dev,
                           uint32_t *status_dev, void *stream);
 
+/* ez_lattice_sums with the derivatives of the results with respect to the
+ * generator matrix (reverse mode through every step of the quadrature; the
+ * derivative of the quadrature value on the given plan, lam held fixed).
+ *   n_results <= 2
+ *   grad_dev : batch x n_results x d x d doubles, grad_dev[((b*n_results + r)*d + i)*d + j]
+ *              = d result_r / d A_ij of lattice b (NULL: values only)
+ * Errors: as ez_lattice_sums; EZ_ERR_INVALID_ARG for n_results > 2 with grad_dev. */
+ez_status ez_lattice_sums_grad(int batch, int d, const double *A_dev, int n_nu, const double *nu_host,
+                               int n_terms, const int *term_result, const double *term_coef,
+                               const int *term_nfac, const int *term_fac, const int *term_mult,
+                               int n_results, const ez_quad_spec *specs, int n_specs, double *out_dev,
+                               double *grad_dev, uint32_t *status_dev, void *stream);
+
 /* Kernel timing (tracing aid).  When enabled, every kernel the library launches
  * is bracketed by a pair of HIP events recorded on the launch stream; reading
  * synchronises the recorded events and returns the accumulated elapsed time and
@@ -140,7 +156,8 @@ ez_status ez_lattice_sums(int batch, int d, const double *A_dev, int n_nu, const
 #define EZ_KERNEL_HADAMARD 2   /* Taylor / Hadamard part on (0, eps)     */
 #define EZ_KERNEL_FINALIZE 3   /* fixed-order reduction                  */
 #define EZ_KERNEL_EPSTEIN 4    /* Z(x, y) at arbitrary points            */
-#define EZ_KERNEL_COUNT 5
+#define EZ_KERNEL_NODES_ADJ 5  /* quadrature nodes with the adjoint pass  */
+#define EZ_KERNEL_COUNT 6
 ez_status ez_timing_enable(int enable);
 ez_status ez_timing_reset(void);
 ez_status ez_timing_read(int kernel, double *total_ms, int64_t *launches);

@@ -241,3 +241,25 @@ def direct_atm(A, L: int) -> float:
 
 def num_threads() -> int:
     return lib().ezo_num_threads()
+
+
+# ----------------------------------------------------------------- derivatives
+def grad_fd(f, A, h: float = 1e-3) -> np.ndarray:
+    """d f / d A_ij of a scalar function of the generator matrix by the
+    fourth-order central difference
+        (f(A - 2h E_ij) - 8 f(A - h E_ij) + 8 f(A + h E_ij) - f(A + 2h E_ij)) / (12 h),
+    truncation error h^4 f^(5) / 30.  With f an oracle lattice sum on a fixed plan
+    this is the derivative of the oracle's value on that plan (nodes fixed in
+    fractional coordinates, which is how the plan is defined)."""
+    A = np.array(A, dtype=np.float64)
+    d = A.shape[0]
+    g = np.zeros((d, d))
+    for i in range(d):
+        for j in range(d):
+            vals = []
+            for s in (-2, -1, 1, 2):
+                B = A.copy()
+                B[i, j] += s * h
+                vals.append(f(B))
+            g[i, j] = (vals[0] - 8.0 * vals[1] + 8.0 * vals[2] - vals[3]) / (12.0 * h)
+    return g

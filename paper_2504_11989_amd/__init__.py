@@ -6,8 +6,12 @@ GPU are passed to the C ABI as device pointers on torch's current stream.
 
     epstein_zeta(A, nu, x, y)        Z_{A Z^d, nu}(x, y), complex
     nbody_lattice_sum(A, nu, spec)   zeta^(n)_Lambda(nu) for a batch of lattices
-    atm_energy(A, spec)              ATM cohesive energy per particle
-    lattice_sums(A, nu, terms, ...)  several product integrals per lattice
+    atm_energy(A, spec)              ATM cohesive energy per particle (and dE/dA)
+    lattice_sums(A, nu, terms, ...)  several product integrals per lattice (and d/dA)
+
+Differentiable forms (torch.autograd.Function over the adjoint kernels) are in
+paper_2504_11989_amd.autograd; the LJ + ATM enthalpy and its minimisation in
+paper_2504_11989_amd.enthalpy.
 """
 from __future__ import annotations
 
@@ -104,24 +108,31 @@ def nbody_lattice_sum(A, nu: Sequence[float], spec=None, with_status=False):
     return (out, st) if with_status else out
 
 
-def atm_energy(A, spec=None, with_status=False):
-    """ATM cohesive energy per particle for each lattice of the batch: float64 (batch,)."""
+def atm_energy(A, spec=None, with_status=False, grad=False):
+    """ATM cohesive energy per particle for each lattice of the batch: float64 (batch,).
+    grad=True also returns dE/dA, float64 (batch, d, d)."""
     torch = _torch()
     A, b, d = _lattices(A)
     sp = _spec(spec)
     out = torch.empty(b, dtype=torch.float64, device=A.device)
     st = torch.zeros(b, dtype=torch.int32, device=A.device)
-    check(lib().ez_atm_energy(b, d, _dptr(A), ctypes.byref(sp), _dptr(out), None, _dptr(st),
-                              _stream_ptr(A.device)))
-    return (out, st) if with_status else out
+    g = torch.empty((b, d, d), dtype=torch.float64, device=A.device) if grad else None
+    check(lib().ez_atm_energy(b, d, _dptr(A), ctypes.byref(sp), _dptr(out), _dptr(g) if grad else None,
+                              _dptr(st), _stream_ptr(A.device)))
+    ret = (out, g) if grad else (out,)
+    if with_status:
+        ret = ret + (st,)
+    return ret if len(ret) > 1 else ret[0]
 
 
-def lattice_sums(A, nu: Sequence[float], terms: Iterable, n_results: int, specs=None, with_status=False):
+def lattice_sums(A, nu: Sequence[float], terms: Iterable, n_results: int, specs=None, with_status=False,
+                 grad=False):
     """Several results per lattice, result_r = sum of coef * V int_BZ prod Z_nu^mult dk.
 
     terms: iterable of (result_index, coef, [(nu_index, multiplicity), ...]).
     specs: None, one spec, or a list with one spec per lattice.
-    Returns float64 tensor (batch, n_results)."""
+    Returns float64 tensor (batch, n_results); grad=True (n_results <= 2) also
+    returns the derivatives with respect to A, float64 (batch, n_results, d, d)."""
     torch = _torch()
     A, b, d = _lattices(A)
     nu_h, n_nu = _host_f64(nu)
@@ -149,9 +160,14 @@ def lattice_sums(A, nu: Sequence[float], terms: Iterable, n_results: int, specs=
     sp_arr = (QuadSpec * len(sp_list))(*sp_list)
     out = torch.empty((b, n_results), dtype=torch.float64, device=A.device)
     st = torch.zeros(b, dtype=torch.int32, device=A.device)
-    check(lib().ez_lattice_sums(b, d, _dptr(A), n_nu, nu_h, nt, res, coef, nfac, fac, mult, int(n_results),
-                                sp_arr, len(sp_list), _dptr(out), _dptr(st), _stream_ptr(A.device)))
-    return (out, st) if with_status else out
+    g = torch.empty((b, n_results, d, d), dtype=torch.float64, device=A.device) if grad else None
+    check(lib().ez_lattice_sums_grad(b, d, _dptr(A), n_nu, nu_h, nt, res, coef, nfac, fac, mult, int(n_results),
+                                     sp_arr, len(sp_list), _dptr(out), _dptr(g) if grad else None, _dptr(st),
+                                     _stream_ptr(A.device)))
+    ret = (out, g) if grad else (out,)
+    if with_status:
+        ret = ret + (st,)
+    return ret if len(ret) > 1 else ret[0]
 
 
 def version() -> str:

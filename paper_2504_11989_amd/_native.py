@@ -20,10 +20,10 @@ FLAG_SINGULAR, FLAG_CAPACITY, FLAG_NONFINITE, FLAG_HADAMARD, FLAG_POLE = 0x1, 0x
 PREC_FP64, PREC_MIXED = 0, 1
 
 # every symbol declared in include/ezeta.h
-EXPORTED = ("ez_epstein_zeta", "ez_nbody_lattice_sum", "ez_atm_energy", "ez_lattice_sums",
+EXPORTED = ("ez_epstein_zeta", "ez_nbody_lattice_sum", "ez_atm_energy", "ez_lattice_sums", "ez_lattice_sums_grad",
             "ez_timing_enable", "ez_timing_reset", "ez_timing_read",
             "ez_last_error", "ez_finalize", "ez_version")
-KERNEL_SETUP, KERNEL_NODES, KERNEL_HADAMARD, KERNEL_FINALIZE, KERNEL_EPSTEIN = 0, 1, 2, 3, 4
+KERNEL_SETUP, KERNEL_NODES, KERNEL_HADAMARD, KERNEL_FINALIZE, KERNEL_EPSTEIN, KERNEL_NODES_ADJ = 0, 1, 2, 3, 4, 5
 
 
 class EzError(RuntimeError):
@@ -68,6 +68,9 @@ def lib():
     L.ez_lattice_sums.restype = I
     L.ez_lattice_sums.argtypes = [I, I, VP, I, P, I, IP, P, IP, IP, IP, I, ctypes.POINTER(QuadSpec), I,
                                   VP, VP, VP]
+    L.ez_lattice_sums_grad.restype = I
+    L.ez_lattice_sums_grad.argtypes = [I, I, VP, I, P, I, IP, P, IP, IP, IP, I, ctypes.POINTER(QuadSpec), I,
+                                       VP, VP, VP, VP]
     L.ez_last_error.restype = ctypes.c_char_p
     L.ez_last_error.argtypes = []
     L.ez_finalize.restype = I

@@ -144,7 +144,7 @@ struct DevPlan {
 struct DeviceState {
     std::map<std::string, DevPlan *> plans;
     std::vector<std::string> plan_order;
-    DevBuf meta, real, rn, rows, rec, tile_part, dir_part, dir_flag, probe_val, tensor;
+    DevBuf meta, real, rn, rows, rec, tile_part, dir_part, dir_flag, probe_val, tensor, tile_grad, dir_grad;
     DevBuf gmeta, greal, grec;   // general-x Epstein tables
 };
 
@@ -482,15 +482,21 @@ int rec_capacity(int d, double lam, double acut) {
     return (int)std::ceil(kOmega[d] * std::pow(R + kSkew, d)) + 16;
 }
 
+// grad_dev (may be NULL): batch x n_res x d x d derivatives of the results with respect to A
 ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog, const std::vector<EzCombo> &combos,
-                   const ez_quad_spec *specs, int n_specs, double *out_dev, uint32_t *status_dev, hipStream_t stream) {
+                   const ez_quad_spec *specs, int n_specs, double *out_dev, uint32_t *status_dev, hipStream_t stream,
+                   double *grad_dev = nullptr) {
     int dev = 0;
     EZ_HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lock(g_mu);
     DeviceState *S = device_state(dev);
     DevPlan *P = nullptr;
     if (combos.size() < 2) return fail(EZ_ERR_INVALID_ARG, "internal: expansion with fewer than 2 terms");
-    const int ndb = std::min(EZ_HDIR, 256 / (int)combos.size());
+    const bool grad = grad_dev != nullptr;
+    if (grad && prog.n_res > EZ_GRAD_RES_MAX)
+        return fail(EZ_ERR_INVALID_ARG, "derivatives are available for at most 2 results per call");
+    const int ndb = std::min(grad ? EZ_HDIR_GRAD : EZ_HDIR, 256 / (int)combos.size());
+    const int n_ch = grad ? 1 + d * (d + 1) / 2 : 1;
     int ell_max = 0;
     for (int i = 0; i < n_specs; ++i) ell_max = std::max(ell_max, specs[i].ell);
     int maxdeg = 0;          // highest power of u^2 in the (0, eps) product polynomials
@@ -514,7 +520,7 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     EzTables tab;
     tab.real_cap = real_capacity(d, lam_max, acut, false);
     tab.rec_cap = rec_capacity(d, lam_min, acut);
-    tab.rstride = 4 * ((3 + prog.n_nu + 3) / 4);
+    tab.rstride = 4 * ((3 + (grad ? 2 : 1) * prog.n_nu + 3) / 4);
     tab.row_cap = tab.real_cap;
     if ((st = grow(S->meta, sizeof(EzLatMeta) * batch)) ||
         (st = grow(S->real, sizeof(double) * (size_t)batch * tab.real_cap * tab.rstride)) ||
@@ -524,8 +530,11 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
         (st = grow(S->tile_part, sizeof(double) * 2 * (size_t)P->n_tiles * prog.n_res)) ||
         (st = grow(S->dir_part, sizeof(double) * (size_t)P->n_dirs * prog.n_res)) ||
         (st = grow(S->dir_flag, sizeof(uint32_t) * (size_t)P->n_dirs)) ||
-        (st = grow(S->probe_val, sizeof(double) * (size_t)batch * n_slice * P->n_probe * prog.n_nu * (EZ_ELL_MAX + 1))) ||
-        (st = grow(S->tensor, sizeof(double) * (size_t)batch * prog.n_nu * EZ_TDIM)))
+        (st = grow(S->probe_val, sizeof(double) * (size_t)batch * n_slice * P->n_probe * n_ch * prog.n_nu * (EZ_ELL_MAX + 1))) ||
+        (st = grow(S->tensor, sizeof(double) * (size_t)batch * n_ch * prog.n_nu * EZ_TDIM)))
+        return st;
+    if (grad && ((st = grow(S->tile_grad, sizeof(double) * 12 * (size_t)P->n_tiles * prog.n_res)) ||
+                 (st = grow(S->dir_grad, sizeof(double) * 6 * (size_t)P->n_dirs * prog.n_res))))
         return st;
     tab.real = (double *)S->real.p;
     tab.rn = (int *)S->rn.p;
@@ -540,6 +549,7 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     sa.tab = tab;
     sa.a_cut = acut;
     sa.general_x = 0;
+    sa.grad = grad ? 1 : 0;
     sa.status_out = nullptr;
     EZ_HIP_TRY(timed(EZ_KERNEL_SETUP, stream, [&] { return ez_launch_setup(sa, batch, stream); }));
 
@@ -553,6 +563,7 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     qa.n_dir_blk = ndb;
     qa.poly_deg = maxdeg <= 12 ? 13 : 33;
     qa.n_slice = n_slice;
+    qa.n_ch = n_ch;
     qa.n_probe = P->n_probe;
     qa.ell_probe = P->ell_probe;
     qa.probe_off = P->probe_off;
@@ -569,8 +580,16 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     qa.dir_flag = (uint32_t *)S->dir_flag.p;
     qa.out = out_dev;
     qa.status = status_dev;
-    EZ_HIP_TRY(timed(EZ_KERNEL_NODES, stream, [&] { return ez_launch_nodes(qa, P->n_tiles, stream); }));
-    EZ_HIP_TRY(timed(EZ_KERNEL_HADAMARD, stream, [&] { return ez_launch_hadamard(qa, P->n_htiles, stream); }));
+    qa.tile_grad = grad ? (double *)S->tile_grad.p : nullptr;
+    qa.dir_grad = grad ? (double *)S->dir_grad.p : nullptr;
+    qa.grad_out = grad_dev;
+    if (grad) {
+        EZ_HIP_TRY(timed(EZ_KERNEL_NODES_ADJ, stream, [&] { return ez_launch_nodes_adj(qa, P->n_tiles, stream); }));
+        EZ_HIP_TRY(timed(EZ_KERNEL_HADAMARD, stream, [&] { return ez_launch_hadamard_adj(qa, P->n_htiles, stream); }));
+    } else {
+        EZ_HIP_TRY(timed(EZ_KERNEL_NODES, stream, [&] { return ez_launch_nodes(qa, P->n_tiles, stream); }));
+        EZ_HIP_TRY(timed(EZ_KERNEL_HADAMARD, stream, [&] { return ez_launch_hadamard(qa, P->n_htiles, stream); }));
+    }
     EZ_HIP_TRY(timed(EZ_KERNEL_FINALIZE, stream, [&] { return ez_launch_finalize(qa, stream); }));
     return EZ_OK;
 }
@@ -601,6 +620,7 @@ ez_status ez_finalize(void) {
         for (auto &p : S->plans) free_plan(p.second);
         free_buf(S->meta); free_buf(S->real); free_buf(S->rec); free_buf(S->rn); free_buf(S->rows);
         free_buf(S->tile_part); free_buf(S->dir_part); free_buf(S->dir_flag); free_buf(S->probe_val); free_buf(S->tensor);
+        free_buf(S->tile_grad); free_buf(S->dir_grad);
         free_buf(S->gmeta); free_buf(S->greal); free_buf(S->grec);
         delete S;
     }
@@ -609,15 +629,17 @@ ez_status ez_finalize(void) {
     return EZ_OK;
 }
 
-ez_status ez_lattice_sums(int batch, int d, const double *A_dev, int n_nu, const double *nu_host, int n_terms,
-                          const int *term_result, const double *term_coef, const int *term_nfac,
-                          const int *term_fac, const int *term_mult, int n_results, const ez_quad_spec *specs,
-                          int n_specs, double *out_dev, uint32_t *status_dev, void *stream) {
+ez_status ez_lattice_sums_grad(int batch, int d, const double *A_dev, int n_nu, const double *nu_host, int n_terms,
+                               const int *term_result, const double *term_coef, const int *term_nfac,
+                               const int *term_fac, const int *term_mult, int n_results, const ez_quad_spec *specs,
+                               int n_specs, double *out_dev, double *grad_dev, uint32_t *status_dev, void *stream) {
     ez_status st = check_common(batch, d, A_dev, specs, out_dev);
     if (st) return st;
     if (!nu_host || !term_result || !term_coef || !term_nfac || !term_fac || !term_mult)
         return fail(EZ_ERR_INVALID_ARG, "null pointer argument");
     if (n_specs != 1 && n_specs != batch) return fail(EZ_ERR_INVALID_ARG, "n_specs must be 1 or batch");
+    if (grad_dev && n_results > EZ_GRAD_RES_MAX)
+        return fail(EZ_ERR_INVALID_ARG, "derivatives are available for at most 2 results per call");
     if (n_nu < 1 || n_nu > EZ_NU_MAX || n_terms < 1 || n_terms > EZ_TERM_MAX)
         return fail(EZ_ERR_INVALID_ARG, "n_nu and n_terms must be in [1, 8]");
     int ell_max = 0;
@@ -637,7 +659,15 @@ ez_status ez_lattice_sums(int batch, int d, const double *A_dev, int n_nu, const
     EzProgram prog;
     std::vector<EzCombo> combos;
     if ((st = build_program(d, nu, terms, n_results, ell_max, prog, combos))) return st;
-    return run_sums(batch, d, A_dev, prog, combos, specs, n_specs, out_dev, status_dev, (hipStream_t)stream);
+    return run_sums(batch, d, A_dev, prog, combos, specs, n_specs, out_dev, status_dev, (hipStream_t)stream, grad_dev);
+}
+
+ez_status ez_lattice_sums(int batch, int d, const double *A_dev, int n_nu, const double *nu_host, int n_terms,
+                          const int *term_result, const double *term_coef, const int *term_nfac,
+                          const int *term_fac, const int *term_mult, int n_results, const ez_quad_spec *specs,
+                          int n_specs, double *out_dev, uint32_t *status_dev, void *stream) {
+    return ez_lattice_sums_grad(batch, d, A_dev, n_nu, nu_host, n_terms, term_result, term_coef, term_nfac, term_fac,
+                                term_mult, n_results, specs, n_specs, out_dev, nullptr, status_dev, stream);
 }
 
 ez_status ez_nbody_lattice_sum(int batch, int d, const double *A_dev, int n, const double *nu_host,
@@ -670,7 +700,6 @@ ez_status ez_atm_energy(int batch, int d, const double *A_dev, const ez_quad_spe
     ez_status st = check_common(batch, d, A_dev, spec, E_dev);
     if (st) return st;
     if ((st = check_spec(*spec))) return st;
-    if (dEdA_dev) return fail(EZ_ERR_UNSUPPORTED, "dE/dA is not available in this build");
     // nu set {-1, 1, 3, 5};  E = 1/24 Z3^3 - 3/16 Z-1 Z5^2 + 3/8 Z1 Z3 Z5
     std::vector<double> nu = {-1.0, 1.0, 3.0, 5.0};
     Term t0{0, 1.0 / 24.0, {{2, 3}}};
@@ -679,7 +708,7 @@ ez_status ez_atm_energy(int batch, int d, const double *A_dev, const ez_quad_spe
     EzProgram prog;
     std::vector<EzCombo> combos;
     if ((st = build_program(d, nu, {t0, t1, t2}, 1, spec->ell, prog, combos))) return st;
-    return run_sums(batch, d, A_dev, prog, combos, spec, 1, E_dev, status_dev, (hipStream_t)stream);
+    return run_sums(batch, d, A_dev, prog, combos, spec, 1, E_dev, status_dev, (hipStream_t)stream, dEdA_dev);
 }
 
 ez_status ez_epstein_zeta(int d, const double *A_dev, int n_nu, const double *nu_host, int64_t n_pts,
@@ -734,6 +763,7 @@ ez_status ez_epstein_zeta(int d, const double *A_dev, int n_nu, const double *nu
     sa.tab = tab;
     sa.a_cut = a_cut;
     sa.general_x = 1;
+    sa.grad = 0;
     sa.status_out = status_dev;
     EZ_HIP_TRY(timed(EZ_KERNEL_SETUP, s, [&] { return ez_launch_setup(sa, 1, s); }));
     EzEpsteinArgs ea;

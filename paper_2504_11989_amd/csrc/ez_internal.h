@@ -13,6 +13,8 @@
 #define EZ_TDIM 525      // monomials of even degree <= 2 EZ_ELL_MAX in 3 variables
 #define EZ_HDIR 64       // quadrature directions per workgroup of the Hadamard direction kernel
 #define EZ_SLICE_MAX 8   // table slices of the probe kernel
+#define EZ_GRAD_RES_MAX 2  // results per call when strain derivatives are requested
+#define EZ_HDIR_GRAD 16  // directions per workgroup of the Hadamard adjoint kernel
 
 // Which lattice sums one call computes (host-built, passed by value).
 // Exponent nu_i enters the reciprocal sum through E_{p_i}(a), p_i = (nu_i - d + 2)/2

@@ -10,6 +10,7 @@ struct EzSetupArgs {
     EzTables tab;
     double a_cut;
     int general_x;             // 0: pairs table for x = 0; 1: full table for general x
+    int grad;                  // pairs mode: also store the strain weights -4 Gamma(nu/2+1, a)/(Gamma(nu/2) r^{nu+2})
     uint32_t *status_out;      // general-x mode: receives the lattice flags (may be NULL)
 };
 
@@ -36,10 +37,11 @@ struct EzQuadArgs {
     int poly_deg;              // 13 or 33: coefficients kept in the (0, eps) product polynomials
     int n_probe, ell_probe;    // probe directions per lattice, Taylor order they carry
     int n_slice;               // table slices per probe set (workgroups that split the sums)
+    int n_ch;                  // 1 (values) or 1 + d(d+1)/2 (values and strain derivatives)
     int probe_off;             // offset of the probe directions (n_probe x d) in rules
     int pinv_off[EZ_ELL_MAX + 1];  // offsets of the least-squares inverses (nmono x n_probe) in rules
-    double *probe_val;         // [batch][n_slice][n_probe][n_nu][EZ_ELL_MAX + 1] partial sums
-    double *tensor;            // [batch][n_nu][EZ_TDIM] coefficients of C_k in w_hat monomials
+    double *probe_val;         // [batch][n_slice][n_probe][n_ch * n_nu][EZ_ELL_MAX + 1] partial sums
+    double *tensor;            // [batch][n_ch * n_nu][EZ_TDIM] coefficients of C_k in w_hat monomials
     int n_combo;
     EzCombo combo[EZ_COMBO_MAX];
     const EzLatMeta *meta;
@@ -48,7 +50,10 @@ struct EzQuadArgs {
     double *tile_part;         // [n_tiles][n_res][2] double-double partials
     double *dir_part;          // [n_dirs][n_res] Hadamard part per direction (times 2 w_v)
     uint32_t *dir_flag;        // [n_dirs] flags (Hadamard mu = 0)
+    double *tile_grad;         // [n_tiles][n_res][6][2] strain-derivative partials (gradient calls)
+    double *dir_grad;          // [n_dirs][n_res][6] (gradient calls)
     double *out;               // [batch][n_res]
+    double *grad_out;          // [batch][n_res][d][d] d result / d A, or NULL
     uint32_t *status;          // [batch] or NULL
 };
 
@@ -67,4 +72,6 @@ hipError_t ez_launch_setup(const EzSetupArgs &args, int batch, hipStream_t strea
 hipError_t ez_launch_nodes(const EzQuadArgs &args, int n_tiles, hipStream_t stream);
 hipError_t ez_launch_hadamard(const EzQuadArgs &args, int n_htiles, hipStream_t stream);
 hipError_t ez_launch_finalize(const EzQuadArgs &args, hipStream_t stream);
+hipError_t ez_launch_nodes_adj(const EzQuadArgs &args, int n_tiles, hipStream_t stream);
+hipError_t ez_launch_hadamard_adj(const EzQuadArgs &args, int n_htiles, hipStream_t stream);
 hipError_t ez_launch_epstein(const EzEpsteinArgs &args, hipStream_t stream);

@@ -1,0 +1,297 @@
+// ez_nodes.hip -- quadrature nodes on (eps, 1/2] and the final reduction.
+//
+// ez_node_kernel    : one thread per node k = u w: Z_nu(k) for the exponent set by
+//                     the split (real-space table + reciprocal table), the products
+//                     of the terms, weight, then a double-double reduction to one
+//                     partial per 256-node tile (paper, Sec. 2, Theorem (Epstein
+//                     representation); Sec. 3, Corollary (Duffy transformation)).
+// ez_finalize_kernel: fixed-order double-double sum of tiles and directions; the
+//                     derivatives with respect to A when requested.
+#include "ez_quad_common.h"
+
+namespace {
+
+template <int D, int NNU, int SET>
+__global__ __launch_bounds__(EZ_TILE) void ez_node_kernel(EzQuadArgs args) {
+    const int tile = blockIdx.x;
+    const int inst = find_segment(args.tile_begin, args.batch, tile);
+    const EzInstPlan P = args.plans[inst];
+    const EzLatMeta *M = args.meta + inst;
+    const int n_res = args.prog.n_res;
+    const int node = (tile - args.tile_begin[inst]) * EZ_TILE + threadIdx.x;
+    const int n_nodes = P.n_dir * P.n_u;
+
+    double res[EZ_RES_MAX];
+#pragma unroll
+    for (int r = 0; r < EZ_RES_MAX; ++r) res[r] = 0.0;
+
+    if (M->status == 0 && node < n_nodes) {
+        const int dir = node / P.n_u;
+        const int iu = node - dir * P.n_u;
+        double B[D * D];
+#pragma unroll
+        for (int i = 0; i < D * D; ++i) B[i] = M->B[i];
+        double w[3] = {0.0, 0.0, 0.0}, wh[3] = {0.0, 0.0, 0.0}, wv;
+        ez_direction<D>(P, args.rules, B, dir, w, &wv, wh);
+        const double u = args.rules[P.urule + iu];
+        const double wu = args.rules[P.urule + P.n_u + iu];
+        double k[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < D; ++i) k[i] = u * w[i];
+        double W = 2.0 * wv * wu;
+#pragma unroll
+        for (int i = 0; i < D - 1; ++i) W *= u;
+
+        double accr[NNU], acck[NNU];
+#pragma unroll
+        for (int i = 0; i < NNU; ++i) { accr[i] = 0.0; acck[i] = 0.0; }
+
+        // real space: sum over pairs of 2 W_nu(z) Re e^{2 pi i k.z}, k.z = theta.n with
+        // theta = A^T k = u w_hat.  Row by row (n2, n3 fixed, consecutive n1) the phase
+        // advances by c1 = e^{2 pi i theta_1}; from row to row within a plane by
+        // c2^{dn2} c1^{dn1}; each plane starts from one sincos.
+        {
+            const int rs = args.tab.rstride;
+            const double *rt = args.tab.real + (size_t)inst * args.tab.real_cap * rs;
+            const int *rows = args.tab.rows + (size_t)inst * args.tab.row_cap * 8;
+            const int n_rows = M->n_rows;
+            double th[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int i = 0; i < D; ++i) th[i] = u * wh[i];
+            double c1r, c1i, c2r = 1.0, c2i = 0.0;
+            ez_sincos2pi(th[0], &c1i, &c1r);
+            if (D > 1) ez_sincos2pi(th[1], &c2i, &c2r);
+            double br = 1.0, bi = 0.0;
+            for (int r = 0; r < n_rows; ++r) {
+                const int *R = rows + (size_t)r * 8;
+                const int first = R[0], cnt = R[1];
+                if (R[5]) {
+                    double ph = th[0] * (double)R[2];
+                    if (D > 1) ph = fma(th[1], (double)R[3], ph);
+                    if (D > 2) ph = fma(th[2], (double)R[4], ph);
+                    const double2 sc = ez_sincos2pi_ool(ph);
+                    bi = sc.x;
+                    br = sc.y;
+                } else {
+                    for (int j = 0; j < R[7]; ++j) cmul(br, bi, c2r, c2i);
+                    const int dl = R[6];
+                    if (dl > 0) for (int j = 0; j < dl; ++j) cmul(br, bi, c1r, c1i);
+                    else for (int j = 0; j < -dl; ++j) cmul(br, bi, c1r, -c1i);
+                }
+                double pr = br, pi = bi;
+                const double *e = rt + (size_t)first * rs;
+                for (int j = 0; j < cnt; ++j, e += rs) {
+#pragma unroll
+                    for (int i = 0; i < NNU; ++i) accr[i] = fma(e[3 + i], pr, accr[i]);
+                    cmul(pr, pi, c1r, c1i);
+                }
+            }
+        }
+
+        // reciprocal space: sum over m* of E_{p_nu}(pi lam^2 |m* + k|^2).  Entry 0 is
+        // m* = 0, where a = alpha |k|^2 can be small (series of E1); every other entry
+        // has a >= alpha / (4 |A|_F^2) >= 1/4 (the setup raises lam to ensure it), so the
+        // main loop is one branch-free formula with E1 from the wide rational.
+        const double *kt = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
+        const int n_rec = M->n_rec;
+        const double alpha = M->alpha, acut = M->a_cut;
+        const bool need_e1 = pset_need_e1<SET, NNU>(args.prog), need_half = pset_need_half<SET, NNU>(args.prog);
+        {
+            double rho = k[0] * k[0];
+            if (D > 1) rho = fma(k[1], k[1], rho);
+            if (D > 2) rho = fma(k[2], k[2], rho);
+            const double a = alpha * rho;
+            if (a <= acut) {
+                const double ex = ez_expm(a);
+                const double inv = ez_rcp(a);
+                double E1 = 0.0;
+                if (need_e1) E1 = (a < 0.25) ? ez_e1_series(a) : ex * ez_e1w_scaled(inv);
+                const double Eh = need_half ? ez_ehalf(a) : 0.0;
+#pragma unroll
+                for (int i = 0; i < NNU; ++i)
+                    acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
+            }
+        }
+        for (int q = 1; q < n_rec; ++q) {
+            const double *e = kt + (size_t)q * 4;
+            double qx = e[0] + k[0];
+            double rho = qx * qx;
+            if (D > 1) { double qy = e[1] + k[1]; rho = fma(qy, qy, rho); }
+            if (D > 2) { double qz = e[2] + k[2]; rho = fma(qz, qz, rho); }
+            const double a = alpha * rho;
+            if (a <= acut) {
+                const double ex = ez_expm(a);
+                const double inv = ez_rcp(a);
+                const double E1 = need_e1 ? ex * ez_e1w_scaled(inv) : 0.0;
+                const double Eh = need_half ? ez_ehalf(a) : 0.0;
+#pragma unroll
+                for (int i = 0; i < NNU; ++i)
+                    acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
+            }
+        }
+
+        double Z[NNU];
+#pragma unroll
+        for (int i = 0; i < NNU; ++i) Z[i] = accr[i] + M->K[i] * acck[i] - M->self_[i];
+
+        for (int t = 0; t < args.prog.n_terms; ++t) {
+            double prod = args.prog.term_coef[t];
+            for (int f = 0; f < args.prog.term_nfac[t]; ++f) {
+                const int fi = args.prog.term_fac[t][f];
+                double z = Z[0];
+#pragma unroll
+                for (int i = 1; i < NNU; ++i) z = (fi == i) ? Z[i] : z;
+                for (int m = 0; m < args.prog.term_mult[t][f]; ++m) prod *= z;
+            }
+            const int rr = args.prog.term_res[t];
+#pragma unroll
+            for (int r = 0; r < EZ_RES_MAX; ++r)
+                if (rr == r) res[r] += prod;
+        }
+#pragma unroll
+        for (int r = 0; r < EZ_RES_MAX; ++r) res[r] *= W;
+    }
+
+    // tile reduction: wave butterflies, then the four waves in fixed order
+    __shared__ double red[EZ_RES_MAX][EZ_TILE / 64][2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int r = 0; r < EZ_RES_MAX; ++r) {
+        if (r < n_res) {
+            ez_dd v = ez_dd_wave_sum(ez_dd{res[r], 0.0});
+            if (lane == 0) { red[r][wave][0] = v.hi; red[r][wave][1] = v.lo; }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < n_res) {
+        const int r = threadIdx.x;
+        ez_dd s{red[r][0][0], red[r][0][1]};
+        for (int wv = 1; wv < EZ_TILE / 64; ++wv) s = ez_dd_add(s, ez_dd{red[r][wv][0], red[r][wv][1]});
+        args.tile_part[((size_t)tile * n_res + r) * 2 + 0] = s.hi;
+        args.tile_part[((size_t)tile * n_res + r) * 2 + 1] = s.lo;
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void ez_finalize_kernel(EzQuadArgs args) {
+    const int inst = blockIdx.x;
+    const int n_res = args.prog.n_res;
+    const int tb = args.tile_begin[inst], te = args.tile_begin[inst + 1];
+    const int db = args.dir_begin[inst], de = args.dir_begin[inst + 1];
+    __shared__ double red[256 / 64][2];
+    __shared__ uint32_t flag_sh;
+    if (threadIdx.x == 0) flag_sh = 0;
+    __syncthreads();
+    uint32_t fl = 0;
+    for (int g = db + (int)threadIdx.x; g < de; g += 256) fl |= args.dir_flag[g];
+    if (fl) atomicOr(&flag_sh, 1u);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int r = 0; r < n_res; ++r) {
+        ez_dd s{0.0, 0.0};
+        for (int t = tb + (int)threadIdx.x; t < te; t += 256)
+            s = ez_dd_add(s, ez_dd{args.tile_part[((size_t)t * n_res + r) * 2], args.tile_part[((size_t)t * n_res + r) * 2 + 1]});
+        for (int g = db + (int)threadIdx.x; g < de; g += 256)
+            s = ez_dd_add_d(s, args.dir_part[(size_t)g * n_res + r]);
+        s = ez_dd_wave_sum(s);
+        __syncthreads();
+        if (lane == 0) { red[wave][0] = s.hi; red[wave][1] = s.lo; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            ez_dd tot{red[0][0], red[0][1]};
+            for (int w = 1; w < 256 / 64; ++w) tot = ez_dd_add(tot, ez_dd{red[w][0], red[w][1]});
+            double v = tot.hi + tot.lo;
+            uint32_t st = args.meta[inst].status;
+            if (flag_sh) st |= 0x8u;
+            if (st) v = __longlong_as_double(0x7ff8000000000000ll);
+            else if (!isfinite(v)) st |= 0x4u;
+            args.out[(size_t)inst * n_res + r] = v;
+            if (args.status && r == 0) args.status[inst] = st;
+        }
+    }
+    if (!args.grad_out) return;
+    // d result / d A = S A^{-T}, S the symmetric strain derivative (d(d+1)/2 components)
+    const int d = args.prog.d, ns = d * (d + 1) / 2;
+    __shared__ double Ssh[6];
+    for (int r = 0; r < n_res; ++r) {
+        for (int sc = 0; sc < ns; ++sc) {
+            ez_dd s{0.0, 0.0};
+            for (int t = tb + (int)threadIdx.x; t < te; t += 256)
+                s = ez_dd_add(s, ez_dd{args.tile_grad[(((size_t)t * n_res + r) * 6 + sc) * 2],
+                                       args.tile_grad[(((size_t)t * n_res + r) * 6 + sc) * 2 + 1]});
+            for (int g = db + (int)threadIdx.x; g < de; g += 256)
+                s = ez_dd_add_d(s, args.dir_grad[((size_t)g * n_res + r) * 6 + sc]);
+            s = ez_dd_wave_sum(s);
+            __syncthreads();
+            if (lane == 0) { red[wave][0] = s.hi; red[wave][1] = s.lo; }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                ez_dd tot{red[0][0], red[0][1]};
+                for (int w = 1; w < 256 / 64; ++w) tot = ez_dd_add(tot, ez_dd{red[w][0], red[w][1]});
+                Ssh[sc] = tot.hi + tot.lo;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const EzLatMeta *M = args.meta + inst;
+            double Sf[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+            for (int a = 0; a < d; ++a) Sf[a][a] = Ssh[a];
+            if (d > 1) { Sf[0][1] = Sf[1][0] = Ssh[d]; }
+            if (d > 2) { Sf[0][2] = Sf[2][0] = Ssh[d + 1]; Sf[1][2] = Sf[2][1] = Ssh[d + 2]; }
+            const bool bad = M->status != 0 || flag_sh;
+            for (int a = 0; a < d; ++a)
+                for (int b = 0; b < d; ++b) {
+                    double g = 0.0;
+                    for (int c = 0; c < d; ++c) g = fma(Sf[a][c], M->B[c * d + b], g);
+                    args.grad_out[(((size_t)inst * n_res + r) * d + a) * d + b] =
+                        bad ? __longlong_as_double(0x7ff8000000000000ll) : g;
+                }
+        }
+        __syncthreads();
+    }
+}
+
+template <int D, int NNU, int SET = 0>
+hipError_t launch_nodes_t(const EzQuadArgs &args, int n_tiles, hipStream_t stream) {
+    hipLaunchKernelGGL((ez_node_kernel<D, NNU, SET>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
+    return hipGetLastError();
+}
+
+template <int D>
+hipError_t launch_nodes_d(const EzQuadArgs &args, int n_tiles, hipStream_t stream) {
+    if (D == 3 && args.prog.pset == 1) return launch_nodes_t<D, 4, 1>(args, n_tiles, stream);
+    if (D == 2 && args.prog.pset == 2) return launch_nodes_t<D, 4, 2>(args, n_tiles, stream);
+    if (D == 1 && args.prog.pset == 3) return launch_nodes_t<D, 4, 3>(args, n_tiles, stream);
+    if (D == 3 && args.prog.pset == 4) return launch_nodes_t<D, 7, 4>(args, n_tiles, stream);
+    switch (args.prog.n_nu) {
+        case 1: return launch_nodes_t<D, 1>(args, n_tiles, stream);
+        case 2: return launch_nodes_t<D, 2>(args, n_tiles, stream);
+        case 3: return launch_nodes_t<D, 3>(args, n_tiles, stream);
+        case 4: return launch_nodes_t<D, 4>(args, n_tiles, stream);
+        case 5: return launch_nodes_t<D, 5>(args, n_tiles, stream);
+        case 6: return launch_nodes_t<D, 6>(args, n_tiles, stream);
+        case 7: return launch_nodes_t<D, 7>(args, n_tiles, stream);
+        case 8: return launch_nodes_t<D, 8>(args, n_tiles, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t ez_launch_nodes_impl(const EzQuadArgs &args, int n_tiles, hipStream_t stream) {
+    switch (args.prog.d) {
+        case 1: return launch_nodes_d<1>(args, n_tiles, stream);
+        case 2: return launch_nodes_d<2>(args, n_tiles, stream);
+        case 3: return launch_nodes_d<3>(args, n_tiles, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t ez_launch_nodes(const EzQuadArgs &args, int n_tiles, hipStream_t stream) {
+    return ez_launch_nodes_impl(args, n_tiles, stream);
+}
+
+hipError_t ez_launch_finalize(const EzQuadArgs &args, hipStream_t stream) {
+    hipLaunchKernelGGL(ez_finalize_kernel, dim3(args.batch), dim3(256), 0, stream, args);
+    return hipGetLastError();
+}

@@ -1,0 +1,99 @@
+// ez_quad_common.h -- device helpers shared by the quadrature kernels
+// (ez_nodes.hip, ez_nodes_adj.hip, ez_hadamard.hip, ez_hadamard_adj.hip).
+//
+// The quadrature of products of Epstein zeta functions over the Brillouin zone
+// (paper, Sec. 2, Theorem (Epstein representation); Sec. 3, Corollary (Duffy
+// transformation) and the meromorphic continuation):
+//
+//   zeta = 2 sum_{p,j} int_0^{1/2} u^{d-1} int_{[0,1]^{d-1}} f(u w(v)) dv du,
+//   w(v) = A^{-T} sigma^j (p1 v1, ..., p_{d-1} v_{d-1}, 1),
+//
+// with u in (eps, 1/2] on quadrature nodes and u in (0, eps) through the Taylor
+// expansion of Z^reg and closed-form Hadamard integrals.
+//
+// Direction numbering: dir = block * n_q^{d-1} + iv, block = j 2^{d-1} + ip,
+// bit b of ip set <=> p_{b+1} = -1, iv = sum_b iv_b n_q^b; node = dir * n_u + iu.
+#pragma once
+#include "ez_internal.h"
+#include "ez_math.h"
+#include "ez_kernels.h"
+
+namespace {
+
+__device__ __forceinline__ int find_segment(const int *begin, int n, int x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (begin[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int D>
+__device__ __forceinline__ void ez_direction(const EzInstPlan &P, const double *rules, const double *B,
+                                             int dir, double *w, double *wv, double *what = nullptr) {
+    int nv = 1;
+#pragma unroll
+    for (int i = 0; i < D - 1; ++i) nv *= P.n_q;
+    const int np = 1 << (D - 1);
+    const int block = dir / nv;
+    int iv = dir - block * nv;
+    const int j = block / np, ip = block - j * np;
+    double x[3] = {0.0, 0.0, 0.0};
+    double weight = 1.0;
+#pragma unroll
+    for (int b = 0; b < D - 1; ++b) {
+        int ib = iv % P.n_q;
+        iv /= P.n_q;
+        double v = rules[P.vrule + ib];
+        weight *= rules[P.vrule + P.n_q + ib];
+        x[b] = ((ip >> b) & 1) ? -v : v;
+    }
+    x[D - 1] = 1.0;
+    double wh[3];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        int src = i - j;
+        if (src < 0) src += D;
+        wh[i] = (src == 0) ? x[0] : (src == 1 ? x[1] : x[2]);
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) s = fma(B[i * D + c], wh[c], s);
+        w[i] = s;
+        if (what) what[i] = wh[i];
+    }
+    *wv = weight;
+}
+
+// complex multiply (a r + i a i)(b r + i b i)
+__device__ __forceinline__ void cmul(double &ar, double &ai, double br, double bi) {
+    const double r = fma(ar, br, -ai * bi);
+    const double i = fma(ar, bi, ai * br);
+    ar = r;
+    ai = i;
+}
+
+template <int SET>
+__device__ __forceinline__ int pset_p2(const EzProgram &prog, int i) {
+    if constexpr (SET == 0) return prog.p2[i];
+    else return ez_pset(SET).p2[i];
+}
+template <int SET, int NNU>
+__device__ __forceinline__ bool pset_need_e1(const EzProgram &prog) {
+    if constexpr (SET == 0) return prog.need_e1 != 0;
+    bool r = false;
+    for (int i = 0; i < NNU; ++i) r = r || ((ez_pset(SET).p2[i] & 1) == 0 && ez_pset(SET).p2[i] >= 2);
+    return r;
+}
+template <int SET, int NNU>
+__device__ __forceinline__ bool pset_need_half(const EzProgram &prog) {
+    if constexpr (SET == 0) return prog.need_half != 0;
+    bool r = false;
+    for (int i = 0; i < NNU; ++i) r = r || (ez_pset(SET).p2[i] & 1);
+    return r;
+}
+
+}  // namespace

@@ -211,7 +211,18 @@ __global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
                 double w = ez_gamma_upper(0.5 * nu, a) * ez_rgamma(0.5 * nu) * pow(r2, -0.5 * nu);
                 e[3 + i] = 2.0 * w;
             }
-            for (int i = 3 + args.prog.n_nu; i < rs; ++i) e[i] = 0.0;
+            int used = 3 + args.prog.n_nu;
+            if (args.grad) {
+                // strain weights: d(2 W_nu)/d|z|^2 times 2 (from d|z|^2 = 2 z^T G z), with
+                // dW_nu/d|z|^2 = -Gamma(nu/2 + 1, a) / (Gamma(nu/2) |z|^{nu+2})
+                for (int i = 0; i < args.prog.n_nu; ++i) {
+                    double nu = args.prog.nu[i];
+                    e[used + i] = -4.0 * ez_gamma_upper(0.5 * nu + 1.0, a) * ez_rgamma(0.5 * nu) *
+                                  pow(r2, -0.5 * nu - 1.0);
+                }
+                used += args.prog.n_nu;
+            }
+            for (int i = used; i < rs; ++i) e[i] = 0.0;
         }
     }
     __syncthreads();

@@ -73,8 +73,16 @@ def test_host_validation_errors():
     assert L.ez_epstein_zeta(3, dummy, 0, nu, 1, dummy, dummy, 0.0, 0.0, dummy, None, None) == 1
     assert L.ez_epstein_zeta(3, dummy, 1, nu_inf, 1, dummy, dummy, 0.0, 0.0, dummy, None, None) == 1
     assert L.ez_epstein_zeta(3, dummy, 1, nu, -1, dummy, dummy, 0.0, 0.0, dummy, None, None) == 1
-    # dE/dA is not provided by this build
-    assert L.ez_atm_energy(1, 3, dummy, ctypes.byref(_spec(nat)), dummy, dummy, None, None) == 4
+    # derivatives: at most 2 results per call
+    one = (ctypes.c_int * 3)(0, 1, 2)
+    cf = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
+    nf = (ctypes.c_int * 3)(1, 1, 1)
+    fac = (ctypes.c_int * 12)()
+    mult = (ctypes.c_int * 12)(2, 0, 0, 0, 2, 0, 0, 0, 2, 0, 0, 0)
+    sp = (nat.QuadSpec * 1)(_spec(nat))
+    assert L.ez_lattice_sums_grad(1, 3, dummy, 1, nu, 3, one, cf, nf, fac, mult, 3, sp, 1, dummy, dummy,
+                                  None, None) == 1
+    assert b"at most 2" in L.ez_last_error()
 
 
 def test_version_string():
