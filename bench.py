@@ -26,23 +26,23 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_VALU_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 METRIC = "ATM lattice sums/s and Epstein-zeta evals/s at 1e-12 rel err, FP64 vs mixed"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nodes_c2.json")
-KERNEL_SOURCES = ["ez_quad.hip", "ez_math.h", "ez_internal.h", "e1_rational.h"]
+KERNEL_SOURCES = ["ez_nodes.hip", "ez_quad_common.h", "ez_math.h", "ez_internal.h", "ez_kernels.h", "e1_rational.h"]
 
 
 def node_kernel_flops_per_node(lam_rel: float, a_cut: float, n_nu: int, d: int = 3) -> float:
-    """Algorithmic FP64 flops of one quadrature node (unit-density lattice):
-    N_rec reciprocal terms x (8 for |m*+k|^2, 70 for exp + E1, 30 for the E_p ladder
-    and accumulation of 4 exponents) + N_real real-space pairs x (5 dot + 20 cos +
-    2 per exponent), with N_rec = |ball of radius sqrt(a_cut/pi)/lam| and
-    N_real = |ball of radius lam sqrt(a_cut/pi)| / 2 (lattice and reciprocal lattice
-    of unit covolume)."""
+    """Algorithmic FP64 flops of one quadrature node (unit-density lattice), FMA = 2:
+    N_rec reciprocal terms x (8 for |m*+k|^2, 70 for exp + E1, 7.5 per exponent for
+    the E_p recurrence and accumulation) + N_real real-space pairs x (6 for the
+    complex rotation that advances e^{2 pi i k.z} + 2 per exponent), with
+    N_rec = |ball of radius sqrt(a_cut/pi)/lam| and N_real = |ball of radius
+    lam sqrt(a_cut/pi)| / 2 (lattice and reciprocal lattice of unit covolume)."""
     import math
     r = math.sqrt(a_cut / math.pi)
     ball = {1: 2.0, 2: math.pi, 3: 4.0 * math.pi / 3.0}[d]
     n_rec = ball * (r / lam_rel) ** d
     n_real = 0.5 * ball * (r * lam_rel) ** d
     rec_term = 8.0 + 70.0 + 7.5 * n_nu
-    real_term = (2 * d - 1) + 20.0 + 2.0 * n_nu
+    real_term = 6.0 + 2.0 * n_nu
     return n_rec * rec_term + n_real * real_term
 
 
@@ -72,6 +72,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run three 1 GiB device-to-device copies (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the lattice sums shard trivially "
@@ -80,6 +83,16 @@ def main() -> int:
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = 1 << 27                     # 2^27 doubles = 1 GiB
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_copy": n * 8, "copies": 3}), flush=True)
+        return 0
 
     import paper_2504_11989_amd as ez
     from paper_2504_11989_amd import _native as nat
@@ -102,20 +115,51 @@ def main() -> int:
     got = out.cpu().numpy()
     max_rel = max(abs(got[i] - gold["atm"][n]) / abs(gold["atm"][n]) for i, n in enumerate(names))
 
-    nat.timing_reset()
-    nat.timing_enable(True)
+    # timed region: K steps, nothing else on the stream
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         out = ez.atm_energy(A, spec)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    elapsed = t1 - t0
+    ms_step = 1e3 * elapsed / args.steps
+
+    # per-kernel times: HIP events recorded by the library on the launch stream
+    nat.timing_reset()
+    nat.timing_enable(True)
+    for _ in range(min(args.steps, 50)):
+        ez.atm_energy(A, spec)
+    torch.cuda.synchronize()
     nat.timing_enable(False)
     kt = {k: nat.timing_read(i) for k, i in [("setup", nat.KERNEL_SETUP), ("nodes", nat.KERNEL_NODES),
                                               ("hadamard", nat.KERNEL_HADAMARD),
                                               ("finalize", nat.KERNEL_FINALIZE)]}
-    elapsed = t1 - t0
-    ms_step = 1e3 * elapsed / args.steps
+
+    # the same workload with dE/dA (adjoint kernels), timed the same way
+    adj = None
+    if not args.no_adjoint:
+        for _ in range(max(1, args.warmup // 2)):
+            ez.atm_energy(A, spec, grad=True)
+        nat.timing_reset()
+        nat.timing_enable(True)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        n_adj = max(1, args.steps // 2)
+        for _ in range(n_adj):
+            Eg, gA = ez.atm_energy(A, spec, grad=True)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        nat.timing_enable(False)
+        na = nat.timing_read(nat.KERNEL_NODES_ADJ)
+        eg = Eg.cpu().numpy()
+        adj = {"unit": "ATM lattice sums with dE/dA per s", "value": len(names) * n_adj / (tb - ta),
+               "ms_per_step": 1e3 * (tb - ta) / n_adj,
+               "node_adj_kernel_ms": round(na[0] / max(1, na[1]), 5),
+               "max_rel_err_vs_oracle": max(abs(eg[i] - gold["atm"][n]) / abs(gold["atm"][n])
+                                            for i, n in enumerate(names)),
+               "homogeneity_residual": float(max(abs(np.trace(A[i].cpu().numpy().T @ gA[i].cpu().numpy())
+                                                     + 9.0 * eg[i]) / abs(9.0 * eg[i]) for i in range(len(names))))}
     sums_per_s = len(names) * args.steps / elapsed
     evals_per_s = len(names) * nodes * n_nu * args.steps / elapsed
 
@@ -152,6 +196,7 @@ def main() -> int:
         "max_rel_err_vs_oracle": max_rel,
         "kernel_ms": {k: round(v[0] / max(1, v[1]), 5) for k, v in kt.items()},
         "roofline": roofline,
+        "adjoint": adj,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

@@ -136,3 +136,20 @@ def test_c2_full_size_vs_stored_oracle(ez):
     got = ez.atm_energy(A, g["spec"]).cpu().numpy()
     for i, n in enumerate(names):
         assert rel(got[i], g["atm"][n]) <= TOL, n
+
+
+# ---------------------------------------------------------------- ring n-body sums, nu = 6
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6])
+def test_ring_nbody_sums_cubic(ez, n):
+    """zeta^(n)_{Z^3}(6, ..., 6) for n = 2..6 (Sec. 2, Definition (many-body zeta))"""
+    spec = W.SPEC_SMALL_3D
+    got = ez.nbody_lattice_sum(W.sc(), [6.0] * n, spec).item()
+    ref = O.nbody(W.sc(), [6.0] * n, spec)
+    assert rel(got, ref) <= TOL, (n, got, ref)
+
+
+def test_ring_two_body_is_epstein_full_plan(ez):
+    """zeta^(2)(6, 6) = Z_12(0) (Sec. 2, Corollary) on the full plan"""
+    got = ez.nbody_lattice_sum(W.sc(), [6.0, 6.0], W.SPEC_FULL_3D).item()
+    ref = O.epstein(W.sc(), 12.0, [0, 0, 0], [0, 0, 0]).real
+    assert rel(got, ref) <= TOL
