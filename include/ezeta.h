@@ -69,8 +69,19 @@ typedef struct ez_quad_spec {
     double lam;
     double a_cut;
     int32_t precision; /* EZ_PREC_FP64 */
-    int32_t flags;     /* 0 */
+    int32_t flags;     /* execution options below (0: defaults); equal for all specs of a call */
 } ez_quad_spec;
+
+/* spec.flags: how the work is scheduled (results do not depend on them beyond
+ * the order of floating-point sums in the node reduction, which stays fixed)
+ *  EZ_SPEC_PERSISTENT : the node kernel runs as a persistent grid that takes node
+ *                       tiles from a work queue, costliest tiles first
+ *  EZ_SPEC_SERIAL     : the Taylor/Hadamard branch runs on the caller's stream
+ *                       after the nodes instead of concurrently on a second stream
+ *  EZ_SPEC_BPC(n)     : persistent workgroups per CU (0: as many as fit) */
+#define EZ_SPEC_PERSISTENT 0x1
+#define EZ_SPEC_SERIAL 0x2
+#define EZ_SPEC_BPC(n) (((n) & 0xFF) << 8)
 
 /* Epstein zeta Z_{Lambda,nu}(x, y) = sum'_{z in Lambda} e^{-2 pi i y.z} |z - x|^{-nu},
  * meromorphically continued in nu (paper, Sec. 2, Definition (Epstein zeta

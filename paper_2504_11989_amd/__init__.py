@@ -126,13 +126,15 @@ def atm_energy(A, spec=None, with_status=False, grad=False):
 
 
 def lattice_sums(A, nu: Sequence[float], terms: Iterable, n_results: int, specs=None, with_status=False,
-                 grad=False):
+                 grad=False, out=None, status=None):
     """Several results per lattice, result_r = sum of coef * V int_BZ prod Z_nu^mult dk.
 
     terms: iterable of (result_index, coef, [(nu_index, multiplicity), ...]).
     specs: None, one spec, or a list with one spec per lattice.
     Returns float64 tensor (batch, n_results); grad=True (n_results <= 2) also
-    returns the derivatives with respect to A, float64 (batch, n_results, d, d)."""
+    returns the derivatives with respect to A, float64 (batch, n_results, d, d).
+    out / status: optional preallocated result (batch, n_results) float64 and
+    status (batch,) int32 tensors (nothing is allocated then, e.g. under graph capture)."""
     torch = _torch()
     A, b, d = _lattices(A)
     nu_h, n_nu = _host_f64(nu)
@@ -158,8 +160,16 @@ def lattice_sums(A, nu: Sequence[float], terms: Iterable, n_results: int, specs=
     else:
         sp_list = [_spec(s) for s in specs]
     sp_arr = (QuadSpec * len(sp_list))(*sp_list)
-    out = torch.empty((b, n_results), dtype=torch.float64, device=A.device)
-    st = torch.zeros(b, dtype=torch.int32, device=A.device)
+    if out is None:
+        out = torch.empty((b, n_results), dtype=torch.float64, device=A.device)
+    elif out.shape != (b, n_results) or out.dtype != torch.float64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor of shape (batch, n_results)")
+    if status is None:
+        st = torch.zeros(b, dtype=torch.int32, device=A.device)
+    elif status.shape != (b,) or status.dtype != torch.int32:
+        raise ValueError("status must be an int32 tensor of shape (batch,)")
+    else:
+        st = status
     g = torch.empty((b, n_results, d, d), dtype=torch.float64, device=A.device) if grad else None
     check(lib().ez_lattice_sums_grad(b, d, _dptr(A), n_nu, nu_h, nt, res, coef, nfac, fac, mult, int(n_results),
                                      sp_arr, len(sp_list), _dptr(out), _dptr(g) if grad else None, _dptr(st),

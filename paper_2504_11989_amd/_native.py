@@ -18,6 +18,12 @@ STATUS_NAMES = {0: "EZ_OK", 1: "EZ_ERR_INVALID_ARG", 2: "EZ_ERR_SINGULAR_LATTICE
                 4: "EZ_ERR_UNSUPPORTED", 5: "EZ_ERR_NOMEM", 6: "EZ_ERR_HIP"}
 FLAG_SINGULAR, FLAG_CAPACITY, FLAG_NONFINITE, FLAG_HADAMARD, FLAG_POLE = 0x1, 0x2, 0x4, 0x8, 0x10
 PREC_FP64, PREC_MIXED = 0, 1
+SPEC_PERSISTENT, SPEC_SERIAL = 0x1, 0x2
+
+
+def spec_bpc(n: int) -> int:
+    """spec.flags bits for n persistent workgroups per CU (0: as many as fit)"""
+    return (int(n) & 0xFF) << 8
 
 # every symbol declared in include/ezeta.h
 EXPORTED = ("ez_epstein_zeta", "ez_nbody_lattice_sum", "ez_atm_energy", "ez_lattice_sums", "ez_lattice_sums_grad",
@@ -42,7 +48,7 @@ class QuadSpec(ctypes.Structure):
     def from_dict(cls, s: dict) -> "QuadSpec":
         return cls(int(s.get("n_q", 14)), int(s.get("n_panels", 7)), int(s.get("n_g", 16)),
                    int(s.get("ell", 4)), float(s.get("eps", 1e-2)), float(s.get("lam", 1.0)),
-                   float(s.get("a_cut", 36.0)), int(s.get("precision", PREC_FP64)), 0)
+                   float(s.get("a_cut", 36.0)), int(s.get("precision", PREC_FP64)), int(s.get("flags", 0)))
 
 
 _lib = None

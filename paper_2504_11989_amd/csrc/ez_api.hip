@@ -134,7 +134,7 @@ ez_status grow(DevBuf &b, size_t bytes) {
 
 // A plan depends only on (d, batch, specs): rule tables, per-lattice plans, prefixes.
 struct DevPlan {
-    DevBuf rules, plans, tile_begin, dir_begin, htile_begin;
+    DevBuf rules, plans, tile_begin, dir_begin, htile_begin, tile_order;
     int n_tiles = 0, n_dirs = 0, n_htiles = 0;
     int n_probe = 0, ell_probe = 0, probe_off = 0;
     int pinv_off[EZ_ELL_MAX + 1] = {0};
@@ -146,6 +146,10 @@ struct DeviceState {
     std::vector<std::string> plan_order;
     DevBuf meta, real, rn, rows, rec, tile_part, dir_part, dir_flag, probe_val, tensor, tile_grad, dir_grad;
     DevBuf gmeta, greal, grec;   // general-x Epstein tables
+    DevBuf queue;                // work-queue position of the persistent node kernel
+    int n_cu = 0;
+    hipStream_t side = nullptr;  // second stream: Hadamard branch concurrent with the nodes
+    hipEvent_t ev_setup = nullptr, ev_had = nullptr;
 };
 
 std::mutex g_mu;
@@ -203,7 +207,7 @@ void free_buf(DevBuf &b) {
 
 void free_plan(DevPlan *p) {
     free_buf(p->rules); free_buf(p->plans); free_buf(p->tile_begin); free_buf(p->dir_begin);
-    free_buf(p->htile_begin);
+    free_buf(p->htile_begin); free_buf(p->tile_order);
     delete p;
 }
 
@@ -217,6 +221,8 @@ ez_status check_spec(const ez_quad_spec &s) {
     if (!(s.lam >= 0.0 && s.lam <= 8.0)) return fail(EZ_ERR_INVALID_ARG, "spec.lam must be in [0, 8]");
     if (!(s.a_cut >= 0.0 && s.a_cut <= 200.0)) return fail(EZ_ERR_INVALID_ARG, "spec.a_cut must be in [0, 200]");
     if (s.precision != EZ_PREC_FP64) return fail(EZ_ERR_UNSUPPORTED, "spec.precision: only EZ_PREC_FP64 here");
+    if (s.flags & ~(EZ_SPEC_PERSISTENT | EZ_SPEC_SERIAL | 0xFF00))
+        return fail(EZ_ERR_INVALID_ARG, "spec.flags: unknown bits");
     return EZ_OK;
 }
 
@@ -327,6 +333,9 @@ std::string plan_key(int d, int batch, const ez_quad_spec *specs, int n_specs, i
     return k;
 }
 
+// volume of the unit ball in d dimensions
+const double kOmega[4] = {0.0, 2.0, M_PI, 4.0 * M_PI / 3.0};
+
 // ndb: directions per workgroup of the Hadamard direction kernel
 ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, int n_specs, int ndb, DevPlan **out) {
     std::string key = plan_key(d, batch, specs, n_specs, ndb);
@@ -398,6 +407,25 @@ ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, 
     tb[batch] = (int)tiles;
     db[batch] = (int)dirs;
     hb[batch] = (int)htiles;
+    // order in which the persistent node kernel takes the tiles: costliest first
+    // (nodes in the tile x model cost of one node at the lattice's lam)
+    std::vector<int> order((size_t)tiles);
+    {
+        std::vector<double> cost((size_t)tiles);
+        for (int b = 0; b < batch; ++b) {
+            const ez_quad_spec &s = specs[n_specs == 1 ? 0 : b];
+            const EzInstPlan &ip = P->host_plans[b];
+            const long long nn = (long long)ip.n_dir * ip.n_u;
+            const double R = std::sqrt(spec_acut(s) / M_PI), lam = spec_lam(s);
+            const double per_node = kOmega[d] * (std::pow(R / lam, d) * 108.0 + 0.5 * std::pow(R * lam, d) * 14.0);
+            for (int t = tb[b]; t < tb[b + 1]; ++t) {
+                const long long first = (long long)(t - tb[b]) * EZ_TILE;
+                cost[t] = (double)std::min<long long>(EZ_TILE, nn - first) * per_node;
+            }
+        }
+        for (size_t t = 0; t < order.size(); ++t) order[t] = (int)t;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    }
     // probe directions and least-squares inverses for the Taylor coefficients
     {
         int lp = 0;
@@ -444,7 +472,8 @@ ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, 
         (st = grow(P->plans, sizeof(EzInstPlan) * batch)) ||
         (st = grow(P->tile_begin, sizeof(int) * (batch + 1))) ||
         (st = grow(P->dir_begin, sizeof(int) * (batch + 1))) ||
-        (st = grow(P->htile_begin, sizeof(int) * (batch + 1)))) {
+        (st = grow(P->htile_begin, sizeof(int) * (batch + 1))) ||
+        (st = grow(P->tile_order, sizeof(int) * std::max<size_t>(1, order.size())))) {
         free_plan(P);
         return st;
     }
@@ -453,7 +482,9 @@ ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, 
         hipMemcpy(P->plans.p, P->host_plans.data(), sizeof(EzInstPlan) * batch, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(P->tile_begin.p, tb.data(), sizeof(int) * (batch + 1), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(P->dir_begin.p, db.data(), sizeof(int) * (batch + 1), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(P->htile_begin.p, hb.data(), sizeof(int) * (batch + 1), hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(P->htile_begin.p, hb.data(), sizeof(int) * (batch + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        (!order.empty() &&
+         hipMemcpy(P->tile_order.p, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice) != hipSuccess)) {
         free_plan(P);
         return fail(EZ_ERR_HIP, "upload of the quadrature plan failed");
     }
@@ -469,7 +500,6 @@ ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, 
     return EZ_OK;
 }
 
-const double kOmega[4] = {0.0, 2.0, M_PI, 4.0 * M_PI / 3.0};
 const double kSkew = 2.5;   // bound on (1/2) sum |a_i| / V^{1/d} assumed for table capacity
 
 int real_capacity(int d, double lam, double acut, bool general) {
@@ -507,8 +537,18 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     }
     if (maxdeg > 32)
         return fail(EZ_ERR_UNSUPPORTED, "Taylor product of degree > 32 in u^2 on (0, eps): lower ell or the multiplicity");
+    const int flags = specs[0].flags;
+    for (int i = 1; i < n_specs; ++i)
+        if (specs[i].flags != flags) return fail(EZ_ERR_INVALID_ARG, "all specs of one call must share flags");
     ez_status st = get_plan(S, d, batch, specs, n_specs, ndb, &P);
     if (st) return st;
+    if (!S->side) {
+        EZ_HIP_TRY(hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking));
+        EZ_HIP_TRY(hipEventCreateWithFlags(&S->ev_setup, hipEventDisableTiming));
+        EZ_HIP_TRY(hipEventCreateWithFlags(&S->ev_had, hipEventDisableTiming));
+        EZ_HIP_TRY(hipDeviceGetAttribute(&S->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    }
+    if ((st = grow(S->queue, 256))) return st;
     const int n_pblk = (P->n_probe + 63) / 64;
     const int n_slice = std::max(1, std::min(EZ_SLICE_MAX, 512 / std::max(1, batch * n_pblk)));
     double lam_min = 1e300, lam_max = 0.0, acut = spec_acut(specs[0]);
@@ -583,12 +623,38 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     qa.tile_grad = grad ? (double *)S->tile_grad.p : nullptr;
     qa.dir_grad = grad ? (double *)S->dir_grad.p : nullptr;
     qa.grad_out = grad_dev;
+    qa.n_tiles = P->n_tiles;
+    qa.tile_order = (const int *)P->tile_order.p;
+    qa.queue = (int *)S->queue.p;
+
+    // The Hadamard branch (probe, tensor, direction kernels) depends only on the
+    // setup: it runs on a second stream, concurrently with the node kernel, and the
+    // caller's stream waits for it before the final reduction (event edges, so the
+    // sequence can be captured into a graph).  EZ_SPEC_SERIAL keeps it on `stream`.
+    hipStream_t hs = stream;
+    if (!(flags & EZ_SPEC_SERIAL)) {
+        EZ_HIP_TRY(hipEventRecord(S->ev_setup, stream));
+        EZ_HIP_TRY(hipStreamWaitEvent(S->side, S->ev_setup, 0));
+        hs = S->side;
+    }
+    if (grad)
+        EZ_HIP_TRY(timed(EZ_KERNEL_HADAMARD, hs, [&] { return ez_launch_hadamard_adj(qa, P->n_htiles, hs); }));
+    else
+        EZ_HIP_TRY(timed(EZ_KERNEL_HADAMARD, hs, [&] { return ez_launch_hadamard(qa, P->n_htiles, hs); }));
     if (grad) {
         EZ_HIP_TRY(timed(EZ_KERNEL_NODES_ADJ, stream, [&] { return ez_launch_nodes_adj(qa, P->n_tiles, stream); }));
-        EZ_HIP_TRY(timed(EZ_KERNEL_HADAMARD, stream, [&] { return ez_launch_hadamard_adj(qa, P->n_htiles, stream); }));
+    } else if (flags & EZ_SPEC_PERSISTENT) {
+        int bpc = (flags >> 8) & 0xFF;
+        if (bpc == 0) bpc = ez_nodes_blocks_per_cu(qa);
+        const int nblk = std::max(1, std::min(P->n_tiles, S->n_cu * bpc));
+        EZ_HIP_TRY(ez_launch_fill_int(qa.queue, 1, 0, stream));
+        EZ_HIP_TRY(timed(EZ_KERNEL_NODES, stream, [&] { return ez_launch_nodes_persistent(qa, nblk, stream); }));
     } else {
         EZ_HIP_TRY(timed(EZ_KERNEL_NODES, stream, [&] { return ez_launch_nodes(qa, P->n_tiles, stream); }));
-        EZ_HIP_TRY(timed(EZ_KERNEL_HADAMARD, stream, [&] { return ez_launch_hadamard(qa, P->n_htiles, stream); }));
+    }
+    if (hs != stream) {
+        EZ_HIP_TRY(hipEventRecord(S->ev_had, hs));
+        EZ_HIP_TRY(hipStreamWaitEvent(stream, S->ev_had, 0));
     }
     EZ_HIP_TRY(timed(EZ_KERNEL_FINALIZE, stream, [&] { return ez_launch_finalize(qa, stream); }));
     return EZ_OK;
@@ -620,7 +686,13 @@ ez_status ez_finalize(void) {
         for (auto &p : S->plans) free_plan(p.second);
         free_buf(S->meta); free_buf(S->real); free_buf(S->rec); free_buf(S->rn); free_buf(S->rows);
         free_buf(S->tile_part); free_buf(S->dir_part); free_buf(S->dir_flag); free_buf(S->probe_val); free_buf(S->tensor);
-        free_buf(S->tile_grad); free_buf(S->dir_grad);
+        free_buf(S->tile_grad); free_buf(S->dir_grad); free_buf(S->queue);
+        if (S->side) {
+            (void)hipStreamSynchronize(S->side);
+            (void)hipStreamDestroy(S->side);
+            (void)hipEventDestroy(S->ev_setup);
+            (void)hipEventDestroy(S->ev_had);
+        }
         free_buf(S->gmeta); free_buf(S->greal); free_buf(S->grec);
         delete S;
     }

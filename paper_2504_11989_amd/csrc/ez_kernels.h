@@ -31,6 +31,9 @@ struct EzQuadArgs {
     int batch;
     const EzInstPlan *plans;
     const int *tile_begin;     // batch + 1 prefix of node tiles
+    int n_tiles;               // node tiles of the whole batch
+    const int *tile_order;     // persistent node kernel: tiles in the order they are taken (costliest first)
+    int *queue;                // persistent node kernel: next position in tile_order (reset before launch)
     const int *dir_begin;      // batch + 1 prefix of directions
     const int *htile_begin;    // batch + 1 prefix of Hadamard direction tiles
     int n_dir_blk;             // directions per Hadamard direction workgroup (<= EZ_HDIR)
@@ -70,6 +73,11 @@ struct EzEpsteinArgs {
 
 hipError_t ez_launch_setup(const EzSetupArgs &args, int batch, hipStream_t stream);
 hipError_t ez_launch_nodes(const EzQuadArgs &args, int n_tiles, hipStream_t stream);
+// persistent form: n_blocks workgroups take tiles from args.queue until all are done
+hipError_t ez_launch_nodes_persistent(const EzQuadArgs &args, int n_blocks, hipStream_t stream);
+// blocks of the persistent node kernel that fit on one CU at once
+int ez_nodes_blocks_per_cu(const EzQuadArgs &args);
+hipError_t ez_launch_fill_int(int *p, int n, int value, hipStream_t stream);
 hipError_t ez_launch_hadamard(const EzQuadArgs &args, int n_htiles, hipStream_t stream);
 hipError_t ez_launch_finalize(const EzQuadArgs &args, hipStream_t stream);
 hipError_t ez_launch_nodes_adj(const EzQuadArgs &args, int n_tiles, hipStream_t stream);

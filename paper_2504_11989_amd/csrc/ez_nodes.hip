@@ -12,8 +12,7 @@
 namespace {
 
 template <int D, int NNU, int SET>
-__global__ __launch_bounds__(EZ_TILE) void ez_node_kernel(EzQuadArgs args) {
-    const int tile = blockIdx.x;
+__device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile) {
     const int inst = find_segment(args.tile_begin, args.batch, tile);
     const EzInstPlan P = args.plans[inst];
     const EzLatMeta *M = args.meta + inst;
@@ -172,6 +171,33 @@ __global__ __launch_bounds__(EZ_TILE) void ez_node_kernel(EzQuadArgs args) {
     }
 }
 
+// one workgroup per tile
+template <int D, int NNU, int SET>
+__global__ __launch_bounds__(EZ_TILE) void ez_node_kernel(EzQuadArgs args) {
+    node_tile<D, NNU, SET>(args, (int)blockIdx.x);
+}
+
+// persistent: a fixed grid of workgroups takes tiles from a queue, costliest first;
+// every workgroup leaves once the queue position passes the last tile
+template <int D, int NNU, int SET>
+__global__ __launch_bounds__(EZ_TILE) void ez_node_persist_kernel(EzQuadArgs args) {
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(args.queue, 1);
+        __syncthreads();
+        // the tile index is uniform over the workgroup: keep it in scalar registers
+        const int t = __builtin_amdgcn_readfirstlane(next);
+        __syncthreads();
+        if (t >= args.n_tiles) break;
+        node_tile<D, NNU, SET>(args, __builtin_amdgcn_readfirstlane(args.tile_order[t]));
+    }
+}
+
+__global__ void ez_fill_int_kernel(int *p, int n, int value) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = value;
+}
+
 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void ez_finalize_kernel(EzQuadArgs args) {
@@ -251,36 +277,54 @@ __global__ __launch_bounds__(256) void ez_finalize_kernel(EzQuadArgs args) {
     }
 }
 
+// mode 0: one workgroup per tile (n = tiles); mode 1: persistent (n = workgroups);
+// mode 2: report the persistent kernel's resident workgroups per CU in *n
 template <int D, int NNU, int SET = 0>
-hipError_t launch_nodes_t(const EzQuadArgs &args, int n_tiles, hipStream_t stream) {
-    hipLaunchKernelGGL((ez_node_kernel<D, NNU, SET>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
+hipError_t launch_nodes_t(const EzQuadArgs &args, int n_tiles, hipStream_t stream, int mode = 0, int *bpc = nullptr) {
+    if (mode == 2) {
+        static int cached = 0;
+        if (!cached) {
+            int nb = 0;
+            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ez_node_persist_kernel<D, NNU, SET>,
+                                                                        EZ_TILE, 0);
+            if (e != hipSuccess) return e;
+            cached = nb > 0 ? nb : 1;
+        }
+        *bpc = cached;
+        return hipSuccess;
+    }
+    if (mode == 1)
+        hipLaunchKernelGGL((ez_node_persist_kernel<D, NNU, SET>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
+    else
+        hipLaunchKernelGGL((ez_node_kernel<D, NNU, SET>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
     return hipGetLastError();
 }
 
 template <int D>
-hipError_t launch_nodes_d(const EzQuadArgs &args, int n_tiles, hipStream_t stream) {
-    if (D == 3 && args.prog.pset == 1) return launch_nodes_t<D, 4, 1>(args, n_tiles, stream);
-    if (D == 2 && args.prog.pset == 2) return launch_nodes_t<D, 4, 2>(args, n_tiles, stream);
-    if (D == 1 && args.prog.pset == 3) return launch_nodes_t<D, 4, 3>(args, n_tiles, stream);
-    if (D == 3 && args.prog.pset == 4) return launch_nodes_t<D, 7, 4>(args, n_tiles, stream);
+hipError_t launch_nodes_d(const EzQuadArgs &args, int n_tiles, hipStream_t stream, int mode, int *bpc) {
+    if (D == 3 && args.prog.pset == 1) return launch_nodes_t<D, 4, 1>(args, n_tiles, stream, mode, bpc);
+    if (D == 2 && args.prog.pset == 2) return launch_nodes_t<D, 4, 2>(args, n_tiles, stream, mode, bpc);
+    if (D == 1 && args.prog.pset == 3) return launch_nodes_t<D, 4, 3>(args, n_tiles, stream, mode, bpc);
+    if (D == 3 && args.prog.pset == 4) return launch_nodes_t<D, 7, 4>(args, n_tiles, stream, mode, bpc);
     switch (args.prog.n_nu) {
-        case 1: return launch_nodes_t<D, 1>(args, n_tiles, stream);
-        case 2: return launch_nodes_t<D, 2>(args, n_tiles, stream);
-        case 3: return launch_nodes_t<D, 3>(args, n_tiles, stream);
-        case 4: return launch_nodes_t<D, 4>(args, n_tiles, stream);
-        case 5: return launch_nodes_t<D, 5>(args, n_tiles, stream);
-        case 6: return launch_nodes_t<D, 6>(args, n_tiles, stream);
-        case 7: return launch_nodes_t<D, 7>(args, n_tiles, stream);
-        case 8: return launch_nodes_t<D, 8>(args, n_tiles, stream);
+        case 1: return launch_nodes_t<D, 1>(args, n_tiles, stream, mode, bpc);
+        case 2: return launch_nodes_t<D, 2>(args, n_tiles, stream, mode, bpc);
+        case 3: return launch_nodes_t<D, 3>(args, n_tiles, stream, mode, bpc);
+        case 4: return launch_nodes_t<D, 4>(args, n_tiles, stream, mode, bpc);
+        case 5: return launch_nodes_t<D, 5>(args, n_tiles, stream, mode, bpc);
+        case 6: return launch_nodes_t<D, 6>(args, n_tiles, stream, mode, bpc);
+        case 7: return launch_nodes_t<D, 7>(args, n_tiles, stream, mode, bpc);
+        case 8: return launch_nodes_t<D, 8>(args, n_tiles, stream, mode, bpc);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t ez_launch_nodes_impl(const EzQuadArgs &args, int n_tiles, hipStream_t stream) {
+hipError_t ez_launch_nodes_impl(const EzQuadArgs &args, int n_tiles, hipStream_t stream, int mode = 0,
+                                int *bpc = nullptr) {
     switch (args.prog.d) {
-        case 1: return launch_nodes_d<1>(args, n_tiles, stream);
-        case 2: return launch_nodes_d<2>(args, n_tiles, stream);
-        case 3: return launch_nodes_d<3>(args, n_tiles, stream);
+        case 1: return launch_nodes_d<1>(args, n_tiles, stream, mode, bpc);
+        case 2: return launch_nodes_d<2>(args, n_tiles, stream, mode, bpc);
+        case 3: return launch_nodes_d<3>(args, n_tiles, stream, mode, bpc);
         default: return hipErrorInvalidValue;
     }
 }
@@ -289,6 +333,21 @@ hipError_t ez_launch_nodes_impl(const EzQuadArgs &args, int n_tiles, hipStream_t
 
 hipError_t ez_launch_nodes(const EzQuadArgs &args, int n_tiles, hipStream_t stream) {
     return ez_launch_nodes_impl(args, n_tiles, stream);
+}
+
+hipError_t ez_launch_nodes_persistent(const EzQuadArgs &args, int n_blocks, hipStream_t stream) {
+    return ez_launch_nodes_impl(args, n_blocks, stream, 1);
+}
+
+int ez_nodes_blocks_per_cu(const EzQuadArgs &args) {
+    int bpc = 1;
+    if (ez_launch_nodes_impl(args, 0, nullptr, 2, &bpc) != hipSuccess) return 1;
+    return bpc;
+}
+
+hipError_t ez_launch_fill_int(int *p, int n, int value, hipStream_t stream) {
+    hipLaunchKernelGGL(ez_fill_int_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, p, n, value);
+    return hipGetLastError();
 }
 
 hipError_t ez_launch_finalize(const EzQuadArgs &args, hipStream_t stream) {

@@ -1,0 +1,102 @@
+"""GPU: batched scans with uneven per-lattice plans, the persistent node kernel,
+the concurrent Hadamard branch, HIP-graph replay and the autotuner."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ez():
+    import paper_2504_11989_amd as ez
+    ez.version()
+    return ez
+
+
+def small_scan(count=6, lam=1.3):
+    ca, nside, A = W.c3_scan()
+    ns = 16 + (np.arange(count) * 3) % 9                 # uneven small plans: 16..24 per side
+    specs = [W.c3_spec(int(n), lam=lam) for n in ns]
+    return A[:count], specs
+
+
+def oracle_scan(A, spec):
+    return [O.atm(A, spec)] + [O.nbody(A, [nu] * 3, spec) for nu in (3.0, 6.0, 9.0, 12.0)]
+
+
+def test_scan_uneven_plans_vs_oracle(ez):
+    from paper_2504_11989_amd.batch import scan_sums
+    A, specs = small_scan()
+    got = scan_sums(A, specs).cpu().numpy()
+    for i in range(len(A)):
+        ref = oracle_scan(A[i], specs[i])
+        for r in range(5):
+            assert abs(got[i, r] - ref[r]) <= TOL * abs(ref[r]), (i, r, got[i, r], ref[r])
+
+
+def test_mixed_lam_in_one_call(ez):
+    from paper_2504_11989_amd.batch import scan_sums
+    A, specs = small_scan(4)
+    for i, lam in enumerate([1.0, 1.2, 1.4, 1.6]):
+        specs[i] = dict(specs[i], lam=lam)
+    got = scan_sums(A, specs).cpu().numpy()
+    for i in range(4):
+        ref = oracle_scan(A[i], specs[i])
+        for r in range(5):
+            assert abs(got[i, r] - ref[r]) <= TOL * abs(ref[r]), (i, r)
+
+
+@pytest.mark.parametrize("flags", [0x1, 0x1 | (1 << 8), 0x1 | (3 << 8), 0x2, 0x3])
+def test_schedules_give_identical_results(ez, flags):
+    """persistent queue, workgroups per CU and the serial Hadamard branch change the
+    schedule only: every tile and direction partial is the same, so are the sums"""
+    from paper_2504_11989_amd.batch import scan_sums
+    A, specs = small_scan(8)
+    ref = scan_sums(A, specs).cpu().numpy()
+    got = scan_sums(A, [dict(s, flags=flags) for s in specs]).cpu().numpy()
+    assert np.array_equal(got, ref)
+    lat = np.stack([W.sc(), W.fcc(), W.bcc()])
+    e0 = ez.atm_energy(lat, W.SPEC_SMALL_3D).cpu().numpy()
+    e1 = ez.atm_energy(lat, dict(W.SPEC_SMALL_3D, flags=flags)).cpu().numpy()
+    assert np.array_equal(e0, e1)
+
+
+def test_graph_replay_matches_eager(ez):
+    """captured once, replayed several times with eager work in between; every
+    replay equals the eager result, also after new lattices are copied in"""
+    from paper_2504_11989_amd.batch import SCAN_NU, SCAN_TERMS, GraphedLatticeSums, scan_sums
+    A, specs = small_scan(8)
+    eager = scan_sums(A, specs).cpu().numpy()
+    g = GraphedLatticeSums(A, SCAN_NU, SCAN_TERMS, 5, specs)
+    for rep in range(3):
+        out = g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager), rep
+        # eager work on the library and on torch between replays
+        scan_sums(A[::-1].copy(), specs[::-1]).cpu()
+        (torch.ones(1 << 20, device="cuda", dtype=torch.float64) * 2.0).sum().item()
+    A2 = A.copy()
+    A2[:, 2, 2] *= 1.05
+    g.A.copy_(torch.as_tensor(A2, device="cuda"))
+    out = g.replay()
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), scan_sums(A2, specs).cpu().numpy())
+    assert np.array_equal(g.status.cpu().numpy(), np.zeros(8, dtype=np.int32))
+
+
+def test_autotune_picks_a_valid_configuration(ez):
+    from paper_2504_11989_amd import autotune
+    from paper_2504_11989_amd.batch import SCAN_NU, SCAN_TERMS, scan_sums
+    A, specs = small_scan(8)
+    res = autotune.tune(A, SCAN_NU, SCAN_TERMS, 5, specs, lams=(1.0, 1.3),
+                        schedules=autotune.DEFAULT_SCHEDULES[:2], reps=2)
+    assert res["lam"] in (1.0, 1.3) and res["ms"] > 0 and len(res["table"]) == 3
+    tuned = scan_sums(A, autotune.apply(specs, res["lam"], res["flags"])).cpu().numpy()
+    base = scan_sums(A, autotune.apply(specs, 1.3, 0)).cpu().numpy()
+    assert np.all(np.abs(tuned - base) <= 1e-12 * np.abs(base))
