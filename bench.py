@@ -129,6 +129,69 @@ def c3_scan_leg(args) -> dict:
     }
 
 
+def c4_grid_leg(args) -> dict:
+    """Mixed precision: Z_nu(x_j, y_m) for nu in {-1, 1, 3, 5}, 512 shifts x uniform in the
+    cell (seed 4) and 8192 points y uniform in the reciprocal cell (seed 40), on each
+    of the sc/fcc/bcc lattices at unit density: 16.8 M Epstein evaluations per lattice,
+    as FP64 matrix products (plain) and with the far table entries as split-BF16
+    products (mixed).  Errors: mixed against FP64 over the whole grid, both against
+    the oracle at 16 sampled (x, y) pairs per lattice."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import workloads as W
+    import paper_2504_11989_amd as ez
+
+    nu = [-1.0, 1.0, 3.0, 5.0]
+    out = {"workload": "Z_nu(x_j, y_m), nu in {-1,1,3,5}, 512 shifts (seed 4) x 8192 reciprocal-cell points "
+                       "(seed 40), sc/fcc/bcc at unit density", "lattices": {}}
+    tot = {False: 0.0, True: 0.0}
+    worst = {"mixed_vs_fp64": 0.0, "fp64_vs_oracle": 0.0, "mixed_vs_oracle": 0.0, "bound_max": 0.0}
+    rng = np.random.default_rng(7)
+    for name, A_np in W.c2_lattices().items():
+        A = torch.tensor(A_np, device="cuda")
+        xs_np, ys_np = W.c4_shifts(A_np), W.c4_points(A_np)
+        xs, ys = torch.tensor(xs_np, device="cuda"), torch.tensor(ys_np, device="cuda")
+        res = {}
+        for mixed in (False, True):
+            ez.epstein_grid(A, nu, xs, ys, mixed=mixed)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.c4_reps):
+                z = ez.epstein_grid(A, nu, xs, ys, mixed=mixed, with_bound=mixed)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / args.c4_reps
+            tot[mixed] += dt
+            res[mixed] = (z, dt)
+        z64 = res[False][0]
+        zm, bound = res[True][0]
+        err = ((zm - z64).abs() / z64.abs().clamp(min=1.0)).max().item()
+        bmax = bound.max().item()
+        idx = [(int(rng.integers(512)), int(rng.integers(8192))) for _ in range(16)]
+        e64 = em = 0.0
+        for j, m in idx:
+            for k, v in enumerate(nu):
+                ref = oracle.epstein(A_np, v, xs_np[j], ys_np[m])
+                den = max(abs(ref), 1.0)
+                e64 = max(e64, abs(z64[k, j, m].item() - ref) / den)
+                em = max(em, abs(zm[k, j, m].item() - ref) / den)
+        worst["mixed_vs_fp64"] = max(worst["mixed_vs_fp64"], err)
+        worst["fp64_vs_oracle"] = max(worst["fp64_vs_oracle"], e64)
+        worst["mixed_vs_oracle"] = max(worst["mixed_vs_oracle"], em)
+        worst["bound_max"] = max(worst["bound_max"], bmax)
+        out["lattices"][name] = {"fp64_ms": 1e3 * res[False][1], "mixed_ms": 1e3 * res[True][1]}
+        del z64, zm, bound, res
+    evals = 3 * len(nu) * 512 * 8192
+    out.update({
+        "epstein_evals_per_s_fp64": evals / tot[False], "epstein_evals_per_s_mixed": evals / tot[True],
+        "speedup_mixed_vs_fp64": tot[False] / tot[True],
+        "max_err_mixed_vs_fp64": worst["mixed_vs_fp64"], "max_err_fp64_vs_oracle": worst["fp64_vs_oracle"],
+        "max_err_mixed_vs_oracle": worst["mixed_vs_oracle"], "max_a_priori_bound_mixed": worst["bound_max"],
+        "error_measure": "|dZ| / max(|Z|, 1) per element"})
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +201,8 @@ def main() -> int:
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the batched 4096-lattice scan leg")
     ap.add_argument("--c3-reps", type=int, default=3)
+    ap.add_argument("--no-c4", action="store_true", help="skip the mixed-precision Epstein grid leg")
+    ap.add_argument("--c4-reps", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 1 GiB device-to-device copies (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -263,10 +328,13 @@ def main() -> int:
         "roofline": roofline,
         "adjoint": adj,
         "c3_scan": None,
+        "c4_grid": None,
         "cpu_baseline": None,
     }
     if not args.no_c3:
         line["c3_scan"] = c3_scan_leg(args)
+    if not args.no_c4:
+        line["c4_grid"] = c4_grid_leg(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec)
     print(json.dumps(line), flush=True)

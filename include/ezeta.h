@@ -103,6 +103,30 @@ ez_status ez_epstein_zeta(int d, const double *A_dev, int n_nu, const double *nu
                           double lam, double a_cut, double *out_dev, uint32_t *status_dev,
                           void *stream);
 
+/* Epstein zeta on a grid: Z_{Lambda,nu_k}(x_j, y_m) for every exponent, shift x_j
+ * and point y_m (paper, Sec. 2, Definition (Epstein zeta function)), with the
+ * real-space sum sum_z W_nu(|z - x_j|) e^{-2 pi i y_m.z} and the reciprocal sum
+ * sum_m* e^{-2 pi i m*.x_j} G_nu(|m* + y_m|) each computed as one matrix product
+ * over the lattice-point tables (MFMA).
+ *   A_dev   : d*d doubles (one lattice)
+ *   x_dev   : n_x x d shifts, y_dev : n_y x d points (Cartesian, row-major)
+ *   precision : EZ_PREC_FP64 (FP64 products throughout) or EZ_PREC_MIXED (table
+ *             entries whose weight exceeds e^{-18} for some x or y in FP64, the rest
+ *             as split-BF16 products with FP32 accumulation per 32 entries and FP64
+ *             accumulation across them)
+ *   out_dev : n_nu x n_x x n_y x 2 doubles, (re, im) of Z(nu_k; x_j, y_m) at
+ *             out_dev[2*((k*n_x + j)*n_y + m) + {0,1}]
+ *   bound_dev : NULL or n_nu x n_x doubles: an a-priori bound of
+ *             max_m |Z_mixed - Z_fp64| for each (nu_k, x_j) (zeros for FP64)
+ *   status_dev : 1 uint32 (lattice flags, EZ_FLAG_POLE at nu = d, y in Lambda*), may be NULL
+ * The call reads the lattice table sizes back once (it synchronises `stream`
+ * after the setup kernel), so it cannot be captured into a graph.
+ * Errors: EZ_ERR_INVALID_ARG (d, sizes, null pointers, non-finite nu, precision). */
+ez_status ez_epstein_grid(int d, const double *A_dev, int n_nu, const double *nu_host, int n_x,
+                          const double *x_dev, int n_y, const double *y_dev, double lam, double a_cut,
+                          int precision, double *out_dev, double *bound_dev, uint32_t *status_dev,
+                          void *stream);
+
 /* n-body zeta zeta^(n)_Lambda(nu) (paper, Sec. 2, Definition (Many-body zeta
  * function)) by the Epstein representation V int_BZ prod_i Z_{Lambda,nu_i}(k) dk
  * (Sec. 2, Theorem) with the Duffy transform and the Hadamard continuation
@@ -168,7 +192,8 @@ ez_status ez_lattice_sums_grad(int batch, int d, const double *A_dev, int n_nu, 
 #define EZ_KERNEL_FINALIZE 3   /* fixed-order reduction                  */
 #define EZ_KERNEL_EPSTEIN 4    /* Z(x, y) at arbitrary points            */
 #define EZ_KERNEL_NODES_ADJ 5  /* quadrature nodes with the adjoint pass  */
-#define EZ_KERNEL_COUNT 6
+#define EZ_KERNEL_GRID 6       /* Z on a (shift x point) grid            */
+#define EZ_KERNEL_COUNT 7
 ez_status ez_timing_enable(int enable);
 ez_status ez_timing_reset(void);
 ez_status ez_timing_read(int kernel, double *total_ms, int64_t *launches);

@@ -5,6 +5,7 @@ Thin Python layer over libezeta.so (see include/ezeta.h): torch tensors on the
 GPU are passed to the C ABI as device pointers on torch's current stream.
 
     epstein_zeta(A, nu, x, y)        Z_{A Z^d, nu}(x, y), complex
+    epstein_grid(A, nu, xs, ys)      Z on every (shift, point) pair, FP64 or mixed precision
     nbody_lattice_sum(A, nu, spec)   zeta^(n)_Lambda(nu) for a batch of lattices
     atm_energy(A, spec)              ATM cohesive energy per particle (and dE/dA)
     lattice_sums(A, nu, terms, ...)  several product integrals per lattice (and d/dA)
@@ -21,7 +22,7 @@ from typing import Iterable, Sequence
 from ._native import (FLAG_CAPACITY, FLAG_HADAMARD, FLAG_NONFINITE, FLAG_POLE, FLAG_SINGULAR,
                       PREC_FP64, PREC_MIXED, EzError, QuadSpec, check, lib)
 
-__all__ = ["epstein_zeta", "nbody_lattice_sum", "atm_energy", "lattice_sums", "QuadSpec", "EzError",
+__all__ = ["epstein_zeta", "epstein_grid", "nbody_lattice_sum", "atm_energy", "lattice_sums", "QuadSpec", "EzError",
            "DEFAULT_SPEC", "FLAG_SINGULAR", "FLAG_CAPACITY", "FLAG_NONFINITE", "FLAG_HADAMARD",
            "FLAG_POLE", "version", "finalize"]
 
@@ -93,6 +94,34 @@ def epstein_zeta(A, nu: Sequence[float], x, y, lam: float = 0.0, a_cut: float = 
                                 _dptr(out), _dptr(st), _stream_ptr(A.device)))
     z = torch.view_as_complex(out)
     return (z, st) if with_status else z
+
+
+def epstein_grid(A, nu: Sequence[float], x, y, lam: float = 0.0, a_cut: float = 0.0, mixed: bool = False,
+                 with_bound: bool = False, with_status: bool = False):
+    """Z_{A Z^d, nu_k}(x_j, y_m) for every exponent, shift and point: complex128
+    tensor (len(nu), n_x, n_y).  mixed=True: split-BF16 products for the far table
+    entries (see include/ezeta.h); with_bound also returns the a-priori bound of
+    max_m |Z_mixed - Z_fp64| per (nu_k, x_j), float64 (len(nu), n_x)."""
+    torch = _torch()
+    A, b, d = _lattices(A)
+    if b != 1:
+        raise ValueError("epstein_grid takes one lattice")
+    x = _dev_f64(x, A.device).reshape(-1, d).contiguous()
+    y = _dev_f64(y, A.device).reshape(-1, d).contiguous()
+    nu_h, n_nu = _host_f64(nu)
+    out = torch.empty((n_nu, x.shape[0], y.shape[0], 2), dtype=torch.float64, device=A.device)
+    bound = torch.empty((n_nu, x.shape[0]), dtype=torch.float64, device=A.device) if with_bound else None
+    st = torch.zeros(1, dtype=torch.int32, device=A.device)
+    check(lib().ez_epstein_grid(d, _dptr(A), n_nu, nu_h, x.shape[0], _dptr(x), y.shape[0], _dptr(y), float(lam),
+                                float(a_cut), PREC_MIXED if mixed else PREC_FP64, _dptr(out),
+                                _dptr(bound) if with_bound else None, _dptr(st), _stream_ptr(A.device)))
+    z = torch.view_as_complex(out)
+    ret = (z,)
+    if with_bound:
+        ret = ret + (bound,)
+    if with_status:
+        ret = ret + (st,)
+    return ret if len(ret) > 1 else ret[0]
 
 
 def nbody_lattice_sum(A, nu: Sequence[float], spec=None, with_status=False):

@@ -26,10 +26,11 @@ def spec_bpc(n: int) -> int:
     return (int(n) & 0xFF) << 8
 
 # every symbol declared in include/ezeta.h
-EXPORTED = ("ez_epstein_zeta", "ez_nbody_lattice_sum", "ez_atm_energy", "ez_lattice_sums", "ez_lattice_sums_grad",
+EXPORTED = ("ez_epstein_zeta", "ez_epstein_grid", "ez_nbody_lattice_sum", "ez_atm_energy", "ez_lattice_sums", "ez_lattice_sums_grad",
             "ez_timing_enable", "ez_timing_reset", "ez_timing_read",
             "ez_last_error", "ez_finalize", "ez_version")
-KERNEL_SETUP, KERNEL_NODES, KERNEL_HADAMARD, KERNEL_FINALIZE, KERNEL_EPSTEIN, KERNEL_NODES_ADJ = 0, 1, 2, 3, 4, 5
+KERNEL_SETUP, KERNEL_NODES, KERNEL_HADAMARD, KERNEL_FINALIZE, KERNEL_EPSTEIN, KERNEL_NODES_ADJ, KERNEL_GRID = (
+    0, 1, 2, 3, 4, 5, 6)
 
 
 class EzError(RuntimeError):
@@ -66,6 +67,8 @@ def lib():
     I64 = ctypes.c_int64
     L.ez_epstein_zeta.restype = I
     L.ez_epstein_zeta.argtypes = [I, VP, I, P, I64, VP, VP, D, D, VP, VP, VP]
+    L.ez_epstein_grid.restype = I
+    L.ez_epstein_grid.argtypes = [I, VP, I, P, I, VP, I, VP, D, D, I, VP, VP, VP, VP]
     L.ez_nbody_lattice_sum.restype = I
     L.ez_nbody_lattice_sum.argtypes = [I, I, VP, I, P, ctypes.POINTER(QuadSpec), VP, VP, VP]
     L.ez_atm_energy.restype = I

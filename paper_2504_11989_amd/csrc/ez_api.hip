@@ -14,6 +14,7 @@
 #include "../../include/ezeta.h"
 #include "ez_internal.h"
 #include "ez_kernels.h"
+#include "ez_grid.h"
 
 namespace {
 
@@ -147,6 +148,9 @@ struct DeviceState {
     DevBuf meta, real, rn, rows, rec, tile_part, dir_part, dir_flag, probe_val, tensor, tile_grad, dir_grad;
     DevBuf gmeta, greal, grec;   // general-x Epstein tables
     DevBuf queue;                // work-queue position of the persistent node kernel
+    // Epstein grid workspace
+    DevBuf g_pts_x, g_pts_y, g_perm, g_counts, g_A64r, g_B64r, g_A64k, g_B64k, g_R, g_Q, g_wsum, g_stat;
+    DevBuf g_Ahr, g_Alr, g_Bhr, g_Blr, g_Ahk, g_Alk, g_Bhk, g_Blk;
     int n_cu = 0;
     hipStream_t side = nullptr;  // second stream: Hadamard branch concurrent with the nodes
     hipEvent_t ev_setup = nullptr, ev_had = nullptr;
@@ -660,6 +664,48 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     return EZ_OK;
 }
 
+// tables of one lattice for general shifts x (every z, every m*, no weights)
+ez_status general_setup(DeviceState *S, int d, const double *A_dev, double lam, double a_cut, uint32_t *status_dev,
+                        hipStream_t s, EzTables *tab_out) {
+    EzProgram prog;
+    std::memset(&prog, 0, sizeof(prog));
+    prog.d = d;
+    prog.n_nu = 0;   // general-x tables carry no weights
+    EzTables tab;
+    tab.real_cap = real_capacity(d, lam, a_cut, true);
+    tab.rec_cap = rec_capacity(d, lam, a_cut);
+    tab.rstride = 4;
+    tab.row_cap = 0;
+    tab.rn = nullptr;
+    tab.rows = nullptr;
+    ez_status st;
+    if ((st = grow(S->gmeta, sizeof(EzLatMeta))) ||
+        (st = grow(S->greal, sizeof(double) * (size_t)tab.real_cap * tab.rstride)) ||
+        (st = grow(S->grec, sizeof(double) * (size_t)tab.rec_cap * 4)))
+        return st;
+    tab.real = (double *)S->greal.p;
+    tab.rec = (double *)S->grec.p;
+    // a one-lattice plan carrying lam
+    ez_quad_spec sp;
+    std::memset(&sp, 0, sizeof(sp));
+    sp.n_q = 1; sp.n_panels = 1; sp.n_g = 1; sp.ell = 0; sp.eps = 0.01; sp.lam = lam; sp.a_cut = a_cut;
+    DevPlan *P = nullptr;
+    if ((st = get_plan(S, d, 1, &sp, 1, 256, &P))) return st;
+    EzSetupArgs sa;
+    sa.prog = prog;
+    sa.A = A_dev;
+    sa.plans = (const EzInstPlan *)P->plans.p;
+    sa.meta = (EzLatMeta *)S->gmeta.p;
+    sa.tab = tab;
+    sa.a_cut = a_cut;
+    sa.general_x = 1;
+    sa.grad = 0;
+    sa.status_out = status_dev;
+    EZ_HIP_TRY(timed(EZ_KERNEL_SETUP, s, [&] { return ez_launch_setup(sa, 1, s); }));
+    *tab_out = tab;
+    return EZ_OK;
+}
+
 ez_status check_common(int batch, int d, const double *A_dev, const ez_quad_spec *spec, const void *out) {
     if (d < 1 || d > 3) return fail(EZ_ERR_INVALID_ARG, "d must be 1, 2 or 3");
     if (batch < 1) return fail(EZ_ERR_INVALID_ARG, "batch must be >= 1");
@@ -687,6 +733,10 @@ ez_status ez_finalize(void) {
         free_buf(S->meta); free_buf(S->real); free_buf(S->rec); free_buf(S->rn); free_buf(S->rows);
         free_buf(S->tile_part); free_buf(S->dir_part); free_buf(S->dir_flag); free_buf(S->probe_val); free_buf(S->tensor);
         free_buf(S->tile_grad); free_buf(S->dir_grad); free_buf(S->queue);
+        for (DevBuf *b : {&S->g_pts_x, &S->g_pts_y, &S->g_perm, &S->g_counts, &S->g_A64r, &S->g_B64r, &S->g_A64k,
+                          &S->g_B64k, &S->g_R, &S->g_Q, &S->g_wsum, &S->g_stat, &S->g_Ahr, &S->g_Alr, &S->g_Bhr,
+                          &S->g_Blr, &S->g_Ahk, &S->g_Alk, &S->g_Bhk, &S->g_Blk})
+            free_buf(*b);
         if (S->side) {
             (void)hipStreamSynchronize(S->side);
             (void)hipStreamDestroy(S->side);
@@ -803,41 +853,9 @@ ez_status ez_epstein_zeta(int d, const double *A_dev, int n_nu, const double *nu
     EZ_HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lock(g_mu);
     DeviceState *S = device_state(dev);
-    EzProgram prog;
-    std::memset(&prog, 0, sizeof(prog));
-    prog.d = d;
-    prog.n_nu = 0;   // general-x tables carry no weights
     EzTables tab;
-    tab.real_cap = real_capacity(d, lam, a_cut, true);
-    tab.rec_cap = rec_capacity(d, lam, a_cut);
-    tab.rstride = 4;
-    tab.row_cap = 0;
-    tab.rn = nullptr;
-    tab.rows = nullptr;
-    ez_status st;
-    if ((st = grow(S->gmeta, sizeof(EzLatMeta))) ||
-        (st = grow(S->greal, sizeof(double) * (size_t)tab.real_cap * tab.rstride)) ||
-        (st = grow(S->grec, sizeof(double) * (size_t)tab.rec_cap * 4)))
-        return st;
-    tab.real = (double *)S->greal.p;
-    tab.rec = (double *)S->grec.p;
-    // a one-lattice plan carrying lam
-    ez_quad_spec sp;
-    std::memset(&sp, 0, sizeof(sp));
-    sp.n_q = 1; sp.n_panels = 1; sp.n_g = 1; sp.ell = 0; sp.eps = 0.01; sp.lam = lam; sp.a_cut = a_cut;
-    DevPlan *P = nullptr;
-    if ((st = get_plan(S, d, 1, &sp, 1, 256, &P))) return st;
-    EzSetupArgs sa;
-    sa.prog = prog;
-    sa.A = A_dev;
-    sa.plans = (const EzInstPlan *)P->plans.p;
-    sa.meta = (EzLatMeta *)S->gmeta.p;
-    sa.tab = tab;
-    sa.a_cut = a_cut;
-    sa.general_x = 1;
-    sa.grad = 0;
-    sa.status_out = status_dev;
-    EZ_HIP_TRY(timed(EZ_KERNEL_SETUP, s, [&] { return ez_launch_setup(sa, 1, s); }));
+    ez_status st = general_setup(S, d, A_dev, lam, a_cut, status_dev, s, &tab);
+    if (st) return st;
     EzEpsteinArgs ea;
     std::memset(&ea, 0, sizeof(ea));
     ea.d = d;
@@ -851,6 +869,111 @@ ez_status ez_epstein_zeta(int d, const double *A_dev, int n_nu, const double *nu
     ea.out = out_dev;
     ea.status = status_dev;
     EZ_HIP_TRY(timed(EZ_KERNEL_EPSTEIN, s, [&] { return ez_launch_epstein(ea, s); }));
+    return EZ_OK;
+}
+
+ez_status ez_epstein_grid(int d, const double *A_dev, int n_nu, const double *nu_host, int n_x, const double *x_dev,
+                          int n_y, const double *y_dev, double lam, double a_cut, int precision, double *out_dev,
+                          double *bound_dev, uint32_t *status_dev, void *stream) {
+    if (d < 1 || d > 3) return fail(EZ_ERR_INVALID_ARG, "d must be 1, 2 or 3");
+    if (!A_dev || !nu_host || !x_dev || !y_dev || !out_dev) return fail(EZ_ERR_INVALID_ARG, "null pointer argument");
+    if (n_nu < 1 || n_nu > EZ_NU_MAX) return fail(EZ_ERR_INVALID_ARG, "n_nu must be in [1, 8]");
+    if (n_x < 1 || n_y < 1 || n_x > (1 << 16) || n_y > (1 << 22))
+        return fail(EZ_ERR_INVALID_ARG, "need 1 <= n_x <= 65536 and 1 <= n_y <= 4194304");
+    if (precision != EZ_PREC_FP64 && precision != EZ_PREC_MIXED)
+        return fail(EZ_ERR_INVALID_ARG, "precision must be EZ_PREC_FP64 or EZ_PREC_MIXED");
+    if (!(lam >= 0.0 && lam <= 8.0) || !(a_cut >= 0.0 && a_cut <= 200.0))
+        return fail(EZ_ERR_INVALID_ARG, "lam in [0, 8], a_cut in [0, 200]");
+    for (int i = 0; i < n_nu; ++i)
+        if (!std::isfinite(nu_host[i]) || std::fabs(nu_host[i]) > 64.0)
+            return fail(EZ_ERR_INVALID_ARG, "nu must be finite, |nu| <= 64");
+    if (lam == 0.0) lam = 1.0;
+    if (a_cut == 0.0) a_cut = 36.0;
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    EZ_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_mu);
+    DeviceState *S = device_state(dev);
+    ez_status st;
+    if ((st = grow(S->g_stat, 256))) return st;
+    uint32_t *stat = status_dev ? status_dev : (uint32_t *)S->g_stat.p;
+    EzTables tab;
+    if ((st = general_setup(S, d, A_dev, lam, a_cut, stat, s, &tab))) return st;
+    // table sizes size the products: one read-back after the setup
+    EzLatMeta meta;
+    EZ_HIP_TRY(hipMemcpyAsync(&meta, S->gmeta.p, sizeof(EzLatMeta), hipMemcpyDeviceToHost, s));
+    EZ_HIP_TRY(hipStreamSynchronize(s));
+    const int nr = meta.status ? 0 : meta.n_real, nk = meta.status ? 0 : meta.n_rec;
+    EzGridArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.d = d;
+    g.n_nu = n_nu;
+    for (int i = 0; i < n_nu; ++i) g.nu[i] = nu_host[i];
+    g.n_x = n_x;
+    g.n_y = n_y;
+    g.Mp = (n_x + 127) / 128 * 128;
+    g.Np = (n_y + 127) / 128 * 128;
+    g.Kr_pad = (nr + 31) / 32 * 32 + 32;
+    g.Kk_pad = (nk + 31) / 32 * 32 + 32;
+    g.Krn_pad = g.Krf_pad = g.Kr_pad;
+    g.Kkn_pad = g.Kkf_pad = g.Kk_pad;
+    g.mixed = precision == EZ_PREC_MIXED ? 1 : 0;
+    g.a_near = 18.0;
+    g.ladder = 1;
+    for (int i = 0; i < n_nu; ++i) {
+        const double p2 = nu_host[i] - d + 2.0;
+        if (p2 != std::floor(p2) || std::fabs(p2) > 64.0) g.ladder = 0;
+        g.p2[i] = g.ladder ? (int)p2 : 0;
+    }
+    g.meta = (const EzLatMeta *)S->gmeta.p;
+    g.tab = tab;
+    g.x = x_dev;
+    g.y = y_dev;
+    const size_t Mp = g.Mp, Np = g.Np, Kr = g.Kr_pad, Kk = g.Kk_pad, nn = n_nu;
+    if ((st = grow(S->g_pts_x, sizeof(double) * 8 * (size_t)n_x)) ||
+        (st = grow(S->g_pts_y, sizeof(double) * 4 * (size_t)n_y)) ||
+        (st = grow(S->g_perm, sizeof(int) * (Kr + Kk))) ||
+        (st = grow(S->g_counts, sizeof(int) * 8 + sizeof(double) * EZ_NU_MAX)) ||
+        (st = grow(S->g_A64r, sizeof(double) * nn * Mp * Kr)) ||
+        (st = grow(S->g_B64r, sizeof(double) * Kr * 2 * Np)) ||
+        (st = grow(S->g_A64k, sizeof(double) * 2 * Mp * Kk)) ||
+        (st = grow(S->g_B64k, sizeof(double) * Kk * nn * Np)) ||
+        (st = grow(S->g_R, sizeof(double) * nn * Mp * 2 * Np)) ||
+        (st = grow(S->g_Q, sizeof(double) * 2 * Mp * nn * Np)) ||
+        (st = grow(S->g_wsum, sizeof(double) * 2 * (nn * Mp + nn * Kk))))
+        return st;
+    if (g.mixed &&
+        ((st = grow(S->g_Ahr, 2 * nn * Mp * Kr)) || (st = grow(S->g_Alr, 2 * nn * Mp * Kr)) ||
+         (st = grow(S->g_Bhr, 2 * 2 * Np * Kr)) || (st = grow(S->g_Blr, 2 * 2 * Np * Kr)) ||
+         (st = grow(S->g_Ahk, 2 * 2 * Mp * Kk)) || (st = grow(S->g_Alk, 2 * 2 * Mp * Kk)) ||
+         (st = grow(S->g_Bhk, 2 * nn * Np * Kk)) || (st = grow(S->g_Blk, 2 * nn * Np * Kk))))
+        return st;
+    g.pts_x = (double *)S->g_pts_x.p;
+    g.pts_y = (double *)S->g_pts_y.p;
+    g.perm_real = (int *)S->g_perm.p;
+    g.perm_rec = g.perm_real + Kr;
+    g.counts = (int *)S->g_counts.p;
+    g.kpref = (double *)(g.counts + 8);
+    g.A64r = (double *)S->g_A64r.p;
+    g.B64r = (double *)S->g_B64r.p;
+    g.A64k = (double *)S->g_A64k.p;
+    g.B64k = (double *)S->g_B64k.p;
+    g.R = (double *)S->g_R.p;
+    g.Q = (double *)S->g_Q.p;
+    g.wsum = (double *)S->g_wsum.p;
+    g.gmax = g.wsum + nn * Mp;
+    g.wall = g.gmax + nn * Kk;
+    g.gall = g.wall + nn * Mp;
+    if (g.mixed) {
+        g.Ahr = (__bf16 *)S->g_Ahr.p; g.Alr = (__bf16 *)S->g_Alr.p;
+        g.Bhr = (__bf16 *)S->g_Bhr.p; g.Blr = (__bf16 *)S->g_Blr.p;
+        g.Ahk = (__bf16 *)S->g_Ahk.p; g.Alk = (__bf16 *)S->g_Alk.p;
+        g.Bhk = (__bf16 *)S->g_Bhk.p; g.Blk = (__bf16 *)S->g_Blk.p;
+    }
+    g.out = out_dev;
+    g.bound = bound_dev;
+    g.status_acc = stat;
+    EZ_HIP_TRY(timed(EZ_KERNEL_GRID, s, [&] { return ez_grid_launch(g, s); }));
     return EZ_OK;
 }
 

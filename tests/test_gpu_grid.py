@@ -1,0 +1,86 @@
+"""GPU: Epstein zeta on (shift x point) grids through the matrix-product kernels,
+FP64 and mixed precision, against the oracle and the pointwise GPU kernel."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+NU = [-1.0, 1.0, 3.0, 5.0]
+
+
+@pytest.fixture(scope="module")
+def ez():
+    import paper_2504_11989_amd as ez
+    ez.version()
+    return ez
+
+
+def close(a, b, tol):
+    return np.abs(a - b) <= tol * np.maximum(np.abs(b), 1.0)
+
+
+@pytest.mark.parametrize("name", ["sc", "fcc", "bcc"])
+def test_grid_fp64_vs_oracle(ez, name):
+    A = W.c2_lattices()[name]
+    xs = W.c4_shifts(A, count=70)
+    ys = W.c4_points(A, count=200)
+    z = ez.epstein_grid(A, NU, xs, ys).cpu().numpy()
+    rng = np.random.default_rng(11)
+    for _ in range(24):
+        j, m = int(rng.integers(70)), int(rng.integers(200))
+        for k, nu in enumerate(NU):
+            ref = O.epstein(A, nu, xs[j], ys[m])
+            assert abs(z[k, j, m] - ref) <= 1e-12 * max(abs(ref), 1.0), (name, j, m, nu, z[k, j, m], ref)
+
+
+def test_grid_matches_pointwise_kernel_everywhere(ez):
+    A = W.c2_lattices()["fcc"]
+    xs = W.c4_shifts(A, count=65)
+    ys = W.c4_points(A, count=130)
+    z = ez.epstein_grid(A, NU, xs, ys).cpu().numpy()
+    X = np.repeat(xs, len(ys), axis=0)
+    Y = np.tile(ys, (len(xs), 1))
+    p = ez.epstein_zeta(A, NU, X, Y).cpu().numpy().reshape(len(NU), len(xs), len(ys))
+    assert np.all(close(z, p, 1e-12))
+
+
+def test_grid_lattice_points_and_shifted_cells(ez):
+    """x on the lattice (self term), x outside the cell (quasi-periodicity), y on the
+    reciprocal lattice (continuation at m* + y = 0 for nu > d)"""
+    A = W.c2_lattices()["bcc"]
+    B = np.linalg.inv(A).T
+    xs = np.stack([np.zeros(3), A[:, 0], A @ np.array([0.3, -1.2, 2.7]), A @ np.array([0.5, 0.5, 0.5])])
+    ys = np.stack([np.zeros(3), B[:, 1], B @ np.array([0.2, 0.1, -0.4]), B @ np.array([1.3, -0.25, 0.0])])
+    z = ez.epstein_grid(A, [5.0, 6.5], xs, ys).cpu().numpy()
+    for j in range(4):
+        for m in range(4):
+            for k, nu in enumerate([5.0, 6.5]):
+                ref = O.epstein(A, nu, xs[j], ys[m])
+                assert abs(z[k, j, m] - ref) <= 1e-12 * max(abs(ref), 1.0), (j, m, nu)
+
+
+def test_grid_pole_flag(ez):
+    A = W.c2_lattices()["sc"]
+    z, st = ez.epstein_grid(A, [3.0], np.array([[0.1, 0.2, 0.3]]), np.zeros((1, 3)), with_status=True)
+    assert st.item() & 0x10
+    assert np.isnan(z.cpu().numpy()).all()
+
+
+@pytest.mark.parametrize("name", ["sc", "fcc", "bcc"])
+def test_grid_mixed_within_bound_and_1e10(ez, name):
+    A = W.c2_lattices()[name]
+    xs = W.c4_shifts(A, count=128)
+    ys = W.c4_points(A, count=512)
+    z64 = ez.epstein_grid(A, NU, xs, ys).cpu().numpy()
+    zm, bound = ez.epstein_grid(A, NU, xs, ys, mixed=True, with_bound=True)
+    zm, bound = zm.cpu().numpy(), bound.cpu().numpy()
+    diff = np.abs(zm - z64)
+    # the a-priori bound holds for every element of its row
+    assert np.all(diff.max(axis=2) <= bound), (diff.max(axis=2) / bound).max()
+    # relative error against the FP64 values, normalised by max(|Z|, 1)
+    rel = diff / np.maximum(np.abs(z64), 1.0)
+    assert rel.max() <= 1e-10, rel.max()

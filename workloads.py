@@ -116,6 +116,13 @@ def c4_shifts(A: np.ndarray, seed: int = 4, count: int = 512) -> np.ndarray:
     return t @ np.asarray(A).T
 
 
+def c4_points(A: np.ndarray, seed: int = 40, count: int = 8192) -> np.ndarray:
+    """Points of the reciprocal cell y = A^{-T} s, s ~ U[-1/2,1/2)^d (rows are points)."""
+    rng = np.random.default_rng(seed)
+    s = rng.random((count, A.shape[0])) - 0.5
+    return s @ np.linalg.inv(np.asarray(A))
+
+
 def c5_perturbed(seed: int = 5, count: int = 64):
     """Generator matrices with entries perturbed by up to +-10% from unit-density fcc / bcc."""
     rng = np.random.default_rng(seed)
