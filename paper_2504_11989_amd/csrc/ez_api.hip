@@ -564,6 +564,8 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     EzTables tab;
     tab.real_cap = real_capacity(d, lam_max, acut, false);
     tab.rec_cap = rec_capacity(d, lam_min, acut);
+    if (tab.rec_cap > EZ_KCULL)
+        return fail(EZ_ERR_UNSUPPORTED, "reciprocal table too large for this lam and a_cut (raise spec.lam)");
     tab.rstride = 4 * ((3 + (grad ? 2 : 1) * prog.n_nu + 3) / 4);
     tab.row_cap = tab.real_cap;
     if ((st = grow(S->meta, sizeof(EzLatMeta) * batch)) ||

@@ -12,6 +12,7 @@
 #define EZ_TILE 256      // quadrature nodes per workgroup of the node kernel
 #define EZ_TDIM 525      // monomials of even degree <= 2 EZ_ELL_MAX in 3 variables
 #define EZ_HDIR 64       // quadrature directions per workgroup of the Hadamard direction kernel
+#define EZ_KCULL 8192    // reciprocal table capacity per lattice in the quadrature (node tiles list it in LDS)
 #define EZ_SLICE_MAX 8   // table slices of the probe kernel
 #define EZ_GRAD_RES_MAX 2  // results per call when strain derivatives are requested
 #define EZ_HDIR_GRAD 16  // directions per workgroup of the Hadamard adjoint kernel

@@ -24,9 +24,18 @@ __device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile
 #pragma unroll
     for (int r = 0; r < EZ_RES_MAX; ++r) res[r] = 0.0;
 
-    if (M->status == 0 && node < n_nodes) {
-        const int dir = node / P.n_u;
-        const int iu = node - dir * P.n_u;
+    // reciprocal entries this tile needs, in table order (see below)
+    __shared__ unsigned short klist[EZ_KCULL];
+    __shared__ double kbox[EZ_TILE / 64][6];
+    __shared__ int kwave[EZ_TILE / 64];
+    __shared__ int kcount;
+
+    if (M->status == 0) {                         // uniform over the workgroup
+        const bool valid = node < n_nodes;
+        // threads past the last node take the tile's first node (geometry only)
+        const int nd = valid ? node : (tile - args.tile_begin[inst]) * EZ_TILE;
+        const int dir = nd / P.n_u;
+        const int iu = nd - dir * P.n_u;
         double B[D * D];
 #pragma unroll
         for (int i = 0; i < D * D; ++i) B[i] = M->B[i];
@@ -45,11 +54,72 @@ __device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile
 #pragma unroll
         for (int i = 0; i < NNU; ++i) { accr[i] = 0.0; acck[i] = 0.0; }
 
+        const double *kt = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
+        const int n_rec = M->n_rec;
+        const double alpha = M->alpha, acut = M->a_cut;
+        // The table covers every node of the cell; a tile needs only the entries
+        // within the cutoff radius of some of its nodes.  With c and r_t the centre
+        // and half-diagonal of the bounding box of the tile's k, an entry with
+        // |m* + c| > sqrt(a_cut / alpha) + r_t is beyond the cutoff for every node
+        // of the tile.  The others are listed in table order (so each node adds the
+        // same nonzero terms in the same order as over the whole table); the host
+        // keeps the table capacity within the list (EZ_KCULL entries).
+        {
+            const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+            double bl[3] = {k[0], k[1], k[2]}, bh[3] = {k[0], k[1], k[2]};
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int m = 32; m >= 1; m >>= 1) {
+                    bl[i] = fmin(bl[i], __shfl_xor(bl[i], m, 64));
+                    bh[i] = fmax(bh[i], __shfl_xor(bh[i], m, 64));
+                }
+            if (lane == 0)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) { kbox[wave][i] = bl[i]; kbox[wave][3 + i] = bh[i]; }
+            if (threadIdx.x == 0) kcount = 0;
+            __syncthreads();
+            double c[3] = {0.0, 0.0, 0.0}, rt2 = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                double lo = kbox[0][i], hi = kbox[0][3 + i];
+                for (int w2 = 1; w2 < EZ_TILE / 64; ++w2) { lo = fmin(lo, kbox[w2][i]); hi = fmax(hi, kbox[w2][3 + i]); }
+                c[i] = 0.5 * (lo + hi);
+                rt2 += 0.25 * (hi - lo) * (hi - lo);
+            }
+            const double rmax = (sqrt(acut / alpha) + sqrt(rt2)) * (1.0 + 1e-9) + 1e-12;
+            for (int base = 1; base < n_rec; base += EZ_TILE) {
+                const int q = base + (int)threadIdx.x;
+                bool keep = false;
+                if (q < n_rec) {
+                    const double *e = kt + (size_t)q * 4;
+                    double d2 = 0.0;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) { const double t = e[i] + c[i]; d2 = fma(t, t, d2); }
+                    keep = d2 <= rmax * rmax;
+                }
+                const unsigned long long bal = __ballot(keep);
+                const int before = __popcll(bal & ((1ull << lane) - 1ull));
+                if (lane == 0) kwave[wave] = __popcll(bal);
+                __syncthreads();
+                int off = kcount;
+                for (int w2 = 0; w2 < wave; ++w2) off += kwave[w2];
+                if (keep) klist[off + before] = (unsigned short)q;   // q < n_rec <= rec_cap <= EZ_KCULL
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    int tot = 0;
+                    for (int w2 = 0; w2 < EZ_TILE / 64; ++w2) tot += kwave[w2];
+                    kcount += tot;
+                }
+                __syncthreads();
+            }
+        }
+
         // real space: sum over pairs of 2 W_nu(z) Re e^{2 pi i k.z}, k.z = theta.n with
         // theta = A^T k = u w_hat.  Row by row (n2, n3 fixed, consecutive n1) the phase
         // advances by c1 = e^{2 pi i theta_1}; from row to row within a plane by
         // c2^{dn2} c1^{dn1}; each plane starts from one sincos.
-        {
+        if (valid) {
             const int rs = args.tab.rstride;
             const double *rt = args.tab.real + (size_t)inst * args.tab.real_cap * rs;
             const int *rows = args.tab.rows + (size_t)inst * args.tab.row_cap * 8;
@@ -91,11 +161,8 @@ __device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile
         // m* = 0, where a = alpha |k|^2 can be small (series of E1); every other entry
         // has a >= alpha / (4 |A|_F^2) >= 1/4 (the setup raises lam to ensure it), so the
         // main loop is one branch-free formula with E1 from the wide rational.
-        const double *kt = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
-        const int n_rec = M->n_rec;
-        const double alpha = M->alpha, acut = M->a_cut;
         const bool need_e1 = pset_need_e1<SET, NNU>(args.prog), need_half = pset_need_half<SET, NNU>(args.prog);
-        {
+        if (valid) {
             double rho = k[0] * k[0];
             if (D > 1) rho = fma(k[1], k[1], rho);
             if (D > 2) rho = fma(k[2], k[2], rho);
@@ -111,7 +178,7 @@ __device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile
                     acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
             }
         }
-        for (int q = 1; q < n_rec; ++q) {
+        auto rec_term = [&](int q) {
             const double *e = kt + (size_t)q * 4;
             double qx = e[0] + k[0];
             double rho = qx * qx;
@@ -127,28 +194,32 @@ __device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile
                 for (int i = 0; i < NNU; ++i)
                     acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
             }
-        }
+        };
+        if (valid) {
+            const int nk = kcount;
+            for (int j = 0; j < nk; ++j) rec_term(__builtin_amdgcn_readfirstlane((int)klist[j]));
 
-        double Z[NNU];
+            double Z[NNU];
 #pragma unroll
-        for (int i = 0; i < NNU; ++i) Z[i] = accr[i] + M->K[i] * acck[i] - M->self_[i];
+            for (int i = 0; i < NNU; ++i) Z[i] = accr[i] + M->K[i] * acck[i] - M->self_[i];
 
-        for (int t = 0; t < args.prog.n_terms; ++t) {
-            double prod = args.prog.term_coef[t];
-            for (int f = 0; f < args.prog.term_nfac[t]; ++f) {
-                const int fi = args.prog.term_fac[t][f];
-                double z = Z[0];
+            for (int t = 0; t < args.prog.n_terms; ++t) {
+                double prod = args.prog.term_coef[t];
+                for (int f = 0; f < args.prog.term_nfac[t]; ++f) {
+                    const int fi = args.prog.term_fac[t][f];
+                    double z = Z[0];
 #pragma unroll
-                for (int i = 1; i < NNU; ++i) z = (fi == i) ? Z[i] : z;
-                for (int m = 0; m < args.prog.term_mult[t][f]; ++m) prod *= z;
+                    for (int i = 1; i < NNU; ++i) z = (fi == i) ? Z[i] : z;
+                    for (int m = 0; m < args.prog.term_mult[t][f]; ++m) prod *= z;
+                }
+                const int rr = args.prog.term_res[t];
+#pragma unroll
+                for (int r = 0; r < EZ_RES_MAX; ++r)
+                    if (rr == r) res[r] += prod;
             }
-            const int rr = args.prog.term_res[t];
 #pragma unroll
-            for (int r = 0; r < EZ_RES_MAX; ++r)
-                if (rr == r) res[r] += prod;
+            for (int r = 0; r < EZ_RES_MAX; ++r) res[r] *= W;
         }
-#pragma unroll
-        for (int r = 0; r < EZ_RES_MAX; ++r) res[r] *= W;
     }
 
     // tile reduction: wave butterflies, then the four waves in fixed order
