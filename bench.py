@@ -263,6 +263,8 @@ def main() -> int:
     torch.cuda.synchronize()
     nat.timing_enable(False)
     kt = {k: nat.timing_read(i) for k, i in [("setup", nat.KERNEL_SETUP), ("nodes", nat.KERNEL_NODES),
+                                              ("nodes_tail", nat.KERNEL_NODES_TAIL),
+                                              ("taylor", nat.KERNEL_TAYLOR),
                                               ("hadamard", nat.KERNEL_HADAMARD),
                                               ("finalize", nat.KERNEL_FINALIZE)]}
 
@@ -293,7 +295,9 @@ def main() -> int:
     sums_per_s = len(names) * args.steps / elapsed
     evals_per_s = len(names) * nodes * n_nu * args.steps / elapsed
 
-    node_ms = kt["nodes"][0] / max(1, kt["nodes"][1])
+    # node stage: the tile kernel plus, when the tile count passes a multiple of a
+    # round of workgroups by a little, the split kernel that takes the last tiles
+    node_ms = kt["nodes"][0] / max(1, kt["nodes"][1]) + kt["nodes_tail"][0] / max(1, kt["nodes"][1])
     flops_launch = node_kernel_flops_per_node(spec["lam"], spec["a_cut"], n_nu) * nodes * len(names)
     achieved = flops_launch / (node_ms * 1e-3) / 1e12
     traffic = None
@@ -303,7 +307,9 @@ def main() -> int:
             traffic = tr["bytes_per_launch"]
     roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP64_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_VALU_TFLOPS, 5), "traffic": traffic,
-                "kernel": "ez_node_kernel<3,4>", "kernel_ms": round(node_ms, 5),
+                "kernel": "ez_node_kernel<3,4,1>" + (" + ez_node_split_kernel<3,4,1> (last tiles)"
+                                                     if kt["nodes_tail"][1] else ""),
+                "kernel_ms": round(node_ms, 5),
                 "flops_per_launch": flops_launch}
 
     line = {

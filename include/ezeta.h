@@ -17,7 +17,8 @@
  *  - Argument errors are detected on the host before any launch and returned
  *    as ez_status; per-lattice problems found on the device (singular or
  *    too-skewed lattice, non-finite result) set bits in status_dev[i] and
- *    write NaN to that lattice's results without failing the batch.
+ *    write NaN to that lattice's results without failing the batch.  Every
+ *    status_dev entry is written by the call (no zeroing needed beforehand).
  *  - Calls that overlap on one device are serialised by the caller's stream
  *    order; the library workspace is shared per device, so concurrent calls
  *    from different host threads on one device must use one stream.
@@ -78,9 +79,17 @@ typedef struct ez_quad_spec {
  *                       tiles from a work queue, costliest tiles first
  *  EZ_SPEC_SERIAL     : the Taylor/Hadamard branch runs on the caller's stream
  *                       after the nodes instead of concurrently on a second stream
- *  EZ_SPEC_BPC(n)     : persistent workgroups per CU (0: as many as fit) */
+ *  EZ_SPEC_BPC(n)     : persistent workgroups per CU (0: as many as fit)
+ *  EZ_SPEC_NO_SPLIT   : value calls hand the last node tiles, when they would
+ *                       fill at most a quarter of a round of workgroups over the
+ *                       device, to a kernel that shares each node's terms among
+ *                       16 waves on four CUs; this flag keeps every tile in the
+ *                       tile kernel (the split changes the order in which a
+ *                       node's terms are added, so the two agree to rounding,
+ *                       not bit for bit) */
 #define EZ_SPEC_PERSISTENT 0x1
 #define EZ_SPEC_SERIAL 0x2
+#define EZ_SPEC_NO_SPLIT 0x4
 #define EZ_SPEC_BPC(n) (((n) & 0xFF) << 8)
 
 /* Epstein zeta Z_{Lambda,nu}(x, y) = sum'_{z in Lambda} e^{-2 pi i y.z} |z - x|^{-nu},
@@ -188,12 +197,14 @@ ez_status ez_lattice_sums_grad(int batch, int d, const double *A_dev, int n_nu, 
  * launch count of one kernel kind.  Costs two event records per launch. */
 #define EZ_KERNEL_SETUP 0      /* per-lattice tables                    */
 #define EZ_KERNEL_NODES 1      /* quadrature nodes on (eps, 1/2]         */
-#define EZ_KERNEL_HADAMARD 2   /* Taylor / Hadamard part on (0, eps)     */
+#define EZ_KERNEL_HADAMARD 2   /* Hadamard part on (0, eps), directions  */
 #define EZ_KERNEL_FINALIZE 3   /* fixed-order reduction                  */
 #define EZ_KERNEL_EPSTEIN 4    /* Z(x, y) at arbitrary points            */
 #define EZ_KERNEL_NODES_ADJ 5  /* quadrature nodes with the adjoint pass  */
 #define EZ_KERNEL_GRID 6       /* Z on a (shift x point) grid            */
-#define EZ_KERNEL_COUNT 7
+#define EZ_KERNEL_NODES_TAIL 7 /* last node tiles, terms split over waves */
+#define EZ_KERNEL_TAYLOR 8     /* probe values and Taylor tensors          */
+#define EZ_KERNEL_COUNT 9
 ez_status ez_timing_enable(int enable);
 ez_status ez_timing_reset(void);
 ez_status ez_timing_read(int kernel, double *total_ms, int64_t *launches);

@@ -131,7 +131,7 @@ def nbody_lattice_sum(A, nu: Sequence[float], spec=None, with_status=False):
     nu_h, n = _host_f64(nu)
     sp = _spec(spec)
     out = torch.empty(b, dtype=torch.float64, device=A.device)
-    st = torch.zeros(b, dtype=torch.int32, device=A.device)
+    st = torch.empty(b, dtype=torch.int32, device=A.device)
     check(lib().ez_nbody_lattice_sum(b, d, _dptr(A), n, nu_h, ctypes.byref(sp), _dptr(out), _dptr(st),
                                      _stream_ptr(A.device)))
     return (out, st) if with_status else out
@@ -144,7 +144,7 @@ def atm_energy(A, spec=None, with_status=False, grad=False):
     A, b, d = _lattices(A)
     sp = _spec(spec)
     out = torch.empty(b, dtype=torch.float64, device=A.device)
-    st = torch.zeros(b, dtype=torch.int32, device=A.device)
+    st = torch.empty(b, dtype=torch.int32, device=A.device)
     g = torch.empty((b, d, d), dtype=torch.float64, device=A.device) if grad else None
     check(lib().ez_atm_energy(b, d, _dptr(A), ctypes.byref(sp), _dptr(out), _dptr(g) if grad else None,
                               _dptr(st), _stream_ptr(A.device)))
@@ -194,7 +194,7 @@ def lattice_sums(A, nu: Sequence[float], terms: Iterable, n_results: int, specs=
     elif out.shape != (b, n_results) or out.dtype != torch.float64 or not out.is_contiguous():
         raise ValueError("out must be a contiguous float64 tensor of shape (batch, n_results)")
     if status is None:
-        st = torch.zeros(b, dtype=torch.int32, device=A.device)
+        st = torch.empty(b, dtype=torch.int32, device=A.device)
     elif status.shape != (b,) or status.dtype != torch.int32:
         raise ValueError("status must be an int32 tensor of shape (batch,)")
     else:

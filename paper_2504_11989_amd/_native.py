@@ -18,7 +18,7 @@ STATUS_NAMES = {0: "EZ_OK", 1: "EZ_ERR_INVALID_ARG", 2: "EZ_ERR_SINGULAR_LATTICE
                 4: "EZ_ERR_UNSUPPORTED", 5: "EZ_ERR_NOMEM", 6: "EZ_ERR_HIP"}
 FLAG_SINGULAR, FLAG_CAPACITY, FLAG_NONFINITE, FLAG_HADAMARD, FLAG_POLE = 0x1, 0x2, 0x4, 0x8, 0x10
 PREC_FP64, PREC_MIXED = 0, 1
-SPEC_PERSISTENT, SPEC_SERIAL = 0x1, 0x2
+SPEC_PERSISTENT, SPEC_SERIAL, SPEC_NO_SPLIT = 0x1, 0x2, 0x4
 
 
 def spec_bpc(n: int) -> int:
@@ -29,8 +29,8 @@ def spec_bpc(n: int) -> int:
 EXPORTED = ("ez_epstein_zeta", "ez_epstein_grid", "ez_nbody_lattice_sum", "ez_atm_energy", "ez_lattice_sums", "ez_lattice_sums_grad",
             "ez_timing_enable", "ez_timing_reset", "ez_timing_read",
             "ez_last_error", "ez_finalize", "ez_version")
-KERNEL_SETUP, KERNEL_NODES, KERNEL_HADAMARD, KERNEL_FINALIZE, KERNEL_EPSTEIN, KERNEL_NODES_ADJ, KERNEL_GRID = (
-    0, 1, 2, 3, 4, 5, 6)
+(KERNEL_SETUP, KERNEL_NODES, KERNEL_HADAMARD, KERNEL_FINALIZE, KERNEL_EPSTEIN, KERNEL_NODES_ADJ, KERNEL_GRID,
+ KERNEL_NODES_TAIL, KERNEL_TAYLOR) = (0, 1, 2, 3, 4, 5, 6, 7, 8)
 
 
 class EzError(RuntimeError):

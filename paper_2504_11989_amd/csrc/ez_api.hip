@@ -145,7 +145,8 @@ struct DevPlan {
 struct DeviceState {
     std::map<std::string, DevPlan *> plans;
     std::vector<std::string> plan_order;
-    DevBuf meta, real, rn, rows, rec, tile_part, dir_part, dir_flag, probe_val, tensor, tile_grad, dir_grad;
+    DevBuf meta, real, rn, rows, rec, tile_part, sub_part, tail_acc, tail_cnt, dir_part, dir_flag, probe_val, tensor,
+        tile_grad, dir_grad;
     DevBuf gmeta, greal, grec;   // general-x Epstein tables
     DevBuf queue;                // work-queue position of the persistent node kernel
     // Epstein grid workspace
@@ -225,7 +226,7 @@ ez_status check_spec(const ez_quad_spec &s) {
     if (!(s.lam >= 0.0 && s.lam <= 8.0)) return fail(EZ_ERR_INVALID_ARG, "spec.lam must be in [0, 8]");
     if (!(s.a_cut >= 0.0 && s.a_cut <= 200.0)) return fail(EZ_ERR_INVALID_ARG, "spec.a_cut must be in [0, 200]");
     if (s.precision != EZ_PREC_FP64) return fail(EZ_ERR_UNSUPPORTED, "spec.precision: only EZ_PREC_FP64 here");
-    if (s.flags & ~(EZ_SPEC_PERSISTENT | EZ_SPEC_SERIAL | 0xFF00))
+    if (s.flags & ~(EZ_SPEC_PERSISTENT | EZ_SPEC_SERIAL | EZ_SPEC_NO_SPLIT | 0xFF00))
         return fail(EZ_ERR_INVALID_ARG, "spec.flags: unknown bits");
     return EZ_OK;
 }
@@ -506,6 +507,37 @@ ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, 
 
 const double kSkew = 2.5;   // bound on (1/2) sum |a_i| / V^{1/d} assumed for table capacity
 
+// 1/Gamma(x), zero at the poles
+double rgamma_host(double x) { return (x <= 0.0 && x == std::floor(x)) ? 0.0 : 1.0 / std::tgamma(x); }
+
+// lattice-independent factors of the per-exponent constants of the split: the
+// reciprocal prefactor pi^{nu-d/2}/Gamma(nu/2) (times alpha^{(d-nu)/2}/V on the
+// device), the self-term factor 1/Gamma(nu/2+1), and V times the coefficient of
+// the singular part |k|^{nu-d}: Gamma((d-nu)/2) pi^{nu-d/2}/Gamma(nu/2), or for
+// nu = d + 2m the coefficient of |k|^{2m} log(pi |k|^2),
+// (-1)^{m+1} pi^{2m+d/2} / (Gamma(m+d/2) m!)
+void fill_nu_constants(const EzProgram &prog, EzSetupArgs &sa) {
+    std::memset(sa.nuc, 0, sizeof(sa.nuc));
+    const double d = (double)prog.d;
+    for (int i = 0; i < prog.n_nu; ++i) {
+        const double nu = prog.nu[i];
+        const double rg = rgamma_host(0.5 * nu);
+        const double c0 = std::pow(M_PI, nu - 0.5 * d) * rg;
+        sa.nuc[i][0] = c0;
+        sa.nuc[i][1] = rgamma_host(0.5 * nu + 1.0);
+        const int m = prog.logm[i];
+        if (m >= 0) {
+            double mf = 1.0;
+            for (int j = 2; j <= m; ++j) mf *= (double)j;
+            sa.nuc[i][2] = std::pow(M_PI, 2.0 * m + 0.5 * d) * rgamma_host(m + 0.5 * d) *
+                           (((m + 1) & 1) ? -1.0 : 1.0) / mf;
+        } else {
+            sa.nuc[i][2] = c0 * std::tgamma(0.5 * (d - nu));
+        }
+        sa.nuc[i][3] = rg;
+    }
+}
+
 int real_capacity(int d, double lam, double acut, bool general) {
     double R = lam * std::sqrt(acut / M_PI) + (general ? kSkew : 0.0);
     double n = kOmega[d] * std::pow(R + kSkew, d);
@@ -568,7 +600,24 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
         return fail(EZ_ERR_UNSUPPORTED, "reciprocal table too large for this lam and a_cut (raise spec.lam)");
     tab.rstride = 4 * ((3 + (grad ? 2 : 1) * prog.n_nu + 3) / 4);
     tab.row_cap = tab.real_cap;
+    // Tail of the node tiles: the tile kernel runs in rounds of (CUs x its workgroups
+    // per CU); when the last round would hold only a few tiles (at most a quarter of
+    // a round), those tiles go to the split kernel, which shares each node's terms
+    // among 16 waves on four CUs (value calls without EZ_SPEC_NO_SPLIT; the adjoint
+    // keeps whole tiles).
+    int n_main = P->n_tiles;
+    if (!grad && !(flags & EZ_SPEC_NO_SPLIT)) {
+        EzQuadArgs probe_args;
+        std::memset(&probe_args, 0, sizeof(probe_args));
+        probe_args.prog = prog;
+        const int round = S->n_cu * ez_nodes_tile_blocks_per_cu(probe_args);
+        const int tail = round > 0 ? P->n_tiles % round : 0;
+        if (P->n_tiles > round && tail > 0 && tail <= round / 4) n_main = P->n_tiles - tail;
+    }
     if ((st = grow(S->meta, sizeof(EzLatMeta) * batch)) ||
+        (st = grow(S->sub_part, sizeof(double) * 2 * (EZ_TILE / 64) * (size_t)std::max(1, P->n_tiles - n_main) * prog.n_res)) ||
+        (st = grow(S->tail_acc, sizeof(double) * (EZ_TILE / 64) * EZ_TAIL_PARTS * 2 * 64 *
+                                    (size_t)std::max(1, P->n_tiles - n_main) * prog.n_nu)) ||
         (st = grow(S->real, sizeof(double) * (size_t)batch * tab.real_cap * tab.rstride)) ||
         (st = grow(S->rn, sizeof(int) * 4 * (size_t)batch * tab.real_cap)) ||
         (st = grow(S->rows, sizeof(int) * 8 * (size_t)batch * tab.row_cap)) ||
@@ -597,6 +646,7 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     sa.general_x = 0;
     sa.grad = grad ? 1 : 0;
     sa.status_out = nullptr;
+    fill_nu_constants(prog, sa);
     EZ_HIP_TRY(timed(EZ_KERNEL_SETUP, stream, [&] { return ez_launch_setup(sa, batch, stream); }));
 
     EzQuadArgs qa;
@@ -630,23 +680,36 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     qa.dir_grad = grad ? (double *)S->dir_grad.p : nullptr;
     qa.grad_out = grad_dev;
     qa.n_tiles = P->n_tiles;
+    qa.n_main = n_main;
+    qa.sub_part = (double *)S->sub_part.p;
+    qa.tail_acc = (double *)S->tail_acc.p;
+    {   // group counters: zero when allocated, then reset by the kernel that uses them
+        const size_t had = S->tail_cnt.bytes;
+        if ((st = grow(S->tail_cnt, sizeof(int) * (EZ_TILE / 64) * (size_t)std::max(1, P->n_tiles - n_main)))) return st;
+        if (S->tail_cnt.bytes != had)
+            EZ_HIP_TRY(ez_launch_fill_int((int *)S->tail_cnt.p, (int)(S->tail_cnt.bytes / sizeof(int)), 0, stream));
+    }
+    qa.tail_cnt = (int *)S->tail_cnt.p;
     qa.tile_order = (const int *)P->tile_order.p;
     qa.queue = (int *)S->queue.p;
 
-    // The Hadamard branch (probe, tensor, direction kernels) depends only on the
-    // setup: it runs on a second stream, concurrently with the node kernel, and the
+    // The Taylor/Hadamard branch depends only on the setup.  Its probe and tensor
+    // kernels are short and run on the caller's stream before the nodes (on a second
+    // queue they would wait for slots until the node kernel drains).  The direction
+    // kernel runs on a second stream, concurrently with the node kernels, and the
     // caller's stream waits for it before the final reduction (event edges, so the
     // sequence can be captured into a graph).  EZ_SPEC_SERIAL keeps it on `stream`.
+    auto had = [&](hipStream_t s, int part) {
+        return grad ? ez_launch_hadamard_adj(qa, P->n_htiles, s, part) : ez_launch_hadamard(qa, P->n_htiles, s, part);
+    };
+    EZ_HIP_TRY(timed(EZ_KERNEL_TAYLOR, stream, [&] { return had(stream, EZ_HAD_PRE); }));
     hipStream_t hs = stream;
     if (!(flags & EZ_SPEC_SERIAL)) {
         EZ_HIP_TRY(hipEventRecord(S->ev_setup, stream));
         EZ_HIP_TRY(hipStreamWaitEvent(S->side, S->ev_setup, 0));
         hs = S->side;
     }
-    if (grad)
-        EZ_HIP_TRY(timed(EZ_KERNEL_HADAMARD, hs, [&] { return ez_launch_hadamard_adj(qa, P->n_htiles, hs); }));
-    else
-        EZ_HIP_TRY(timed(EZ_KERNEL_HADAMARD, hs, [&] { return ez_launch_hadamard(qa, P->n_htiles, hs); }));
+    EZ_HIP_TRY(timed(EZ_KERNEL_HADAMARD, hs, [&] { return had(hs, EZ_HAD_DIR); }));
     if (grad) {
         EZ_HIP_TRY(timed(EZ_KERNEL_NODES_ADJ, stream, [&] { return ez_launch_nodes_adj(qa, P->n_tiles, stream); }));
     } else if (flags & EZ_SPEC_PERSISTENT) {
@@ -656,8 +719,10 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
         EZ_HIP_TRY(ez_launch_fill_int(qa.queue, 1, 0, stream));
         EZ_HIP_TRY(timed(EZ_KERNEL_NODES, stream, [&] { return ez_launch_nodes_persistent(qa, nblk, stream); }));
     } else {
-        EZ_HIP_TRY(timed(EZ_KERNEL_NODES, stream, [&] { return ez_launch_nodes(qa, P->n_tiles, stream); }));
+        EZ_HIP_TRY(timed(EZ_KERNEL_NODES, stream, [&] { return ez_launch_nodes(qa, n_main, stream); }));
     }
+    if (n_main < P->n_tiles)
+        EZ_HIP_TRY(timed(EZ_KERNEL_NODES_TAIL, stream, [&] { return ez_launch_nodes_split(qa, stream); }));
     if (hs != stream) {
         EZ_HIP_TRY(hipEventRecord(S->ev_had, hs));
         EZ_HIP_TRY(hipStreamWaitEvent(stream, S->ev_had, 0));
@@ -703,6 +768,7 @@ ez_status general_setup(DeviceState *S, int d, const double *A_dev, double lam, 
     sa.general_x = 1;
     sa.grad = 0;
     sa.status_out = status_dev;
+    fill_nu_constants(prog, sa);
     EZ_HIP_TRY(timed(EZ_KERNEL_SETUP, s, [&] { return ez_launch_setup(sa, 1, s); }));
     *tab_out = tab;
     return EZ_OK;
@@ -733,7 +799,7 @@ ez_status ez_finalize(void) {
         DeviceState *S = kv.second;
         for (auto &p : S->plans) free_plan(p.second);
         free_buf(S->meta); free_buf(S->real); free_buf(S->rec); free_buf(S->rn); free_buf(S->rows);
-        free_buf(S->tile_part); free_buf(S->dir_part); free_buf(S->dir_flag); free_buf(S->probe_val); free_buf(S->tensor);
+        free_buf(S->tile_part); free_buf(S->sub_part); free_buf(S->tail_acc); free_buf(S->tail_cnt); free_buf(S->dir_part); free_buf(S->dir_flag); free_buf(S->probe_val); free_buf(S->tensor);
         free_buf(S->tile_grad); free_buf(S->dir_grad); free_buf(S->queue);
         for (DevBuf *b : {&S->g_pts_x, &S->g_pts_y, &S->g_perm, &S->g_counts, &S->g_A64r, &S->g_B64r, &S->g_A64k,
                           &S->g_B64k, &S->g_R, &S->g_Q, &S->g_wsum, &S->g_stat, &S->g_Ahr, &S->g_Alr, &S->g_Bhr,

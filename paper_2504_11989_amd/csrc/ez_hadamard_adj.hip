@@ -218,51 +218,55 @@ __global__ __launch_bounds__(256) void ez_hadamard_adj_kernel(EzQuadArgs args) {
 
 
 template <int D, int NNU, int PD>
-hipError_t launch_had_t(const EzQuadArgs &args, int n_htiles, hipStream_t stream) {
-    const int nblk = (args.n_probe + 63) / 64;
-    const int nch = true ? args.n_ch : 1;
-    hipLaunchKernelGGL((ez_probe_kernel<D, NNU, true>), dim3(args.batch * nblk * args.n_slice * nch), dim3(64 * EZ_HW),
-                       0, stream, args);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    int tdim = 0;
-    for (int k = 0; k <= args.ell_probe; ++k) tdim += nmono(D, 2 * k);
-    const int ngrp = (tdim + EZ_TOUT - 1) / EZ_TOUT;
-    hipLaunchKernelGGL((ez_tensor_kernel<D, NNU>), dim3(args.batch * NNU * nch * ngrp), dim3(256), 0, stream, args);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+hipError_t launch_had_t(const EzQuadArgs &args, int n_htiles, hipStream_t stream, int part) {
+    hipError_t e = hipSuccess;
+    if (part & EZ_HAD_PRE) {            // probe values and Taylor tensors
+        const int nblk = (args.n_probe + 63) / 64;
+        const int nch = true ? args.n_ch : 1;
+        hipLaunchKernelGGL((ez_probe_kernel<D, NNU, true>), dim3(args.batch * nblk * args.n_slice * nch), dim3(64 * EZ_HW),
+                           0, stream, args);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        int tdim = 0;
+        for (int k = 0; k <= args.ell_probe; ++k) tdim += nmono(D, 2 * k);
+        const int ngrp = (tdim + EZ_TOUT - 1) / EZ_TOUT;
+        hipLaunchKernelGGL((ez_tensor_kernel<D, NNU>), dim3(args.batch * NNU * nch * ngrp), dim3(256), 0, stream, args);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (!(part & EZ_HAD_DIR)) return hipSuccess;   // direction kernel
     hipLaunchKernelGGL((ez_hadamard_adj_kernel<D, NNU, PD>), dim3(n_htiles), dim3(256), 0, stream, args);
     return hipGetLastError();
 }
 
 template <int D, int NNU>
-hipError_t launch_had_p(const EzQuadArgs &args, int n_htiles, hipStream_t stream) {
-    if (args.poly_deg == 13) return launch_had_t<D, NNU, 13>(args, n_htiles, stream);
-    if (args.poly_deg == 33) return launch_had_t<D, NNU, 33>(args, n_htiles, stream);
+hipError_t launch_had_p(const EzQuadArgs &args, int n_htiles, hipStream_t stream, int part) {
+    if (args.poly_deg == 13) return launch_had_t<D, NNU, 13>(args, n_htiles, stream, part);
+    if (args.poly_deg == 33) return launch_had_t<D, NNU, 33>(args, n_htiles, stream, part);
     return hipErrorInvalidValue;
 }
 
 template <int D>
-hipError_t launch_had_d(const EzQuadArgs &args, int n_htiles, hipStream_t stream) {
+hipError_t launch_had_d(const EzQuadArgs &args, int n_htiles, hipStream_t stream, int part) {
     switch (args.prog.n_nu) {
-        case 1: return launch_had_p<D, 1>(args, n_htiles, stream);
-        case 2: return launch_had_p<D, 2>(args, n_htiles, stream);
-        case 3: return launch_had_p<D, 3>(args, n_htiles, stream);
-        case 4: return launch_had_p<D, 4>(args, n_htiles, stream);
-        case 5: return launch_had_p<D, 5>(args, n_htiles, stream);
-        case 6: return launch_had_p<D, 6>(args, n_htiles, stream);
-        case 7: return launch_had_p<D, 7>(args, n_htiles, stream);
-        case 8: return launch_had_p<D, 8>(args, n_htiles, stream);
+        case 1: return launch_had_p<D, 1>(args, n_htiles, stream, part);
+        case 2: return launch_had_p<D, 2>(args, n_htiles, stream, part);
+        case 3: return launch_had_p<D, 3>(args, n_htiles, stream, part);
+        case 4: return launch_had_p<D, 4>(args, n_htiles, stream, part);
+        case 5: return launch_had_p<D, 5>(args, n_htiles, stream, part);
+        case 6: return launch_had_p<D, 6>(args, n_htiles, stream, part);
+        case 7: return launch_had_p<D, 7>(args, n_htiles, stream, part);
+        case 8: return launch_had_p<D, 8>(args, n_htiles, stream, part);
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-hipError_t ez_launch_hadamard_adj(const EzQuadArgs &args, int n_htiles, hipStream_t stream) {
+hipError_t ez_launch_hadamard_adj(const EzQuadArgs &args, int n_htiles, hipStream_t stream, int part) {
     switch (args.prog.d) {
-        case 1: return launch_had_d<1>(args, n_htiles, stream);
-        case 2: return launch_had_d<2>(args, n_htiles, stream);
-        case 3: return launch_had_d<3>(args, n_htiles, stream);
+        case 1: return launch_had_d<1>(args, n_htiles, stream, part);
+        case 2: return launch_had_d<2>(args, n_htiles, stream, part);
+        case 3: return launch_had_d<3>(args, n_htiles, stream, part);
         default: return hipErrorInvalidValue;
     }
 }

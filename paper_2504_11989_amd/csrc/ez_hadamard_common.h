@@ -100,19 +100,29 @@ __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta 
         const double *rt = args.tab.real + (size_t)inst * args.tab.real_cap * rs;
         const int n_real = M->n_real;
         const int woff = dch ? 3 + NNU : 3;
-        for (int p = slice * EZ_HW + part; p < n_real; p += EZ_HW * n_slice) {
-            const double *e = rt + (size_t)p * rs;
-            double t = 0.0;
+        // two entries per pass (their loads issued together), added in table order
+        const int step = EZ_HW * n_slice;
+        for (int p = slice * EZ_HW + part; p < n_real; p += 2 * step) {
+            const bool two = p + step < n_real;
+            const double *e0 = rt + (size_t)p * rs;
+            const double *e1 = rt + (size_t)(two ? p + step : p) * rs;
+            double ew0[NNU], ew1[NNU], t0 = 0.0, t1 = 0.0;
 #pragma unroll
-            for (int i = 0; i < D; ++i) t = fma(w[i], e[i], t);
-            const double x = (2.0 * EZ_PI * t) * (2.0 * EZ_PI * t);
-            double term = dch ? e[sa] * e[sb] : 1.0;
+            for (int i = 0; i < D; ++i) { t0 = fma(w[i], e0[i], t0); t1 = fma(w[i], e1[i], t1); }
+#pragma unroll
+            for (int i = 0; i < NNU; ++i) { ew0[i] = e0[woff + i]; ew1[i] = two ? e1[woff + i] : 0.0; }
+            const double x0 = (2.0 * EZ_PI * t0) * (2.0 * EZ_PI * t0);
+            const double x1 = (2.0 * EZ_PI * t1) * (2.0 * EZ_PI * t1);
+            double term0 = dch ? e0[sa] * e0[sb] : 1.0;
+            double term1 = dch ? e1[sa] * e1[sb] : 1.0;
 #pragma unroll
             for (int k = 0; k <= EZ_ELL_MAX; ++k) {
                 if (k <= ell) {
 #pragma unroll
-                    for (int i = 0; i < NNU; ++i) C[i][k] = fma(e[woff + i], term, C[i][k]);
-                    term *= -x * (1.0 / ((2.0 * k + 1.0) * (2.0 * k + 2.0)));
+                    for (int i = 0; i < NNU; ++i) C[i][k] = fma(ew1[i], term1, fma(ew0[i], term0, C[i][k]));
+                    const double f = 1.0 / ((2.0 * k + 1.0) * (2.0 * k + 2.0));
+                    term0 *= -x0 * f;
+                    term1 *= -x1 * f;
                 }
             }
         }
@@ -198,6 +208,66 @@ __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta 
             }
         }
     }
+    // m* = 0 (slice 0; exponent i on wave i mod EZ_HW): regular part of K E_p(alpha |k|^2)
+    // as a series in a = alpha w2 u^2; a term K c_J (alpha w2)^J has strain derivative
+    // -(I + 2 J w w^T / w2) times itself
+    if (slice == 0) {
+        const double aw = alpha * w2;
+        const double rw2 = dch ? ww / w2 : 0.0;
+#pragma unroll
+        for (int i = 0; i < NNU; ++i) {
+            if (i % EZ_HW != part) continue;
+            const double s = 0.5 * ((double)D - prog.nu[i]);
+            const int m = prog.logm[i];
+            const double K = M->K[i];
+            if (m < 0) {
+                double awj = 1.0, jf = 1.0;
+#pragma unroll
+                for (int j = 0; j <= EZ_ELL_MAX; ++j) {
+                    if (j <= ell) {
+                        if (j > 0) { awj *= aw; jf *= (double)j; }
+                        double v = -K * (((j & 1) ? -awj : awj) / (jf * (s + (double)j)));
+                        if (dch) v *= -delta - 2.0 * (double)j * rw2;
+                        C[i][j] += v;
+                    }
+                }
+            } else {
+                // K [ (-1)^{m+1}/m! a^m ln lam^2 + (-1)^m/m! ( a^m (-gamma - sum_{j>=1} (-a)^j/(j j!))
+                //     - e^{-a} sum_{i<m} (-1)^i i! a^{m-i-1} ) ]  as a power series in a
+                const double sm = (m & 1) ? -1.0 : 1.0;
+                double mf = 1.0;
+                for (int j = 2; j <= m; ++j) mf *= (double)j;
+                const double lnl2 = log(M->lam * M->lam);
+                double awj = 1.0;
+#pragma unroll
+                for (int J = 0; J <= EZ_ELL_MAX; ++J) {
+                    if (J > ell) continue;
+                    double c = 0.0;
+                    if (J == m) c += -sm / mf * lnl2 + sm / mf * (-EZ_EULER);
+                    if (J > m) {
+                        const int j = J - m;
+                        double jf = 1.0;
+                        for (int q = 2; q <= j; ++q) jf *= (double)q;
+                        c += -sm / mf * (((j & 1) ? -1.0 : 1.0) / ((double)j * jf));
+                    }
+                    double iif = 1.0;
+                    for (int ii = 0; ii < m; ++ii) {
+                        if (ii > 0) iif *= (double)ii;
+                        const int r = J - (m - ii - 1);
+                        if (r >= 0) {
+                            double rf = 1.0;
+                            for (int q = 2; q <= r; ++q) rf *= (double)q;
+                            c += -sm / mf * (((ii & 1) ? -iif : iif)) * (((r & 1) ? -1.0 : 1.0) / rf);
+                        }
+                    }
+                    double v = K * c * awj;
+                    if (dch) v *= -delta - 2.0 * (double)J * rw2;
+                    C[i][J] += v;
+                    awj *= aw;
+                }
+            }
+        }
+    }
     // fixed-order sum of the waves' coefficients into wave 0 (LDS reused)
     for (int src = 1; src < EZ_HW; ++src) {
         __syncthreads();
@@ -215,63 +285,6 @@ __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta 
 #pragma unroll
                 for (int k = 0; k <= EZ_ELL_MAX; ++k)
                     if (k <= ell) C[i][k] += lds[(i * (EZ_ELL_MAX + 1) + k) * 64 + lane];
-        }
-    }
-    // m* = 0: regular part of K E_p(alpha |k|^2) as a series in a = alpha w2 u^2;
-    // a term K c_J (alpha w2)^J has strain derivative -(I + 2 J w w^T / w2) times itself
-    if (part != 0 || slice != 0) return;
-    const double aw = alpha * w2;
-    const double rw2 = dch ? ww / w2 : 0.0;
-#pragma unroll
-    for (int i = 0; i < NNU; ++i) {
-        const double s = 0.5 * ((double)D - prog.nu[i]);
-        const int m = prog.logm[i];
-        const double K = M->K[i];
-        if (m < 0) {
-            double awj = 1.0, jf = 1.0;
-#pragma unroll
-            for (int j = 0; j <= EZ_ELL_MAX; ++j) {
-                if (j <= ell) {
-                    if (j > 0) { awj *= aw; jf *= (double)j; }
-                    double v = -K * (((j & 1) ? -awj : awj) / (jf * (s + (double)j)));
-                    if (dch) v *= -delta - 2.0 * (double)j * rw2;
-                    C[i][j] += v;
-                }
-            }
-        } else {
-            // K [ (-1)^{m+1}/m! a^m ln lam^2 + (-1)^m/m! ( a^m (-gamma - sum_{j>=1} (-a)^j/(j j!))
-            //     - e^{-a} sum_{i<m} (-1)^i i! a^{m-i-1} ) ]  as a power series in a
-            const double sm = (m & 1) ? -1.0 : 1.0;
-            double mf = 1.0;
-            for (int j = 2; j <= m; ++j) mf *= (double)j;
-            const double lnl2 = log(M->lam * M->lam);
-            double awj = 1.0;
-#pragma unroll
-            for (int J = 0; J <= EZ_ELL_MAX; ++J) {
-                if (J > ell) continue;
-                double c = 0.0;
-                if (J == m) c += -sm / mf * lnl2 + sm / mf * (-EZ_EULER);
-                if (J > m) {
-                    const int j = J - m;
-                    double jf = 1.0;
-                    for (int q = 2; q <= j; ++q) jf *= (double)q;
-                    c += -sm / mf * (((j & 1) ? -1.0 : 1.0) / ((double)j * jf));
-                }
-                double iif = 1.0;
-                for (int ii = 0; ii < m; ++ii) {
-                    if (ii > 0) iif *= (double)ii;
-                    const int r = J - (m - ii - 1);
-                    if (r >= 0) {
-                        double rf = 1.0;
-                        for (int q = 2; q <= r; ++q) rf *= (double)q;
-                        c += -sm / mf * (((ii & 1) ? -iif : iif)) * (((r & 1) ? -1.0 : 1.0) / rf);
-                    }
-                }
-                double v = K * c * awj;
-                if (dch) v *= -delta - 2.0 * (double)J * rw2;
-                C[i][J] += v;
-                awj *= aw;
-            }
         }
     }
 }
@@ -350,8 +363,16 @@ __global__ __launch_bounds__(256) void ez_tensor_kernel(EzQuadArgs args) {
         const double *pv = args.probe_val + (size_t)inst * S * np * NC * (EZ_ELL_MAX + 1) +
                            (size_t)c * (EZ_ELL_MAX + 1) + k;
         for (int p = pp; p < np; p += 16) {
+            // the slices in fixed order, their loads issued eight at a time
             double v = 0.0;
-            for (int sl = 0; sl < S; ++sl) v += pv[((size_t)sl * np + p) * NC * (EZ_ELL_MAX + 1)];
+            for (int sl0 = 0; sl0 < S; sl0 += 8) {
+                double t[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    t[q] = (sl0 + q < S) ? pv[((size_t)(sl0 + q) * np + p) * NC * (EZ_ELL_MAX + 1)] : 0.0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v += t[q];
+            }
             s = fma(pinv[p], v, s);
         }
     }

@@ -16,6 +16,7 @@
 #define EZ_SLICE_MAX 8   // table slices of the probe kernel
 #define EZ_GRAD_RES_MAX 2  // results per call when strain derivatives are requested
 #define EZ_HDIR_GRAD 16  // directions per workgroup of the Hadamard adjoint kernel
+#define EZ_TAIL_PARTS 4  // workgroups sharing one 64-node group of the tail node tiles
 
 // Which lattice sums one call computes (host-built, passed by value).
 // Exponent nu_i enters the reciprocal sum through E_{p_i}(a), p_i = (nu_i - d + 2)/2
@@ -60,8 +61,7 @@ struct EzLatMeta {
     int n_rec;              // reciprocal entries (all m*, m* = 0 first)
     uint32_t status;
     int n_rows;             // rows of the real-space table (pairs mode)
-    int n_inner;            // reciprocal entries [0, n_inner) may have a < 1; the rest have a >= 1
-    int pad_;
+    int pad_[2];
 };
 
 // Per-lattice quadrature plan (host-built).

@@ -12,6 +12,10 @@ struct EzSetupArgs {
     int general_x;             // 0: pairs table for x = 0; 1: full table for general x
     int grad;                  // pairs mode: also store the strain weights -4 Gamma(nu/2+1, a)/(Gamma(nu/2) r^{nu+2})
     uint32_t *status_out;      // general-x mode: receives the lattice flags (may be NULL)
+    // per exponent, lattice-independent factors (host-computed from nu and d):
+    // [0] pi^{nu-d/2}/Gamma(nu/2), [1] 1/Gamma(nu/2+1), [2] V times the singular
+    // coefficient sig, [3] 1/Gamma(nu/2); 1/Gamma is 0 at the poles
+    double nuc[EZ_NU_MAX][4];
 };
 
 // One term of the (0, eps) expansion: term t with factor slot f taking its singular
@@ -32,6 +36,7 @@ struct EzQuadArgs {
     const EzInstPlan *plans;
     const int *tile_begin;     // batch + 1 prefix of node tiles
     int n_tiles;               // node tiles of the whole batch
+    int n_main;                // tiles [0, n_main) whole, [n_main, n_tiles) split into 64-node groups
     const int *tile_order;     // persistent node kernel: tiles in the order they are taken (costliest first)
     int *queue;                // persistent node kernel: next position in tile_order (reset before launch)
     const int *dir_begin;      // batch + 1 prefix of directions
@@ -51,6 +56,9 @@ struct EzQuadArgs {
     EzTables tab;
     const double *rules;       // Gauss rules (v on [0,1], u on (eps,1/2])
     double *tile_part;         // [n_tiles][n_res][2] double-double partials
+    double *sub_part;          // [4 (n_tiles - n_main)][n_res][2] partials of the 64-node groups
+    double *tail_acc;          // [4 (n_tiles - n_main)][EZ_TAIL_PARTS][2 n_nu][64] partial sums of the split kernel
+    int *tail_cnt;             // [4 (n_tiles - n_main)] parts finished per group (zero between calls)
     double *dir_part;          // [n_dirs][n_res] Hadamard part per direction (times 2 w_v)
     uint32_t *dir_flag;        // [n_dirs] flags (Hadamard mu = 0)
     double *tile_grad;         // [n_tiles][n_res][6][2] strain-derivative partials (gradient calls)
@@ -73,13 +81,21 @@ struct EzEpsteinArgs {
 
 hipError_t ez_launch_setup(const EzSetupArgs &args, int batch, hipStream_t stream);
 hipError_t ez_launch_nodes(const EzQuadArgs &args, int n_tiles, hipStream_t stream);
+// tiles [n_main, n_tiles): EZ_TAIL_PARTS workgroups per 64-node group
+hipError_t ez_launch_nodes_split(const EzQuadArgs &args, hipStream_t stream);
+// workgroups of the tile node kernel that fit on one CU at once
+int ez_nodes_tile_blocks_per_cu(const EzQuadArgs &args);
 // persistent form: n_blocks workgroups take tiles from args.queue until all are done
 hipError_t ez_launch_nodes_persistent(const EzQuadArgs &args, int n_blocks, hipStream_t stream);
 // blocks of the persistent node kernel that fit on one CU at once
 int ez_nodes_blocks_per_cu(const EzQuadArgs &args);
 hipError_t ez_launch_fill_int(int *p, int n, int value, hipStream_t stream);
-hipError_t ez_launch_hadamard(const EzQuadArgs &args, int n_htiles, hipStream_t stream);
+// Taylor/Hadamard branch: part EZ_HAD_PRE = probe and tensor kernels, EZ_HAD_DIR = the
+// direction kernel (it reads the tensors), or both
+#define EZ_HAD_PRE 1
+#define EZ_HAD_DIR 2
+hipError_t ez_launch_hadamard(const EzQuadArgs &args, int n_htiles, hipStream_t stream, int part);
 hipError_t ez_launch_finalize(const EzQuadArgs &args, hipStream_t stream);
 hipError_t ez_launch_nodes_adj(const EzQuadArgs &args, int n_tiles, hipStream_t stream);
-hipError_t ez_launch_hadamard_adj(const EzQuadArgs &args, int n_htiles, hipStream_t stream);
+hipError_t ez_launch_hadamard_adj(const EzQuadArgs &args, int n_htiles, hipStream_t stream, int part);
 hipError_t ez_launch_epstein(const EzEpsteinArgs &args, hipStream_t stream);

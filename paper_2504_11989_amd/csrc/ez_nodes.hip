@@ -1,257 +1,401 @@
 // ez_nodes.hip -- quadrature nodes on (eps, 1/2] and the final reduction.
 //
-// ez_node_kernel    : one thread per node k = u w: Z_nu(k) for the exponent set by
-//                     the split (real-space table + reciprocal table), the products
-//                     of the terms, weight, then a double-double reduction to one
-//                     partial per 256-node tile (paper, Sec. 2, Theorem (Epstein
-//                     representation); Sec. 3, Corollary (Duffy transformation)).
-// ez_finalize_kernel: fixed-order double-double sum of tiles and directions; the
-//                     derivatives with respect to A when requested.
+// ez_node_kernel      : one thread per node k = u w: Z_nu(k) for the exponent set by
+//                       the split (real-space table + reciprocal table), the products
+//                       of the terms, weight, then a double-double reduction to one
+//                       partial per 256-node tile (paper, Sec. 2, Theorem (Epstein
+//                       representation); Sec. 3, Corollary (Duffy transformation)).
+// ez_node_split_kernel: the last few tiles of a call, each node's terms shared by
+//                       16 waves in four workgroups (see below).
+// ez_finalize_kernel  : fixed-order double-double sum of tiles and directions; the
+//                       derivatives with respect to A when requested.
+#include <algorithm>
+
 #include "ez_quad_common.h"
 
 namespace {
 
+// Geometry of node nd: k = u w, theta = u w_hat (so that k.z = theta.n for z = A n)
+// and the quadrature weight W (Duffy Jacobian u^{d-1}, Gauss weights, factor 2).
+template <int D>
+__device__ __forceinline__ void node_geometry(const EzInstPlan &P, const double *rules, const EzLatMeta *M, int nd,
+                                              double *k, double *th, double *W) {
+    const int dir = nd / P.n_u;
+    const int iu = nd - dir * P.n_u;
+    double B[D * D];
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) B[i] = M->B[i];
+    double w[3] = {0.0, 0.0, 0.0}, wh[3] = {0.0, 0.0, 0.0}, wv;
+    ez_direction<D>(P, rules, B, dir, w, &wv, wh);
+    const double u = rules[P.urule + iu];
+    const double wu = rules[P.urule + P.n_u + iu];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { k[i] = 0.0; th[i] = 0.0; }
+#pragma unroll
+    for (int i = 0; i < D; ++i) { k[i] = u * w[i]; th[i] = u * wh[i]; }
+    double Wt = 2.0 * wv * wu;
+#pragma unroll
+    for (int i = 0; i < D - 1; ++i) Wt *= u;
+    *W = Wt;
+}
+
+// The reciprocal table covers every node of the cell; a workgroup needs only the
+// entries within the cutoff radius of some of its nodes.  With c and r_t the
+// centre and half-diagonal of the bounding box of the workgroup's k, an entry with
+// |m* + c| > sqrt(a_cut / alpha) + r_t is beyond the cutoff for every node of it.
+// The others are listed in table order (so each node adds the same nonzero terms
+// in the same order as over the whole table); the host keeps the table capacity
+// within the list (EZ_KCULL entries).  NT threads; returns the list length.
+template <int D, int NT>
+__device__ __forceinline__ int cull_reciprocal(const double *kt, int n_rec, const double *k, double alpha, double acut,
+                                               unsigned short *klist, double (*kbox)[6], int *kwave, int *kcount) {
+    constexpr int NWV = NT / 64;
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    double bl[3] = {k[0], k[1], k[2]}, bh[3] = {k[0], k[1], k[2]};
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            bl[i] = fmin(bl[i], __shfl_xor(bl[i], m, 64));
+            bh[i] = fmax(bh[i], __shfl_xor(bh[i], m, 64));
+        }
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) { kbox[wave][i] = bl[i]; kbox[wave][3 + i] = bh[i]; }
+    if (threadIdx.x == 0) *kcount = 0;
+    __syncthreads();
+    double c[3] = {0.0, 0.0, 0.0}, rt2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        double lo = kbox[0][i], hi = kbox[0][3 + i];
+        for (int w2 = 1; w2 < NWV; ++w2) { lo = fmin(lo, kbox[w2][i]); hi = fmax(hi, kbox[w2][3 + i]); }
+        c[i] = 0.5 * (lo + hi);
+        rt2 += 0.25 * (hi - lo) * (hi - lo);
+    }
+    const double rmax = (sqrt(acut / alpha) + sqrt(rt2)) * (1.0 + 1e-9) + 1e-12;
+    for (int base = 1; base < n_rec; base += NT) {
+        const int q = base + (int)threadIdx.x;
+        bool keep = false;
+        if (q < n_rec) {
+            const double *e = kt + (size_t)q * 4;
+            double d2 = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) { const double t = e[i] + c[i]; d2 = fma(t, t, d2); }
+            keep = d2 <= rmax * rmax;
+        }
+        const unsigned long long bal = __ballot(keep);
+        const int before = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) kwave[wave] = __popcll(bal);
+        __syncthreads();
+        int off = *kcount;
+        for (int w2 = 0; w2 < wave; ++w2) off += kwave[w2];
+        if (keep) klist[off + before] = (unsigned short)q;   // q < n_rec <= rec_cap <= EZ_KCULL
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int w2 = 0; w2 < NWV; ++w2) tot += kwave[w2];
+            *kcount += tot;
+        }
+        __syncthreads();
+    }
+    return *kcount;
+}
+
+// Real space: sum over pairs of 2 W_nu(z) Re e^{2 pi i k.z}, k.z = theta.n, over the
+// rows [r0, r1) of the table.  Row by row (n2, n3 fixed, consecutive n1) the phase
+// advances by c1 = e^{2 pi i theta_1}; from row to row within a plane by
+// c2^{dn2} c1^{dn1}; each plane, and the first row of the range, starts from one sincos.
+template <int D, int NNU>
+__device__ __forceinline__ void real_rows(const EzQuadArgs &args, int inst, const double *th, int r0, int r1,
+                                          double *accr) {
+    const int rs = args.tab.rstride;
+    const double *rt = args.tab.real + (size_t)inst * args.tab.real_cap * rs;
+    const int *rows = args.tab.rows + (size_t)inst * args.tab.row_cap * 8;
+    double c1r, c1i, c2r = 1.0, c2i = 0.0;
+    ez_sincos2pi(th[0], &c1i, &c1r);
+    if (D > 1) ez_sincos2pi(th[1], &c2i, &c2r);
+    double br = 1.0, bi = 0.0;
+    for (int r = r0; r < r1; ++r) {
+        const int *R = rows + (size_t)r * 8;
+        const int first = R[0], cnt = R[1];
+        if (R[5] || r == r0) {
+            double ph = th[0] * (double)R[2];
+            if (D > 1) ph = fma(th[1], (double)R[3], ph);
+            if (D > 2) ph = fma(th[2], (double)R[4], ph);
+            const double2 sc = ez_sincos2pi_ool(ph);
+            bi = sc.x;
+            br = sc.y;
+        } else {
+            for (int j = 0; j < R[7]; ++j) cmul(br, bi, c2r, c2i);
+            const int dl = R[6];
+            if (dl > 0) for (int j = 0; j < dl; ++j) cmul(br, bi, c1r, c1i);
+            else for (int j = 0; j < -dl; ++j) cmul(br, bi, c1r, -c1i);
+        }
+        double pr = br, pi = bi;
+        const double *e = rt + (size_t)first * rs;
+        for (int j = 0; j < cnt; ++j, e += rs) {
+#pragma unroll
+            for (int i = 0; i < NNU; ++i) accr[i] = fma(e[3 + i], pr, accr[i]);
+            cmul(pr, pi, c1r, c1i);
+        }
+    }
+}
+
+// Reciprocal space: sum over m* of E_{p_nu}(pi lam^2 |m* + k|^2).  Entry 0 is m* = 0,
+// where a = alpha |k|^2 can be small (series of E1); every other entry has
+// a >= alpha / (4 |A|_F^2) >= 1/4 (the setup raises lam to ensure it), so the
+// list loop is one branch-free formula with E1 from the wide rational.
 template <int D, int NNU, int SET>
-__device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile) {
+__device__ __forceinline__ void rec_origin(const EzQuadArgs &args, const double *k, double alpha, double acut,
+                                           double *acck) {
+    const bool need_e1 = pset_need_e1<SET, NNU>(args.prog), need_half = pset_need_half<SET, NNU>(args.prog);
+    double rho = k[0] * k[0];
+    if (D > 1) rho = fma(k[1], k[1], rho);
+    if (D > 2) rho = fma(k[2], k[2], rho);
+    const double a = alpha * rho;
+    if (a <= acut) {
+        const double ex = ez_expm(a);
+        const double inv = ez_rcp(a);
+        double E1 = 0.0;
+        if (need_e1) E1 = (a < 0.25) ? ez_e1_series(a) : ex * ez_e1w_scaled(inv);
+        const double Eh = need_half ? ez_ehalf(a) : 0.0;
+#pragma unroll
+        for (int i = 0; i < NNU; ++i)
+            acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
+    }
+}
+
+template <int D, int NNU, int SET>
+__device__ __forceinline__ void rec_list(const EzQuadArgs &args, const double *kt, const unsigned short *klist,
+                                         int j0, int j1, const double *k, double alpha, double acut, double *acck) {
+    const bool need_e1 = pset_need_e1<SET, NNU>(args.prog), need_half = pset_need_half<SET, NNU>(args.prog);
+    for (int j = j0; j < j1; ++j) {
+        const double *e = kt + (size_t)__builtin_amdgcn_readfirstlane((int)klist[j]) * 4;
+        double qx = e[0] + k[0];
+        double rho = qx * qx;
+        if (D > 1) { double qy = e[1] + k[1]; rho = fma(qy, qy, rho); }
+        if (D > 2) { double qz = e[2] + k[2]; rho = fma(qz, qz, rho); }
+        const double a = alpha * rho;
+        if (a <= acut) {
+            const double ex = ez_expm(a);
+            const double inv = ez_rcp(a);
+            const double E1 = need_e1 ? ex * ez_e1w_scaled(inv) : 0.0;
+            const double Eh = need_half ? ez_ehalf(a) : 0.0;
+#pragma unroll
+            for (int i = 0; i < NNU; ++i)
+                acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
+        }
+    }
+}
+
+// Z_nu = real part + K_nu (reciprocal part) - self term, then the weighted
+// products of the program's terms added to res
+template <int NNU>
+__device__ __forceinline__ void node_products(const EzQuadArgs &args, const EzLatMeta *M, const double *accr,
+                                              const double *acck, double W, double *res) {
+    double Z[NNU];
+#pragma unroll
+    for (int i = 0; i < NNU; ++i) Z[i] = accr[i] + M->K[i] * acck[i] - M->self_[i];
+    for (int t = 0; t < args.prog.n_terms; ++t) {
+        double prod = args.prog.term_coef[t];
+        for (int f = 0; f < args.prog.term_nfac[t]; ++f) {
+            const int fi = args.prog.term_fac[t][f];
+            double z = Z[0];
+#pragma unroll
+            for (int i = 1; i < NNU; ++i) z = (fi == i) ? Z[i] : z;
+            for (int m = 0; m < args.prog.term_mult[t][f]; ++m) prod *= z;
+        }
+        const int rr = args.prog.term_res[t];
+#pragma unroll
+        for (int r = 0; r < EZ_RES_MAX; ++r)
+            if (rr == r) res[r] += prod;
+    }
+#pragma unroll
+    for (int r = 0; r < EZ_RES_MAX; ++r) res[r] *= W;
+}
+
+// LDS of the node kernels.  kpool holds the culled reciprocal list (unsigned
+// short); the split path reuses it for its partial sums once the list is done.
+struct NodeLds {
+    double kpool[EZ_KCULL / 4];
+    double kbox[EZ_TILE / 64][6];
+    double red[EZ_RES_MAX][EZ_TILE / 64][2];
+    int kwave[EZ_TILE / 64];
+    int kcount;
+};
+
+template <int D, int NNU, int SET>
+__device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile, NodeLds &L) {
     const int inst = find_segment(args.tile_begin, args.batch, tile);
     const EzInstPlan P = args.plans[inst];
     const EzLatMeta *M = args.meta + inst;
     const int n_res = args.prog.n_res;
     const int node = (tile - args.tile_begin[inst]) * EZ_TILE + threadIdx.x;
     const int n_nodes = P.n_dir * P.n_u;
+    unsigned short *klist = reinterpret_cast<unsigned short *>(L.kpool);
 
     double res[EZ_RES_MAX];
 #pragma unroll
     for (int r = 0; r < EZ_RES_MAX; ++r) res[r] = 0.0;
 
-    // reciprocal entries this tile needs, in table order (see below)
-    __shared__ unsigned short klist[EZ_KCULL];
-    __shared__ double kbox[EZ_TILE / 64][6];
-    __shared__ int kwave[EZ_TILE / 64];
-    __shared__ int kcount;
-
     if (M->status == 0) {                         // uniform over the workgroup
         const bool valid = node < n_nodes;
         // threads past the last node take the tile's first node (geometry only)
         const int nd = valid ? node : (tile - args.tile_begin[inst]) * EZ_TILE;
-        const int dir = nd / P.n_u;
-        const int iu = nd - dir * P.n_u;
-        double B[D * D];
-#pragma unroll
-        for (int i = 0; i < D * D; ++i) B[i] = M->B[i];
-        double w[3] = {0.0, 0.0, 0.0}, wh[3] = {0.0, 0.0, 0.0}, wv;
-        ez_direction<D>(P, args.rules, B, dir, w, &wv, wh);
-        const double u = args.rules[P.urule + iu];
-        const double wu = args.rules[P.urule + P.n_u + iu];
-        double k[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int i = 0; i < D; ++i) k[i] = u * w[i];
-        double W = 2.0 * wv * wu;
-#pragma unroll
-        for (int i = 0; i < D - 1; ++i) W *= u;
+        double k[3], th[3], W;
+        node_geometry<D>(P, args.rules, M, nd, k, th, &W);
 
         double accr[NNU], acck[NNU];
 #pragma unroll
         for (int i = 0; i < NNU; ++i) { accr[i] = 0.0; acck[i] = 0.0; }
 
         const double *kt = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
-        const int n_rec = M->n_rec;
         const double alpha = M->alpha, acut = M->a_cut;
-        // The table covers every node of the cell; a tile needs only the entries
-        // within the cutoff radius of some of its nodes.  With c and r_t the centre
-        // and half-diagonal of the bounding box of the tile's k, an entry with
-        // |m* + c| > sqrt(a_cut / alpha) + r_t is beyond the cutoff for every node
-        // of the tile.  The others are listed in table order (so each node adds the
-        // same nonzero terms in the same order as over the whole table); the host
-        // keeps the table capacity within the list (EZ_KCULL entries).
-        {
-            const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
-            double bl[3] = {k[0], k[1], k[2]}, bh[3] = {k[0], k[1], k[2]};
-#pragma unroll
-            for (int i = 0; i < D; ++i)
-#pragma unroll
-                for (int m = 32; m >= 1; m >>= 1) {
-                    bl[i] = fmin(bl[i], __shfl_xor(bl[i], m, 64));
-                    bh[i] = fmax(bh[i], __shfl_xor(bh[i], m, 64));
-                }
-            if (lane == 0)
-#pragma unroll
-                for (int i = 0; i < 3; ++i) { kbox[wave][i] = bl[i]; kbox[wave][3 + i] = bh[i]; }
-            if (threadIdx.x == 0) kcount = 0;
-            __syncthreads();
-            double c[3] = {0.0, 0.0, 0.0}, rt2 = 0.0;
-#pragma unroll
-            for (int i = 0; i < D; ++i) {
-                double lo = kbox[0][i], hi = kbox[0][3 + i];
-                for (int w2 = 1; w2 < EZ_TILE / 64; ++w2) { lo = fmin(lo, kbox[w2][i]); hi = fmax(hi, kbox[w2][3 + i]); }
-                c[i] = 0.5 * (lo + hi);
-                rt2 += 0.25 * (hi - lo) * (hi - lo);
-            }
-            const double rmax = (sqrt(acut / alpha) + sqrt(rt2)) * (1.0 + 1e-9) + 1e-12;
-            for (int base = 1; base < n_rec; base += EZ_TILE) {
-                const int q = base + (int)threadIdx.x;
-                bool keep = false;
-                if (q < n_rec) {
-                    const double *e = kt + (size_t)q * 4;
-                    double d2 = 0.0;
-#pragma unroll
-                    for (int i = 0; i < D; ++i) { const double t = e[i] + c[i]; d2 = fma(t, t, d2); }
-                    keep = d2 <= rmax * rmax;
-                }
-                const unsigned long long bal = __ballot(keep);
-                const int before = __popcll(bal & ((1ull << lane) - 1ull));
-                if (lane == 0) kwave[wave] = __popcll(bal);
-                __syncthreads();
-                int off = kcount;
-                for (int w2 = 0; w2 < wave; ++w2) off += kwave[w2];
-                if (keep) klist[off + before] = (unsigned short)q;   // q < n_rec <= rec_cap <= EZ_KCULL
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    int tot = 0;
-                    for (int w2 = 0; w2 < EZ_TILE / 64; ++w2) tot += kwave[w2];
-                    kcount += tot;
-                }
-                __syncthreads();
-            }
-        }
-
-        // real space: sum over pairs of 2 W_nu(z) Re e^{2 pi i k.z}, k.z = theta.n with
-        // theta = A^T k = u w_hat.  Row by row (n2, n3 fixed, consecutive n1) the phase
-        // advances by c1 = e^{2 pi i theta_1}; from row to row within a plane by
-        // c2^{dn2} c1^{dn1}; each plane starts from one sincos.
+        const int nk = cull_reciprocal<D, EZ_TILE>(kt, M->n_rec, k, alpha, acut, klist, L.kbox, L.kwave, &L.kcount);
         if (valid) {
-            const int rs = args.tab.rstride;
-            const double *rt = args.tab.real + (size_t)inst * args.tab.real_cap * rs;
-            const int *rows = args.tab.rows + (size_t)inst * args.tab.row_cap * 8;
-            const int n_rows = M->n_rows;
-            double th[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-            for (int i = 0; i < D; ++i) th[i] = u * wh[i];
-            double c1r, c1i, c2r = 1.0, c2i = 0.0;
-            ez_sincos2pi(th[0], &c1i, &c1r);
-            if (D > 1) ez_sincos2pi(th[1], &c2i, &c2r);
-            double br = 1.0, bi = 0.0;
-            for (int r = 0; r < n_rows; ++r) {
-                const int *R = rows + (size_t)r * 8;
-                const int first = R[0], cnt = R[1];
-                if (R[5]) {
-                    double ph = th[0] * (double)R[2];
-                    if (D > 1) ph = fma(th[1], (double)R[3], ph);
-                    if (D > 2) ph = fma(th[2], (double)R[4], ph);
-                    const double2 sc = ez_sincos2pi_ool(ph);
-                    bi = sc.x;
-                    br = sc.y;
-                } else {
-                    for (int j = 0; j < R[7]; ++j) cmul(br, bi, c2r, c2i);
-                    const int dl = R[6];
-                    if (dl > 0) for (int j = 0; j < dl; ++j) cmul(br, bi, c1r, c1i);
-                    else for (int j = 0; j < -dl; ++j) cmul(br, bi, c1r, -c1i);
-                }
-                double pr = br, pi = bi;
-                const double *e = rt + (size_t)first * rs;
-                for (int j = 0; j < cnt; ++j, e += rs) {
-#pragma unroll
-                    for (int i = 0; i < NNU; ++i) accr[i] = fma(e[3 + i], pr, accr[i]);
-                    cmul(pr, pi, c1r, c1i);
-                }
-            }
-        }
-
-        // reciprocal space: sum over m* of E_{p_nu}(pi lam^2 |m* + k|^2).  Entry 0 is
-        // m* = 0, where a = alpha |k|^2 can be small (series of E1); every other entry
-        // has a >= alpha / (4 |A|_F^2) >= 1/4 (the setup raises lam to ensure it), so the
-        // main loop is one branch-free formula with E1 from the wide rational.
-        const bool need_e1 = pset_need_e1<SET, NNU>(args.prog), need_half = pset_need_half<SET, NNU>(args.prog);
-        if (valid) {
-            double rho = k[0] * k[0];
-            if (D > 1) rho = fma(k[1], k[1], rho);
-            if (D > 2) rho = fma(k[2], k[2], rho);
-            const double a = alpha * rho;
-            if (a <= acut) {
-                const double ex = ez_expm(a);
-                const double inv = ez_rcp(a);
-                double E1 = 0.0;
-                if (need_e1) E1 = (a < 0.25) ? ez_e1_series(a) : ex * ez_e1w_scaled(inv);
-                const double Eh = need_half ? ez_ehalf(a) : 0.0;
-#pragma unroll
-                for (int i = 0; i < NNU; ++i)
-                    acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
-            }
-        }
-        auto rec_term = [&](int q) {
-            const double *e = kt + (size_t)q * 4;
-            double qx = e[0] + k[0];
-            double rho = qx * qx;
-            if (D > 1) { double qy = e[1] + k[1]; rho = fma(qy, qy, rho); }
-            if (D > 2) { double qz = e[2] + k[2]; rho = fma(qz, qz, rho); }
-            const double a = alpha * rho;
-            if (a <= acut) {
-                const double ex = ez_expm(a);
-                const double inv = ez_rcp(a);
-                const double E1 = need_e1 ? ex * ez_e1w_scaled(inv) : 0.0;
-                const double Eh = need_half ? ez_ehalf(a) : 0.0;
-#pragma unroll
-                for (int i = 0; i < NNU; ++i)
-                    acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
-            }
-        };
-        if (valid) {
-            const int nk = kcount;
-            for (int j = 0; j < nk; ++j) rec_term(__builtin_amdgcn_readfirstlane((int)klist[j]));
-
-            double Z[NNU];
-#pragma unroll
-            for (int i = 0; i < NNU; ++i) Z[i] = accr[i] + M->K[i] * acck[i] - M->self_[i];
-
-            for (int t = 0; t < args.prog.n_terms; ++t) {
-                double prod = args.prog.term_coef[t];
-                for (int f = 0; f < args.prog.term_nfac[t]; ++f) {
-                    const int fi = args.prog.term_fac[t][f];
-                    double z = Z[0];
-#pragma unroll
-                    for (int i = 1; i < NNU; ++i) z = (fi == i) ? Z[i] : z;
-                    for (int m = 0; m < args.prog.term_mult[t][f]; ++m) prod *= z;
-                }
-                const int rr = args.prog.term_res[t];
-#pragma unroll
-                for (int r = 0; r < EZ_RES_MAX; ++r)
-                    if (rr == r) res[r] += prod;
-            }
-#pragma unroll
-            for (int r = 0; r < EZ_RES_MAX; ++r) res[r] *= W;
+            real_rows<D, NNU>(args, inst, th, 0, M->n_rows, accr);
+            rec_origin<D, NNU, SET>(args, k, alpha, acut, acck);
+            rec_list<D, NNU, SET>(args, kt, klist, 0, nk, k, alpha, acut, acck);
+            node_products<NNU>(args, M, accr, acck, W, res);
         }
     }
 
     // tile reduction: wave butterflies, then the four waves in fixed order
-    __shared__ double red[EZ_RES_MAX][EZ_TILE / 64][2];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int r = 0; r < EZ_RES_MAX; ++r) {
         if (r < n_res) {
             ez_dd v = ez_dd_wave_sum(ez_dd{res[r], 0.0});
-            if (lane == 0) { red[r][wave][0] = v.hi; red[r][wave][1] = v.lo; }
+            if (lane == 0) { L.red[r][wave][0] = v.hi; L.red[r][wave][1] = v.lo; }
         }
     }
     __syncthreads();
     if (threadIdx.x < n_res) {
         const int r = threadIdx.x;
-        ez_dd s{red[r][0][0], red[r][0][1]};
-        for (int wv = 1; wv < EZ_TILE / 64; ++wv) s = ez_dd_add(s, ez_dd{red[r][wv][0], red[r][wv][1]});
+        ez_dd s{L.red[r][0][0], L.red[r][0][1]};
+        for (int wv = 1; wv < EZ_TILE / 64; ++wv) s = ez_dd_add(s, ez_dd{L.red[r][wv][0], L.red[r][wv][1]});
         args.tile_part[((size_t)tile * n_res + r) * 2 + 0] = s.hi;
         args.tile_part[((size_t)tile * n_res + r) * 2 + 1] = s.lo;
     }
 }
 
-// one workgroup per tile
+// The last tiles of a call.  The tile kernel's workgroups run in rounds of (CUs x
+// workgroups per CU); when the tile count is just above a multiple of a round, the
+// last round holds a few tiles whose waves then run alone on their SIMDs for about
+// the time of a full round.  The host hands those tiles [n_main, n_tiles) to the
+// split kernel instead, launched after the tile kernel with one workgroup per CU:
+// each 64-node group of a tail tile is shared by EZ_TAIL_PARTS workgroups of four
+// waves, and wave s of part p takes the (4 p + s)-th of 4 EZ_TAIL_PARTS contiguous
+// shares of the real-space rows and of the culled reciprocal list (share 0 also
+// m* = 0) for all 64 nodes.  A workgroup adds its waves' partial sums in LDS in
+// wave order and stores them; the last of the group's workgroups to finish (a
+// counter, reset by that workgroup) adds the stored parts in part order, forms the
+// products and writes the 64-node partial to sub_part.  The finalize kernel adds
+// the four partials of a tile in the order the tile path adds its four waves.
+template <int D, int NNU, int SET>
+__device__ __forceinline__ void node_group_split(const EzQuadArgs &args, const int g, const int p, NodeLds &L) {
+    constexpr int NS = EZ_TILE / 64;              // waves per workgroup, = 64-node groups per tile
+    constexpr int NSH = NS * EZ_TAIL_PARTS;       // shares of a group's terms
+    const int tile = args.n_main + g / NS;
+    const int quarter = g % NS;
+    const int lane = (int)threadIdx.x & 63, s = (int)threadIdx.x >> 6;
+    const int j = p * NS + s;                     // this wave's share
+    const int inst = find_segment(args.tile_begin, args.batch, tile);
+    const EzInstPlan P = args.plans[inst];
+    const EzLatMeta *M = args.meta + inst;
+    const int n_res = args.prog.n_res;
+    const int tile0 = (tile - args.tile_begin[inst]) * EZ_TILE;
+    const int node = tile0 + quarter * 64 + lane;
+    const int n_nodes = P.n_dir * P.n_u;
+    unsigned short *klist = reinterpret_cast<unsigned short *>(L.kpool);
+
+    const bool ok = M->status == 0;               // uniform over the workgroup
+    const bool valid = node < n_nodes;
+    double accr[NNU], acck[NNU], W = 0.0;
+#pragma unroll
+    for (int i = 0; i < NNU; ++i) { accr[i] = 0.0; acck[i] = 0.0; }
+    if (ok) {
+        double k[3], th[3];
+        node_geometry<D>(P, args.rules, M, valid ? node : tile0, k, th, &W);
+        const double *kt = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
+        const double alpha = M->alpha, acut = M->a_cut;
+        const int nk = cull_reciprocal<D, EZ_TILE>(kt, M->n_rec, k, alpha, acut, klist, L.kbox, L.kwave, &L.kcount);
+        if (valid) {
+            const int n_rows = M->n_rows;
+            real_rows<D, NNU>(args, inst, th, j * n_rows / NSH, (j + 1) * n_rows / NSH, accr);
+            if (j == 0) rec_origin<D, NNU, SET>(args, k, alpha, acut, acck);
+            rec_list<D, NNU, SET>(args, kt, klist, j * nk / NSH, (j + 1) * nk / NSH, k, alpha, acut, acck);
+        }
+    }
+    __syncthreads();                              // the list is done: kpool takes the partial sums
+    double *acc = L.kpool;                        // [2 NNU][64]
+    for (int w = 0; w < NS; ++w) {
+        if (s == w) {
+#pragma unroll
+            for (int i = 0; i < NNU; ++i) {
+                acc[i * 64 + lane] = (w == 0) ? accr[i] : acc[i * 64 + lane] + accr[i];
+                acc[(NNU + i) * 64 + lane] = (w == 0) ? acck[i] : acc[(NNU + i) * 64 + lane] + acck[i];
+            }
+        }
+        __syncthreads();
+    }
+    if (s != 0) return;
+
+    // wave 0: store this part; the group's last part adds them all
+    constexpr int PART = 2 * NNU * 64;
+    double *mine = args.tail_acc + ((size_t)g * EZ_TAIL_PARTS + p) * PART;
+#pragma unroll
+    for (int i = 0; i < 2 * NNU; ++i) mine[i * 64 + lane] = acc[i * 64 + lane];
+    __threadfence();
+    int old = 0;
+    if (lane == 0) old = atomicAdd(args.tail_cnt + g, 1);
+    old = __shfl(old, 0, 64);
+    if (old != EZ_TAIL_PARTS - 1) return;
+    __threadfence();
+    if (lane == 0) args.tail_cnt[g] = 0;          // ready for the next call
+
+    double res[EZ_RES_MAX];
+#pragma unroll
+    for (int r = 0; r < EZ_RES_MAX; ++r) res[r] = 0.0;
+    if (ok && valid) {
+        const double *parts = args.tail_acc + (size_t)g * EZ_TAIL_PARTS * PART;
+#pragma unroll
+        for (int i = 0; i < NNU; ++i) {
+            double a = parts[i * 64 + lane], b = parts[(NNU + i) * 64 + lane];
+            for (int q = 1; q < EZ_TAIL_PARTS; ++q) {
+                a += parts[(size_t)q * PART + i * 64 + lane];
+                b += parts[(size_t)q * PART + (NNU + i) * 64 + lane];
+            }
+            accr[i] = a;
+            acck[i] = b;
+        }
+        node_products<NNU>(args, M, accr, acck, W, res);
+    }
+#pragma unroll
+    for (int r = 0; r < EZ_RES_MAX; ++r) {
+        if (r < n_res) {
+            ez_dd v = ez_dd_wave_sum(ez_dd{res[r], 0.0});
+            if (lane == 0) {
+                args.sub_part[((size_t)g * n_res + r) * 2 + 0] = v.hi;
+                args.sub_part[((size_t)g * n_res + r) * 2 + 1] = v.lo;
+            }
+        }
+    }
+}
+
+// one workgroup per tile (tiles [0, n_main))
 template <int D, int NNU, int SET>
 __global__ __launch_bounds__(EZ_TILE) void ez_node_kernel(EzQuadArgs args) {
-    node_tile<D, NNU, SET>(args, (int)blockIdx.x);
+    __shared__ NodeLds L;
+    node_tile<D, NNU, SET>(args, (int)blockIdx.x, L);
 }
 
 // persistent: a fixed grid of workgroups takes tiles from a queue, costliest first;
-// every workgroup leaves once the queue position passes the last tile
+// every workgroup leaves once the queue position passes the last tile.  Tiles from
+// n_main on are left to the split kernel.
 template <int D, int NNU, int SET>
 __global__ __launch_bounds__(EZ_TILE) void ez_node_persist_kernel(EzQuadArgs args) {
+    __shared__ NodeLds L;
     __shared__ int next;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(args.queue, 1);
@@ -260,8 +404,17 @@ __global__ __launch_bounds__(EZ_TILE) void ez_node_persist_kernel(EzQuadArgs arg
         const int t = __builtin_amdgcn_readfirstlane(next);
         __syncthreads();
         if (t >= args.n_tiles) break;
-        node_tile<D, NNU, SET>(args, __builtin_amdgcn_readfirstlane(args.tile_order[t]));
+        const int tile = __builtin_amdgcn_readfirstlane(args.tile_order[t]);
+        if (tile < args.n_main) node_tile<D, NNU, SET>(args, tile, L);
     }
+}
+
+// the tail: workgroup b takes part b % EZ_TAIL_PARTS of 64-node group b / EZ_TAIL_PARTS
+template <int D, int NNU, int SET>
+__global__ __launch_bounds__(EZ_TILE) void ez_node_split_kernel(EzQuadArgs args) {
+    __shared__ NodeLds L;
+    const int b = (int)blockIdx.x;
+    node_group_split<D, NNU, SET>(args, b / EZ_TAIL_PARTS, b % EZ_TAIL_PARTS, L);
 }
 
 __global__ void ez_fill_int_kernel(int *p, int n, int value) {
@@ -271,6 +424,18 @@ __global__ void ez_fill_int_kernel(int *p, int n, int value) {
 
 
 // ---------------------------------------------------------------------------
+// partial of tile t: from the tile kernels, or the split kernel's four 64-node
+// partials added in the order of the tile kernel's four waves
+__device__ __forceinline__ ez_dd tile_value(const EzQuadArgs &args, int t, int r, int n_res) {
+    if (t < args.n_main)
+        return ez_dd{args.tile_part[((size_t)t * n_res + r) * 2], args.tile_part[((size_t)t * n_res + r) * 2 + 1]};
+    const size_t g0 = (size_t)(t - args.n_main) * (EZ_TILE / 64);
+    ez_dd s{args.sub_part[(g0 * n_res + r) * 2], args.sub_part[(g0 * n_res + r) * 2 + 1]};
+    for (int q = 1; q < EZ_TILE / 64; ++q)
+        s = ez_dd_add(s, ez_dd{args.sub_part[((g0 + q) * n_res + r) * 2], args.sub_part[((g0 + q) * n_res + r) * 2 + 1]});
+    return s;
+}
+
 __global__ __launch_bounds__(256) void ez_finalize_kernel(EzQuadArgs args) {
     const int inst = blockIdx.x;
     const int n_res = args.prog.n_res;
@@ -287,7 +452,7 @@ __global__ __launch_bounds__(256) void ez_finalize_kernel(EzQuadArgs args) {
     for (int r = 0; r < n_res; ++r) {
         ez_dd s{0.0, 0.0};
         for (int t = tb + (int)threadIdx.x; t < te; t += 256)
-            s = ez_dd_add(s, ez_dd{args.tile_part[((size_t)t * n_res + r) * 2], args.tile_part[((size_t)t * n_res + r) * 2 + 1]});
+            s = ez_dd_add(s, tile_value(args, t, r, n_res));
         for (int g = db + (int)threadIdx.x; g < de; g += 256)
             s = ez_dd_add_d(s, args.dir_part[(size_t)g * n_res + r]);
         s = ez_dd_wave_sum(s);
@@ -349,7 +514,8 @@ __global__ __launch_bounds__(256) void ez_finalize_kernel(EzQuadArgs args) {
 }
 
 // mode 0: one workgroup per tile (n = tiles); mode 1: persistent (n = workgroups);
-// mode 2: report the persistent kernel's resident workgroups per CU in *n
+// mode 2: report the persistent kernel's resident workgroups per CU in *bpc;
+// mode 3: split kernel (n = workgroups); mode 4: the tile kernel's workgroups per CU
 template <int D, int NNU, int SET = 0>
 hipError_t launch_nodes_t(const EzQuadArgs &args, int n_tiles, hipStream_t stream, int mode = 0, int *bpc = nullptr) {
     if (mode == 2) {
@@ -364,10 +530,40 @@ hipError_t launch_nodes_t(const EzQuadArgs &args, int n_tiles, hipStream_t strea
         *bpc = cached;
         return hipSuccess;
     }
-    if (mode == 1)
+    if (mode == 4) {
+        static int cached_t = 0;
+        if (!cached_t) {
+            int nb = 0;
+            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ez_node_kernel<D, NNU, SET>, EZ_TILE, 0);
+            if (e != hipSuccess) return e;
+            cached_t = nb > 0 ? nb : 1;
+        }
+        *bpc = cached_t;
+        return hipSuccess;
+    }
+    if (mode == 3) {
+        // unused dynamic LDS (more than half a CU's LDS with the static part, within the
+        // per-workgroup limit) keeps the split kernel at one workgroup per CU, so that
+        // its few workgroups spread over the device instead of filling a few CUs
+        static int pad = -1;
+        if (pad < 0) {
+            hipFuncAttributes fa;
+            int dev = 0, per_cu = 0, per_blk = 0;
+            hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&ez_node_split_kernel<D, NNU, SET>));
+            if (e == hipSuccess) e = hipGetDevice(&dev);
+            if (e == hipSuccess) e = hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+            if (e == hipSuccess) e = hipDeviceGetAttribute(&per_blk, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+            if (e != hipSuccess) return e;
+            const long want = (long)per_cu / 2 + 1024 - (long)fa.sharedSizeBytes;
+            const long cap = (long)per_blk - (long)fa.sharedSizeBytes;
+            pad = (int)std::max(0L, std::min(want, cap));
+        }
+        hipLaunchKernelGGL((ez_node_split_kernel<D, NNU, SET>), dim3(n_tiles), dim3(EZ_TILE), pad, stream, args);
+    } else if (mode == 1) {
         hipLaunchKernelGGL((ez_node_persist_kernel<D, NNU, SET>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
-    else
+    } else {
         hipLaunchKernelGGL((ez_node_kernel<D, NNU, SET>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
+    }
     return hipGetLastError();
 }
 
@@ -404,6 +600,18 @@ hipError_t ez_launch_nodes_impl(const EzQuadArgs &args, int n_tiles, hipStream_t
 
 hipError_t ez_launch_nodes(const EzQuadArgs &args, int n_tiles, hipStream_t stream) {
     return ez_launch_nodes_impl(args, n_tiles, stream);
+}
+
+hipError_t ez_launch_nodes_split(const EzQuadArgs &args, hipStream_t stream) {
+    const int groups = (args.n_tiles - args.n_main) * (EZ_TILE / 64);
+    if (groups <= 0) return hipSuccess;
+    return ez_launch_nodes_impl(args, groups * EZ_TAIL_PARTS, stream, 3);
+}
+
+int ez_nodes_tile_blocks_per_cu(const EzQuadArgs &args) {
+    int bpc = 1;
+    if (ez_launch_nodes_impl(args, 0, nullptr, 4, &bpc) != hipSuccess) return 1;
+    return bpc;
 }
 
 hipError_t ez_launch_nodes_persistent(const EzQuadArgs &args, int n_blocks, hipStream_t stream) {

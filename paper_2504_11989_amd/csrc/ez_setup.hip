@@ -10,29 +10,27 @@
 // Reciprocal space: every m* with |m*| <= sqrt(a_cut/pi)/lam + r_BZ, m* = 0 first,
 // where r_BZ bounds |k| over the reduced cell B[-1/2,1/2]^d of the nodes.
 //
-// One workgroup per lattice; point order is the enumeration order of the
-// integer box, made deterministic by a ballot/prefix compaction.
+// One workgroup of 1024 threads per lattice.  The kernel is latency-bound (a
+// handful of lattices per call), so it is laid out to keep its critical path
+// short: every thread derives the lattice constants and both enumeration boxes
+// in registers (no serial section on one lane), the two boxes are enumerated in
+// one index space, and the incomplete-gamma weights, the row records and the
+// per-exponent constants are computed in one parallel phase.  Point order is
+// the enumeration order of the integer box (n_1 fastest), made deterministic by
+// a ballot/prefix compaction with one barrier per chunk.
 #include "ez_internal.h"
 #include "ez_math.h"
 #include "ez_kernels.h"
 
 namespace {
 
-constexpr int SB = 256;   // threads per setup workgroup
+constexpr int SB = 1024;        // threads per setup workgroup
+constexpr int NW = SB / 64;     // waves
 
-struct SetupShared {
-    double A[9], Ai[9], B[9];
-    double V, lam, alpha, Rr, Rk;
-    int lo[3], hi[3];        // enumeration box
-    long long nbox;
-    int count;
-    uint32_t status;
-    int wave_tot[SB / 64];
-};
-
-__device__ void mat_inverse(int d, const double *M, double *Mi, double *det) {
-    if (d == 1) { *det = M[0]; Mi[0] = 1.0 / M[0]; return; }
-    if (d == 2) {
+template <int d>
+__device__ __forceinline__ void mat_inverse(const double *M, double *Mi, double *det) {
+    if constexpr (d == 1) { *det = M[0]; Mi[0] = 1.0 / M[0]; return; }
+    if constexpr (d == 2) {
         double dt = M[0] * M[3] - M[1] * M[2];
         *det = dt;
         Mi[0] = M[3] / dt; Mi[1] = -M[1] / dt; Mi[2] = -M[2] / dt; Mi[3] = M[0] / dt;
@@ -50,7 +48,8 @@ __device__ void mat_inverse(int d, const double *M, double *Mi, double *det) {
 }
 
 // half of the largest |M s|, s in {+-1}^d: bounds |M t| over t in [-1/2,1/2]^d
-__device__ double half_diag(int d, const double *M) {
+template <int d>
+__device__ __forceinline__ double half_diag(const double *M) {
     double best = 0.0;
     for (int s = 0; s < (1 << d); ++s) {
         double n2 = 0.0;
@@ -64,111 +63,155 @@ __device__ double half_diag(int d, const double *M) {
     return 0.5 * sqrt(best);
 }
 
-// Block-wide deterministic compaction: returns this thread's slot (or -1) and
-// advances sh->count by the number of kept items, in thread order.
-__device__ int compact_slot(bool keep, SetupShared *sh) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    unsigned long long m = __ballot(keep);
-    int before = __popcll(m & ((1ull << lane) - 1ull));
-    if (lane == 0) sh->wave_tot[wave] = __popcll(m);
-    __syncthreads();
-    int off = sh->count;
-    for (int w = 0; w < wave; ++w) off += sh->wave_tot[w];
-    int slot = keep ? off + before : -1;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int tot = 0;
-        for (int w = 0; w < SB / 64; ++w) tot += sh->wave_tot[w];
-        sh->count += tot;
-    }
-    __syncthreads();
-    return slot;
-}
-
-__device__ void box_index(long long idx, const int *lo, const int *hi, int d, int *n) {
-    for (int i = 0; i < 3; ++i) n[i] = 0;
+// integer box |n_i| <= h_i with h_i = floor(R * norm_i); false if it is too large
+template <int d>
+__device__ __forceinline__ bool make_box(double R, const double *norm2, int *h, int *nbox) {
+    long long nb = 1;
+    for (int i = 0; i < 3; ++i) h[i] = 0;
     for (int i = 0; i < d; ++i) {
-        long long w = hi[i] - lo[i] + 1;
-        n[i] = lo[i] + (int)(idx % w);
-        idx /= w;
+        const double hb = floor(R * sqrt(norm2[i]));
+        if (!(hb <= 67108864.0)) return false;
+        h[i] = (int)hb;
+        nb *= (long long)(2 * h[i] + 1);
+    }
+    if (nb > (1ll << 26)) return false;
+    *nbox = (int)nb;
+    return true;
+}
+
+// box index -> integer point, n_1 fastest
+template <int d>
+__device__ __forceinline__ void box_point(int idx, const int *h, int *n) {
+    n[0] = n[1] = n[2] = 0;
+    for (int i = 0; i < d; ++i) {
+        const int w = 2 * h[i] + 1;
+        const int q = idx / w;
+        n[i] = idx - q * w - h[i];
+        idx = q;
     }
 }
 
-__global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
-    __shared__ SetupShared sh;
-    const int inst = blockIdx.x;
-    const int d = args.prog.d;
-    const EzInstPlan plan = args.plans[inst];
-    EzLatMeta *meta = args.meta + inst;
-    const double lam_rel = plan.lam_rel;
-    const double a_cut = args.a_cut;
+// Gamma(s, a) = a^s E_{1-s}(a) for 2 s an integer (the quadrature exponents are
+// integers, so nu/2 and nu/2 + 1 always are), through the E_p recurrences
+// (out of line: the kernel runs 1024-thread workgroups within 128 registers)
+__device__ __attribute__((noinline)) double gamma_upper_half(int s2, double a) {
+    const int p2 = 2 - s2;
+    const double e = exp(-a), inv = 1.0 / a;
+    const double E1 = ((p2 & 1) == 0 && p2 >= 2) ? ez_e1(a, e, inv) : 0.0;
+    const double Eh = (p2 & 1) ? ez_ehalf(a) : 0.0;
+    return pow(a, 0.5 * (double)s2) * ez_ep_from(p2, a, e, inv, E1, Eh);
+}
 
-    if (threadIdx.x == 0) {
-        uint32_t st = 0;
-        for (int i = 0; i < 9; ++i) sh.A[i] = 0.0;
-        for (int i = 0; i < d * d; ++i) {
-            sh.A[i] = args.A[(size_t)inst * d * d + i];
-            if (!isfinite(sh.A[i])) st |= 0x1u;
-        }
-        double det = 0.0;
-        if (!st) {
-            mat_inverse(d, sh.A, sh.Ai, &det);
-            if (!(fabs(det) > 1e-300) || !isfinite(det)) st |= 0x1u;
-        }
-        if (!st) {
-            for (int i = 0; i < d; ++i)
-                for (int j = 0; j < d; ++j) sh.B[i * d + j] = sh.Ai[j * d + i];
-            sh.V = fabs(det);
-            sh.lam = lam_rel * pow(sh.V, 1.0 / d);
-            // every m* != 0 then has pi lam^2 |m* + k|^2 >= 1/4 for the quadrature nodes
-            // k in B[-1/2,1/2]^d (|m* + k| >= sigma_min(B)/2 >= 1/(2 |A|_F)); the node
-            // kernel's rational E1 is fitted for arguments >= 1/4
-            if (!args.general_x) {
-                double fro2 = 0.0;
-                for (int i = 0; i < d * d; ++i) fro2 += sh.A[i] * sh.A[i];
-                sh.lam = fmax(sh.lam, sqrt(fro2 / EZ_PI) * (1.0 + 1e-12));
-            }
-            sh.alpha = EZ_PI * sh.lam * sh.lam;
-            sh.Rr = sh.lam * sqrt(a_cut / EZ_PI);
-            sh.Rk = sqrt(a_cut / EZ_PI) / sh.lam;
-            if (args.general_x) sh.Rr += half_diag(d, sh.A);
-            // box for |A n| <= Rr: |n_i| <= Rr |row_i(A^{-1})|
-            long long nb = 1;
-            for (int i = 0; i < 3; ++i) { sh.lo[i] = 0; sh.hi[i] = 0; }
-            for (int i = 0; i < d; ++i) {
-                double r = 0.0;
-                for (int j = 0; j < d; ++j) r += sh.Ai[i * d + j] * sh.Ai[i * d + j];
-                int h = (int)floor(sh.Rr * sqrt(r));
-                sh.lo[i] = -h; sh.hi[i] = h;
-                nb *= (long long)(2 * h + 1);
-            }
-            sh.nbox = nb;
-            if (nb > (1ll << 26)) st |= 0x2u;
-        }
-        sh.status = st;
-        sh.count = 0;
+// Deterministic two-list compaction of one chunk.  Each list keeps a running
+// count that every thread carries in a register; the per-wave totals are double
+// buffered in LDS (chunk parity), so one barrier per chunk suffices: a buffer is
+// rewritten two chunks later, after a barrier that every reader has passed.
+// The barrier orders LDS only; global stores made between calls are ordered by
+// a __syncthreads() of the caller.
+struct Compact {
+    int cnt[2];
+    int chunk;
+};
+
+__device__ __forceinline__ void compact2(bool k0, bool k1, Compact &c, int (*wt)[2][NW], int *slot0, int *slot1) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned long long b0 = __ballot(k0), b1 = __ballot(k1);
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    const int buf = c.chunk & 1;
+    if (lane == 0) { wt[buf][0][wave] = __popcll(b0); wt[buf][1][wave] = __popcll(b1); }
+    // orders the LDS totals only: the table stores of earlier chunks need not
+    // complete before the barrier (the caller fences them once, after the loop)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    int o0 = c.cnt[0], o1 = c.cnt[1], t0 = 0, t1 = 0;
+    for (int w = 0; w < NW; ++w) {
+        const int a = wt[buf][0][w], b = wt[buf][1][w];
+        if (w < wave) { o0 += a; o1 += b; }
+        t0 += a; t1 += b;
     }
-    __syncthreads();
-    if (sh.status) {
-        if (threadIdx.x == 0) {
-            meta->status = sh.status; meta->n_real = 0; meta->n_rec = 0;
-            if (args.status_out) args.status_out[0] = sh.status;
+    *slot0 = k0 ? o0 + __popcll(b0 & lt) : -1;
+    *slot1 = k1 ? o1 + __popcll(b1 & lt) : -1;
+    c.cnt[0] += t0;
+    c.cnt[1] += t1;
+    ++c.chunk;
+}
+
+template <int D>
+__global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
+    __shared__ int wt[2][2][NW];
+    const int inst = blockIdx.x;
+    const int tid = threadIdx.x;
+    constexpr int d = D;
+    const double lam_rel = args.plans[inst].lam_rel;
+    const double a_cut = args.a_cut;
+    EzLatMeta *meta = args.meta + inst;
+
+    // ---------------- lattice constants (every thread, identical values) ----------------
+    uint32_t st = 0;
+    double A[9], Ai[9], B[9];
+    for (int i = 0; i < 9; ++i) { A[i] = 0.0; Ai[i] = 0.0; B[i] = 0.0; }
+    for (int i = 0; i < d * d; ++i) {
+        A[i] = args.A[(size_t)inst * d * d + i];
+        if (!isfinite(A[i])) st |= 0x1u;
+    }
+    double det = 0.0;
+    if (!st) {
+        mat_inverse<D>(A, Ai, &det);
+        if (!(fabs(det) > 1e-300) || !isfinite(det)) st |= 0x1u;
+    }
+    double V = 0.0, lam = 0.0, alpha = 0.0, Rr = 0.0, Rk = 0.0;
+    int hr[3] = {0, 0, 0}, hk[3] = {0, 0, 0}, nbox_r = 0, nbox_k = 0;
+    if (!st) {
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j) B[i * d + j] = Ai[j * d + i];
+        V = fabs(det);
+        lam = lam_rel * pow(V, 1.0 / d);
+        // every m* != 0 then has pi lam^2 |m* + k|^2 >= 1/4 for the quadrature nodes
+        // k in B[-1/2,1/2]^d (|m* + k| >= sigma_min(B)/2 >= 1/(2 |A|_F)); the node
+        // kernel's rational E1 is fitted for arguments >= 1/4
+        if (!args.general_x) {
+            double fro2 = 0.0;
+            for (int i = 0; i < d * d; ++i) fro2 += A[i] * A[i];
+            lam = fmax(lam, sqrt(fro2 / EZ_PI) * (1.0 + 1e-12));
+        }
+        alpha = EZ_PI * lam * lam;
+        Rr = lam * sqrt(a_cut / EZ_PI);
+        if (args.general_x) Rr += half_diag<D>(A);
+        // real box for |A n| <= Rr: |n_i| <= Rr |row_i(A^{-1})|
+        // reciprocal box for |B m| <= Rk + r_BZ: |m_i| <= R |row_i(B^{-1})| = R |col_i(A)|
+        Rk = sqrt(a_cut / EZ_PI) / lam + half_diag<D>(B);
+        double nr[3] = {0.0, 0.0, 0.0}, nk[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j) { nr[i] += Ai[i * d + j] * Ai[i * d + j]; nk[i] += A[j * d + i] * A[j * d + i]; }
+        if (!make_box<D>(Rr, nr, hr, &nbox_r) || !make_box<D>(Rk, nk, hk, &nbox_k)) st |= 0x2u;
+    }
+    if (st) {                                      // uniform over the workgroup
+        if (tid == 0) {
+            meta->status = st; meta->n_real = 0; meta->n_rec = 0; meta->n_rows = 0;
+            if (args.status_out) args.status_out[0] = st;
         }
         return;
     }
 
-    // ---------------- real-space table ----------------
+    // ---------------- both tables: real box, then reciprocal box ----------------
     const int rs = args.tab.rstride;
     double *rtab = args.tab.real + (size_t)inst * args.tab.real_cap * rs;
-    const double Rr2 = sh.Rr * sh.Rr;
-    for (long long base = 0; base < sh.nbox; base += SB) {
-        long long idx = base + threadIdx.x;
-        bool keep = false;
-        double z[3] = {0.0, 0.0, 0.0};
+    double *ktab = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
+    int *rn = args.general_x ? nullptr : args.tab.rn + (size_t)inst * args.tab.real_cap * 4;
+    const double Rr2 = Rr * Rr, Rk2 = Rk * Rk;
+    if (tid == 0) { ktab[0] = 0.0; ktab[1] = 0.0; ktab[2] = 0.0; ktab[3] = 0.0; }   // m* = 0 first
+    Compact cp;
+    cp.cnt[0] = 0; cp.cnt[1] = 1; cp.chunk = 0;
+    const int n_all = nbox_r + nbox_k;
+    for (int base = 0; base < n_all; base += SB) {
+        const int idx = base + tid;
+        bool keep_r = false, keep_k = false;
+        double v[3] = {0.0, 0.0, 0.0};
         int n[3] = {0, 0, 0};
-        if (idx < sh.nbox) {
-            box_index(idx, sh.lo, sh.hi, d, n);
-            bool nonzero = (n[0] | n[1] | n[2]) != 0;
+        if (idx < nbox_r) {
+            box_point<D>(idx, hr, n);
+            const bool nonzero = (n[0] | n[1] | n[2]) != 0;
             // pairs mode: keep the representative whose last nonzero coordinate is > 0
             bool half = true;
             if (!args.general_x) {
@@ -178,193 +221,133 @@ __global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
             }
             for (int i = 0; i < d; ++i) {
                 double s = 0.0;
-                for (int j = 0; j < d; ++j) s += sh.A[i * d + j] * (double)n[j];
-                z[i] = s;
+                for (int j = 0; j < d; ++j) s += A[i * d + j] * (double)n[j];
+                v[i] = s;
             }
-            double r2 = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
-            keep = (args.general_x ? true : nonzero) && half && r2 <= Rr2;
+            const double r2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+            keep_r = (args.general_x ? true : nonzero) && half && r2 <= Rr2;
+        } else if (idx < n_all) {
+            box_point<D>(idx - nbox_r, hk, n);
+            for (int i = 0; i < d; ++i) {
+                double s = 0.0;
+                for (int j = 0; j < d; ++j) s += B[i * d + j] * (double)n[j];
+                v[i] = s;
+            }
+            const double r2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+            keep_k = ((n[0] | n[1] | n[2]) != 0) && r2 <= Rk2;
         }
-        int slot = compact_slot(keep, &sh);
-        if (keep) {
-            if (slot < args.tab.real_cap) {
-                double *e = rtab + (size_t)slot * rs;
-                e[0] = z[0]; e[1] = z[1]; e[2] = z[2];
-                if (!args.general_x) {
-                    int *ni = args.tab.rn + ((size_t)inst * args.tab.real_cap + slot) * 4;
-                    ni[0] = n[0]; ni[1] = n[1]; ni[2] = n[2]; ni[3] = 0;
-                }
-            } else {
-                atomicOr(&sh.status, 0x2u);
-            }
+        int sr, sk;
+        compact2(keep_r, keep_k, cp, wt, &sr, &sk);
+        if (keep_r && sr < args.tab.real_cap) {
+            double *e = rtab + (size_t)sr * rs;
+            e[0] = v[0]; e[1] = v[1]; e[2] = v[2];
+            if (rn) { int *ni = rn + (size_t)sr * 4; ni[0] = n[0]; ni[1] = n[1]; ni[2] = n[2]; ni[3] = 0; }
         }
-    }
-    __syncthreads();
-    const int n_real = min(sh.count, args.tab.real_cap);
-    // weights (pairs mode only; general-x weights depend on x)
-    if (!args.general_x) {
-        for (int t = threadIdx.x; t < n_real; t += SB) {
-            double *e = rtab + (size_t)t * rs;
-            double r2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
-            double a = EZ_PI * r2 / (sh.lam * sh.lam);
-            for (int i = 0; i < args.prog.n_nu; ++i) {
-                double nu = args.prog.nu[i];
-                double w = ez_gamma_upper(0.5 * nu, a) * ez_rgamma(0.5 * nu) * pow(r2, -0.5 * nu);
-                e[3 + i] = 2.0 * w;
-            }
-            int used = 3 + args.prog.n_nu;
-            if (args.grad) {
-                // strain weights: d(2 W_nu)/d|z|^2 times 2 (from d|z|^2 = 2 z^T G z), with
-                // dW_nu/d|z|^2 = -Gamma(nu/2 + 1, a) / (Gamma(nu/2) |z|^{nu+2})
-                for (int i = 0; i < args.prog.n_nu; ++i) {
-                    double nu = args.prog.nu[i];
-                    e[used + i] = -4.0 * ez_gamma_upper(0.5 * nu + 1.0, a) * ez_rgamma(0.5 * nu) *
-                                  pow(r2, -0.5 * nu - 1.0);
-                }
-                used += args.prog.n_nu;
-            }
-            for (int i = used; i < rs; ++i) e[i] = 0.0;
+        if (keep_k && sk < args.tab.rec_cap) {
+            double *e = ktab + (size_t)sk * 4;
+            e[0] = v[0]; e[1] = v[1]; e[2] = v[2];
+            e[3] = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
         }
     }
-    __syncthreads();
-    // rows of the real-space table (pairs mode)
+    if (cp.cnt[0] > args.tab.real_cap || cp.cnt[1] > args.tab.rec_cap) st |= 0x2u;   // uniform
+    const int n_real = min(cp.cnt[0], args.tab.real_cap);
+    const int n_rec = min(cp.cnt[1], args.tab.rec_cap);
+    __syncthreads();                               // table entries visible to the workgroup
+
+    // ---------------- row starts of the real-space table (pairs mode) ----------------
+    int *rows = args.general_x ? nullptr : args.tab.rows + (size_t)inst * args.tab.row_cap * 8;
+    int n_rows = 0;
     if (!args.general_x) {
-        const int *rn = args.tab.rn + (size_t)inst * args.tab.real_cap * 4;
-        int *rows = args.tab.rows + (size_t)inst * args.tab.row_cap * 8;
-        if (threadIdx.x == 0) sh.count = 0;
-        __syncthreads();
+        Compact rc;
+        rc.cnt[0] = 0; rc.cnt[1] = 0; rc.chunk = cp.chunk;
         for (int base = 0; base < n_real; base += SB) {
-            const int t = base + (int)threadIdx.x;
+            const int t = base + tid;
             bool start = false;
-            if (t < n_real) {
+            if (t < n_real)
                 start = (t == 0) || rn[4 * t + 1] != rn[4 * (t - 1) + 1] || rn[4 * t + 2] != rn[4 * (t - 1) + 2];
-            }
-            int slot = compact_slot(start, &sh);
+            int slot, unused;
+            compact2(start, false, rc, wt, &slot, &unused);
             if (start && slot < args.tab.row_cap) {
-                int cnt = 1;
-                while (t + cnt < n_real && rn[4 * (t + cnt) + 1] == rn[4 * t + 1] && rn[4 * (t + cnt) + 2] == rn[4 * t + 2]) ++cnt;
                 int *R = rows + (size_t)slot * 8;
-                R[0] = t; R[1] = cnt; R[2] = rn[4 * t]; R[3] = rn[4 * t + 1]; R[4] = rn[4 * t + 2];
-            } else if (start) {
-                atomicOr(&sh.status, 0x2u);
+                R[0] = t; R[2] = rn[4 * t]; R[3] = rn[4 * t + 1]; R[4] = rn[4 * t + 2];
             }
         }
-        __syncthreads();
-        const int n_rows = min(sh.count, args.tab.row_cap);
-        for (int r = threadIdx.x; r < n_rows; r += SB) {
+        if (rc.cnt[0] > args.tab.row_cap) st |= 0x2u;
+        n_rows = min(rc.cnt[0], args.tab.row_cap);
+        __syncthreads();                           // row starts visible to the workgroup
+    }
+
+    if (tid == 0) {
+        for (int i = 0; i < 9; ++i) { meta->A[i] = A[i]; meta->B[i] = B[i]; }
+        meta->V = V;
+        meta->lam = lam;
+        meta->alpha = alpha;
+        meta->a_cut = a_cut;
+        meta->n_real = n_real;
+        meta->n_rec = n_rec;
+        meta->n_rows = n_rows;
+        meta->status = st;
+        if (args.status_out) args.status_out[0] = st;
+    }
+
+    // ---------------- one parallel phase: per-exponent constants, row records, weights ----------------
+    // items [0, 3 EZ_NU_MAX): constant c of exponent i (K, self, sig); then the
+    // n_rows row records; then (entry, exponent) weight pairs (pairs mode)
+    const int n_nu = args.prog.n_nu;
+    const int n_const = 3 * EZ_NU_MAX;
+    const int n_items = n_const + n_rows + (args.general_x ? 0 : n_real * n_nu);
+    for (int j = tid; j < n_items; j += SB) {
+        if (j < n_const) {
+            const int i = j / 3, c = j - 3 * i;
+            double val = 0.0;
+            if (i < n_nu) {
+                const double nu = args.prog.nu[i];
+                if (c == 0) val = args.nuc[i][0] / V * pow(alpha, 0.5 * (d - nu));
+                else if (c == 1) val = pow(EZ_PI / (lam * lam), 0.5 * nu) * args.nuc[i][1];
+                else val = args.nuc[i][2] / V;
+            }
+            (c == 0 ? meta->K : c == 1 ? meta->self_ : meta->sig)[i] = val;
+        } else if (j < n_const + n_rows) {
+            // row r covers entries [R[0], next start): consecutive n1 at fixed (n2, n3)
+            const int r = j - n_const;
             int *R = rows + (size_t)r * 8;
+            const int next = (r + 1 < n_rows) ? rows[(size_t)(r + 1) * 8] : n_real;
+            R[1] = next - R[0];
             const int *Rp = rows + (size_t)(r > 0 ? r - 1 : 0) * 8;
             const bool np = (r == 0) || R[4] != Rp[4];
             R[5] = np ? 1 : 0;
             R[6] = np ? 0 : R[2] - Rp[2];
             R[7] = np ? 0 : R[3] - Rp[3];
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) meta->n_rows = n_rows;
-    } else if (threadIdx.x == 0) {
-        meta->n_rows = 0;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        sh.count = 0;
-        // reciprocal box: |B m| <= Rk + r_BZ  ->  |m_i| <= R |row_i(B^{-1})| = R |col_i(A)|
-        double R = sh.Rk + half_diag(d, sh.B);
-        long long nb = 1;
-        for (int i = 0; i < 3; ++i) { sh.lo[i] = 0; sh.hi[i] = 0; }
-        for (int i = 0; i < d; ++i) {
-            double r = 0.0;
-            for (int j = 0; j < d; ++j) r += sh.A[j * d + i] * sh.A[j * d + i];
-            int h = (int)floor(R * sqrt(r));
-            sh.lo[i] = -h; sh.hi[i] = h;
-            nb *= (long long)(2 * h + 1);
-        }
-        sh.nbox = nb;
-        if (nb > (1ll << 26)) sh.status |= 0x2u;
-        sh.Rk = R;
-        // m* = 0 first
-        double *e = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
-        e[0] = e[1] = e[2] = e[3] = 0.0;
-        sh.count = 1;
-    }
-    __syncthreads();
-    double *ktab = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
-    const double Rk2 = sh.Rk * sh.Rk;
-    // inner: entries that can reach a = alpha |m* + k|^2 < 1 for a node k in B[-1/2,1/2]^d.
-    // |m* + k| >= sigma_min(B) (|m|_inf - 1/2) and sigma_min(B) >= 1/|A|_F give the test.
-    double fro2 = 0.0;
-    for (int i = 0; i < d * d; ++i) fro2 += sh.A[i] * sh.A[i];
-    int n_inner = 1;
-    for (int pass = 0; pass < 2; ++pass) {
-        if (sh.status & 0x2u) break;
-        for (long long base = 0; base < sh.nbox; base += SB) {
-            long long idx = base + threadIdx.x;
-            bool keep = false;
-            double m[3] = {0.0, 0.0, 0.0};
-            if (idx < sh.nbox) {
-                int n[3];
-                box_index(idx, sh.lo, sh.hi, d, n);
-                for (int i = 0; i < d; ++i) {
-                    double s = 0.0;
-                    for (int j = 0; j < d; ++j) s += sh.B[i * d + j] * (double)n[j];
-                    m[i] = s;
-                }
-                double r2 = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
-                int ninf = max(abs(n[0]), max(abs(n[1]), abs(n[2])));
-                double g = (double)ninf - 0.5;
-                bool inner = sh.alpha * g * g < fro2;
-                keep = ((n[0] | n[1] | n[2]) != 0) && r2 <= Rk2 && (pass == 0 ? inner : !inner);
+        } else {
+            const int q = j - n_const - n_rows;
+            const int t = q / n_nu, i = q - t * n_nu;
+            double *e = rtab + (size_t)t * rs;
+            const double r2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+            const double a = EZ_PI * r2 / (lam * lam);
+            const double nu = args.prog.nu[i];
+            e[3 + i] = 2.0 * gamma_upper_half((int)nu, a) * args.nuc[i][3] * pow(r2, -0.5 * nu);
+            int used = 3 + n_nu;
+            if (args.grad) {
+                // strain weights: d(2 W_nu)/d|z|^2 times 2 (from d|z|^2 = 2 z^T G z), with
+                // dW_nu/d|z|^2 = -Gamma(nu/2 + 1, a) / (Gamma(nu/2) |z|^{nu+2})
+                e[used + i] = -4.0 * gamma_upper_half((int)nu + 2, a) * args.nuc[i][3] *
+                              pow(r2, -0.5 * nu - 1.0);
+                used += n_nu;
             }
-            int slot = compact_slot(keep, &sh);
-            if (keep) {
-                if (slot < args.tab.rec_cap) {
-                    double *e = ktab + (size_t)slot * 4;
-                    e[0] = m[0]; e[1] = m[1]; e[2] = m[2];
-                    e[3] = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
-                } else {
-                    atomicOr(&sh.status, 0x2u);
-                }
-            }
+            if (i == 0)
+                for (int c = used; c < rs; ++c) e[c] = 0.0;
         }
-        if (pass == 0) n_inner = sh.count;
-        __syncthreads();
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < 9; ++i) { meta->A[i] = sh.A[i]; meta->B[i] = sh.B[i]; }
-        meta->V = sh.V;
-        meta->lam = sh.lam;
-        meta->alpha = sh.alpha;
-        meta->a_cut = a_cut;
-        for (int i = 0; i < EZ_NU_MAX; ++i) { meta->K[i] = 0.0; meta->self_[i] = 0.0; meta->sig[i] = 0.0; }
-        for (int i = 0; i < args.prog.n_nu; ++i) {
-            double nu = args.prog.nu[i];
-            double s = 0.5 * (d - nu);
-            double rg = ez_rgamma(0.5 * nu);
-            double cp = pow(EZ_PI, nu - 0.5 * d) * rg / sh.V;
-            meta->K[i] = cp * pow(sh.alpha, s);
-            meta->self_[i] = pow(EZ_PI / (sh.lam * sh.lam), 0.5 * nu) * ez_rgamma(0.5 * nu + 1.0);
-            int m = args.prog.logm[i];
-            if (m >= 0) {
-                double mf = 1.0;
-                for (int j = 2; j <= m; ++j) mf *= (double)j;
-                meta->sig[i] = pow(EZ_PI, 2.0 * m + 0.5 * d) * ez_rgamma(m + 0.5 * d) *
-                               (((m + 1) & 1) ? -1.0 : 1.0) / mf / sh.V;
-            } else {
-                meta->sig[i] = cp * tgamma(s);
-            }
-        }
-        meta->n_real = n_real;
-        meta->n_rec = min(sh.count, args.tab.rec_cap);
-        meta->n_inner = min(n_inner, meta->n_rec);
-        uint32_t st = sh.status;
-        if (sh.count > args.tab.rec_cap) st |= 0x2u;
-        meta->status = st;
-        if (args.status_out) args.status_out[0] = st;
     }
 }
 
 }  // namespace
 
 hipError_t ez_launch_setup(const EzSetupArgs &args, int batch, hipStream_t stream) {
-    hipLaunchKernelGGL(ez_setup_kernel, dim3(batch), dim3(SB), 0, stream, args);
+    switch (args.prog.d) {
+        case 1: hipLaunchKernelGGL(ez_setup_kernel<1>, dim3(batch), dim3(SB), 0, stream, args); break;
+        case 2: hipLaunchKernelGGL(ez_setup_kernel<2>, dim3(batch), dim3(SB), 0, stream, args); break;
+        case 3: hipLaunchKernelGGL(ez_setup_kernel<3>, dim3(batch), dim3(SB), 0, stream, args); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }

@@ -100,3 +100,45 @@ def test_autotune_picks_a_valid_configuration(ez):
     tuned = scan_sums(A, autotune.apply(specs, res["lam"], res["flags"])).cpu().numpy()
     base = scan_sums(A, autotune.apply(specs, 1.3, 0)).cpu().numpy()
     assert np.all(np.abs(tuned - base) <= 1e-12 * np.abs(base))
+
+
+def tail_launches(ez, fn):
+    from paper_2504_11989_amd import _native as nat
+    nat.timing_reset()
+    nat.timing_enable(True)
+    out = fn()
+    torch.cuda.synchronize()
+    nat.timing_enable(False)
+    return out, nat.timing_read(nat.KERNEL_NODES_TAIL)[1]
+
+
+def test_tail_split_full_c2_plan(ez):
+    """3 x 1029 tiles: the 15 past three rounds of 1024 workgroups go to the split
+    kernel; same sums as the tile kernel alone up to the order of each node's
+    terms, and the persistent schedule splits the same tiles (bit-identical)"""
+    from paper_2504_11989_amd import _native as nat
+    lat = np.stack([W.sc(), W.fcc(), W.bcc()])
+    spec = dict(W.SPEC_FULL_3D)
+    split, n_tail = tail_launches(ez, lambda: ez.atm_energy(lat, spec).cpu().numpy())
+    assert n_tail == 1
+    whole, n0 = tail_launches(ez, lambda: ez.atm_energy(lat, dict(spec, flags=nat.SPEC_NO_SPLIT)).cpu().numpy())
+    assert n0 == 0
+    assert np.all(np.abs(split - whole) <= 1e-13 * np.abs(whole)), (split, whole)
+    pers = ez.atm_energy(lat, dict(spec, flags=nat.SPEC_PERSISTENT)).cpu().numpy()
+    assert np.array_equal(pers, split)
+
+
+def test_tail_split_partial_last_tile(ez):
+    """one lattice, 12 x 15^2 directions x 104 u-nodes = 280800 nodes: 1097 tiles,
+    the last holding 224 nodes; the 73 tail tiles (partial one included) by the
+    split kernel, against the tile kernel alone and the oracle"""
+    from paper_2504_11989_amd import _native as nat
+    sp = dict(W.SPEC_FULL_3D, n_q=15, n_panels=8, n_g=13)
+    assert W.n_nodes(3, sp) == 280800
+    A = W.sc()[None]
+    split, n_tail = tail_launches(ez, lambda: ez.atm_energy(A, sp).cpu().numpy()[0])
+    assert n_tail == 1
+    whole = ez.atm_energy(A, dict(sp, flags=nat.SPEC_NO_SPLIT)).cpu().numpy()[0]
+    assert abs(split - whole) <= 1e-13 * abs(whole), (split, whole)
+    ref = O.atm(W.sc(), sp)
+    assert abs(split - ref) <= TOL * abs(ref), (split, ref)
