@@ -6,7 +6,7 @@
 //                       partial per 256-node tile (paper, Sec. 2, Theorem (Epstein
 //                       representation); Sec. 3, Corollary (Duffy transformation)).
 // ez_node_split_kernel: the last few tiles of a call, each node's terms shared by
-//                       16 waves in four workgroups (see below).
+//                       many waves (see below).
 // ez_finalize_kernel  : fixed-order double-double sum of tiles and directions; the
 //                       derivatives with respect to A when requested.
 #include <algorithm>
@@ -216,16 +216,19 @@ __device__ __forceinline__ void node_products(const EzQuadArgs &args, const EzLa
 
 // LDS of the node kernels.  kpool holds the culled reciprocal list (unsigned
 // short); the split path reuses it for its partial sums once the list is done.
+template <int NW>
 struct NodeLds {
     double kpool[EZ_KCULL / 4];
-    double kbox[EZ_TILE / 64][6];
+    double kbox[NW][6];
     double red[EZ_RES_MAX][EZ_TILE / 64][2];
-    int kwave[EZ_TILE / 64];
+    int kwave[NW];
     int kcount;
 };
+using TileLds = NodeLds<EZ_TILE / 64>;
+using TailLds = NodeLds<EZ_TAIL_WAVES>;
 
 template <int D, int NNU, int SET>
-__device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile, NodeLds &L) {
+__device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile, TileLds &L) {
     const int inst = find_segment(args.tile_begin, args.batch, tile);
     const EzInstPlan P = args.plans[inst];
     const EzLatMeta *M = args.meta + inst;
@@ -284,20 +287,23 @@ __device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile
 // last round holds a few tiles whose waves then run alone on their SIMDs for about
 // the time of a full round.  The host hands those tiles [n_main, n_tiles) to the
 // split kernel instead, launched after the tile kernel with one workgroup per CU:
-// each 64-node group of a tail tile is shared by EZ_TAIL_PARTS workgroups of four
-// waves, and wave s of part p takes the (4 p + s)-th of 4 EZ_TAIL_PARTS contiguous
-// shares of the real-space rows and of the culled reciprocal list (share 0 also
-// m* = 0) for all 64 nodes.  A workgroup adds its waves' partial sums in LDS in
-// wave order and stores them; the last of the group's workgroups to finish (a
-// counter, reset by that workgroup) adds the stored parts in part order, forms the
-// products and writes the 64-node partial to sub_part.  The finalize kernel adds
-// the four partials of a tile in the order the tile path adds its four waves.
+// each 64-node group of a tail tile is shared by EZ_TAIL_PARTS workgroups of
+// EZ_TAIL_WAVES waves, and wave s of part p takes the (EZ_TAIL_WAVES p + s)-th of
+// EZ_TAIL_WAVES EZ_TAIL_PARTS contiguous shares of the real-space rows and of the
+// culled reciprocal list (share 0 also m* = 0) for all 64 nodes.  A workgroup adds
+// its waves' partial sums in LDS in wave order.  With several parts, each stores
+// its sums and the last of the group's workgroups to finish (a counter, reset by
+// that workgroup) adds the stored parts in part order; wave 0 of the workgroup
+// holding the total forms the products and writes the 64-node partial to
+// sub_part.  The finalize kernel adds the four partials of a tile in the order the
+// tile path adds its four waves.
 template <int D, int NNU, int SET>
-__device__ __forceinline__ void node_group_split(const EzQuadArgs &args, const int g, const int p, NodeLds &L) {
-    constexpr int NS = EZ_TILE / 64;              // waves per workgroup, = 64-node groups per tile
+__device__ __forceinline__ void node_group_split(const EzQuadArgs &args, const int g, const int p, TailLds &L) {
+    constexpr int NS = EZ_TAIL_WAVES;             // waves per workgroup
     constexpr int NSH = NS * EZ_TAIL_PARTS;       // shares of a group's terms
-    const int tile = args.n_main + g / NS;
-    const int quarter = g % NS;
+    constexpr int GPT = EZ_TILE / 64;             // 64-node groups per tile
+    const int tile = args.n_main + g / GPT;
+    const int quarter = g % GPT;
     const int lane = (int)threadIdx.x & 63, s = (int)threadIdx.x >> 6;
     const int j = p * NS + s;                     // this wave's share
     const int inst = find_segment(args.tile_begin, args.batch, tile);
@@ -319,7 +325,7 @@ __device__ __forceinline__ void node_group_split(const EzQuadArgs &args, const i
         node_geometry<D>(P, args.rules, M, valid ? node : tile0, k, th, &W);
         const double *kt = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
         const double alpha = M->alpha, acut = M->a_cut;
-        const int nk = cull_reciprocal<D, EZ_TILE>(kt, M->n_rec, k, alpha, acut, klist, L.kbox, L.kwave, &L.kcount);
+        const int nk = cull_reciprocal<D, 64 * NS>(kt, M->n_rec, k, alpha, acut, klist, L.kbox, L.kwave, &L.kcount);
         if (valid) {
             const int n_rows = M->n_rows;
             real_rows<D, NNU>(args, inst, th, j * n_rows / NSH, (j + 1) * n_rows / NSH, accr);
@@ -341,34 +347,39 @@ __device__ __forceinline__ void node_group_split(const EzQuadArgs &args, const i
     }
     if (s != 0) return;
 
-    // wave 0: store this part; the group's last part adds them all
-    constexpr int PART = 2 * NNU * 64;
-    double *mine = args.tail_acc + ((size_t)g * EZ_TAIL_PARTS + p) * PART;
-#pragma unroll
-    for (int i = 0; i < 2 * NNU; ++i) mine[i * 64 + lane] = acc[i * 64 + lane];
-    __threadfence();
-    int old = 0;
-    if (lane == 0) old = atomicAdd(args.tail_cnt + g, 1);
-    old = __shfl(old, 0, 64);
-    if (old != EZ_TAIL_PARTS - 1) return;
-    __threadfence();
-    if (lane == 0) args.tail_cnt[g] = 0;          // ready for the next call
-
     double res[EZ_RES_MAX];
 #pragma unroll
     for (int r = 0; r < EZ_RES_MAX; ++r) res[r] = 0.0;
-    if (ok && valid) {
-        const double *parts = args.tail_acc + (size_t)g * EZ_TAIL_PARTS * PART;
+    if constexpr (EZ_TAIL_PARTS > 1) {
+        // wave 0: store this part; the group's last part adds them all
+        constexpr int PART = 2 * NNU * 64;
+        double *mine = args.tail_acc + ((size_t)g * EZ_TAIL_PARTS + p) * PART;
 #pragma unroll
-        for (int i = 0; i < NNU; ++i) {
-            double a = parts[i * 64 + lane], b = parts[(NNU + i) * 64 + lane];
-            for (int q = 1; q < EZ_TAIL_PARTS; ++q) {
-                a += parts[(size_t)q * PART + i * 64 + lane];
-                b += parts[(size_t)q * PART + (NNU + i) * 64 + lane];
+        for (int i = 0; i < 2 * NNU; ++i) mine[i * 64 + lane] = acc[i * 64 + lane];
+        __threadfence();
+        int old = 0;
+        if (lane == 0) old = atomicAdd(args.tail_cnt + g, 1);
+        old = __shfl(old, 0, 64);
+        if (old != EZ_TAIL_PARTS - 1) return;
+        __threadfence();
+        if (lane == 0) args.tail_cnt[g] = 0;      // ready for the next call
+        if (ok && valid) {
+            const double *parts = args.tail_acc + (size_t)g * EZ_TAIL_PARTS * PART;
+#pragma unroll
+            for (int i = 0; i < NNU; ++i) {
+                double a = parts[i * 64 + lane], b = parts[(NNU + i) * 64 + lane];
+                for (int q = 1; q < EZ_TAIL_PARTS; ++q) {
+                    a += parts[(size_t)q * PART + i * 64 + lane];
+                    b += parts[(size_t)q * PART + (NNU + i) * 64 + lane];
+                }
+                accr[i] = a;
+                acck[i] = b;
             }
-            accr[i] = a;
-            acck[i] = b;
+            node_products<NNU>(args, M, accr, acck, W, res);
         }
+    } else if (ok && valid) {
+#pragma unroll
+        for (int i = 0; i < NNU; ++i) { accr[i] = acc[i * 64 + lane]; acck[i] = acc[(NNU + i) * 64 + lane]; }
         node_products<NNU>(args, M, accr, acck, W, res);
     }
 #pragma unroll
@@ -386,7 +397,7 @@ __device__ __forceinline__ void node_group_split(const EzQuadArgs &args, const i
 // one workgroup per tile (tiles [0, n_main))
 template <int D, int NNU, int SET>
 __global__ __launch_bounds__(EZ_TILE) void ez_node_kernel(EzQuadArgs args) {
-    __shared__ NodeLds L;
+    __shared__ TileLds L;
     node_tile<D, NNU, SET>(args, (int)blockIdx.x, L);
 }
 
@@ -395,7 +406,7 @@ __global__ __launch_bounds__(EZ_TILE) void ez_node_kernel(EzQuadArgs args) {
 // n_main on are left to the split kernel.
 template <int D, int NNU, int SET>
 __global__ __launch_bounds__(EZ_TILE) void ez_node_persist_kernel(EzQuadArgs args) {
-    __shared__ NodeLds L;
+    __shared__ TileLds L;
     __shared__ int next;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(args.queue, 1);
@@ -411,8 +422,8 @@ __global__ __launch_bounds__(EZ_TILE) void ez_node_persist_kernel(EzQuadArgs arg
 
 // the tail: workgroup b takes part b % EZ_TAIL_PARTS of 64-node group b / EZ_TAIL_PARTS
 template <int D, int NNU, int SET>
-__global__ __launch_bounds__(EZ_TILE) void ez_node_split_kernel(EzQuadArgs args) {
-    __shared__ NodeLds L;
+__global__ __launch_bounds__(64 * EZ_TAIL_WAVES) void ez_node_split_kernel(EzQuadArgs args) {
+    __shared__ TailLds L;
     const int b = (int)blockIdx.x;
     node_group_split<D, NNU, SET>(args, b / EZ_TAIL_PARTS, b % EZ_TAIL_PARTS, L);
 }
@@ -558,7 +569,7 @@ hipError_t launch_nodes_t(const EzQuadArgs &args, int n_tiles, hipStream_t strea
             const long cap = (long)per_blk - (long)fa.sharedSizeBytes;
             pad = (int)std::max(0L, std::min(want, cap));
         }
-        hipLaunchKernelGGL((ez_node_split_kernel<D, NNU, SET>), dim3(n_tiles), dim3(EZ_TILE), pad, stream, args);
+        hipLaunchKernelGGL((ez_node_split_kernel<D, NNU, SET>), dim3(n_tiles), dim3(64 * EZ_TAIL_WAVES), pad, stream, args);
     } else if (mode == 1) {
         hipLaunchKernelGGL((ez_node_persist_kernel<D, NNU, SET>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
     } else {
