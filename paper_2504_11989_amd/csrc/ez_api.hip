@@ -580,7 +580,7 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     if (st) return st;
     if (!S->side) {
         EZ_HIP_TRY(hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking));
-        EZ_HIP_TRY(hipEventCreateWithFlags(&S->ev_setup, hipEventDisableTiming));
+        EZ_HIP_TRY(hipEventCreate(&S->ev_setup));     // recorded by a kernel launch (needs timing)
         EZ_HIP_TRY(hipEventCreateWithFlags(&S->ev_had, hipEventDisableTiming));
         EZ_HIP_TRY(hipDeviceGetAttribute(&S->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     }
@@ -699,17 +699,24 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     // kernel runs on a second stream, concurrently with the node kernels, and the
     // caller's stream waits for it before the final reduction (event edges, so the
     // sequence can be captured into a graph).  EZ_SPEC_SERIAL keeps it on `stream`.
-    auto had = [&](hipStream_t s, int part) {
-        return grad ? ez_launch_hadamard_adj(qa, P->n_htiles, s, part) : ez_launch_hadamard(qa, P->n_htiles, s, part);
+    auto had = [&](hipStream_t s, int part, hipEvent_t done) {
+        return grad ? ez_launch_hadamard_adj(qa, P->n_htiles, s, part, done)
+                    : ez_launch_hadamard(qa, P->n_htiles, s, part, done);
     };
-    EZ_HIP_TRY(timed(EZ_KERNEL_TAYLOR, stream, [&] { return had(stream, EZ_HAD_PRE); }));
+    // The fork event is recorded by the tensor launch itself (no marker packet between
+    // the tensors and the node kernel), or by hipEventRecord while the stream is captured.
+    const bool side = !(flags & EZ_SPEC_SERIAL);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    EZ_HIP_TRY(hipStreamIsCapturing(stream, &cap));
+    const bool ext = side && cap == hipStreamCaptureStatusNone;
+    EZ_HIP_TRY(timed(EZ_KERNEL_TAYLOR, stream, [&] { return had(stream, EZ_HAD_PRE, ext ? S->ev_setup : nullptr); }));
     hipStream_t hs = stream;
-    if (!(flags & EZ_SPEC_SERIAL)) {
-        EZ_HIP_TRY(hipEventRecord(S->ev_setup, stream));
+    if (side) {
+        if (!ext) EZ_HIP_TRY(hipEventRecord(S->ev_setup, stream));
         EZ_HIP_TRY(hipStreamWaitEvent(S->side, S->ev_setup, 0));
         hs = S->side;
     }
-    EZ_HIP_TRY(timed(EZ_KERNEL_HADAMARD, hs, [&] { return had(hs, EZ_HAD_DIR); }));
+    EZ_HIP_TRY(timed(EZ_KERNEL_HADAMARD, hs, [&] { return had(hs, EZ_HAD_DIR, nullptr); }));
     if (grad) {
         EZ_HIP_TRY(timed(EZ_KERNEL_NODES_ADJ, stream, [&] { return ez_launch_nodes_adj(qa, P->n_tiles, stream); }));
     } else if (flags & EZ_SPEC_PERSISTENT) {

@@ -1,6 +1,8 @@
 // ez_hadamard.hip -- the Hadamard part on (0, eps) (paper, Sec. 3, Taylor
 // expansion of Z^reg and closed-form Hadamard integrals): probe, tensor and
 // direction kernels.
+#include <hip/hip_ext.h>
+
 #include "ez_hadamard_common.h"
 
 namespace {
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(256) void ez_hadamard_kernel(EzQuadArgs args) {
 // poly <- poly * sum_k c_k u^{2k}, truncated to PD coefficients
 
 template <int D, int NNU, int PD>
-hipError_t launch_had_t(const EzQuadArgs &args, int n_htiles, hipStream_t stream, int part) {
+hipError_t launch_had_t(const EzQuadArgs &args, int n_htiles, hipStream_t stream, int part, hipEvent_t pre_done) {
     hipError_t e = hipSuccess;
     if (part & EZ_HAD_PRE) {            // probe values and Taylor tensors
         const int nblk = (args.n_probe + 63) / 64;
@@ -152,7 +154,13 @@ hipError_t launch_had_t(const EzQuadArgs &args, int n_htiles, hipStream_t stream
         int tdim = 0;
         for (int k = 0; k <= args.ell_probe; ++k) tdim += nmono(D, 2 * k);
         const int ngrp = (tdim + EZ_TOUT - 1) / EZ_TOUT;
-        hipLaunchKernelGGL((ez_tensor_kernel<D, NNU>), dim3(args.batch * NNU * nch * ngrp), dim3(256), 0, stream, args);
+        // pre_done (if given) is recorded by the tensor launch itself: no marker packet
+        // on `stream` between the tensors and the node kernel
+        if (pre_done)
+            hipExtLaunchKernelGGL((ez_tensor_kernel<D, NNU>), dim3(args.batch * NNU * nch * ngrp), dim3(256), 0, stream,
+                                  nullptr, pre_done, 0, args);
+        else
+            hipLaunchKernelGGL((ez_tensor_kernel<D, NNU>), dim3(args.batch * NNU * nch * ngrp), dim3(256), 0, stream, args);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (!(part & EZ_HAD_DIR)) return hipSuccess;   // direction kernel
@@ -161,34 +169,34 @@ hipError_t launch_had_t(const EzQuadArgs &args, int n_htiles, hipStream_t stream
 }
 
 template <int D, int NNU>
-hipError_t launch_had_p(const EzQuadArgs &args, int n_htiles, hipStream_t stream, int part) {
-    if (args.poly_deg == 13) return launch_had_t<D, NNU, 13>(args, n_htiles, stream, part);
-    if (args.poly_deg == 33) return launch_had_t<D, NNU, 33>(args, n_htiles, stream, part);
+hipError_t launch_had_p(const EzQuadArgs &args, int n_htiles, hipStream_t stream, int part, hipEvent_t pre_done) {
+    if (args.poly_deg == 13) return launch_had_t<D, NNU, 13>(args, n_htiles, stream, part, pre_done);
+    if (args.poly_deg == 33) return launch_had_t<D, NNU, 33>(args, n_htiles, stream, part, pre_done);
     return hipErrorInvalidValue;
 }
 
 template <int D>
-hipError_t launch_had_d(const EzQuadArgs &args, int n_htiles, hipStream_t stream, int part) {
+hipError_t launch_had_d(const EzQuadArgs &args, int n_htiles, hipStream_t stream, int part, hipEvent_t pre_done) {
     switch (args.prog.n_nu) {
-        case 1: return launch_had_p<D, 1>(args, n_htiles, stream, part);
-        case 2: return launch_had_p<D, 2>(args, n_htiles, stream, part);
-        case 3: return launch_had_p<D, 3>(args, n_htiles, stream, part);
-        case 4: return launch_had_p<D, 4>(args, n_htiles, stream, part);
-        case 5: return launch_had_p<D, 5>(args, n_htiles, stream, part);
-        case 6: return launch_had_p<D, 6>(args, n_htiles, stream, part);
-        case 7: return launch_had_p<D, 7>(args, n_htiles, stream, part);
-        case 8: return launch_had_p<D, 8>(args, n_htiles, stream, part);
+        case 1: return launch_had_p<D, 1>(args, n_htiles, stream, part, pre_done);
+        case 2: return launch_had_p<D, 2>(args, n_htiles, stream, part, pre_done);
+        case 3: return launch_had_p<D, 3>(args, n_htiles, stream, part, pre_done);
+        case 4: return launch_had_p<D, 4>(args, n_htiles, stream, part, pre_done);
+        case 5: return launch_had_p<D, 5>(args, n_htiles, stream, part, pre_done);
+        case 6: return launch_had_p<D, 6>(args, n_htiles, stream, part, pre_done);
+        case 7: return launch_had_p<D, 7>(args, n_htiles, stream, part, pre_done);
+        case 8: return launch_had_p<D, 8>(args, n_htiles, stream, part, pre_done);
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-hipError_t ez_launch_hadamard(const EzQuadArgs &args, int n_htiles, hipStream_t stream, int part) {
+hipError_t ez_launch_hadamard(const EzQuadArgs &args, int n_htiles, hipStream_t stream, int part, hipEvent_t pre_done) {
     switch (args.prog.d) {
-        case 1: return launch_had_d<1>(args, n_htiles, stream, part);
-        case 2: return launch_had_d<2>(args, n_htiles, stream, part);
-        case 3: return launch_had_d<3>(args, n_htiles, stream, part);
+        case 1: return launch_had_d<1>(args, n_htiles, stream, part, pre_done);
+        case 2: return launch_had_d<2>(args, n_htiles, stream, part, pre_done);
+        case 3: return launch_had_d<3>(args, n_htiles, stream, part, pre_done);
         default: return hipErrorInvalidValue;
     }
 }

@@ -91,11 +91,14 @@ hipError_t ez_launch_nodes_persistent(const EzQuadArgs &args, int n_blocks, hipS
 int ez_nodes_blocks_per_cu(const EzQuadArgs &args);
 hipError_t ez_launch_fill_int(int *p, int n, int value, hipStream_t stream);
 // Taylor/Hadamard branch: part EZ_HAD_PRE = probe and tensor kernels, EZ_HAD_DIR = the
-// direction kernel (it reads the tensors), or both
+// direction kernel (it reads the tensors), or both; pre_done (may be NULL) is recorded
+// when the tensors are complete
 #define EZ_HAD_PRE 1
 #define EZ_HAD_DIR 2
-hipError_t ez_launch_hadamard(const EzQuadArgs &args, int n_htiles, hipStream_t stream, int part);
+hipError_t ez_launch_hadamard(const EzQuadArgs &args, int n_htiles, hipStream_t stream, int part,
+                              hipEvent_t pre_done = nullptr);
 hipError_t ez_launch_finalize(const EzQuadArgs &args, hipStream_t stream);
 hipError_t ez_launch_nodes_adj(const EzQuadArgs &args, int n_tiles, hipStream_t stream);
-hipError_t ez_launch_hadamard_adj(const EzQuadArgs &args, int n_htiles, hipStream_t stream, int part);
+hipError_t ez_launch_hadamard_adj(const EzQuadArgs &args, int n_htiles, hipStream_t stream, int part,
+                                  hipEvent_t pre_done = nullptr);
 hipError_t ez_launch_epstein(const EzEpsteinArgs &args, hipStream_t stream);

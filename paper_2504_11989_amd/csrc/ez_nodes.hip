@@ -169,12 +169,26 @@ template <int D, int NNU, int SET>
 __device__ __forceinline__ void rec_list(const EzQuadArgs &args, const double *kt, const unsigned short *klist,
                                          int j0, int j1, const double *k, double alpha, double acut, double *acck) {
     const bool need_e1 = pset_need_e1<SET, NNU>(args.prog), need_half = pset_need_half<SET, NNU>(args.prog);
+    if (j0 >= j1) return;
+    // software pipeline: the list index two entries ahead and the table entry one
+    // entry ahead are loaded while the current term is evaluated
+    auto entry = [&](int j) { return kt + (size_t)__builtin_amdgcn_readfirstlane((int)klist[j]) * 4; };
+    int qn = (int)klist[j0 + 1 < j1 ? j0 + 1 : j0];
+    const double *en = entry(j0);
+    double m0 = en[0], m1 = D > 1 ? en[1] : 0.0, m2 = D > 2 ? en[2] : 0.0;
     for (int j = j0; j < j1; ++j) {
-        const double *e = kt + (size_t)__builtin_amdgcn_readfirstlane((int)klist[j]) * 4;
-        double qx = e[0] + k[0];
+        const double c0 = m0, c1 = m1, c2 = m2;
+        {
+            const double *e2 = kt + (size_t)__builtin_amdgcn_readfirstlane(qn) * 4;
+            m0 = e2[0];
+            if (D > 1) m1 = e2[1];
+            if (D > 2) m2 = e2[2];
+            qn = (int)klist[j + 2 < j1 ? j + 2 : j1 - 1];
+        }
+        double qx = c0 + k[0];
         double rho = qx * qx;
-        if (D > 1) { double qy = e[1] + k[1]; rho = fma(qy, qy, rho); }
-        if (D > 2) { double qz = e[2] + k[2]; rho = fma(qz, qz, rho); }
+        if (D > 1) { double qy = c1 + k[1]; rho = fma(qy, qy, rho); }
+        if (D > 2) { double qz = c2 + k[2]; rho = fma(qz, qz, rho); }
         const double a = alpha * rho;
         if (a <= acut) {
             const double ex = ez_expm(a);
