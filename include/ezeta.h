@@ -77,8 +77,9 @@ typedef struct ez_quad_spec {
  * the order of floating-point sums in the node reduction, which stays fixed)
  *  EZ_SPEC_PERSISTENT : the node kernel runs as a persistent grid that takes node
  *                       tiles from a work queue, costliest tiles first
- *  EZ_SPEC_SERIAL     : the Taylor/Hadamard branch runs on the caller's stream
- *                       after the nodes instead of concurrently on a second stream
+ *  EZ_SPEC_SERIAL     : the Hadamard direction kernel runs on the caller's stream
+ *                       before the nodes instead of concurrently on a second
+ *                       stream (calls with derivatives always run this way)
  *  EZ_SPEC_BPC(n)     : persistent workgroups per CU (0: as many as fit)
  *  EZ_SPEC_NO_SPLIT   : value calls hand the last node tiles, when they would
  *                       fill at most a quarter of a round of workgroups over the

@@ -705,7 +705,11 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     };
     // The fork event is recorded by the tensor launch itself (no marker packet between
     // the tensors and the node kernel), or by hipEventRecord while the stream is captured.
-    const bool side = !(flags & EZ_SPEC_SERIAL);
+    // dE/dA calls keep the direction kernel on the caller's stream before the nodes: the
+    // adjoint direction and node kernels cannot share a SIMD's registers, so on a second
+    // queue the direction kernel would only start as the adjoint node kernel drains and
+    // end well after it (C2: 1.015 ms per step there, 0.978 ms in order)
+    const bool side = !(flags & EZ_SPEC_SERIAL) && !grad;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     EZ_HIP_TRY(hipStreamIsCapturing(stream, &cap));
     const bool ext = side && cap == hipStreamCaptureStatusNone;

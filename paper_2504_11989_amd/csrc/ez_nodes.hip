@@ -39,68 +39,6 @@ __device__ __forceinline__ void node_geometry(const EzInstPlan &P, const double 
     *W = Wt;
 }
 
-// The reciprocal table covers every node of the cell; a workgroup needs only the
-// entries within the cutoff radius of some of its nodes.  With c and r_t the
-// centre and half-diagonal of the bounding box of the workgroup's k, an entry with
-// |m* + c| > sqrt(a_cut / alpha) + r_t is beyond the cutoff for every node of it.
-// The others are listed in table order (so each node adds the same nonzero terms
-// in the same order as over the whole table); the host keeps the table capacity
-// within the list (EZ_KCULL entries).  NT threads; returns the list length.
-template <int D, int NT>
-__device__ __forceinline__ int cull_reciprocal(const double *kt, int n_rec, const double *k, double alpha, double acut,
-                                               unsigned short *klist, double (*kbox)[6], int *kwave, int *kcount) {
-    constexpr int NWV = NT / 64;
-    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
-    double bl[3] = {k[0], k[1], k[2]}, bh[3] = {k[0], k[1], k[2]};
-#pragma unroll
-    for (int i = 0; i < D; ++i)
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) {
-            bl[i] = fmin(bl[i], __shfl_xor(bl[i], m, 64));
-            bh[i] = fmax(bh[i], __shfl_xor(bh[i], m, 64));
-        }
-    if (lane == 0)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) { kbox[wave][i] = bl[i]; kbox[wave][3 + i] = bh[i]; }
-    if (threadIdx.x == 0) *kcount = 0;
-    __syncthreads();
-    double c[3] = {0.0, 0.0, 0.0}, rt2 = 0.0;
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-        double lo = kbox[0][i], hi = kbox[0][3 + i];
-        for (int w2 = 1; w2 < NWV; ++w2) { lo = fmin(lo, kbox[w2][i]); hi = fmax(hi, kbox[w2][3 + i]); }
-        c[i] = 0.5 * (lo + hi);
-        rt2 += 0.25 * (hi - lo) * (hi - lo);
-    }
-    const double rmax = (sqrt(acut / alpha) + sqrt(rt2)) * (1.0 + 1e-9) + 1e-12;
-    for (int base = 1; base < n_rec; base += NT) {
-        const int q = base + (int)threadIdx.x;
-        bool keep = false;
-        if (q < n_rec) {
-            const double *e = kt + (size_t)q * 4;
-            double d2 = 0.0;
-#pragma unroll
-            for (int i = 0; i < D; ++i) { const double t = e[i] + c[i]; d2 = fma(t, t, d2); }
-            keep = d2 <= rmax * rmax;
-        }
-        const unsigned long long bal = __ballot(keep);
-        const int before = __popcll(bal & ((1ull << lane) - 1ull));
-        if (lane == 0) kwave[wave] = __popcll(bal);
-        __syncthreads();
-        int off = *kcount;
-        for (int w2 = 0; w2 < wave; ++w2) off += kwave[w2];
-        if (keep) klist[off + before] = (unsigned short)q;   // q < n_rec <= rec_cap <= EZ_KCULL
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int tot = 0;
-            for (int w2 = 0; w2 < NWV; ++w2) tot += kwave[w2];
-            *kcount += tot;
-        }
-        __syncthreads();
-    }
-    return *kcount;
-}
-
 // Real space: sum over pairs of 2 W_nu(z) Re e^{2 pi i k.z}, k.z = theta.n, over the
 // rows [r0, r1) of the table.  Row by row (n2, n3 fixed, consecutive n1) the phase
 // advances by c1 = e^{2 pi i theta_1}; from row to row within a plane by

@@ -47,9 +47,18 @@ __global__ __launch_bounds__(EZ_TILE) void ez_node_adj_kernel(EzQuadArgs args) {
         for (int s = 0; s < NS; ++s) S[r][s] = 0.0;
     }
 
-    if (M->status == 0 && node < n_nodes) {
-        const int dir = node / P.n_u;
-        const int iu = node - dir * P.n_u;
+    // reciprocal entries this tile needs, in table order (cull_reciprocal)
+    __shared__ unsigned short klist[EZ_KCULL];
+    __shared__ double kbox[EZ_TILE / 64][6];
+    __shared__ int kwave[EZ_TILE / 64];
+    __shared__ int kcount;
+
+    if (M->status == 0) {                         // uniform over the workgroup
+        const bool valid = node < n_nodes;
+        // threads past the last node take the tile's first node (geometry only)
+        const int nd = valid ? node : (tile - args.tile_begin[inst]) * EZ_TILE;
+        const int dir = nd / P.n_u;
+        const int iu = nd - dir * P.n_u;
         double B[D * D];
 #pragma unroll
         for (int i = 0; i < D * D; ++i) B[i] = M->B[i];
@@ -78,6 +87,11 @@ __global__ __launch_bounds__(EZ_TILE) void ez_node_adj_kernel(EzQuadArgs args) {
         const int n_rec = M->n_rec;
         const double alpha = M->alpha, acut = M->a_cut;
         const bool need_e1 = pset_need_e1<SET, NNU>(args.prog), need_half = pset_need_half<SET, NNU>(args.prog);
+        // m* = 0, then the culled list: the entries left out are beyond the cutoff for
+        // every node of the tile, so both passes add the same terms in the same order
+        const int nk = cull_reciprocal<D, EZ_TILE>(kt, n_rec, k, alpha, acut, klist, kbox, kwave, &kcount);
+        auto entry = [&](int j) { return j == 0 ? 0 : __builtin_amdgcn_readfirstlane((int)klist[j - 1]); };
+        if (valid) {
 
         // ---- pass 1: Z_nu(k) ----
         double accr[NNU], acck[NNU];
@@ -110,8 +124,8 @@ __global__ __launch_bounds__(EZ_TILE) void ez_node_adj_kernel(EzQuadArgs args) {
                 }
             }
         }
-        for (int q = 0; q < n_rec; ++q) {
-            const double *e = kt + (size_t)q * 4;
+        for (int j = 0; j <= nk; ++j) {
+            const double *e = kt + (size_t)entry(j) * 4;
             double qv[3] = {0.0, 0.0, 0.0};
 #pragma unroll
             for (int i = 0; i < D; ++i) qv[i] = e[i] + k[i];
@@ -228,8 +242,8 @@ __global__ __launch_bounds__(EZ_TILE) void ez_node_adj_kernel(EzQuadArgs args) {
             }
         }
         // ---- pass 2, reciprocal space: S_r += 2 alpha (sum_nu fbar K E_{p-1}) (m*+k)(m*+k)^T ----
-        for (int q = 0; q < n_rec; ++q) {
-            const double *e = kt + (size_t)q * 4;
+        for (int j = 0; j <= nk; ++j) {
+            const double *e = kt + (size_t)entry(j) * 4;
             double qv[3] = {0.0, 0.0, 0.0};
 #pragma unroll
             for (int i = 0; i < D; ++i) qv[i] = e[i] + k[i];
@@ -255,6 +269,7 @@ __global__ __launch_bounds__(EZ_TILE) void ez_node_adj_kernel(EzQuadArgs args) {
                 }
             }
         }
+        }   // valid
     }
 
     // tile reduction of the values and the strain tensors
