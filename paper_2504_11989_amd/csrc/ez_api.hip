@@ -605,12 +605,15 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     // a round), those tiles go to the split kernel, which shares each node's terms
     // among 16 waves on four CUs (value calls without EZ_SPEC_NO_SPLIT; the adjoint
     // keeps whole tiles).
-    int n_main = P->n_tiles;
-    if (!grad && !(flags & EZ_SPEC_NO_SPLIT)) {
+    int round = 0;                     // tile-kernel workgroups resident on the device at once
+    {
         EzQuadArgs probe_args;
         std::memset(&probe_args, 0, sizeof(probe_args));
         probe_args.prog = prog;
-        const int round = S->n_cu * ez_nodes_tile_blocks_per_cu(probe_args);
+        round = S->n_cu * ez_nodes_tile_blocks_per_cu(probe_args);
+    }
+    int n_main = P->n_tiles;
+    if (!grad && !(flags & EZ_SPEC_NO_SPLIT)) {
         const int tail = round > 0 ? P->n_tiles % round : 0;
         if (P->n_tiles > round && tail > 0 && tail <= round / 4) n_main = P->n_tiles - tail;
     }
@@ -710,15 +713,27 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     // queue the direction kernel would only start as the adjoint node kernel drains and
     // end well after it (C2: 1.015 ms per step there, 0.978 ms in order)
     const bool side = !(flags & EZ_SPEC_SERIAL) && !grad;
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    EZ_HIP_TRY(hipStreamIsCapturing(stream, &cap));
-    const bool ext = side && cap == hipStreamCaptureStatusNone;
-    EZ_HIP_TRY(timed(EZ_KERNEL_TAYLOR, stream, [&] { return had(stream, EZ_HAD_PRE, ext ? S->ev_setup : nullptr); }));
+    // Batches whose node tiles fill more than eight rounds of the device are bound by
+    // throughput, not latency: there the probe and tensor kernels go to the second
+    // stream as well, where their work fills slots beside the node kernel's instead of
+    // preceding it (C3 scan).
+    const bool big = side && P->n_tiles > 8 * round;
     hipStream_t hs = stream;
-    if (side) {
-        if (!ext) EZ_HIP_TRY(hipEventRecord(S->ev_setup, stream));
+    if (big) {
+        EZ_HIP_TRY(hipEventRecord(S->ev_setup, stream));
         EZ_HIP_TRY(hipStreamWaitEvent(S->side, S->ev_setup, 0));
         hs = S->side;
+        EZ_HIP_TRY(timed(EZ_KERNEL_TAYLOR, hs, [&] { return had(hs, EZ_HAD_PRE, nullptr); }));
+    } else {
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        EZ_HIP_TRY(hipStreamIsCapturing(stream, &cap));
+        const bool ext = side && cap == hipStreamCaptureStatusNone;
+        EZ_HIP_TRY(timed(EZ_KERNEL_TAYLOR, stream, [&] { return had(stream, EZ_HAD_PRE, ext ? S->ev_setup : nullptr); }));
+        if (side) {
+            if (!ext) EZ_HIP_TRY(hipEventRecord(S->ev_setup, stream));
+            EZ_HIP_TRY(hipStreamWaitEvent(S->side, S->ev_setup, 0));
+            hs = S->side;
+        }
     }
     EZ_HIP_TRY(timed(EZ_KERNEL_HADAMARD, hs, [&] { return had(hs, EZ_HAD_DIR, nullptr); }));
     if (grad) {
