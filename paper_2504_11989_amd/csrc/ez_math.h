@@ -126,6 +126,18 @@ __device__ __forceinline__ double ez_ep_from(int p2, double a, double e, double 
     return E;
 }
 
+// sqrt(pi a) e^a erfc(sqrt a) for a >= 1/4 from the rational fit, given t = 1/a; then
+// E_{1/2}(a) = e^{-a} h / a uses the term's e^{-a} and 1/a (no erfc, no second exp)
+__device__ __forceinline__ double ez_ehw_scaled(double t) {
+    double P = ez_ehw_p[EZ_E1W_DEG], Q = ez_ehw_q[EZ_E1W_DEG];
+#pragma unroll
+    for (int j = EZ_E1W_DEG - 1; j >= 0; --j) {
+        P = ez_fma3(P, t, ez_ehw_p[j]);
+        Q = ez_fma3(Q, t, ez_ehw_q[j]);
+    }
+    return P * ez_rcp(Q);
+}
+
 __device__ __forceinline__ double ez_ehalf(double a) {
     double r = sqrt(a);
     return 1.7724538509055160272981674833411452 * erfc(r) / r;   // sqrt(pi) erfc(sqrt a)/sqrt a

@@ -96,7 +96,7 @@ __device__ __forceinline__ void rec_origin(const EzQuadArgs &args, const double 
         const double inv = ez_rcp(a);
         double E1 = 0.0;
         if (need_e1) E1 = (a < 0.25) ? ez_e1_series(a) : ex * ez_e1w_scaled(inv);
-        const double Eh = need_half ? ez_ehalf(a) : 0.0;
+        const double Eh = need_half ? ((a < 0.25) ? ez_ehalf(a) : ex * inv * ez_ehw_scaled(inv)) : 0.0;
 #pragma unroll
         for (int i = 0; i < NNU; ++i)
             acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
@@ -132,7 +132,7 @@ __device__ __forceinline__ void rec_list(const EzQuadArgs &args, const double *k
             const double ex = ez_expm(a);
             const double inv = ez_rcp(a);
             const double E1 = need_e1 ? ex * ez_e1w_scaled(inv) : 0.0;
-            const double Eh = need_half ? ez_ehalf(a) : 0.0;
+            const double Eh = need_half ? ex * inv * ez_ehw_scaled(inv) : 0.0;
 #pragma unroll
             for (int i = 0; i < NNU; ++i)
                 acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);

@@ -138,7 +138,7 @@ __global__ __launch_bounds__(EZ_TILE) void ez_node_adj_kernel(EzQuadArgs args) {
                 const double inv = ez_rcp(a);
                 double E1 = 0.0;
                 if (need_e1) E1 = (a < 0.25) ? ez_e1_small(a) : ex * ez_e1w_scaled(inv);
-                const double Eh = need_half ? ez_ehalf(a) : 0.0;
+                const double Eh = need_half ? ((a < 0.25) ? ez_ehalf(a) : ex * inv * ez_ehw_scaled(inv)) : 0.0;
 #pragma unroll
                 for (int i = 0; i < NNU; ++i)
                     acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(EZ_TILE) void ez_node_adj_kernel(EzQuadArgs args) {
                 const double inv = ez_rcp(a);
                 double E1 = 0.0;
                 if (need_e1) E1 = (a < 0.25) ? ez_e1_small(a) : ex * ez_e1w_scaled(inv);
-                const double Eh = need_half ? ez_ehalf(a) : 0.0;
+                const double Eh = need_half ? ((a < 0.25) ? ez_ehalf(a) : ex * inv * ez_ehw_scaled(inv)) : 0.0;
                 double Em[NNU];
 #pragma unroll
                 for (int i = 0; i < NNU; ++i) Em[i] = ez_ep_from(pset_p2<SET>(args.prog, i) - 2, a, ex, inv, E1, Eh);
