@@ -399,24 +399,27 @@ __device__ __forceinline__ ez_dd tile_value(const EzQuadArgs &args, int t, int r
     return s;
 }
 
-__global__ __launch_bounds__(256) void ez_finalize_kernel(EzQuadArgs args) {
+// one workgroup of FT threads per lattice (the sums are short: latency-bound)
+constexpr int FT = 1024;
+
+__global__ __launch_bounds__(FT) void ez_finalize_kernel(EzQuadArgs args) {
     const int inst = blockIdx.x;
     const int n_res = args.prog.n_res;
     const int tb = args.tile_begin[inst], te = args.tile_begin[inst + 1];
     const int db = args.dir_begin[inst], de = args.dir_begin[inst + 1];
-    __shared__ double red[256 / 64][2];
+    __shared__ double red[FT / 64][2];
     __shared__ uint32_t flag_sh;
     if (threadIdx.x == 0) flag_sh = 0;
     __syncthreads();
     uint32_t fl = 0;
-    for (int g = db + (int)threadIdx.x; g < de; g += 256) fl |= args.dir_flag[g];
+    for (int g = db + (int)threadIdx.x; g < de; g += FT) fl |= args.dir_flag[g];
     if (fl) atomicOr(&flag_sh, 1u);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int r = 0; r < n_res; ++r) {
         ez_dd s{0.0, 0.0};
-        for (int t = tb + (int)threadIdx.x; t < te; t += 256)
+        for (int t = tb + (int)threadIdx.x; t < te; t += FT)
             s = ez_dd_add(s, tile_value(args, t, r, n_res));
-        for (int g = db + (int)threadIdx.x; g < de; g += 256)
+        for (int g = db + (int)threadIdx.x; g < de; g += FT)
             s = ez_dd_add_d(s, args.dir_part[(size_t)g * n_res + r]);
         s = ez_dd_wave_sum(s);
         __syncthreads();
@@ -424,7 +427,7 @@ __global__ __launch_bounds__(256) void ez_finalize_kernel(EzQuadArgs args) {
         __syncthreads();
         if (threadIdx.x == 0) {
             ez_dd tot{red[0][0], red[0][1]};
-            for (int w = 1; w < 256 / 64; ++w) tot = ez_dd_add(tot, ez_dd{red[w][0], red[w][1]});
+            for (int w = 1; w < FT / 64; ++w) tot = ez_dd_add(tot, ez_dd{red[w][0], red[w][1]});
             double v = tot.hi + tot.lo;
             uint32_t st = args.meta[inst].status;
             if (flag_sh) st |= 0x8u;
@@ -441,10 +444,10 @@ __global__ __launch_bounds__(256) void ez_finalize_kernel(EzQuadArgs args) {
     for (int r = 0; r < n_res; ++r) {
         for (int sc = 0; sc < ns; ++sc) {
             ez_dd s{0.0, 0.0};
-            for (int t = tb + (int)threadIdx.x; t < te; t += 256)
+            for (int t = tb + (int)threadIdx.x; t < te; t += FT)
                 s = ez_dd_add(s, ez_dd{args.tile_grad[(((size_t)t * n_res + r) * 6 + sc) * 2],
                                        args.tile_grad[(((size_t)t * n_res + r) * 6 + sc) * 2 + 1]});
-            for (int g = db + (int)threadIdx.x; g < de; g += 256)
+            for (int g = db + (int)threadIdx.x; g < de; g += FT)
                 s = ez_dd_add_d(s, args.dir_grad[((size_t)g * n_res + r) * 6 + sc]);
             s = ez_dd_wave_sum(s);
             __syncthreads();
@@ -452,7 +455,7 @@ __global__ __launch_bounds__(256) void ez_finalize_kernel(EzQuadArgs args) {
             __syncthreads();
             if (threadIdx.x == 0) {
                 ez_dd tot{red[0][0], red[0][1]};
-                for (int w = 1; w < 256 / 64; ++w) tot = ez_dd_add(tot, ez_dd{red[w][0], red[w][1]});
+                for (int w = 1; w < FT / 64; ++w) tot = ez_dd_add(tot, ez_dd{red[w][0], red[w][1]});
                 Ssh[sc] = tot.hi + tot.lo;
             }
         }
@@ -593,6 +596,6 @@ hipError_t ez_launch_fill_int(int *p, int n, int value, hipStream_t stream) {
 }
 
 hipError_t ez_launch_finalize(const EzQuadArgs &args, hipStream_t stream) {
-    hipLaunchKernelGGL(ez_finalize_kernel, dim3(args.batch), dim3(256), 0, stream, args);
+    hipLaunchKernelGGL(ez_finalize_kernel, dim3(args.batch), dim3(FT), 0, stream, args);
     return hipGetLastError();
 }

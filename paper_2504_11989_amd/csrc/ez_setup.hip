@@ -91,15 +91,14 @@ __device__ __forceinline__ void box_point(int idx, const int *h, int *n) {
     }
 }
 
-// Gamma(s, a) = a^s E_{1-s}(a) for 2 s an integer (the quadrature exponents are
-// integers, so nu/2 and nu/2 + 1 always are), through the E_p recurrences
-// (out of line: the kernel runs 1024-thread workgroups within 128 registers)
-__device__ __attribute__((noinline)) double gamma_upper_half(int s2, double a) {
-    const int p2 = 2 - s2;
+// E_{p}(a) for 2p an integer through the E_p recurrences (the quadrature exponents are
+// integers, so the weights need p = 1 - nu/2 and p = -nu/2).  Out of line: the kernel
+// runs 1024-thread workgroups within 128 registers.
+__device__ __attribute__((noinline)) double ep_half(int p2, double a) {
     const double e = exp(-a), inv = 1.0 / a;
     const double E1 = ((p2 & 1) == 0 && p2 >= 2) ? ez_e1(a, e, inv) : 0.0;
     const double Eh = (p2 & 1) ? ez_ehalf(a) : 0.0;
-    return pow(a, 0.5 * (double)s2) * ez_ep_from(p2, a, e, inv, E1, Eh);
+    return ez_ep_from(p2, a, e, inv, E1, Eh);
 }
 
 // Deterministic two-list compaction of one chunk.  Each list keeps a running
@@ -323,15 +322,20 @@ __global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
             const int t = q / n_nu, i = q - t * n_nu;
             double *e = rtab + (size_t)t * rs;
             const double r2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
-            const double a = EZ_PI * r2 / (lam * lam);
+            const double pl = EZ_PI / (lam * lam);
+            const double a = pl * r2;
             const double nu = args.prog.nu[i];
-            e[3 + i] = 2.0 * gamma_upper_half((int)nu, a) * args.nuc[i][3] * pow(r2, -0.5 * nu);
+            // 2 W_nu = 2 Gamma(nu/2, a) |z|^{-nu} / Gamma(nu/2) with Gamma(s, a) = a^s E_{1-s}(a)
+            // and a = (pi/lam^2) |z|^2: the powers of |z| cancel, 2 W_nu = 2 (pi/lam^2)^{nu/2}
+            // E_{1-nu/2}(a) / Gamma(nu/2)
+            const double pw = pow(pl, 0.5 * nu);
+            e[3 + i] = 2.0 * args.nuc[i][3] * pw * ep_half(2 - (int)nu, a);
             int used = 3 + n_nu;
             if (args.grad) {
                 // strain weights: d(2 W_nu)/d|z|^2 times 2 (from d|z|^2 = 2 z^T G z), with
                 // dW_nu/d|z|^2 = -Gamma(nu/2 + 1, a) / (Gamma(nu/2) |z|^{nu+2})
-                e[used + i] = -4.0 * gamma_upper_half((int)nu + 2, a) * args.nuc[i][3] *
-                              pow(r2, -0.5 * nu - 1.0);
+                //              = -(pi/lam^2)^{nu/2+1} E_{-nu/2}(a) / Gamma(nu/2)
+                e[used + i] = -4.0 * args.nuc[i][3] * (pw * pl) * ep_half(-(int)nu, a);
                 used += n_nu;
             }
             if (i == 0)
