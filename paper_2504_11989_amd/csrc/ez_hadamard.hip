@@ -73,24 +73,32 @@ __global__ __launch_bounds__(256) void ez_hadamard_kernel(EzQuadArgs args) {
         poly[0] = 1.0;
 #pragma unroll
         for (int J = 1; J < PD; ++J) poly[J] = 0.0;
-        int deg = 0;
+        int deg = 0, rest = 0;
         for (int f = 0; f < nf; ++f) {
             const int i = prog.term_fac[t][f];
             for (int q = 0; q < cb.j[f]; ++q) c *= ssh[myd][i];
+            for (int rep = 0; rep < prog.term_mult[t][f] - cb.j[f]; ++rep) deg = min(deg + ell, PD - 1);
+            rest += prog.term_mult[t][f] - cb.j[f];
+        }
+        // the Taylor factors in one loop of `rest` multiplications (factor f taken
+        // mult_f - j_f times in turn): the lanes of a wave hold different combinations
+        // and differ only in its trip count
+        int f = 0, left = nf > 0 ? prog.term_mult[t][0] - cb.j[0] : 0;
+        for (int m = 0; m < rest; ++m) {
+            while (left == 0) { ++f; left = prog.term_mult[t][f] - cb.j[f]; }
+            --left;
+            const int i = prog.term_fac[t][f];
             double Ck[EZ_ELL_MAX + 1];
 #pragma unroll
             for (int kk = 0; kk <= EZ_ELL_MAX; ++kk) Ck[kk] = (kk <= ell) ? Csh[myd][i][kk] : 0.0;
-            for (int rep = 0; rep < prog.term_mult[t][f] - cb.j[f]; ++rep) {
-                // poly <- poly * sum_k C_k u^{2k}, truncated to PD coefficients
+            // poly <- poly * sum_k C_k u^{2k}, truncated to PD coefficients
 #pragma unroll
-                for (int J = PD - 1; J >= 0; --J) {
-                    double sacc = 0.0;
+            for (int J = PD - 1; J >= 0; --J) {
+                double sacc = 0.0;
 #pragma unroll
-                    for (int kk = 0; kk <= EZ_ELL_MAX; ++kk)
-                        if (kk <= J) sacc = fma(poly[J - kk], Ck[kk], sacc);
-                    poly[J] = sacc;
-                }
-                deg = min(deg + ell, PD - 1);
+                for (int kk = 0; kk <= EZ_ELL_MAX; ++kk)
+                    if (kk <= J) sacc = fma(poly[J - kk], Ck[kk], sacc);
+                poly[J] = sacc;
             }
         }
         // fp int_0^eps u^{mu-1} L^Q du, mu = d + E + 2J:

@@ -72,21 +72,46 @@ __device__ __forceinline__ double had_sum(const double (&p)[PD], int deg, int E,
 // Adjoint of the direction kernel: the (0, eps) part and its strain derivative.
 // Under the strain G at fixed fractional direction, sigma |w|^e moves by
 // -(I + e w w^T/|w|^2) times itself, L(u) = log(pi u^2 |w|^2) by -2 w w^T/|w|^2,
-// and C_k by the strain channels of the tensors.  ndb <= EZ_HDIR_GRAD directions
-// per workgroup; one thread per (direction, combination) evaluates the value and
-// the d(d+1)/2 derivative components.
+// and C_k by the strain channels of the tensors.  A workgroup takes ndb <=
+// EZ_HDIR_GRAD directions (ndb n_combo <= 256).  Phase 1 contracts the tensors of
+// every channel, one thread per (channel, direction, order k); in phase 2 one thread
+// per (direction, combination) builds the product polynomial with its derivative
+// along each of the d(d+1)/2 strain components; phase 3 sums the combinations in
+// fixed order.
+// LDS (dynamic, laid out by had_adj_lds): staged tensors, C_k per (direction,
+// channel), direction data, and the value and derivatives per (direction, combination).
+struct HadAdjLds {
+    int tsh, csh, ssh, dsh, whsh, psh, vsh, bad, bytes;   // offsets in doubles; bytes in total
+};
+
+__host__ __device__ inline int had_adj_tdim(int D, int ell) {
+    int tdim = 0;
+    for (int k = 0; k <= ell; ++k) tdim += D == 1 ? 1 : (D == 2 ? 2 * k + 1 : (2 * k + 1) * (2 * k + 2) / 2);
+    return tdim;
+}
+
+// tdim: tensor coefficients per channel (of the largest Taylor order of the batch)
+__host__ __device__ inline HadAdjLds had_adj_lds(int NNU, int NCH, int ndb, int nc, int tdim) {
+    HadAdjLds L;
+    const int ts = NCH * NNU * tdim < EZ_HADJ_TSTAGE ? NCH * NNU * tdim : EZ_HADJ_TSTAGE;
+    L.tsh = 0;
+    L.csh = ts;
+    L.ssh = L.csh + ndb * NCH * NNU * (EZ_ELL_MAX + 1);
+    L.dsh = L.ssh + ndb * NNU;
+    L.whsh = L.dsh + ndb * 3;
+    L.psh = L.whsh + ndb * 3;
+    L.vsh = L.psh + ndb * 6;
+    L.bad = L.vsh + ndb * nc * NCH;
+    L.bytes = 8 * L.bad + 4 * ndb;
+    return L;
+}
+
 template <int D, int NNU, int PD>
 __global__ __launch_bounds__(256) void ez_hadamard_adj_kernel(EzQuadArgs args) {
     constexpr int NS = D * (D + 1) / 2;
     constexpr int NCH = 1 + NS;
-    __shared__ double Tsh[NNU * EZ_TDIM];
-    __shared__ double Csh[EZ_HDIR_GRAD][NCH][NNU][EZ_ELL_MAX + 1];
-    __shared__ double ssh[EZ_HDIR_GRAD][NNU];   // sigma_i |w|^{nu_i - d}
-    __shared__ double dsh[EZ_HDIR_GRAD][3];     // 2 w_v, log(pi eps^2 |w|^2), validity
-    __shared__ double whsh[EZ_HDIR_GRAD][3];    // w_hat
-    __shared__ double psh[EZ_HDIR_GRAD][6];     // w_a w_b / |w|^2 per strain component
-    __shared__ double vsh[256][NCH];            // value and derivatives of each (direction, combination)
-    __shared__ uint32_t fsh_bad[EZ_HDIR_GRAD];
+    constexpr int KS = EZ_ELL_MAX + 1;
+    extern __shared__ double lds_dyn[];
     const int blk = blockIdx.x;
     const int inst = find_segment(args.htile_begin, args.batch, blk);
     const EzInstPlan P = args.plans[inst];
@@ -109,8 +134,16 @@ __global__ __launch_bounds__(256) void ez_hadamard_adj_kernel(EzQuadArgs args) {
         }
         return;
     }
-    int tdim = 0;
-    for (int k = 0; k <= ell; ++k) tdim += nmono(D, 2 * k);
+    const HadAdjLds L = had_adj_lds(NNU, NCH, ndb, nc, had_adj_tdim(D, args.ell_probe));
+    double *Tsh = lds_dyn + L.tsh;
+    double *Csh = lds_dyn + L.csh;                              // [ndb][NCH][NNU][KS]
+    double (*ssh)[NNU] = reinterpret_cast<double (*)[NNU]>(lds_dyn + L.ssh);   // sigma_i |w|^{nu_i - d}
+    double (*dsh)[3] = reinterpret_cast<double (*)[3]>(lds_dyn + L.dsh);       // 2 w_v, log(pi eps^2 |w|^2), validity
+    double (*whsh)[3] = reinterpret_cast<double (*)[3]>(lds_dyn + L.whsh);     // w_hat
+    double (*psh)[6] = reinterpret_cast<double (*)[6]>(lds_dyn + L.psh);       // w_a w_b / |w|^2 per strain component
+    double (*vsh)[NCH] = reinterpret_cast<double (*)[NCH]>(lds_dyn + L.vsh);   // per (direction, combination)
+    uint32_t *fsh_bad = reinterpret_cast<uint32_t *>(lds_dyn + L.bad);
+    const int tdim = had_adj_tdim(D, ell);
     if (tid < ndb) {
         const int dl = d0 + tid;
         const bool valid = dl < P.n_dir;
@@ -133,10 +166,32 @@ __global__ __launch_bounds__(256) void ez_hadamard_adj_kernel(EzQuadArgs args) {
         for (int s = 0; s < NS; ++s) psh[tid][s] = w[ez_sa(D, s)] * w[ez_sb(D, s)] / w2;
         fsh_bad[tid] = 0u;
     }
-    // phase 1: C_k(w) of every channel from the tensors
-    for (int ch = 0; ch < NCH; ++ch)
-        contract_tensor<D, NNU>(args, inst, ch * NNU, NNU * NCH, ndb, ell, tdim, Tsh, whsh, &Csh[0][ch][0][0],
-                                NCH * NNU * (EZ_ELL_MAX + 1), EZ_ELL_MAX + 1);
+    // phase 1: C_k(w) of every channel from the tensors, as many channels staged at a
+    // time as the LDS holds (at least one: NNU tdim <= EZ_HADJ_TSTAGE)
+    {
+        const int NC = NNU * NCH;
+        const int cb = min(NCH, EZ_HADJ_TSTAGE / (NNU * tdim));
+        const double *T = args.tensor + (size_t)inst * NC * EZ_TDIM;
+        for (int c0 = 0; c0 < NCH; c0 += cb) {
+            const int cn = min(cb, NCH - c0);
+            __syncthreads();
+            for (int idx = tid; idx < cn * NNU * tdim; idx += 256) {
+                const int row = idx / tdim;
+                Tsh[idx] = T[(size_t)(c0 * NNU + row) * EZ_TDIM + (idx - row * tdim)];
+            }
+            __syncthreads();
+            for (int idx = tid; idx < cn * ndb * (ell + 1); idx += 256) {
+                const int cc = idx / (ndb * (ell + 1));
+                const int r = idx - cc * ndb * (ell + 1);
+                const int dd = r / (ell + 1), k = r - dd * (ell + 1);
+                double acc[NNU];
+                contract_order<D, NNU>(Tsh + cc * NNU * tdim, tdim, k, whsh[dd][0], whsh[dd][1], whsh[dd][2], acc);
+                double *Co = Csh + ((size_t)(dd * NCH + c0 + cc) * NNU) * KS + k;
+#pragma unroll
+                for (int i = 0; i < NNU; ++i) Co[i * KS] = acc[i];
+            }
+        }
+    }
     __syncthreads();
 
     // phase 2: one (direction, combination) per thread
@@ -147,47 +202,45 @@ __global__ __launch_bounds__(256) void ez_hadamard_adj_kernel(EzQuadArgs args) {
         const int t = cb.t;
         const int nf = prog.term_nfac[t];
         double c = cb.coef, jsum = 0.0, jse = 0.0;
-        double poly[PD];
-        poly[0] = 1.0;
-#pragma unroll
-        for (int J = 1; J < PD; ++J) poly[J] = 0.0;
-        int deg = 0;
+        int deg = 0, rest = 0;
         for (int f = 0; f < nf; ++f) {
             const int i = prog.term_fac[t][f];
             for (int q = 0; q < cb.j[f]; ++q) c *= ssh[myd][i];
             jsum += (double)cb.j[f];
             jse += (double)cb.j[f] * prog.e[i];
-            double Ck[EZ_ELL_MAX + 1];
-#pragma unroll
-            for (int kk = 0; kk <= EZ_ELL_MAX; ++kk) Ck[kk] = (kk <= ell) ? Csh[myd][0][i][kk] : 0.0;
-            for (int rep = 0; rep < prog.term_mult[t][f] - cb.j[f]; ++rep) {
-                poly_mul_trunc<PD>(poly, Ck);
-                deg = min(deg + ell, PD - 1);
-            }
+            for (int rep = 0; rep < prog.term_mult[t][f] - cb.j[f]; ++rep) deg = min(deg + ell, PD - 1);
+            rest += prog.term_mult[t][f] - cb.j[f];
         }
         const double Leps = dsh[myd][1];
-        double base_m1 = 0.0;
-        const double base = had_sum<D, PD>(poly, deg, cb.E, cb.Q, P.eps, Leps, &base_m1, &bad);
-        vsh[tid][0] = c * base;
-#pragma unroll
+        const double *Cd = Csh + (size_t)myd * NCH * NNU * KS;
+#pragma unroll 1
         for (int s = 0; s < NS; ++s) {
+            // (p, dp): the product polynomial and its derivative along strain component s
             double p[PD], dp[PD];
             p[0] = 1.0;
             dp[0] = 0.0;
 #pragma unroll
             for (int J = 1; J < PD; ++J) { p[J] = 0.0; dp[J] = 0.0; }
-            for (int f = 0; f < nf; ++f) {
+            // the Taylor factors of the product in one loop of `rest` multiplications
+            // (factor f taken mult_f - j_f times in turn), so that the lanes of a wave,
+            // which hold different combinations, differ only in its trip count
+            int f = 0, left = nf > 0 ? prog.term_mult[t][0] - cb.j[0] : 0;
+            for (int m = 0; m < rest; ++m) {
+                while (left == 0) { ++f; left = prog.term_mult[t][f] - cb.j[f]; }
+                --left;
                 const int i = prog.term_fac[t][f];
                 double Ck[EZ_ELL_MAX + 1], dCk[EZ_ELL_MAX + 1];
 #pragma unroll
                 for (int kk = 0; kk <= EZ_ELL_MAX; ++kk) {
-                    Ck[kk] = (kk <= ell) ? Csh[myd][0][i][kk] : 0.0;
-                    dCk[kk] = (kk <= ell) ? Csh[myd][1 + s][i][kk] : 0.0;
+                    Ck[kk] = (kk <= ell) ? Cd[i * KS + kk] : 0.0;
+                    dCk[kk] = (kk <= ell) ? Cd[((1 + s) * NNU + i) * KS + kk] : 0.0;
                 }
-                for (int rep = 0; rep < prog.term_mult[t][f] - cb.j[f]; ++rep) poly_mul_trunc_d<PD>(p, dp, Ck, dCk);
+                poly_mul_trunc_d<PD>(p, dp, Ck, dCk);
             }
-            double dummy = 0.0;
+            double base_m1 = 0.0, dummy = 0.0;
+            const double base = had_sum<D, PD>(p, deg, cb.E, cb.Q, P.eps, Leps, &base_m1, &bad);
             const double dsum = had_sum<D, PD>(dp, deg, cb.E, cb.Q, P.eps, Leps, &dummy, &bad);
+            if (s == 0) vsh[tid][0] = c * base;
             const double Ps = psh[myd][s];
             const double delta = (s < D) ? 1.0 : 0.0;
             vsh[tid][1 + s] = c * (dsum + (-jsum * delta - jse * Ps) * base - 2.0 * (double)cb.Q * Ps * base_m1);
@@ -242,7 +295,9 @@ hipError_t launch_had_t(const EzQuadArgs &args, int n_htiles, hipStream_t stream
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (!(part & EZ_HAD_DIR)) return hipSuccess;   // direction kernel
-    hipLaunchKernelGGL((ez_hadamard_adj_kernel<D, NNU, PD>), dim3(n_htiles), dim3(256), 0, stream, args);
+    const HadAdjLds L = had_adj_lds(NNU, 1 + D * (D + 1) / 2, args.n_dir_blk, args.n_combo, had_adj_tdim(D, args.ell_probe));
+    if (L.bytes > 160 * 1024) return hipErrorInvalidConfiguration;   // a CU's LDS on gfx950
+    hipLaunchKernelGGL((ez_hadamard_adj_kernel<D, NNU, PD>), dim3(n_htiles), dim3(256), L.bytes, stream, args);
     return hipGetLastError();
 }
 

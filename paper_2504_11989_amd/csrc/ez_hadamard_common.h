@@ -385,9 +385,48 @@ __global__ __launch_bounds__(256) void ez_tensor_kernel(EzQuadArgs args) {
     }
 }
 
+// C_k(w) of NNU channels staged at Tsh (NNU rows of tdim coefficients) for one order
+// k: monomials of w_hat of degree 2k in the order a0 desc, a1 desc
+template <int D, int NNU>
+__device__ __forceinline__ void contract_order(const double *Tsh, int tdim, int k, double x0, double x1, double x2,
+                                               double (&acc)[NNU]) {
+    const int g = 2 * k;
+    int off = 0;
+    for (int kk = 0; kk < k; ++kk) off += nmono(D, 2 * kk);
+#pragma unroll
+    for (int i = 0; i < NNU; ++i) acc[i] = 0.0;
+    if (D == 1) {
+        double mono = 1.0;
+        for (int q = 0; q < g; ++q) mono *= x0;
+#pragma unroll
+        for (int i = 0; i < NNU; ++i) acc[i] = Tsh[i * tdim + off] * mono;
+    } else if (D == 2) {
+        int a_idx = 0;
+        for (int a = g; a >= 0; --a, ++a_idx) {
+            double mono = 1.0;
+            for (int q = 0; q < a; ++q) mono *= x0;
+            for (int q = 0; q < g - a; ++q) mono *= x1;
+#pragma unroll
+            for (int i = 0; i < NNU; ++i) acc[i] = fma(Tsh[i * tdim + off + a_idx], mono, acc[i]);
+        }
+    } else {
+        int a_idx = 0;
+        for (int a = g; a >= 0; --a) {
+            double p0 = 1.0;
+            for (int q = 0; q < a; ++q) p0 *= x0;
+            for (int b = g - a; b >= 0; --b, ++a_idx) {
+                double mono = p0;
+                for (int q = 0; q < b; ++q) mono *= x1;
+                for (int q = 0; q < g - a - b; ++q) mono *= x2;
+#pragma unroll
+                for (int i = 0; i < NNU; ++i) acc[i] = fma(Tsh[i * tdim + off + a_idx], mono, acc[i]);
+            }
+        }
+    }
+}
+
 // C_k(w) of the channels [c0, c0 + NNU) for the directions of a workgroup: the
-// tensors staged in LDS, one thread per (direction, order k); monomials of w_hat
-// of degree 2k in the order a0 desc, a1 desc.
+// tensors staged in LDS, one thread per (direction, order k)
 template <int D, int NNU>
 __device__ __forceinline__ void contract_tensor(const EzQuadArgs &args, int inst, int c0, int NC, int ndb, int ell,
                                                 int tdim, double *Tsh, const double (*wsh)[3],
@@ -402,41 +441,8 @@ __device__ __forceinline__ void contract_tensor(const EzQuadArgs &args, int inst
     __syncthreads();
     for (int idx = tid; idx < ndb * (ell + 1); idx += 256) {
         const int dd = idx / (ell + 1), k = idx - dd * (ell + 1);
-        const int g = 2 * k;
-        int off = 0;
-        for (int kk = 0; kk < k; ++kk) off += nmono(D, 2 * kk);
-        const double x0 = wsh[dd][0], x1 = wsh[dd][1], x2 = wsh[dd][2];
         double acc[NNU];
-#pragma unroll
-        for (int i = 0; i < NNU; ++i) acc[i] = 0.0;
-        if (D == 1) {
-            double mono = 1.0;
-            for (int q = 0; q < g; ++q) mono *= x0;
-#pragma unroll
-            for (int i = 0; i < NNU; ++i) acc[i] = Tsh[i * tdim + off] * mono;
-        } else if (D == 2) {
-            int a_idx = 0;
-            for (int a = g; a >= 0; --a, ++a_idx) {
-                double mono = 1.0;
-                for (int q = 0; q < a; ++q) mono *= x0;
-                for (int q = 0; q < g - a; ++q) mono *= x1;
-#pragma unroll
-                for (int i = 0; i < NNU; ++i) acc[i] = fma(Tsh[i * tdim + off + a_idx], mono, acc[i]);
-            }
-        } else {
-            int a_idx = 0;
-            for (int a = g; a >= 0; --a) {
-                double p0 = 1.0;
-                for (int q = 0; q < a; ++q) p0 *= x0;
-                for (int b = g - a; b >= 0; --b, ++a_idx) {
-                    double mono = p0;
-                    for (int q = 0; q < b; ++q) mono *= x1;
-                    for (int q = 0; q < g - a - b; ++q) mono *= x2;
-#pragma unroll
-                    for (int i = 0; i < NNU; ++i) acc[i] = fma(Tsh[i * tdim + off + a_idx], mono, acc[i]);
-                }
-            }
-        }
+        contract_order<D, NNU>(Tsh, tdim, k, wsh[dd][0], wsh[dd][1], wsh[dd][2], acc);
 #pragma unroll
         for (int i = 0; i < NNU; ++i) Cout[dd * cstride_d + i * cstride_c + k] = acc[i];
     }
