@@ -79,7 +79,7 @@ typedef struct ez_quad_spec {
  *                       tiles from a work queue, costliest tiles first
  *  EZ_SPEC_SERIAL     : the Hadamard direction kernel runs on the caller's stream
  *                       before the nodes instead of concurrently on a second
- *                       stream (calls with derivatives always run this way)
+ *                       stream
  *  EZ_SPEC_BPC(n)     : persistent workgroups per CU (0: as many as fit)
  *  EZ_SPEC_NO_SPLIT   : value calls hand the last node tiles, when they would
  *                       fill at most a quarter of a round of workgroups over the

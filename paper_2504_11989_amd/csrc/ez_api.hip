@@ -708,11 +708,10 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     };
     // The fork event is recorded by the tensor launch itself (no marker packet between
     // the tensors and the node kernel), or by hipEventRecord while the stream is captured.
-    // dE/dA calls keep the direction kernel on the caller's stream before the nodes: the
-    // adjoint direction and node kernels cannot share a SIMD's registers, so on a second
-    // queue the direction kernel would only start as the adjoint node kernel drains and
-    // end well after it (C2: 1.015 ms per step there, 0.978 ms in order)
-    const bool side = !(flags & EZ_SPEC_SERIAL) && !grad;
+    // With derivatives the direction kernel only gets slots as the adjoint node kernel
+    // drains, and runs beside its last, partly filled round of tiles (C2: 0.869 ms per
+    // step, 0.901 ms with the direction kernel before the nodes).
+    const bool side = !(flags & EZ_SPEC_SERIAL);
     // Batches whose node tiles fill more than eight rounds of the device are bound by
     // throughput, not latency: there the probe and tensor kernels go to the second
     // stream as well, where their work fills slots beside the node kernel's instead of

@@ -77,6 +77,17 @@ def test_atm_grad_identities(ez, name, seed):
     assert np.linalg.norm(S - S.T) <= 1e-11 * np.linalg.norm(S)
 
 
+def test_grad_schedules_give_identical_results(ez):
+    """the adjoint direction kernel on the second stream (default) or before the
+    nodes on the caller's stream (serial flag): same partials, same sums, bit for bit"""
+    from paper_2504_11989_amd._native import SPEC_SERIAL
+    lat = np.stack([perturbed(W.sc(), 55), perturbed(W.fcc(), 56), perturbed(W.bcc(), 57)])
+    E0, g0 = ez.atm_energy(lat, W.SPEC_SMALL_3D, grad=True)
+    E1, g1 = ez.atm_energy(lat, dict(W.SPEC_SMALL_3D, flags=SPEC_SERIAL), grad=True)
+    assert np.array_equal(E0.cpu().numpy(), E1.cpu().numpy())
+    assert np.array_equal(g0.cpu().numpy(), g1.cpu().numpy())
+
+
 def test_atm_grad_vs_gpu_central_differences(ez):
     A = perturbed(W.bcc(), 55)
     spec = W.SPEC_SMALL_3D
