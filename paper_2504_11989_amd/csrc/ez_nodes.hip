@@ -438,26 +438,40 @@ __global__ __launch_bounds__(FT) void ez_finalize_kernel(EzQuadArgs args) {
         }
     }
     if (!args.grad_out) return;
-    // d result / d A = S A^{-T}, S the symmetric strain derivative (d(d+1)/2 components)
+    // d result / d A = S A^{-T}, S the symmetric strain derivative (d(d+1)/2 components),
+    // all components summed in one sweep: each in the same fixed order as the value
     const int d = args.prog.d, ns = d * (d + 1) / 2;
     __shared__ double Ssh[6];
+    __shared__ double red6[FT / 64][6][2];
     for (int r = 0; r < n_res; ++r) {
-        for (int sc = 0; sc < ns; ++sc) {
-            ez_dd s{0.0, 0.0};
-            for (int t = tb + (int)threadIdx.x; t < te; t += FT)
-                s = ez_dd_add(s, ez_dd{args.tile_grad[(((size_t)t * n_res + r) * 6 + sc) * 2],
-                                       args.tile_grad[(((size_t)t * n_res + r) * 6 + sc) * 2 + 1]});
-            for (int g = db + (int)threadIdx.x; g < de; g += FT)
-                s = ez_dd_add_d(s, args.dir_grad[((size_t)g * n_res + r) * 6 + sc]);
-            s = ez_dd_wave_sum(s);
-            __syncthreads();
-            if (lane == 0) { red[wave][0] = s.hi; red[wave][1] = s.lo; }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                ez_dd tot{red[0][0], red[0][1]};
-                for (int w = 1; w < FT / 64; ++w) tot = ez_dd_add(tot, ez_dd{red[w][0], red[w][1]});
-                Ssh[sc] = tot.hi + tot.lo;
-            }
+        ez_dd s[6];
+#pragma unroll
+        for (int sc = 0; sc < 6; ++sc) s[sc] = ez_dd{0.0, 0.0};
+        for (int t = tb + (int)threadIdx.x; t < te; t += FT) {
+            const double *tg = args.tile_grad + ((size_t)t * n_res + r) * 12;
+#pragma unroll
+            for (int sc = 0; sc < 6; ++sc)
+                if (sc < ns) s[sc] = ez_dd_add(s[sc], ez_dd{tg[2 * sc], tg[2 * sc + 1]});
+        }
+        for (int g = db + (int)threadIdx.x; g < de; g += FT) {
+            const double *dg = args.dir_grad + ((size_t)g * n_res + r) * 6;
+#pragma unroll
+            for (int sc = 0; sc < 6; ++sc)
+                if (sc < ns) s[sc] = ez_dd_add_d(s[sc], dg[sc]);
+        }
+#pragma unroll
+        for (int sc = 0; sc < 6; ++sc) s[sc] = ez_dd_wave_sum(s[sc]);
+        __syncthreads();
+        if (lane == 0) {
+#pragma unroll
+            for (int sc = 0; sc < 6; ++sc) { red6[wave][sc][0] = s[sc].hi; red6[wave][sc][1] = s[sc].lo; }
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < ns) {
+            const int sc = (int)threadIdx.x;
+            ez_dd tot{red6[0][sc][0], red6[0][sc][1]};
+            for (int w = 1; w < FT / 64; ++w) tot = ez_dd_add(tot, ez_dd{red6[w][sc][0], red6[w][sc][1]});
+            Ssh[sc] = tot.hi + tot.lo;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
