@@ -84,9 +84,10 @@ struct HadAdjLds {
     int tsh, csh, ssh, dsh, whsh, psh, vsh, bad, bytes;   // offsets in doubles; bytes in total
 };
 
+// tensor coefficients per channel: monomials of even degree <= 2 ell in D variables
 __host__ __device__ inline int had_adj_tdim(int D, int ell) {
     int tdim = 0;
-    for (int k = 0; k <= ell; ++k) tdim += D == 1 ? 1 : (D == 2 ? 2 * k + 1 : (2 * k + 1) * (2 * k + 2) / 2);
+    for (int k = 0; k <= ell; ++k) tdim += nmono(D, 2 * k);
     return tdim;
 }
 
