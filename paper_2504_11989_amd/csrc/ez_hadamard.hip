@@ -156,7 +156,7 @@ hipError_t launch_had_t(const EzQuadArgs &args, int n_htiles, hipStream_t stream
         const int nblk = (args.n_probe + 63) / 64;
         const int nch = false ? args.n_ch : 1;
         hipLaunchKernelGGL((ez_probe_kernel<D, NNU, false>), dim3(args.batch * nblk * args.n_slice * nch), dim3(64 * EZ_HW),
-                           0, stream, args);
+                           (probe_lds_bytes<NNU, false>(args.ell_probe)), stream, args);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         int tdim = 0;

@@ -135,13 +135,16 @@ __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta 
         const double *kt = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
         const int n_rec = M->n_rec;
         const int nfmax = dch ? 2 * ell + 1 : 2 * ell;
-        for (int base = 1 + slice * EZ_HCH; base < n_rec; base += EZ_HCH * n_slice) {
+        // entries 1 .. n_rec - 1 in equal contiguous shares per slice, in chunks of EZ_HCH
+        const int per = (n_rec - 1 + n_slice - 1) / n_slice;
+        const int lo = 1 + slice * per, hi = min(n_rec, lo + per);
+        for (int base = lo; base < hi; base += EZ_HCH) {
             __syncthreads();
             // F_n for (entry, nu) pairs, one per thread
             for (int task = (int)threadIdx.x; task < EZ_HCH * NNU; task += 64 * EZ_HW) {
                 const int te = task / NNU, i = task - te * NNU;
                 const int q = base + te;
-                if (q < n_rec) {
+                if (q < hi) {
                     const double a0 = alpha * kt[(size_t)q * 4 + 3];
                     const double ex = exp(-a0), inv = ez_rcp(a0);
                     const int p2 = prog.p2[i];
@@ -161,7 +164,7 @@ __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta 
                 }
             }
             __syncthreads();
-            const int cnt = min(EZ_HCH, n_rec - base);
+            const int cnt = min(EZ_HCH, hi - base);
             for (int t = part; t < cnt; t += EZ_HW) {
                 const double *e = kt + (size_t)(base + t) * 4;
                 double b = 0.0;
@@ -268,34 +271,46 @@ __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta 
             }
         }
     }
-    // fixed-order sum of the waves' coefficients into wave 0 (LDS reused)
-    for (int src = 1; src < EZ_HW; ++src) {
-        __syncthreads();
-        if (part == src) {
+    // fixed-order sum of the waves' coefficients into wave 0: waves 1 .. EZ_HW - 1 write
+    // their orders k <= ell to regions of their own (the F_n table is no longer read),
+    // and wave 0 adds the regions in wave order
+    const int KL = ell + 1;
+    __syncthreads();
+    if (part != 0) {
+        double *R = lds + (size_t)(part - 1) * NNU * KL * 64;
+#pragma unroll
+        for (int i = 0; i < NNU; ++i)
+#pragma unroll
+            for (int k = 0; k <= EZ_ELL_MAX; ++k)
+                if (k <= ell) R[(i * KL + k) * 64 + lane] = C[i][k];
+    }
+    __syncthreads();
+    if (part == 0) {
+        for (int src = 1; src < EZ_HW; ++src) {
+            const double *R = lds + (size_t)(src - 1) * NNU * KL * 64;
 #pragma unroll
             for (int i = 0; i < NNU; ++i)
 #pragma unroll
                 for (int k = 0; k <= EZ_ELL_MAX; ++k)
-                    if (k <= ell) lds[(i * (EZ_ELL_MAX + 1) + k) * 64 + lane] = C[i][k];
-        }
-        __syncthreads();
-        if (part == 0) {
-#pragma unroll
-            for (int i = 0; i < NNU; ++i)
-#pragma unroll
-                for (int k = 0; k <= EZ_ELL_MAX; ++k)
-                    if (k <= ell) C[i][k] += lds[(i * (EZ_ELL_MAX + 1) + k) * 64 + lane];
+                    if (k <= ell) C[i][k] += R[(i * KL + k) * 64 + lane];
         }
     }
+}
+
+// dynamic LDS of the probe kernel: the F_n table of one chunk, or the partial
+// coefficients of waves 1 .. EZ_HW - 1 (orders k <= ell)
+template <int NNU, bool GR>
+inline size_t probe_lds_bytes(int ell) {
+    const size_t fsz = (size_t)EZ_HCH * NNU * (GR ? EZ_NF + 1 : EZ_NF);
+    const size_t csz = (size_t)(EZ_HW - 1) * NNU * (ell + 1) * 64;
+    return sizeof(double) * (fsz > csz ? fsz : csz);
 }
 
 // Probe kernel: partial C_k(B w_hat_p) over one table slice for 64 probe directions,
 // one channel (value or strain component).  Grid: batch x probe blocks x slices x channels.
 template <int D, int NNU, bool GR>
 __global__ __launch_bounds__(64 * EZ_HW) void ez_probe_kernel(EzQuadArgs args) {
-    constexpr int FSZ = EZ_HCH * NNU * (GR ? EZ_NF + 1 : EZ_NF);
-    constexpr int CSZ = 64 * NNU * (EZ_ELL_MAX + 1);
-    __shared__ double lds[FSZ > CSZ ? FSZ : CSZ];
+    extern __shared__ double lds[];                 // probe_lds_bytes<NNU, GR>(args.ell_probe)
     const int nblk = (args.n_probe + 63) / 64;
     const int S = args.n_slice, NCH = GR ? args.n_ch : 1;
     const int per_inst = nblk * S * NCH;
