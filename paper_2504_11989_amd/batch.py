@@ -1,4 +1,4 @@
-"""Batched lattice sums: the C3-style scan program and replay of a captured HIP graph.
+"""Batched lattice sums: the 4096-lattice bct scan program and replay of a captured HIP graph.
 
 A scan evaluates many lattices with uneven quadrature plans in one call of the
 library (one launch sequence: setup, the node kernel over every node tile of the

@@ -709,13 +709,14 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     // The fork event is recorded by the tensor launch itself (no marker packet between
     // the tensors and the node kernel), or by hipEventRecord while the stream is captured.
     // With derivatives the direction kernel only gets slots as the adjoint node kernel
-    // drains, and runs beside its last, partly filled round of tiles (C2: 0.869 ms per
-    // step, 0.901 ms with the direction kernel before the nodes).
+    // drains, and runs beside its last, partly filled round of tiles (three-lattice ATM
+    // derivative, 263424 nodes each: 0.869 ms per step, 0.901 ms with the direction
+    // kernel before the nodes).
     const bool side = !(flags & EZ_SPEC_SERIAL);
     // Batches whose node tiles fill more than eight rounds of the device are bound by
     // throughput, not latency: there the probe and tensor kernels go to the second
     // stream as well, where their work fills slots beside the node kernel's instead of
-    // preceding it (C3 scan).
+    // preceding it (the 4096-lattice scan).
     const bool big = side && P->n_tiles > 8 * round;
     hipStream_t hs = stream;
     if (big) {

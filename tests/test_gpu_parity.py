@@ -97,7 +97,7 @@ def test_nbody_3d_small_plan(ez, nus):
 
 
 def test_lattice_sums_multi_result(ez):
-    # C3-style program: zeta(nu,nu,nu) for nu in {3,6,9,12} plus ATM, one node pass
+    # scan-style program: zeta(nu,nu,nu) for nu in {3,6,9,12} plus ATM, one node pass
     nu = [-1.0, 1.0, 3.0, 5.0, 6.0, 9.0, 12.0]
     terms = [(0, 1.0, [(2, 3)]), (1, 1.0, [(4, 3)]), (2, 1.0, [(5, 3)]), (3, 1.0, [(6, 3)]),
              (4, 1.0 / 24.0, [(2, 3)]), (4, -3.0 / 16.0, [(0, 1), (3, 2)]), (4, 3.0 / 8.0, [(1, 1), (2, 1), (3, 1)])]
@@ -128,7 +128,7 @@ def test_determinism(ez):
     assert np.array_equal(a, b)
 
 
-# ---------------------------------------------------------------- full-size C2 (bench config)
+# ---------------------------------------------------------------- full-size three-lattice ATM plan (as timed by bench.py)
 def test_c2_full_size_vs_stored_oracle(ez):
     g = json.load(open(os.path.join(GOLD, "oracle_c2_full.json")))
     names = ["sc", "fcc", "bcc"]
