@@ -170,3 +170,23 @@ def test_enthalpy_minimisation_decreases_and_converges(ez):
     # pure LJ: the minimum from an fcc start is fcc; its energy is below the bcc-start one
     assert H.classify(res["A"][0]) == "fcc"
     assert res["H"][0] <= res["H"][1] + 1e-9
+
+
+def test_eight_exponents_taylor_order_six(ez):
+    """large probe and adjoint-direction LDS layouts (86 and 113 KB): 8 exponents,
+    Taylor order 6 (the oracle's largest), four-factor products (degree 24 on
+    (0, eps)); values against the oracle, derivatives by homogeneity of degree
+    -sum(nu) and the symmetry of the strain derivative"""
+    nu = [-1.0, 1.0, 3.0, 5.0, 6.0, 7.0, 9.0, 12.0]
+    terms = [(0, 1.0, [(0, 1), (1, 1), (2, 1), (3, 1)]), (1, 1.0, [(4, 1), (5, 1), (6, 1), (7, 1)])]
+    spec = dict(W.SPEC_SMALL_3D, ell=6)
+    A = perturbed(W.fcc(), 58)
+    R, g = ez.lattice_sums(A, nu, terms, 2, spec, grad=True)
+    R, g = R[0].cpu().numpy(), g[0].cpu().numpy()
+    for r, nus in enumerate([(-1, 1, 3, 5), (6, 7, 9, 12)]):
+        ref = O.nbody(A, nus, spec)
+        assert abs(R[r] - ref) <= 1e-10 * abs(ref), (r, R[r], ref)
+        deg = -float(sum(nus))
+        assert abs(np.trace(A.T @ g[r]) - deg * R[r]) <= 1e-10 * abs(deg * R[r]), r
+        S = g[r] @ A.T
+        assert np.linalg.norm(S - S.T) <= 1e-10 * np.linalg.norm(S), r
