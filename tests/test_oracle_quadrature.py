@@ -164,3 +164,56 @@ def test_nbody_bound():
         z = O.nbody(A, nus, spec)
         bound = np.prod([O.epstein(A, v, np.zeros(3), np.zeros(3)).real for v in nus])
         assert abs(z) <= bound
+
+
+def _ring_tail_bound(d, nus, L, zeta0):
+    """Bound on the ring summands that the box {-L..L}^d omits, for a lattice
+    whose shortest vector has length >= 1.  A ring configuration with a vertex
+    outside the box has an edge e_i with |e_i|_inf > L/(n-1) (the vertex is a sum
+    of at most n-1 edges); with e_i fixed, the n-2 edges after it are summed
+    freely and the last one is fixed by the closing constraint (its factor is at
+    most 1).  So the omitted part is at most
+        sum_i T_i * prod_{j != i, j != i-1} Z_{nu_j}(0),
+    T_i = sum over lattice points with |n|_inf > L/(n-1) of |z|^-nu_i, bounded
+    for d = 1 by 2 sum_{m > R} m^-nu <= 2 R^(1-nu)/(nu-1) (R = floor(L/(n-1)))."""
+    n = len(nus)
+    assert d == 1
+    R = L // (n - 1)
+    tot = 0.0
+    for i in range(n):
+        T = 2.0 * R ** (1.0 - nus[i]) / (nus[i] - 1.0)
+        prod = 1.0
+        for j in range(n):
+            if j != i and j != (i - 1) % n:
+                prod *= zeta0(nus[j])
+        tot += T * prod
+    return tot
+
+
+@pytest.mark.parametrize("nus,L", [((8, 8, 8, 8), 120), ((6, 7, 8, 9), 120), ((12, 12, 12, 12, 12), 30),
+                                   ((7, 8, 9, 10, 11), 30)])
+def test_ring_sums_1d_against_direct(nus, L):
+    """n = 4, 5 ring sums (paper, Sec. 2, Definition (Many-body zeta function),
+    x^(n) = x^(0)) by the quadrature against the direct ring sum over the box,
+    with the tail bound above: pins the n >= 4 products, their Hadamard
+    expansion with several Taylor factors, and the recursion of the direct sum."""
+    zeta0 = lambda nu: 2.0 * float(mp.zeta(nu))
+    q = O.nbody(Z1, nus, W.SPEC_1D)
+    dsum = O.direct_nbody(Z1, nus, L)
+    bound = _ring_tail_bound(1, nus, L, zeta0)
+    assert abs(q - dsum) <= bound + 1e-13 * abs(q), (q, dsum, bound)
+    # what the two reach in practice (the bound is loose for n = 5)
+    assert abs(q - dsum) <= 5e-13 * abs(q)
+
+
+@pytest.mark.parametrize("nus,L", [((16, 16, 16, 16), 6), ((12, 14, 16, 18), 6), ((16, 16, 16, 16, 16), 4)])
+def test_ring_sums_hex_against_direct(nus, L):
+    """n = 4, 5 on the hexagonal lattice (paper, Sec. 4, the n-body comparison
+    against direct sums) at exponents where the box {-L..L}^2 leaves a tail below
+    1e-13 relative; the direct ring sum has settled (it moves by less than 1e-9
+    from L - 1 to L, and the tail falls off as a high power of L)."""
+    q = O.nbody(W.A_HEX, nus, W.SPEC_2D)
+    dsum = O.direct_nbody(W.A_HEX, nus, L)
+    prev = O.direct_nbody(W.A_HEX, nus, L - 1)
+    assert abs(dsum - prev) <= 1e-9 * abs(dsum)
+    assert abs(q - dsum) <= 1e-13 * abs(q), (q, dsum)
