@@ -54,13 +54,25 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(spec, min_seconds: float = 10.0) -> dict:
     """The oracle (oracle/ezo.c, OpenMP over directions) on the same three
     lattices at the full plan, sc, fcc, bcc in turn, repeated until at least
-    min_seconds of work (a bounded sample of the timed workload)."""
+    min_seconds of work (a bounded sample of the timed workload), with all the
+    host threads; then one lattice sum (sc) on a single thread."""
     import oracle
     import workloads as W
     lats = [W.sc(), W.fcc(), W.bcc()]
+    n_all = oracle.num_threads()
     n = 0
     t0 = time.perf_counter()
     while True:
@@ -69,8 +81,18 @@ def cpu_baseline(spec, min_seconds: float = 10.0) -> dict:
         dt = time.perf_counter() - t0
         if n >= 3 and dt >= min_seconds:
             break
-    return {"value": n / dt, "unit": "ATM lattice sums/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "%d lattice sums (sc, fcc, bcc in turn), full 263424-node plan each, %.1f s" % (n, dt)}
+    oracle.set_num_threads(1)
+    try:
+        t1 = time.perf_counter()
+        oracle.atm(lats[0], spec)
+        dt1 = time.perf_counter() - t1
+    finally:
+        oracle.set_num_threads(n_all)
+    return {"value": n / dt, "unit": "ATM lattice sums/s", "cores": n_all, "kind": "oracle",
+            "sample": "%d lattice sums (sc, fcc, bcc in turn), full 263424-node plan each, %.1f s" % (n, dt),
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "single_thread": {"value": 1.0 / dt1, "unit": "ATM lattice sums/s", "cores": 1,
+                              "sample": "1 lattice sum (sc), full plan, %.1f s" % dt1}}
 
 
 def c3_scan_leg(args) -> dict:
@@ -199,6 +221,95 @@ def c4_grid_leg(args) -> dict:
     return out
 
 
+def c5_leg(args) -> dict:
+    """Differentiation and n-body sums.  (1) dH/dA of H = E_LJ(12-6) + c E_ATM + p V
+    from the adjoint kernels against central differences of the GPU value (h =
+    1e-6) on 16 generator matrices perturbed by up to 10% from fcc/bcc (seed 5),
+    c = 1, p = 0.5.  (2) The (c, p) scan: c in linspace(0, 2, 32), p in
+    linspace(0, 1, 32), BFGS from a perturbed fcc and a perturbed bcc start at
+    every point, all 2048 minimisations batched (one lattice-sum call with
+    derivatives per trial step); the winning lattice per point classified by its
+    neighbour shells.  (3) Ring sums zeta^(n)(6, ..., 6), n = 2..6, on the simple
+    cubic lattice, full plan."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import workloads as W
+    import paper_2504_11989_amd as ez
+    from paper_2504_11989_amd import enthalpy as H
+
+    spec = dict(W.SPEC_SMALL_3D)
+    out = {"workload": "H = E_LJ(12-6) + c E_ATM + p V per particle, 3x3 generator matrices; "
+                       "(c, p) grid 32 x 32, c in [0,2], p in [0,1], starts: fcc and bcc with entries perturbed "
+                       "by up to 10% (seed 5); ring sums zeta^(n)(6,...,6) n = 2..6 on sc; FP64",
+           "plan": spec}
+    # (1) gradient check, batched over the 16 matrices
+    A = W.c5_perturbed(count=16)
+    c, p = 1.0, 0.5
+    At = torch.tensor(A, device="cuda")
+    _, g, _, _ = H.enthalpy(At, c, p, spec)
+    g = g.cpu().numpy()
+    hh = 1e-6
+    fd = np.zeros_like(g)
+    for i in range(3):
+        for j in range(3):
+            Ap, Am = A.copy(), A.copy()
+            Ap[:, i, j] += hh
+            Am[:, i, j] -= hh
+            hp = H.enthalpy(torch.tensor(Ap, device="cuda"), c, p, spec)[0].cpu().numpy()
+            hm = H.enthalpy(torch.tensor(Am, device="cuda"), c, p, spec)[0].cpu().numpy()
+            fd[:, i, j] = (hp - hm) / (2 * hh)
+    err = max(float(np.linalg.norm(g[b] - fd[b]) / np.linalg.norm(fd[b])) for b in range(len(A)))
+    out["grad_check"] = {"matrices": len(A), "c": c, "p": p, "h": hh, "max_rel_err_adjoint_vs_central_fd": err}
+    # (2) the phase scan
+    cs, ps = W.c5_grid(32)
+    starts = W.c5_perturbed(count=2)          # perturbed fcc, perturbed bcc
+    n_eval = {"calls": 0}
+    inner = H.enthalpy
+
+    def counted(*a, **k):
+        n_eval["calls"] += 1
+        return inner(*a, **k)
+
+    H.enthalpy = counted
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = H.phase_scan(cs, ps, starts, spec, max_iter=args.c5_iters, gtol=1e-7)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    finally:
+        H.enthalpy = inner
+    nmin = res["H"].size
+    phase = res["phase"]
+    names, counts = np.unique(phase.astype(str), return_counts=True)
+    out["scan"] = {"grid": [len(cs), len(ps)], "starts": ["fcc", "bcc"], "minimisations": int(nmin),
+                   "seconds": dt, "minimisations_per_s": nmin / dt, "iterations": int(res["iterations"]),
+                   "batched_evaluations": n_eval["calls"],
+                   "lattice_evals_with_grad_per_s": n_eval["calls"] * nmin / dt,
+                   "converged": int(res["converged"].sum()),
+                   "max_grad_norm": float(np.nanmax(res["grad_norm"])),
+                   "phase_counts": {str(k): int(v) for k, v in zip(names, counts)},
+                   "phase_map_rows_c_cols_p": ["".join(str(x)[0] for x in row) for row in phase]}
+    # (3) ring sums on sc, full plan, timed; the small plan against the oracle
+    full = dict(W.SPEC_FULL_3D)
+    ring = {}
+    for n in range(2, 7):
+        v = ez.nbody_lattice_sum(W.sc(), [6.0] * n, full)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            v = ez.nbody_lattice_sum(W.sc(), [6.0] * n, full)
+        torch.cuda.synchronize()
+        vs = ez.nbody_lattice_sum(W.sc(), [6.0] * n, spec).item()
+        ref = oracle.nbody(W.sc(), [6.0] * n, spec)
+        ring[str(n)] = {"value_full_plan": v.item(), "ms": 1e3 * (time.perf_counter() - t0) / 5,
+                        "rel_err_vs_oracle_small_plan": abs(vs - ref) / abs(ref)}
+    out["ring_sums_sc_nu6"] = ring
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,6 +321,8 @@ def main() -> int:
     ap.add_argument("--c3-reps", type=int, default=3)
     ap.add_argument("--no-c4", action="store_true", help="skip the mixed-precision Epstein grid leg")
     ap.add_argument("--c4-reps", type=int, default=3)
+    ap.add_argument("--no-c5", action="store_true", help="skip the enthalpy scan and ring-sum leg")
+    ap.add_argument("--c5-iters", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 1 GiB device-to-device copies (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -346,12 +459,15 @@ def main() -> int:
         "adjoint": adj,
         "c3_scan": None,
         "c4_grid": None,
+        "c5": None,
         "cpu_baseline": None,
     }
     if not args.no_c3:
         line["c3_scan"] = c3_scan_leg(args)
     if not args.no_c4:
         line["c4_grid"] = c4_grid_leg(args)
+    if not args.no_c5:
+        line["c5"] = c5_leg(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec)
     print(json.dumps(line), flush=True)

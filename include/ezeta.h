@@ -55,10 +55,10 @@ typedef enum {
 /* Quadrature plan of the Epstein representation (paper, Sec. 3):
  * v in [0,1]^{d-1}: n_q-point Gauss-Legendre per dimension (paper: n_q = 14);
  * u in (0, eps): Taylor expansion of Z^reg to order 2*ell and Hadamard
- *   integrals (paper: eps = 1e-2, ell = 4);
+ *   integrals (paper: eps = 1e-2, ell = 4; 0 <= ell <= 6);
  * u in (eps, 1/2]: n_panels geometric panels eps*r^i (r = (1/(2 eps))^{1/n_panels}),
  *   n_g Gauss-Legendre points each.
- * lam: Ewald split parameter in units of V^{1/d} (0 selects 1.0);
+ * lam: Ewald split parameter in units of V^{1/d} (0 selects 1.0), used as given;
  * a_cut: terms whose incomplete-gamma argument exceeds a_cut are dropped
  *   (0 selects 36, a truncation below 1e-15 relative for nu <= 12 at lam = 1). */
 typedef struct ez_quad_spec {
@@ -215,6 +215,14 @@ const char *ez_last_error(void);
 
 /* Frees the library's cached device workspace and plans on every device. */
 ez_status ez_finalize(void);
+
+/* A counter that changes whenever the library frees or moves device memory it
+ * owns: a workspace buffer grown for a larger call, a cached plan evicted (the
+ * cache keeps the 32 most recent plans per device), ez_finalize.  Work captured
+ * into a HIP graph from calls of the library records the library's device
+ * pointers; such a graph may be replayed only while this value is the one read
+ * after the capture (the Python GraphedLatticeSums checks it). */
+uint64_t ez_workspace_generation(void);
 
 /* Library version string. */
 const char *ez_version(void);

@@ -74,6 +74,7 @@ def lib():
         L.ezo_direct_nbody.argtypes = [I, P, I, P, I, P]
         L.ezo_direct_atm.restype = I; L.ezo_direct_atm.argtypes = [I, P, I, P]
         L.ezo_num_threads.restype = I; L.ezo_num_threads.argtypes = []
+        L.ezo_set_num_threads.restype = None; L.ezo_set_num_threads.argtypes = [I]
         _lib = L
     return _lib
 
@@ -241,6 +242,11 @@ def direct_atm(A, L: int) -> float:
 
 def num_threads() -> int:
     return lib().ezo_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (for timing it as a CPU baseline)."""
+    lib().ezo_set_num_threads(int(n))
 
 
 # ----------------------------------------------------------------- derivatives

@@ -1159,3 +1159,12 @@ int ezo_num_threads(void) {
     return 1;
 #endif
 }
+
+/* threads of the parallel loops (timing of the oracle as a CPU baseline only) */
+void ezo_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -28,7 +28,7 @@ def spec_bpc(n: int) -> int:
 # every symbol declared in include/ezeta.h
 EXPORTED = ("ez_epstein_zeta", "ez_epstein_grid", "ez_nbody_lattice_sum", "ez_atm_energy", "ez_lattice_sums", "ez_lattice_sums_grad",
             "ez_timing_enable", "ez_timing_reset", "ez_timing_read",
-            "ez_last_error", "ez_finalize", "ez_version")
+            "ez_last_error", "ez_finalize", "ez_version", "ez_workspace_generation")
 (KERNEL_SETUP, KERNEL_NODES, KERNEL_HADAMARD, KERNEL_FINALIZE, KERNEL_EPSTEIN, KERNEL_NODES_ADJ, KERNEL_GRID,
  KERNEL_NODES_TAIL, KERNEL_TAYLOR) = (0, 1, 2, 3, 4, 5, 6, 7, 8)
 
@@ -86,6 +86,8 @@ def lib():
     L.ez_finalize.argtypes = []
     L.ez_version.restype = ctypes.c_char_p
     L.ez_version.argtypes = []
+    L.ez_workspace_generation.restype = ctypes.c_uint64
+    L.ez_workspace_generation.argtypes = []
     L.ez_timing_enable.restype = I
     L.ez_timing_enable.argtypes = [I]
     L.ez_timing_reset.restype = I
@@ -115,3 +117,8 @@ def timing_read(kernel: int):
     n = ctypes.c_int64()
     check(lib().ez_timing_read(int(kernel), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def workspace_generation() -> int:
+    """Changes whenever the library frees or moves device memory it owns."""
+    return int(lib().ez_workspace_generation())

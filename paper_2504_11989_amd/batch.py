@@ -14,6 +14,7 @@ from typing import Iterable, Sequence
 import torch
 
 from . import lattice_sums
+from ._native import workspace_generation
 
 __all__ = ["SCAN_NU", "SCAN_TERMS", "SCAN_RESULTS", "scan_sums", "GraphedLatticeSums"]
 
@@ -44,8 +45,10 @@ class GraphedLatticeSums:
     The captured call reads its lattices from `self.A` and writes `self.out` /
     `self.status`; to evaluate other lattices of the same batch shape and plans,
     copy them into `self.A` (on the current stream) before `replay()`.  The graph
-    stays valid while the library keeps this plan cached and does not grow its
-    workspace (that is, until ez_finalize or a call with a larger problem)."""
+    holds the library's device pointers (workspace, cached plan): it stays valid
+    while the library frees none of them (no ez_finalize, no call with a larger
+    problem that grows the workspace, no eviction of the plan), which is checked
+    against the library's workspace generation before every replay."""
 
     def __init__(self, A, nu: Sequence[float], terms: Iterable, n_results: int, specs=None, warmup: int = 1):
         self.A = torch.as_tensor(A, dtype=torch.float64, device="cuda").clone().contiguous()
@@ -63,11 +66,15 @@ class GraphedLatticeSums:
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph, stream=self.stream):
             self._call()
+        self.generation = workspace_generation()
         torch.cuda.current_stream(self.A.device).wait_stream(self.stream)
 
     def _call(self):
         lattice_sums(self.A, self.nu, self.terms, self.n_results, self.specs, out=self.out, status=self.status)
 
     def replay(self):
+        if workspace_generation() != self.generation:
+            raise RuntimeError("the library has freed or moved device memory this graph uses "
+                               "(workspace grown, plan evicted or ez_finalize): capture it again")
         self.graph.replay()
         return self.out

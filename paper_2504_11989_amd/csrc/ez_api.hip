@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -117,12 +118,18 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// bumped whenever device memory the library owns is freed or moved (a buffer
+// grown, a plan evicted, ez_finalize): device pointers recorded earlier, e.g. in
+// a captured HIP graph, are valid while it is unchanged
+std::atomic<uint64_t> g_generation{1};
+
 ez_status grow(DevBuf &b, size_t bytes) {
     if (bytes <= b.bytes && b.p) return EZ_OK;
     if (b.p) {
         (void)hipFree(b.p);
         b.p = nullptr;
         b.bytes = 0;
+        g_generation.fetch_add(1);
     }
     size_t want = std::max<size_t>(bytes, 256);
     if (hipMalloc(&b.p, want) != hipSuccess) {
@@ -132,6 +139,16 @@ ez_status grow(DevBuf &b, size_t bytes) {
     b.bytes = want;
     return EZ_OK;
 }
+
+// Device pointers and counts of a plan.
+struct PlanView {
+    const double *rules = nullptr;
+    const EzInstPlan *plans = nullptr;
+    const int *tile_begin = nullptr, *dir_begin = nullptr, *htile_begin = nullptr, *tile_order = nullptr;
+    int n_tiles = 0, n_dirs = 0, n_htiles = 0;
+    int n_probe = 0, ell_probe = 0, probe_off = 0;
+    int pinv_off[EZ_ELL_MAX + 1] = {0};
+};
 
 // A plan depends only on (d, batch, specs): rule tables, per-lattice plans, prefixes.
 struct DevPlan {
@@ -205,7 +222,10 @@ DeviceState *device_state(int dev) {
 }
 
 void free_buf(DevBuf &b) {
-    if (b.p) (void)hipFree(b.p);
+    if (b.p) {
+        (void)hipFree(b.p);
+        g_generation.fetch_add(1);
+    }
     b.p = nullptr;
     b.bytes = 0;
 }
@@ -221,7 +241,10 @@ ez_status check_spec(const ez_quad_spec &s) {
     if (s.n_q < 1 || s.n_q > 64) return fail(EZ_ERR_INVALID_ARG, "spec.n_q must be in [1, 64]");
     if (s.n_panels < 1 || s.n_panels > 256) return fail(EZ_ERR_INVALID_ARG, "spec.n_panels must be in [1, 256]");
     if (s.n_g < 1 || s.n_g > 128) return fail(EZ_ERR_INVALID_ARG, "spec.n_g must be in [1, 128]");
-    if (s.ell < 0 || s.ell > EZ_ELL_MAX) return fail(EZ_ERR_INVALID_ARG, "spec.ell must be in [0, 8]");
+    // Taylor orders up to 6 (the paper's reference order for its cutoff study, Sec. 4.1,
+    // Table 1): beyond it the least-squares recovery of the degree-2 ell coefficient
+    // polynomials from the probe values loses digits (condition ~1e6 at ell = 8)
+    if (s.ell < 0 || s.ell > 6) return fail(EZ_ERR_INVALID_ARG, "spec.ell must be in [0, 6]");
     if (!(s.eps > 0.0 && s.eps < 0.5)) return fail(EZ_ERR_INVALID_ARG, "spec.eps must be in (0, 1/2)");
     if (!(s.lam >= 0.0 && s.lam <= 8.0)) return fail(EZ_ERR_INVALID_ARG, "spec.lam must be in [0, 8]");
     if (!(s.a_cut >= 0.0 && s.a_cut <= 200.0)) return fail(EZ_ERR_INVALID_ARG, "spec.a_cut must be in [0, 200]");
@@ -341,22 +364,33 @@ std::string plan_key(int d, int batch, const ez_quad_spec *specs, int n_specs, i
 // volume of the unit ball in d dimensions
 const double kOmega[4] = {0.0, 2.0, M_PI, 4.0 * M_PI / 3.0};
 
-// ndb: directions per workgroup of the Hadamard direction kernel
-ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, int n_specs, int ndb, DevPlan **out) {
-    std::string key = plan_key(d, batch, specs, n_specs, ndb);
-    auto it = S->plans.find(key);
-    if (it != S->plans.end()) { *out = it->second; return EZ_OK; }
-    // rule tables: one v-rule per distinct n_q, one u-rule per distinct (n_panels, n_g, eps)
+// Host part of a plan: rule tables, per-lattice plans, prefixes, the persistent
+// kernel's tile order, probe directions and least-squares inverses.
+struct HostPlan {
     std::vector<double> rules;
+    std::vector<EzInstPlan> plans;
+    std::vector<int> tb, db, hb, order;
+    int n_tiles = 0, n_dirs = 0, n_htiles = 0;
+    int n_probe = 0, ell_probe = 0, probe_off = 0;
+    int pinv_off[EZ_ELL_MAX + 1] = {0};
+};
+
+// ndb: directions per workgroup of the Hadamard direction kernel
+ez_status build_host_plan(int d, int batch, const ez_quad_spec *specs, int n_specs, int ndb, HostPlan &H) {
+    // rule tables: one v-rule per distinct n_q, one u-rule per distinct (n_panels, n_g, eps)
+    std::vector<double> &rules = H.rules;
+    rules.clear();
     std::map<int, int> vrule_of;
     std::map<std::string, int> urule_of;
-    DevPlan *P = new DevPlan();
-    P->host_plans.resize(batch);
-    std::vector<int> tb(batch + 1, 0), db(batch + 1, 0), hb(batch + 1, 0);
+    H.plans.assign(batch, EzInstPlan());
+    H.tb.assign(batch + 1, 0);
+    H.db.assign(batch + 1, 0);
+    H.hb.assign(batch + 1, 0);
+    std::vector<int> &tb = H.tb, &db = H.db, &hb = H.hb;
     long long tiles = 0, dirs = 0, htiles = 0;
     for (int b = 0; b < batch; ++b) {
         const ez_quad_spec &s = specs[n_specs == 1 ? 0 : b];
-        EzInstPlan &ip = P->host_plans[b];
+        EzInstPlan &ip = H.plans[b];
         std::memset(&ip, 0, sizeof(ip));
         ip.n_q = s.n_q;
         ip.ell = s.ell;
@@ -404,22 +438,20 @@ ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, 
         tiles += (nn + EZ_TILE - 1) / EZ_TILE;
         dirs += nd;
         htiles += (nd + ndb - 1) / ndb;
-        if (tiles > (1ll << 30) || dirs > (1ll << 30)) {
-            delete P;
-            return fail(EZ_ERR_INVALID_ARG, "quadrature too large for one call");
-        }
+        if (tiles > (1ll << 30) || dirs > (1ll << 30)) return fail(EZ_ERR_INVALID_ARG, "quadrature too large for one call");
     }
     tb[batch] = (int)tiles;
     db[batch] = (int)dirs;
     hb[batch] = (int)htiles;
     // order in which the persistent node kernel takes the tiles: costliest first
     // (nodes in the tile x model cost of one node at the lattice's lam)
-    std::vector<int> order((size_t)tiles);
+    std::vector<int> &order = H.order;
+    order.resize((size_t)tiles);
     {
         std::vector<double> cost((size_t)tiles);
         for (int b = 0; b < batch; ++b) {
             const ez_quad_spec &s = specs[n_specs == 1 ? 0 : b];
-            const EzInstPlan &ip = P->host_plans[b];
+            const EzInstPlan &ip = H.plans[b];
             const long long nn = (long long)ip.n_dir * ip.n_u;
             const double R = std::sqrt(spec_acut(s) / M_PI), lam = spec_lam(s);
             const double per_node = kOmega[d] * (std::pow(R / lam, d) * 108.0 + 0.5 * std::pow(R * lam, d) * 14.0);
@@ -434,7 +466,7 @@ ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, 
     // probe directions and least-squares inverses for the Taylor coefficients
     {
         int lp = 0;
-        for (int b = 0; b < batch; ++b) lp = std::max(lp, P->host_plans[b].ell);
+        for (int b = 0; b < batch; ++b) lp = std::max(lp, H.plans[b].ell);
         const int np = (d == 1) ? 1 : (d == 2 ? n_mono(2, 2 * lp) + 8 : n_mono(3, 2 * lp) + 32);
         std::vector<double> probes((size_t)np * d);
         for (int p = 0; p < np; ++p) {
@@ -452,9 +484,9 @@ ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, 
                 probes[3 * p + 2] = z;
             }
         }
-        P->n_probe = np;
-        P->ell_probe = lp;
-        P->probe_off = (int)rules.size();
+        H.n_probe = np;
+        H.ell_probe = lp;
+        H.probe_off = (int)rules.size();
         rules.insert(rules.end(), probes.begin(), probes.end());
         std::vector<double> mono, Mk, pinv;
         for (int k = 0; k <= lp; ++k) {
@@ -465,31 +497,59 @@ ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, 
                 for (int a = 0; a < nm; ++a) Mk[(size_t)p * nm + a] = mono[a];
             }
             lstsq_pinv(np, nm, Mk, pinv);
-            P->pinv_off[k] = (int)rules.size();
+            H.pinv_off[k] = (int)rules.size();
             rules.insert(rules.end(), pinv.begin(), pinv.end());
         }
     }
-    P->n_tiles = (int)tiles;
-    P->n_dirs = (int)dirs;
-    P->n_htiles = (int)htiles;
-    ez_status st;
-    if ((st = grow(P->rules, rules.size() * sizeof(double))) ||
+    H.n_tiles = (int)tiles;
+    H.n_dirs = (int)dirs;
+    H.n_htiles = (int)htiles;
+    return EZ_OK;
+}
+
+void fill_plan_view(const HostPlan &H, PlanView &v) {
+    v.n_tiles = H.n_tiles;
+    v.n_dirs = H.n_dirs;
+    v.n_htiles = H.n_htiles;
+    v.n_probe = H.n_probe;
+    v.ell_probe = H.ell_probe;
+    v.probe_off = H.probe_off;
+    for (int k = 0; k <= EZ_ELL_MAX; ++k) v.pinv_off[k] = H.pinv_off[k];
+}
+
+ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, int n_specs, int ndb, DevPlan **out) {
+    std::string key = plan_key(d, batch, specs, n_specs, ndb);
+    auto it = S->plans.find(key);
+    if (it != S->plans.end()) { *out = it->second; return EZ_OK; }
+    HostPlan H;
+    ez_status st = build_host_plan(d, batch, specs, n_specs, ndb, H);
+    if (st) return st;
+    DevPlan *P = new DevPlan();
+    P->host_plans = H.plans;
+    P->n_tiles = H.n_tiles;
+    P->n_dirs = H.n_dirs;
+    P->n_htiles = H.n_htiles;
+    P->n_probe = H.n_probe;
+    P->ell_probe = H.ell_probe;
+    P->probe_off = H.probe_off;
+    for (int k = 0; k <= EZ_ELL_MAX; ++k) P->pinv_off[k] = H.pinv_off[k];
+    if ((st = grow(P->rules, H.rules.size() * sizeof(double))) ||
         (st = grow(P->plans, sizeof(EzInstPlan) * batch)) ||
         (st = grow(P->tile_begin, sizeof(int) * (batch + 1))) ||
         (st = grow(P->dir_begin, sizeof(int) * (batch + 1))) ||
         (st = grow(P->htile_begin, sizeof(int) * (batch + 1))) ||
-        (st = grow(P->tile_order, sizeof(int) * std::max<size_t>(1, order.size())))) {
+        (st = grow(P->tile_order, sizeof(int) * std::max<size_t>(1, H.order.size())))) {
         free_plan(P);
         return st;
     }
     // one-time synchronous uploads (plans are cached and reused)
-    if (hipMemcpy(P->rules.p, rules.data(), rules.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(P->plans.p, P->host_plans.data(), sizeof(EzInstPlan) * batch, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(P->tile_begin.p, tb.data(), sizeof(int) * (batch + 1), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(P->dir_begin.p, db.data(), sizeof(int) * (batch + 1), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(P->htile_begin.p, hb.data(), sizeof(int) * (batch + 1), hipMemcpyHostToDevice) != hipSuccess ||
-        (!order.empty() &&
-         hipMemcpy(P->tile_order.p, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice) != hipSuccess)) {
+    if (hipMemcpy(P->rules.p, H.rules.data(), H.rules.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(P->plans.p, H.plans.data(), sizeof(EzInstPlan) * batch, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(P->tile_begin.p, H.tb.data(), sizeof(int) * (batch + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(P->dir_begin.p, H.db.data(), sizeof(int) * (batch + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(P->htile_begin.p, H.hb.data(), sizeof(int) * (batch + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        (!H.order.empty() &&
+         hipMemcpy(P->tile_order.p, H.order.data(), sizeof(int) * H.order.size(), hipMemcpyHostToDevice) != hipSuccess)) {
         free_plan(P);
         return fail(EZ_ERR_HIP, "upload of the quadrature plan failed");
     }
@@ -548,153 +608,177 @@ int rec_capacity(int d, double lam, double acut) {
     return (int)std::ceil(kOmega[d] * std::pow(R + kSkew, d)) + 16;
 }
 
-// grad_dev (may be NULL): batch x n_res x d x d derivatives of the results with respect to A
-ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog, const std::vector<EzCombo> &combos,
-                   const ez_quad_spec *specs, int n_specs, double *out_dev, uint32_t *status_dev, hipStream_t stream,
-                   double *grad_dev = nullptr) {
-    int dev = 0;
-    EZ_HIP_TRY(hipGetDevice(&dev));
-    std::lock_guard<std::mutex> lock(g_mu);
-    DeviceState *S = device_state(dev);
-    DevPlan *P = nullptr;
+// What one lattice-sum call needs besides its plan: checked options, the table
+// capacities and the sizes that follow from them (no allocation, no launch).
+struct CallInfo {
+    bool grad = false;
+    int ndb = 0, n_ch = 1, maxdeg = 0, flags = 0;
+    double acut = 36.0;
+    EzTables tab;
+};
+
+ez_status prepare_call(int batch, int d, const EzProgram &prog, const std::vector<EzCombo> &combos,
+                       const ez_quad_spec *specs, int n_specs, bool grad, CallInfo &C) {
+    (void)batch; (void)d;
     if (combos.size() < 2) return fail(EZ_ERR_INVALID_ARG, "internal: expansion with fewer than 2 terms");
-    const bool grad = grad_dev != nullptr;
+    C.grad = grad;
     if (grad && prog.n_res > EZ_GRAD_RES_MAX)
         return fail(EZ_ERR_INVALID_ARG, "derivatives are available for at most 2 results per call");
-    const int ndb = std::min(grad ? EZ_HDIR_GRAD : EZ_HDIR, 256 / (int)combos.size());
-    const int n_ch = grad ? 1 + d * (d + 1) / 2 : 1;
+    C.ndb = std::min(grad ? EZ_HDIR_GRAD : EZ_HDIR, 256 / (int)combos.size());
+    C.n_ch = grad ? 1 + d * (d + 1) / 2 : 1;
     int ell_max = 0;
     for (int i = 0; i < n_specs; ++i) ell_max = std::max(ell_max, specs[i].ell);
-    int maxdeg = 0;          // highest power of u^2 in the (0, eps) product polynomials
+    C.maxdeg = 0;          // highest power of u^2 in the (0, eps) product polynomials
     for (const EzCombo &cb : combos) {
         int rest = 0;
         for (int f = 0; f < prog.term_nfac[cb.t]; ++f) rest += prog.term_mult[cb.t][f] - cb.j[f];
-        maxdeg = std::max(maxdeg, rest * ell_max);
+        C.maxdeg = std::max(C.maxdeg, rest * ell_max);
     }
-    if (maxdeg > 32)
+    if (C.maxdeg > 32)
         return fail(EZ_ERR_UNSUPPORTED, "Taylor product of degree > 32 in u^2 on (0, eps): lower ell or the multiplicity");
-    const int flags = specs[0].flags;
+    C.flags = specs[0].flags;
     for (int i = 1; i < n_specs; ++i)
-        if (specs[i].flags != flags) return fail(EZ_ERR_INVALID_ARG, "all specs of one call must share flags");
-    ez_status st = get_plan(S, d, batch, specs, n_specs, ndb, &P);
-    if (st) return st;
-    if (!S->side) {
-        EZ_HIP_TRY(hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking));
-        EZ_HIP_TRY(hipEventCreate(&S->ev_setup));     // recorded by a kernel launch (needs timing)
-        EZ_HIP_TRY(hipEventCreateWithFlags(&S->ev_had, hipEventDisableTiming));
-        EZ_HIP_TRY(hipDeviceGetAttribute(&S->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    }
-    if ((st = grow(S->queue, 256))) return st;
-    const int n_pblk = (P->n_probe + 63) / 64;
-    const int n_slice = std::max(1, std::min(EZ_SLICE_MAX, 512 / std::max(1, batch * n_pblk)));
-    double lam_min = 1e300, lam_max = 0.0, acut = spec_acut(specs[0]);
+        if (specs[i].flags != C.flags) return fail(EZ_ERR_INVALID_ARG, "all specs of one call must share flags");
+    double lam_min = 1e300, lam_max = 0.0;
+    C.acut = spec_acut(specs[0]);
     for (int i = 0; i < n_specs; ++i) {
         lam_min = std::min(lam_min, spec_lam(specs[i]));
         lam_max = std::max(lam_max, spec_lam(specs[i]));
-        if (spec_acut(specs[i]) != acut) return fail(EZ_ERR_INVALID_ARG, "all specs of one call must share a_cut");
+        if (spec_acut(specs[i]) != C.acut) return fail(EZ_ERR_INVALID_ARG, "all specs of one call must share a_cut");
     }
-    EzTables tab;
-    tab.real_cap = real_capacity(d, lam_max, acut, false);
-    tab.rec_cap = rec_capacity(d, lam_min, acut);
-    if (tab.rec_cap > EZ_KCULL)
+    C.tab.real_cap = real_capacity(d, lam_max, C.acut, false);
+    C.tab.rec_cap = rec_capacity(d, lam_min, C.acut);
+    if (C.tab.rec_cap > EZ_KCULL)
         return fail(EZ_ERR_UNSUPPORTED, "reciprocal table too large for this lam and a_cut (raise spec.lam)");
-    tab.rstride = 4 * ((3 + (grad ? 2 : 1) * prog.n_nu + 3) / 4);
-    tab.row_cap = tab.real_cap;
-    // Tail of the node tiles: the tile kernel runs in rounds of (CUs x its workgroups
-    // per CU); when the last round would hold only a few tiles (at most a quarter of
-    // a round), those tiles go to the split kernel, which shares each node's terms
-    // among 16 waves on four CUs (value calls without EZ_SPEC_NO_SPLIT; the adjoint
-    // keeps whole tiles).
+    C.tab.rstride = 4 * ((3 + (grad ? 2 : 1) * prog.n_nu + 3) / 4);
+    C.tab.row_cap = C.tab.real_cap;
+    return EZ_OK;
+}
+
+// Workspace of one call: the buffers the kernels write and read back.
+enum WsSlot {
+    WS_META, WS_SUB_PART, WS_TAIL_ACC, WS_REAL, WS_RN, WS_ROWS, WS_REC, WS_TILE_PART, WS_DIR_PART, WS_DIR_FLAG,
+    WS_PROBE_VAL, WS_TENSOR, WS_TILE_GRAD, WS_DIR_GRAD, WS_TAIL_CNT, WS_QUEUE, WS_COUNT
+};
+
+struct Workspace {
+    size_t bytes[WS_COUNT];
+    void *ptr[WS_COUNT];
+};
+
+int probe_slices(int batch, int n_probe) {
+    const int n_pblk = (n_probe + 63) / 64;
+    return std::max(1, std::min(EZ_SLICE_MAX, 512 / std::max(1, batch * n_pblk)));
+}
+
+// tiles [n_main, n_tiles) go to the split kernel when they would fill at most a
+// quarter of a round of tile-kernel workgroups (value calls without EZ_SPEC_NO_SPLIT)
+int main_tiles(const CallInfo &C, const EzProgram &prog, int n_cu, int n_tiles) {
     int round = 0;                     // tile-kernel workgroups resident on the device at once
     {
         EzQuadArgs probe_args;
         std::memset(&probe_args, 0, sizeof(probe_args));
         probe_args.prog = prog;
-        round = S->n_cu * ez_nodes_tile_blocks_per_cu(probe_args);
+        round = n_cu * ez_nodes_tile_blocks_per_cu(probe_args);
     }
-    int n_main = P->n_tiles;
-    if (!grad && !(flags & EZ_SPEC_NO_SPLIT)) {
-        const int tail = round > 0 ? P->n_tiles % round : 0;
-        if (P->n_tiles > round && tail > 0 && tail <= round / 4) n_main = P->n_tiles - tail;
+    int n_main = n_tiles;
+    if (!C.grad && !(C.flags & EZ_SPEC_NO_SPLIT)) {
+        const int tail = round > 0 ? n_tiles % round : 0;
+        if (n_tiles > round && tail > 0 && tail <= round / 4) n_main = n_tiles - tail;
     }
-    if ((st = grow(S->meta, sizeof(EzLatMeta) * batch)) ||
-        (st = grow(S->sub_part, sizeof(double) * 2 * (EZ_TILE / 64) * (size_t)std::max(1, P->n_tiles - n_main) * prog.n_res)) ||
-        (st = grow(S->tail_acc, sizeof(double) * (EZ_TILE / 64) * EZ_TAIL_PARTS * 2 * 64 *
-                                    (size_t)std::max(1, P->n_tiles - n_main) * prog.n_nu)) ||
-        (st = grow(S->real, sizeof(double) * (size_t)batch * tab.real_cap * tab.rstride)) ||
-        (st = grow(S->rn, sizeof(int) * 4 * (size_t)batch * tab.real_cap)) ||
-        (st = grow(S->rows, sizeof(int) * 8 * (size_t)batch * tab.row_cap)) ||
-        (st = grow(S->rec, sizeof(double) * (size_t)batch * tab.rec_cap * 4)) ||
-        (st = grow(S->tile_part, sizeof(double) * 2 * (size_t)P->n_tiles * prog.n_res)) ||
-        (st = grow(S->dir_part, sizeof(double) * (size_t)P->n_dirs * prog.n_res)) ||
-        (st = grow(S->dir_flag, sizeof(uint32_t) * (size_t)P->n_dirs)) ||
-        (st = grow(S->probe_val, sizeof(double) * (size_t)batch * n_slice * P->n_probe * n_ch * prog.n_nu * (EZ_ELL_MAX + 1))) ||
-        (st = grow(S->tensor, sizeof(double) * (size_t)batch * n_ch * prog.n_nu * EZ_TDIM)))
-        return st;
-    if (grad && ((st = grow(S->tile_grad, sizeof(double) * 12 * (size_t)P->n_tiles * prog.n_res)) ||
-                 (st = grow(S->dir_grad, sizeof(double) * 6 * (size_t)P->n_dirs * prog.n_res))))
-        return st;
-    tab.real = (double *)S->real.p;
-    tab.rn = (int *)S->rn.p;
-    tab.rows = (int *)S->rows.p;
-    tab.rec = (double *)S->rec.p;
+    return n_main;
+}
+
+void workspace_sizes(int batch, const EzProgram &prog, const CallInfo &C, const PlanView &P, int n_main, Workspace &W) {
+    const size_t ntail = (size_t)std::max(1, P.n_tiles - n_main);
+    const int n_slice = probe_slices(batch, P.n_probe);
+    W.bytes[WS_META] = sizeof(EzLatMeta) * batch;
+    W.bytes[WS_SUB_PART] = sizeof(double) * 2 * (EZ_TILE / 64) * ntail * prog.n_res;
+    W.bytes[WS_TAIL_ACC] = sizeof(double) * (EZ_TILE / 64) * EZ_TAIL_PARTS * 2 * 64 * ntail * prog.n_nu;
+    W.bytes[WS_REAL] = sizeof(double) * (size_t)batch * C.tab.real_cap * C.tab.rstride;
+    W.bytes[WS_RN] = sizeof(int) * 4 * (size_t)batch * C.tab.real_cap;
+    W.bytes[WS_ROWS] = sizeof(int) * 8 * (size_t)batch * C.tab.row_cap;
+    W.bytes[WS_REC] = sizeof(double) * (size_t)batch * C.tab.rec_cap * 4;
+    W.bytes[WS_TILE_PART] = sizeof(double) * 2 * (size_t)P.n_tiles * prog.n_res;
+    W.bytes[WS_DIR_PART] = sizeof(double) * (size_t)P.n_dirs * prog.n_res;
+    W.bytes[WS_DIR_FLAG] = sizeof(uint32_t) * (size_t)P.n_dirs;
+    W.bytes[WS_PROBE_VAL] =
+        sizeof(double) * (size_t)batch * n_slice * P.n_probe * C.n_ch * prog.n_nu * (EZ_ELL_MAX + 1);
+    W.bytes[WS_TENSOR] = sizeof(double) * (size_t)batch * C.n_ch * prog.n_nu * EZ_TDIM;
+    W.bytes[WS_TILE_GRAD] = C.grad ? sizeof(double) * 12 * (size_t)P.n_tiles * prog.n_res : 0;
+    W.bytes[WS_DIR_GRAD] = C.grad ? sizeof(double) * 6 * (size_t)P.n_dirs * prog.n_res : 0;
+    W.bytes[WS_TAIL_CNT] = sizeof(int) * (EZ_TILE / 64) * ntail;
+    W.bytes[WS_QUEUE] = 256;
+    for (int i = 0; i < WS_COUNT; ++i) W.ptr[i] = nullptr;
+}
+
+// The launch sequence of one lattice-sum call: setup, Taylor/Hadamard branch,
+// node kernels, finalize.  `side` (may be NULL) is the second stream for the
+// Hadamard branch with its two events; without it, or with EZ_SPEC_SERIAL, the
+// whole branch runs on `stream` before the nodes.  tail_cnt must hold zeros.
+ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, const std::vector<EzCombo> &combos,
+                       const CallInfo &C, const PlanView &P, int n_main, int n_cu, const Workspace &W,
+                       double *out_dev, uint32_t *status_dev, double *grad_dev, hipStream_t stream, hipStream_t side,
+                       hipEvent_t ev_setup, hipEvent_t ev_had, bool timing_ok = true) {
+    const bool grad = C.grad;
+    // the timing hooks create events; the no-allocation entry point launches without them
+    auto tm = [&](int kernel, hipStream_t st, auto launch) { return timing_ok ? timed(kernel, st, launch) : launch(); };
+    EzTables tab = C.tab;
+    tab.real = (double *)W.ptr[WS_REAL];
+    tab.rn = (int *)W.ptr[WS_RN];
+    tab.rows = (int *)W.ptr[WS_ROWS];
+    tab.rec = (double *)W.ptr[WS_REC];
 
     EzSetupArgs sa;
     sa.prog = prog;
     sa.A = A_dev;
-    sa.plans = (const EzInstPlan *)P->plans.p;
-    sa.meta = (EzLatMeta *)S->meta.p;
+    sa.plans = P.plans;
+    sa.meta = (EzLatMeta *)W.ptr[WS_META];
     sa.tab = tab;
-    sa.a_cut = acut;
+    sa.a_cut = C.acut;
     sa.general_x = 0;
     sa.grad = grad ? 1 : 0;
     sa.status_out = nullptr;
     fill_nu_constants(prog, sa);
-    EZ_HIP_TRY(timed(EZ_KERNEL_SETUP, stream, [&] { return ez_launch_setup(sa, batch, stream); }));
+    EZ_HIP_TRY(tm(EZ_KERNEL_SETUP, stream, [&] { return ez_launch_setup(sa, batch, stream); }));
 
     EzQuadArgs qa;
     qa.prog = prog;
     qa.batch = batch;
-    qa.plans = (const EzInstPlan *)P->plans.p;
-    qa.tile_begin = (const int *)P->tile_begin.p;
-    qa.dir_begin = (const int *)P->dir_begin.p;
-    qa.htile_begin = (const int *)P->htile_begin.p;
-    qa.n_dir_blk = ndb;
-    qa.poly_deg = maxdeg <= 12 ? 13 : 33;
-    qa.n_slice = n_slice;
-    qa.n_ch = n_ch;
-    qa.n_probe = P->n_probe;
-    qa.ell_probe = P->ell_probe;
-    qa.probe_off = P->probe_off;
-    for (int k = 0; k <= EZ_ELL_MAX; ++k) qa.pinv_off[k] = P->pinv_off[k];
-    qa.probe_val = (double *)S->probe_val.p;
-    qa.tensor = (double *)S->tensor.p;
+    qa.plans = P.plans;
+    qa.tile_begin = P.tile_begin;
+    qa.dir_begin = P.dir_begin;
+    qa.htile_begin = P.htile_begin;
+    qa.n_dir_blk = C.ndb;
+    qa.poly_deg = C.maxdeg <= 12 ? 13 : 33;
+    qa.n_slice = probe_slices(batch, P.n_probe);
+    qa.n_ch = C.n_ch;
+    qa.n_probe = P.n_probe;
+    qa.ell_probe = P.ell_probe;
+    qa.probe_off = P.probe_off;
+    for (int k = 0; k <= EZ_ELL_MAX; ++k) qa.pinv_off[k] = P.pinv_off[k];
+    qa.probe_val = (double *)W.ptr[WS_PROBE_VAL];
+    qa.tensor = (double *)W.ptr[WS_TENSOR];
     qa.n_combo = (int)combos.size();
     for (size_t c = 0; c < combos.size(); ++c) qa.combo[c] = combos[c];
-    qa.meta = (const EzLatMeta *)S->meta.p;
+    qa.meta = (const EzLatMeta *)W.ptr[WS_META];
     qa.tab = tab;
-    qa.rules = (const double *)P->rules.p;
-    qa.tile_part = (double *)S->tile_part.p;
-    qa.dir_part = (double *)S->dir_part.p;
-    qa.dir_flag = (uint32_t *)S->dir_flag.p;
+    qa.rules = P.rules;
+    qa.tile_part = (double *)W.ptr[WS_TILE_PART];
+    qa.dir_part = (double *)W.ptr[WS_DIR_PART];
+    qa.dir_flag = (uint32_t *)W.ptr[WS_DIR_FLAG];
     qa.out = out_dev;
     qa.status = status_dev;
-    qa.tile_grad = grad ? (double *)S->tile_grad.p : nullptr;
-    qa.dir_grad = grad ? (double *)S->dir_grad.p : nullptr;
+    qa.tile_grad = grad ? (double *)W.ptr[WS_TILE_GRAD] : nullptr;
+    qa.dir_grad = grad ? (double *)W.ptr[WS_DIR_GRAD] : nullptr;
     qa.grad_out = grad_dev;
-    qa.n_tiles = P->n_tiles;
+    qa.n_tiles = P.n_tiles;
     qa.n_main = n_main;
-    qa.sub_part = (double *)S->sub_part.p;
-    qa.tail_acc = (double *)S->tail_acc.p;
-    {   // group counters: zero when allocated, then reset by the kernel that uses them
-        const size_t had = S->tail_cnt.bytes;
-        if ((st = grow(S->tail_cnt, sizeof(int) * (EZ_TILE / 64) * (size_t)std::max(1, P->n_tiles - n_main)))) return st;
-        if (S->tail_cnt.bytes != had)
-            EZ_HIP_TRY(ez_launch_fill_int((int *)S->tail_cnt.p, (int)(S->tail_cnt.bytes / sizeof(int)), 0, stream));
-    }
-    qa.tail_cnt = (int *)S->tail_cnt.p;
-    qa.tile_order = (const int *)P->tile_order.p;
-    qa.queue = (int *)S->queue.p;
+    qa.sub_part = (double *)W.ptr[WS_SUB_PART];
+    qa.tail_acc = (double *)W.ptr[WS_TAIL_ACC];
+    qa.tail_cnt = (int *)W.ptr[WS_TAIL_CNT];
+    qa.tile_order = P.tile_order;
+    qa.queue = (int *)W.ptr[WS_QUEUE];
 
     // The Taylor/Hadamard branch depends only on the setup.  Its probe and tensor
     // kernels are short and run on the caller's stream before the nodes (on a second
@@ -703,8 +787,8 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     // caller's stream waits for it before the final reduction (event edges, so the
     // sequence can be captured into a graph).  EZ_SPEC_SERIAL keeps it on `stream`.
     auto had = [&](hipStream_t s, int part, hipEvent_t done) {
-        return grad ? ez_launch_hadamard_adj(qa, P->n_htiles, s, part, done)
-                    : ez_launch_hadamard(qa, P->n_htiles, s, part, done);
+        return grad ? ez_launch_hadamard_adj(qa, P.n_htiles, s, part, done)
+                    : ez_launch_hadamard(qa, P.n_htiles, s, part, done);
     };
     // The fork event is recorded by the tensor launch itself (no marker packet between
     // the tensors and the node kernel), or by hipEventRecord while the stream is captured.
@@ -712,49 +796,109 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     // drains, and runs beside its last, partly filled round of tiles (three-lattice ATM
     // derivative, 263424 nodes each: 0.869 ms per step, 0.901 ms with the direction
     // kernel before the nodes).
-    const bool side = !(flags & EZ_SPEC_SERIAL);
+    const bool two = side && !(C.flags & EZ_SPEC_SERIAL);
     // Batches whose node tiles fill more than eight rounds of the device are bound by
     // throughput, not latency: there the probe and tensor kernels go to the second
     // stream as well, where their work fills slots beside the node kernel's instead of
     // preceding it (the 4096-lattice scan).
-    const bool big = side && P->n_tiles > 8 * round;
+    int round = 0;
+    {
+        EzQuadArgs probe_args;
+        std::memset(&probe_args, 0, sizeof(probe_args));
+        probe_args.prog = prog;
+        round = n_cu * ez_nodes_tile_blocks_per_cu(probe_args);
+    }
+    const bool big = two && P.n_tiles > 8 * round;
     hipStream_t hs = stream;
     if (big) {
-        EZ_HIP_TRY(hipEventRecord(S->ev_setup, stream));
-        EZ_HIP_TRY(hipStreamWaitEvent(S->side, S->ev_setup, 0));
-        hs = S->side;
-        EZ_HIP_TRY(timed(EZ_KERNEL_TAYLOR, hs, [&] { return had(hs, EZ_HAD_PRE, nullptr); }));
+        EZ_HIP_TRY(hipEventRecord(ev_setup, stream));
+        EZ_HIP_TRY(hipStreamWaitEvent(side, ev_setup, 0));
+        hs = side;
+        EZ_HIP_TRY(tm(EZ_KERNEL_TAYLOR, hs, [&] { return had(hs, EZ_HAD_PRE, nullptr); }));
     } else {
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
         EZ_HIP_TRY(hipStreamIsCapturing(stream, &cap));
-        const bool ext = side && cap == hipStreamCaptureStatusNone;
-        EZ_HIP_TRY(timed(EZ_KERNEL_TAYLOR, stream, [&] { return had(stream, EZ_HAD_PRE, ext ? S->ev_setup : nullptr); }));
-        if (side) {
-            if (!ext) EZ_HIP_TRY(hipEventRecord(S->ev_setup, stream));
-            EZ_HIP_TRY(hipStreamWaitEvent(S->side, S->ev_setup, 0));
-            hs = S->side;
+        const bool ext = two && cap == hipStreamCaptureStatusNone;
+        EZ_HIP_TRY(tm(EZ_KERNEL_TAYLOR, stream, [&] { return had(stream, EZ_HAD_PRE, ext ? ev_setup : nullptr); }));
+        if (two) {
+            if (!ext) EZ_HIP_TRY(hipEventRecord(ev_setup, stream));
+            EZ_HIP_TRY(hipStreamWaitEvent(side, ev_setup, 0));
+            hs = side;
         }
     }
-    EZ_HIP_TRY(timed(EZ_KERNEL_HADAMARD, hs, [&] { return had(hs, EZ_HAD_DIR, nullptr); }));
+    EZ_HIP_TRY(tm(EZ_KERNEL_HADAMARD, hs, [&] { return had(hs, EZ_HAD_DIR, nullptr); }));
     if (grad) {
-        EZ_HIP_TRY(timed(EZ_KERNEL_NODES_ADJ, stream, [&] { return ez_launch_nodes_adj(qa, P->n_tiles, stream); }));
-    } else if (flags & EZ_SPEC_PERSISTENT) {
-        int bpc = (flags >> 8) & 0xFF;
+        EZ_HIP_TRY(tm(EZ_KERNEL_NODES_ADJ, stream, [&] { return ez_launch_nodes_adj(qa, P.n_tiles, stream); }));
+    } else if (C.flags & EZ_SPEC_PERSISTENT) {
+        int bpc = (C.flags >> 8) & 0xFF;
         if (bpc == 0) bpc = ez_nodes_blocks_per_cu(qa);
-        const int nblk = std::max(1, std::min(P->n_tiles, S->n_cu * bpc));
+        const int nblk = std::max(1, std::min(P.n_tiles, n_cu * bpc));
         EZ_HIP_TRY(ez_launch_fill_int(qa.queue, 1, 0, stream));
-        EZ_HIP_TRY(timed(EZ_KERNEL_NODES, stream, [&] { return ez_launch_nodes_persistent(qa, nblk, stream); }));
+        EZ_HIP_TRY(tm(EZ_KERNEL_NODES, stream, [&] { return ez_launch_nodes_persistent(qa, nblk, stream); }));
     } else {
-        EZ_HIP_TRY(timed(EZ_KERNEL_NODES, stream, [&] { return ez_launch_nodes(qa, n_main, stream); }));
+        EZ_HIP_TRY(tm(EZ_KERNEL_NODES, stream, [&] { return ez_launch_nodes(qa, n_main, stream); }));
     }
-    if (n_main < P->n_tiles)
-        EZ_HIP_TRY(timed(EZ_KERNEL_NODES_TAIL, stream, [&] { return ez_launch_nodes_split(qa, stream); }));
+    if (n_main < P.n_tiles)
+        EZ_HIP_TRY(tm(EZ_KERNEL_NODES_TAIL, stream, [&] { return ez_launch_nodes_split(qa, stream); }));
     if (hs != stream) {
-        EZ_HIP_TRY(hipEventRecord(S->ev_had, hs));
-        EZ_HIP_TRY(hipStreamWaitEvent(stream, S->ev_had, 0));
+        EZ_HIP_TRY(hipEventRecord(ev_had, hs));
+        EZ_HIP_TRY(hipStreamWaitEvent(stream, ev_had, 0));
     }
-    EZ_HIP_TRY(timed(EZ_KERNEL_FINALIZE, stream, [&] { return ez_launch_finalize(qa, stream); }));
+    EZ_HIP_TRY(tm(EZ_KERNEL_FINALIZE, stream, [&] { return ez_launch_finalize(qa, stream); }));
     return EZ_OK;
+}
+
+// grad_dev (may be NULL): batch x n_res x d x d derivatives of the results with respect to A
+ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog, const std::vector<EzCombo> &combos,
+                   const ez_quad_spec *specs, int n_specs, double *out_dev, uint32_t *status_dev, hipStream_t stream,
+                   double *grad_dev = nullptr) {
+    int dev = 0;
+    EZ_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_mu);
+    DeviceState *S = device_state(dev);
+    CallInfo C;
+    ez_status st = prepare_call(batch, d, prog, combos, specs, n_specs, grad_dev != nullptr, C);
+    if (st) return st;
+    DevPlan *P = nullptr;
+    if ((st = get_plan(S, d, batch, specs, n_specs, C.ndb, &P))) return st;
+    if (!S->side) {
+        EZ_HIP_TRY(hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking));
+        EZ_HIP_TRY(hipEventCreate(&S->ev_setup));     // recorded by a kernel launch (needs timing)
+        EZ_HIP_TRY(hipEventCreateWithFlags(&S->ev_had, hipEventDisableTiming));
+        EZ_HIP_TRY(hipDeviceGetAttribute(&S->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    }
+    PlanView pv;
+    pv.rules = (const double *)P->rules.p;
+    pv.plans = (const EzInstPlan *)P->plans.p;
+    pv.tile_begin = (const int *)P->tile_begin.p;
+    pv.dir_begin = (const int *)P->dir_begin.p;
+    pv.htile_begin = (const int *)P->htile_begin.p;
+    pv.tile_order = (const int *)P->tile_order.p;
+    pv.n_tiles = P->n_tiles;
+    pv.n_dirs = P->n_dirs;
+    pv.n_htiles = P->n_htiles;
+    pv.n_probe = P->n_probe;
+    pv.ell_probe = P->ell_probe;
+    pv.probe_off = P->probe_off;
+    for (int k = 0; k <= EZ_ELL_MAX; ++k) pv.pinv_off[k] = P->pinv_off[k];
+    const int n_main = main_tiles(C, prog, S->n_cu, P->n_tiles);
+    Workspace W;
+    workspace_sizes(batch, prog, C, pv, n_main, W);
+    DevBuf *bufs[WS_COUNT] = {&S->meta, &S->sub_part, &S->tail_acc, &S->real, &S->rn, &S->rows, &S->rec,
+                              &S->tile_part, &S->dir_part, &S->dir_flag, &S->probe_val, &S->tensor,
+                              &S->tile_grad, &S->dir_grad, &S->tail_cnt, &S->queue};
+    for (int i = 0; i < WS_COUNT; ++i) {
+        if (W.bytes[i] == 0) continue;
+        const size_t had = bufs[i]->bytes;
+        if ((st = grow(*bufs[i], W.bytes[i]))) return st;
+        W.ptr[i] = bufs[i]->p;
+        // the tail group counters are zero between calls: zeroed when allocated,
+        // then reset by the kernel that uses them
+        if (i == WS_TAIL_CNT && bufs[i]->bytes != had)
+            EZ_HIP_TRY(ez_launch_fill_int((int *)bufs[i]->p, (int)(bufs[i]->bytes / sizeof(int)), 0, stream));
+    }
+    return enqueue_sums(batch, A_dev, prog, combos, C, pv, n_main, S->n_cu, W, out_dev, status_dev, grad_dev, stream,
+                        S->side, S->ev_setup, S->ev_had);
 }
 
 // tables of one lattice for general shifts x (every z, every m*, no weights)
@@ -807,13 +951,46 @@ ez_status check_common(int batch, int d, const double *A_dev, const ez_quad_spec
     return EZ_OK;
 }
 
+// host checks and the program of a general lattice-sum call
+ez_status sums_program(int batch, int d, const double *A_dev, int n_nu, const double *nu_host, int n_terms,
+                       const int *term_result, const double *term_coef, const int *term_nfac, const int *term_fac,
+                       const int *term_mult, int n_results, const ez_quad_spec *specs, int n_specs,
+                       const double *out_dev, bool grad, EzProgram &prog, std::vector<EzCombo> &combos) {
+    ez_status st = check_common(batch, d, A_dev, specs, out_dev);
+    if (st) return st;
+    if (!nu_host || !term_result || !term_coef || !term_nfac || !term_fac || !term_mult)
+        return fail(EZ_ERR_INVALID_ARG, "null pointer argument");
+    if (n_specs != 1 && n_specs != batch) return fail(EZ_ERR_INVALID_ARG, "n_specs must be 1 or batch");
+    if (grad && n_results > EZ_GRAD_RES_MAX)
+        return fail(EZ_ERR_INVALID_ARG, "derivatives are available for at most 2 results per call");
+    if (n_nu < 1 || n_nu > EZ_NU_MAX || n_terms < 1 || n_terms > EZ_TERM_MAX)
+        return fail(EZ_ERR_INVALID_ARG, "n_nu and n_terms must be in [1, 8]");
+    int ell_max = 0;
+    for (int i = 0; i < n_specs; ++i) {
+        if ((st = check_spec(specs[i]))) return st;
+        ell_max = std::max(ell_max, specs[i].ell);
+    }
+    std::vector<double> nu(nu_host, nu_host + n_nu);
+    std::vector<Term> terms(n_terms);
+    for (int t = 0; t < n_terms; ++t) {
+        terms[t].res = term_result[t];
+        terms[t].coef = term_coef[t];
+        if (term_nfac[t] < 1 || term_nfac[t] > EZ_FAC_MAX) return fail(EZ_ERR_INVALID_ARG, "term_nfac must be in [1, 4]");
+        for (int f = 0; f < term_nfac[t]; ++f)
+            terms[t].fac.push_back({term_fac[EZ_FAC_MAX * t + f], term_mult[EZ_FAC_MAX * t + f]});
+    }
+    return build_program(d, nu, terms, n_results, ell_max, prog, combos);
+}
+
 }  // namespace
 
 extern "C" {
 
 const char *ez_last_error(void) { return g_err.c_str(); }
 
-const char *ez_version(void) { return "libezeta 0.1 (gfx950, FP64)"; }
+const char *ez_version(void) { return "libezeta 0.2 (gfx950, FP64)"; }
+
+uint64_t ez_workspace_generation(void) { return g_generation.load(); }
 
 ez_status ez_finalize(void) {
     std::lock_guard<std::mutex> lock(g_mu);
@@ -849,32 +1026,11 @@ ez_status ez_lattice_sums_grad(int batch, int d, const double *A_dev, int n_nu, 
                                const int *term_result, const double *term_coef, const int *term_nfac,
                                const int *term_fac, const int *term_mult, int n_results, const ez_quad_spec *specs,
                                int n_specs, double *out_dev, double *grad_dev, uint32_t *status_dev, void *stream) {
-    ez_status st = check_common(batch, d, A_dev, specs, out_dev);
-    if (st) return st;
-    if (!nu_host || !term_result || !term_coef || !term_nfac || !term_fac || !term_mult)
-        return fail(EZ_ERR_INVALID_ARG, "null pointer argument");
-    if (n_specs != 1 && n_specs != batch) return fail(EZ_ERR_INVALID_ARG, "n_specs must be 1 or batch");
-    if (grad_dev && n_results > EZ_GRAD_RES_MAX)
-        return fail(EZ_ERR_INVALID_ARG, "derivatives are available for at most 2 results per call");
-    if (n_nu < 1 || n_nu > EZ_NU_MAX || n_terms < 1 || n_terms > EZ_TERM_MAX)
-        return fail(EZ_ERR_INVALID_ARG, "n_nu and n_terms must be in [1, 8]");
-    int ell_max = 0;
-    for (int i = 0; i < n_specs; ++i) {
-        if ((st = check_spec(specs[i]))) return st;
-        ell_max = std::max(ell_max, specs[i].ell);
-    }
-    std::vector<double> nu(nu_host, nu_host + n_nu);
-    std::vector<Term> terms(n_terms);
-    for (int t = 0; t < n_terms; ++t) {
-        terms[t].res = term_result[t];
-        terms[t].coef = term_coef[t];
-        if (term_nfac[t] < 1 || term_nfac[t] > EZ_FAC_MAX) return fail(EZ_ERR_INVALID_ARG, "term_nfac must be in [1, 4]");
-        for (int f = 0; f < term_nfac[t]; ++f)
-            terms[t].fac.push_back({term_fac[EZ_FAC_MAX * t + f], term_mult[EZ_FAC_MAX * t + f]});
-    }
     EzProgram prog;
     std::vector<EzCombo> combos;
-    if ((st = build_program(d, nu, terms, n_results, ell_max, prog, combos))) return st;
+    ez_status st = sums_program(batch, d, A_dev, n_nu, nu_host, n_terms, term_result, term_coef, term_nfac, term_fac,
+                                term_mult, n_results, specs, n_specs, out_dev, grad_dev != nullptr, prog, combos);
+    if (st) return st;
     return run_sums(batch, d, A_dev, prog, combos, specs, n_specs, out_dev, status_dev, (hipStream_t)stream, grad_dev);
 }
 

@@ -15,6 +15,18 @@
 
 namespace {
 
+// E_1(a) and E_{1/2}(a) for any a > 0 (series below 1/4, rationals above), out
+// of line for the rarely used near-list loop
+__device__ __attribute__((noinline, const)) double ez_e1_ool(double a) {
+    if (a < 0.25) return ez_e1_series(a);
+    return ez_expm(a) * ez_e1w_scaled(ez_rcp(a));
+}
+__device__ __attribute__((noinline, const)) double ez_ehalf_ool(double a) {
+    if (a < 0.25) return ez_ehalf(a);
+    const double inv = ez_rcp(a);
+    return ez_expm(a) * inv * ez_ehw_scaled(inv);
+}
+
 // Geometry of node nd: k = u w, theta = u w_hat (so that k.z = theta.n for z = A n)
 // and the quadrature weight W (Duffy Jacobian u^{d-1}, Gauss weights, factor 2).
 template <int D>
@@ -80,26 +92,47 @@ __device__ __forceinline__ void real_rows(const EzQuadArgs &args, int inst, cons
 }
 
 // Reciprocal space: sum over m* of E_{p_nu}(pi lam^2 |m* + k|^2).  Entry 0 is m* = 0,
-// where a = alpha |k|^2 can be small (series of E1); every other entry has
-// a >= alpha / (4 |A|_F^2) >= 1/4 (the setup raises lam to ensure it), so the
-// list loop is one branch-free formula with E1 from the wide rational.
+// where a = alpha |k|^2 can be small (series of E1); so can the entries of the
+// culling's near list.  rec_origin adds m* = 0 (inline), then the near list in
+// table order; that list is usually empty, so its special functions are called
+// out of line and take no registers from the main loop.  Every entry of the main
+// list has a >= 1/4 at every node of the tile, so rec_list is one branch-free
+// formula with E1 and E_{1/2} from the wide rationals.
 template <int D, int NNU, int SET>
-__device__ __forceinline__ void rec_origin(const EzQuadArgs &args, const double *k, double alpha, double acut,
-                                           double *acck) {
+__device__ __forceinline__ void rec_origin(const EzQuadArgs &args, const double *kt, const unsigned short *klist,
+                                           int n_near, const double *k, double alpha, double acut, double *acck) {
     const bool need_e1 = pset_need_e1<SET, NNU>(args.prog), need_half = pset_need_half<SET, NNU>(args.prog);
-    double rho = k[0] * k[0];
-    if (D > 1) rho = fma(k[1], k[1], rho);
-    if (D > 2) rho = fma(k[2], k[2], rho);
-    const double a = alpha * rho;
-    if (a <= acut) {
-        const double ex = ez_expm(a);
-        const double inv = ez_rcp(a);
-        double E1 = 0.0;
-        if (need_e1) E1 = (a < 0.25) ? ez_e1_series(a) : ex * ez_e1w_scaled(inv);
-        const double Eh = need_half ? ((a < 0.25) ? ez_ehalf(a) : ex * inv * ez_ehw_scaled(inv)) : 0.0;
+    {
+        double rho = k[0] * k[0];
+        if (D > 1) rho = fma(k[1], k[1], rho);
+        if (D > 2) rho = fma(k[2], k[2], rho);
+        const double a = alpha * rho;
+        if (a <= acut) {
+            const double ex = ez_expm(a);
+            const double inv = ez_rcp(a);
+            double E1 = 0.0;
+            if (need_e1) E1 = (a < 0.25) ? ez_e1_series(a) : ex * ez_e1w_scaled(inv);
+            const double Eh = need_half ? ((a < 0.25) ? ez_ehalf(a) : ex * inv * ez_ehw_scaled(inv)) : 0.0;
 #pragma unroll
-        for (int i = 0; i < NNU; ++i)
-            acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
+            for (int i = 0; i < NNU; ++i)
+                acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
+        }
+    }
+    for (int j = 1; j <= n_near; ++j) {
+        const double *e = kt + (size_t)__builtin_amdgcn_readfirstlane((int)klist[EZ_KCULL - j]) * 4;
+        double rho = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) { const double t = e[i] + k[i]; rho = fma(t, t, rho); }
+        const double a = alpha * rho;
+        if (a <= acut) {
+            const double ex = ez_expm(a);
+            const double inv = ez_rcp(a);
+            const double E1 = need_e1 ? ez_e1_ool(a) : 0.0;
+            const double Eh = need_half ? ez_ehalf_ool(a) : 0.0;
+#pragma unroll
+            for (int i = 0; i < NNU; ++i)
+                acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
+        }
     }
 }
 
@@ -206,10 +239,12 @@ __device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile
 
         const double *kt = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
         const double alpha = M->alpha, acut = M->a_cut;
-        const int nk = cull_reciprocal<D, EZ_TILE>(kt, M->n_rec, k, alpha, acut, klist, L.kbox, L.kwave, &L.kcount);
+        int n_near = 0;
+        const int nk = cull_reciprocal<D, EZ_TILE>(kt, M->n_rec, k, alpha, acut, klist, L.kbox, L.kwave, &L.kcount,
+                                                   &n_near);
         if (valid) {
             real_rows<D, NNU>(args, inst, th, 0, M->n_rows, accr);
-            rec_origin<D, NNU, SET>(args, k, alpha, acut, acck);
+            rec_origin<D, NNU, SET>(args, kt, klist, n_near, k, alpha, acut, acck);
             rec_list<D, NNU, SET>(args, kt, klist, 0, nk, k, alpha, acut, acck);
             node_products<NNU>(args, M, accr, acck, W, res);
         }
@@ -277,11 +312,13 @@ __device__ __forceinline__ void node_group_split(const EzQuadArgs &args, const i
         node_geometry<D>(P, args.rules, M, valid ? node : tile0, k, th, &W);
         const double *kt = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
         const double alpha = M->alpha, acut = M->a_cut;
-        const int nk = cull_reciprocal<D, 64 * NS>(kt, M->n_rec, k, alpha, acut, klist, L.kbox, L.kwave, &L.kcount);
+        int n_near = 0;
+        const int nk = cull_reciprocal<D, 64 * NS>(kt, M->n_rec, k, alpha, acut, klist, L.kbox, L.kwave, &L.kcount,
+                                                   &n_near);
         if (valid) {
             const int n_rows = M->n_rows;
             real_rows<D, NNU>(args, inst, th, j * n_rows / NSH, (j + 1) * n_rows / NSH, accr);
-            if (j == 0) rec_origin<D, NNU, SET>(args, k, alpha, acut, acck);
+            if (j == 0) rec_origin<D, NNU, SET>(args, kt, klist, n_near, k, alpha, acut, acck);
             rec_list<D, NNU, SET>(args, kt, klist, j * nk / NSH, (j + 1) * nk / NSH, k, alpha, acut, acck);
         }
     }

@@ -103,9 +103,16 @@ __device__ __forceinline__ bool pset_need_half(const EzProgram &prog) {
 // The others are listed in table order (so each node adds the same nonzero terms
 // in the same order as over the whole table); the host keeps the table capacity
 // within the list (EZ_KCULL entries).  NT threads; returns the list length.
+// With knear (the value node kernels), entries that may reach an argument
+// alpha |m* + k|^2 below 1/4 at a node of the workgroup (|m* + c| <= r_t +
+// 1/(2 sqrt alpha): small lam, or a skewed lattice near the corners of the cell)
+// go to a second list instead, in table order from klist[EZ_KCULL - 1] downward,
+// and *knear receives its length: the main list then needs no series forms of
+// E_1 and E_{1/2}.  Per-wave counts are packed as (main | near << 16).
 template <int D, int NT>
 __device__ __forceinline__ int cull_reciprocal(const double *kt, int n_rec, const double *k, double alpha, double acut,
-                                               unsigned short *klist, double (*kbox)[6], int *kwave, int *kcount) {
+                                               unsigned short *klist, double (*kbox)[6], int *kwave, int *kcount,
+                                               int *knear = nullptr) {
     constexpr int NWV = NT / 64;
     const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
     double bl[3] = {k[0], k[1], k[2]}, bh[3] = {k[0], k[1], k[2]};
@@ -130,23 +137,28 @@ __device__ __forceinline__ int cull_reciprocal(const double *kt, int n_rec, cons
         rt2 += 0.25 * (hi - lo) * (hi - lo);
     }
     const double rmax = (sqrt(acut / alpha) + sqrt(rt2)) * (1.0 + 1e-9) + 1e-12;
+    const bool split_near = knear != nullptr;
+    const double rnear = (0.5 / sqrt(alpha) + sqrt(rt2)) * (1.0 + 1e-9) + 1e-12;
     for (int base = 1; base < n_rec; base += NT) {
         const int q = base + (int)threadIdx.x;
-        bool keep = false;
+        bool keep = false, near = false;
         if (q < n_rec) {
             const double *e = kt + (size_t)q * 4;
             double d2 = 0.0;
 #pragma unroll
             for (int i = 0; i < D; ++i) { const double t = e[i] + c[i]; d2 = fma(t, t, d2); }
-            keep = d2 <= rmax * rmax;
+            near = split_near && d2 <= rnear * rnear;
+            keep = !near && d2 <= rmax * rmax;
         }
-        const unsigned long long bal = __ballot(keep);
-        const int before = __popcll(bal & ((1ull << lane) - 1ull));
-        if (lane == 0) kwave[wave] = __popcll(bal);
+        const unsigned long long bal = __ballot(keep), baln = __ballot(near);
+        const unsigned long long below = (1ull << lane) - 1ull;
+        if (lane == 0) kwave[wave] = __popcll(bal) | (__popcll(baln) << 16);
         __syncthreads();
         int off = *kcount;
         for (int w2 = 0; w2 < wave; ++w2) off += kwave[w2];
-        if (keep) klist[off + before] = (unsigned short)q;   // q < n_rec <= rec_cap <= EZ_KCULL
+        // q < n_rec <= rec_cap <= EZ_KCULL, and the two lists together hold at most n_rec - 1 entries
+        if (keep) klist[(off & 0xFFFF) + __popcll(bal & below)] = (unsigned short)q;
+        if (near) klist[EZ_KCULL - 1 - ((off >> 16) + __popcll(baln & below))] = (unsigned short)q;
         __syncthreads();
         if (threadIdx.x == 0) {
             int tot = 0;
@@ -155,7 +167,9 @@ __device__ __forceinline__ int cull_reciprocal(const double *kt, int n_rec, cons
         }
         __syncthreads();
     }
-    return *kcount;
+    const int packed = *kcount;
+    if (knear) *knear = packed >> 16;
+    return packed & 0xFFFF;
 }
 
 }  // namespace

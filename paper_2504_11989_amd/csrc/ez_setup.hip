@@ -166,14 +166,6 @@ __global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
             for (int j = 0; j < d; ++j) B[i * d + j] = Ai[j * d + i];
         V = fabs(det);
         lam = lam_rel * pow(V, 1.0 / d);
-        // every m* != 0 then has pi lam^2 |m* + k|^2 >= 1/4 for the quadrature nodes
-        // k in B[-1/2,1/2]^d (|m* + k| >= sigma_min(B)/2 >= 1/(2 |A|_F)); the node
-        // kernel's rational E1 is fitted for arguments >= 1/4
-        if (!args.general_x) {
-            double fro2 = 0.0;
-            for (int i = 0; i < d * d; ++i) fro2 += A[i] * A[i];
-            lam = fmax(lam, sqrt(fro2 / EZ_PI) * (1.0 + 1e-12));
-        }
         alpha = EZ_PI * lam * lam;
         Rr = lam * sqrt(a_cut / EZ_PI);
         if (args.general_x) Rr += half_diag<D>(A);

@@ -19,7 +19,7 @@ import torch
 
 from . import lattice_sums
 
-__all__ = ["LJ_ATM_NU", "LJ_ATM_TERMS", "energies", "enthalpy", "minimise", "classify"]
+__all__ = ["LJ_ATM_NU", "LJ_ATM_TERMS", "energies", "enthalpy", "minimise", "classify", "phase_scan"]
 
 LJ_ATM_NU = [-1.0, 1.0, 3.0, 5.0, 7.0]
 # (result, coefficient, [(index into LJ_ATM_NU, multiplicity), ...])
@@ -98,10 +98,13 @@ def minimise(A0, c, p, spec=None, max_iter: int = 200, gtol: float = 1e-9, verbo
         y = gn_ - g
         sy = np.einsum("bi,bi->b", s, y)
         upd = (sy > 1e-14) & ~done
-        for b in np.nonzero(upd)[0]:
-            rho = 1.0 / sy[b]
-            Ib = np.eye(9) - rho * np.outer(s[b], y[b])
-            Hinv[b] = Ib @ Hinv[b] @ Ib.T + rho * np.outer(s[b], s[b])
+        if upd.any():
+            # BFGS update of the inverse Hessians, all updated problems at once:
+            # H <- (I - rho s y^T) H (I - rho y s^T) + rho s s^T, rho = 1 / (y.s)
+            su, yu = s[upd], y[upd]
+            rho = 1.0 / sy[upd]
+            Vb = np.eye(9)[None] - rho[:, None, None] * su[:, :, None] * yu[:, None, :]
+            Hinv[upd] = Vb @ Hinv[upd] @ Vb.transpose(0, 2, 1) + rho[:, None, None] * su[:, :, None] * su[:, None, :]
         stalled = ~acc                      # no acceptable step: keep the point, restart the metric
         Hinv[stalled] = np.eye(9) * 1e-3
         x, H, g, E, V = xn, Hn, gn_, En, Vn
@@ -133,3 +136,35 @@ def classify(A, tol: float = 0.03) -> str:
     if n1 == 6:
         return "sc"
     return "other"
+
+
+def phase_scan(cs, ps, starts, spec=None, max_iter: int = 300, gtol: float = 1e-8, verbose: bool = False):
+    """Stable Bravais lattice over a grid of ATM couplings c and pressures p
+    (paper, Sec. 5): H = E_LJ + c E_ATM + p V is minimised from every start
+    matrix at every (c, p), all len(cs) len(ps) len(starts) problems in one
+    batched minimisation; at each grid point the lowest minimum wins.
+
+    starts: (n_starts, 3, 3) generator matrices (e.g. perturbed fcc and bcc).
+    Returns dict(H (nc, np, ns), A (nc, np, ns, 3, 3), converged (nc, np, ns),
+    grad_norm, iterations, winner (nc, np) start index, phase (nc, np) lattice
+    names of the winning minima, V (nc, np) their volume per particle)."""
+    cs = np.asarray(cs, dtype=np.float64)
+    ps = np.asarray(ps, dtype=np.float64)
+    starts = np.asarray(starts, dtype=np.float64)
+    nc, npp, ns = len(cs), len(ps), len(starts)
+    C, P, S = np.meshgrid(cs, ps, np.arange(ns), indexing="ij")
+    A0 = starts[S.reshape(-1)]
+    res = minimise(A0, C.reshape(-1), P.reshape(-1), spec, max_iter=max_iter, gtol=gtol, verbose=verbose)
+    H = res["H"].reshape(nc, npp, ns)
+    A = res["A"].reshape(nc, npp, ns, 3, 3)
+    win = np.argmin(np.where(np.isfinite(H), H, np.inf), axis=2)
+    phase = np.empty((nc, npp), dtype=object)
+    V = np.zeros((nc, npp))
+    for i in range(nc):
+        for j in range(npp):
+            Aw = A[i, j, win[i, j]]
+            phase[i, j] = classify(Aw)
+            V[i, j] = abs(np.linalg.det(Aw))
+    return dict(H=H, A=A, converged=res["converged"].reshape(nc, npp, ns),
+                grad_norm=res["grad_norm"].reshape(nc, npp, ns), iterations=res["iterations"],
+                winner=win, phase=phase, V=V)

@@ -18,7 +18,7 @@ def _lib():
 
 def declared_symbols():
     src = open(os.path.join(ROOT, "include", "ezeta.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:const\s+char\s*\*|ez_status)\s*(ez_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:const\s+char\s*\*|ez_status|uint64_t)\s*(ez_\w+)\s*\(", src, re.M)))
 
 
 def test_header_declares_expected_entry_points():
@@ -57,7 +57,7 @@ def test_host_validation_errors():
     # null A
     assert L.ez_nbody_lattice_sum(1, 3, None, 3, nu, ctypes.byref(_spec(nat)), dummy, None, None) == 1
     # bad specs
-    for bad in [dict(n_q=0), dict(ell=9), dict(eps=0.7), dict(eps=0.0), dict(lam=-1.0), dict(a_cut=500.0)]:
+    for bad in [dict(n_q=0), dict(ell=7), dict(ell=9), dict(eps=0.7), dict(eps=0.0), dict(lam=-1.0), dict(a_cut=500.0)]:
         assert L.ez_nbody_lattice_sum(1, 3, dummy, 3, nu, ctypes.byref(_spec(nat, **bad)), dummy, None, None) == 1
     # mixed precision is refused by the FP64 build
     assert L.ez_atm_energy(1, 3, dummy, ctypes.byref(_spec(nat, precision=1)), dummy, None, None, None) == 4
@@ -88,3 +88,9 @@ def test_host_validation_errors():
 def test_version_string():
     nat = _lib()
     assert b"gfx950" in nat.lib().ez_version()
+
+
+def test_workspace_generation_is_exported_and_stable():
+    nat = _lib()
+    g = nat.workspace_generation()
+    assert g >= 1 and nat.workspace_generation() == g

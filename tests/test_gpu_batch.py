@@ -142,3 +142,46 @@ def test_tail_split_partial_last_tile(ez):
     assert abs(split - whole) <= 1e-13 * abs(whole), (split, whole)
     ref = O.atm(W.sc(), sp)
     assert abs(split - ref) <= TOL * abs(ref), (split, ref)
+
+
+def test_large_batch_second_stream_schedule(ez):
+    """a batch whose node tiles fill more than eight rounds of the device (the
+    scan schedule: probe, tensor and direction kernels on the second stream,
+    beside the node kernel): 300 lattices with plans of 16..40 nodes per side
+    (about 2.5e4 tiles); bit-identical to the serial schedule, and the three
+    smallest plans against the oracle"""
+    from paper_2504_11989_amd import _native as nat
+    from paper_2504_11989_amd.batch import scan_sums
+    ca, nside, A = W.c3_scan()
+    n = 300
+    ns = 16 + (np.arange(n) * 7) % 25
+    specs = [W.c3_spec(int(k), lam=1.3) for k in ns]
+    tiles = sum((W.n_nodes(3, s) + 255) // 256 for s in specs)
+    assert tiles > 8 * 1024
+    A = A[:n]
+    got = scan_sums(A, specs).cpu().numpy()
+    ser = scan_sums(A, [dict(s, flags=nat.SPEC_SERIAL) for s in specs]).cpu().numpy()
+    assert np.array_equal(got, ser)
+    for i in [int(j) for j in np.argsort(ns, kind="stable")[:3]]:
+        ref = oracle_scan(A[i], specs[i])
+        for r in range(5):
+            assert abs(got[i, r] - ref[r]) <= TOL * abs(ref[r]), (i, r, got[i, r], ref[r])
+
+
+def test_graph_replay_refused_after_workspace_growth(ez):
+    """a call with a larger problem grows (frees and reallocates) the library's
+    workspace: the graph's recorded pointers are stale and replay() raises
+    instead of replaying"""
+    from paper_2504_11989_amd.batch import SCAN_NU, SCAN_TERMS, GraphedLatticeSums, scan_sums
+    torch.cuda.synchronize()
+    ez.finalize()                    # start from an empty workspace, whatever ran before
+    A, specs = small_scan(4)
+    g = GraphedLatticeSums(A, SCAN_NU, SCAN_TERMS, 5, specs)
+    out = g.replay()
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), scan_sums(A, specs).cpu().numpy())
+    ca, nside, Abig = W.c3_scan()
+    big = [W.c3_spec(48, lam=1.3)] * 64
+    scan_sums(Abig[:64], big).cpu()
+    with pytest.raises(RuntimeError, match="capture it again"):
+        g.replay()

@@ -184,9 +184,48 @@ def test_eight_exponents_taylor_order_six(ez):
     R, g = ez.lattice_sums(A, nu, terms, 2, spec, grad=True)
     R, g = R[0].cpu().numpy(), g[0].cpu().numpy()
     for r, nus in enumerate([(-1, 1, 3, 5), (6, 7, 9, 12)]):
-        ref = O.nbody(A, nus, spec)
-        assert abs(R[r] - ref) <= 1e-10 * abs(ref), (r, R[r], ref)
+        # (-1, 1, 3, 5): the Hadamard and node parts (about 7.5e6 each) cancel to
+        # -556, a factor 2.7e4; the bar scales with the parts (see nbody_bar)
+        ref, parts = O.nbody(A, nus, spec, parts=True)
+        kappa = float(np.abs(parts).sum()) / abs(ref)
+        tol = max(1e-12, 4e-15 * kappa)
+        assert abs(R[r] - ref) <= tol * abs(ref), (r, R[r], ref, kappa)
         deg = -float(sum(nus))
-        assert abs(np.trace(A.T @ g[r]) - deg * R[r]) <= 1e-10 * abs(deg * R[r]), r
+        assert abs(np.trace(A.T @ g[r]) - deg * R[r]) <= 4 * tol * abs(deg * R[r]), r
         S = g[r] @ A.T
-        assert np.linalg.norm(S - S.T) <= 1e-10 * np.linalg.norm(S), r
+        assert np.linalg.norm(S - S.T) <= 4 * tol * np.linalg.norm(S), r
+
+
+def test_enthalpy_gradient_finite_coupling_and_pressure(ez):
+    """dH/dA of H = E_LJ + c E_ATM + p V at c, p > 0 (the p V term and its
+    derivative |det A| A^{-T} included): against central differences of the GPU
+    value with h = 1e-6 (rounding of the difference ~ 1e-16 |H| / h, truncation
+    ~ h^2), and against the oracle's fourth-order differences of its own H on the
+    same plan"""
+    from paper_2504_11989_amd import enthalpy as H
+    spec = W.SPEC_SMALL_3D
+    c, p = 1.3, 0.6
+    for seed, A0 in [(71, W.fcc()), (72, W.bcc())]:
+        A = perturbed(A0, seed)
+        Hv, g, E, V = H.enthalpy(torch.tensor(A[None], device="cuda"), c, p, spec)
+        Hv, g = Hv.item(), g[0].cpu().numpy()
+
+        def h_gpu(B):
+            return H.enthalpy(torch.tensor(B[None], device="cuda"), c, p, spec)[0].item()
+
+        def h_oracle(B):
+            elj = 0.5 * O.nbody(B, [5, 7], spec) - O.nbody(B, [3, 3], spec)
+            return elj + c * O.atm(B, spec) + p * abs(np.linalg.det(B))
+
+        assert abs(Hv - h_oracle(A)) <= 1e-12 * abs(Hv)
+        fd = np.zeros((3, 3))
+        hh = 1e-6
+        for i in range(3):
+            for j in range(3):
+                Bp, Bm = A.copy(), A.copy()
+                Bp[i, j] += hh
+                Bm[i, j] -= hh
+                fd[i, j] = (h_gpu(Bp) - h_gpu(Bm)) / (2 * hh)
+        assert relnorm(g, fd) <= 1e-7, (seed, relnorm(g, fd))
+        assert relnorm(g, O.grad_fd(h_oracle, A, h=5e-4)) <= 1e-8, seed
+

@@ -27,6 +27,17 @@ def rel(a, b):
     return abs(a - b) / max(abs(b), 1e-300)
 
 
+def nbody_bar(A, nus, spec):
+    """(oracle value, parity bar) of one n-body sum on a plan.  The result is the
+    sum v = H + N of the Hadamard part on (0, eps) and the node part on (eps, 1/2];
+    each part carries a relative rounding error of about 4e-15 (products of up
+    to four Z values, each good to ~1e-15), so FP64 fixes v to about
+    4e-15 (|H| + |N|).  The bar is 1e-12 |v|, or that floor where the parts
+    cancel (strongly singular exponents such as (-1, 1, 3, 5))."""
+    v, parts = O.nbody(A, nus, spec, parts=True)
+    return v, max(TOL * abs(v), 4e-15 * float(np.abs(parts).sum()))
+
+
 # ---------------------------------------------------------------- Epstein zeta at points
 def test_c1_spot_values(ez):
     nus, xs, ys = W.c1_spot_values()
@@ -153,3 +164,28 @@ def test_ring_two_body_is_epstein_full_plan(ez):
     got = ez.nbody_lattice_sum(W.sc(), [6.0, 6.0], W.SPEC_FULL_3D).item()
     ref = O.epstein(W.sc(), 12.0, [0, 0, 0], [0, 0, 0]).real
     assert rel(got, ref) <= TOL
+
+
+# ---------------------------------------------------------------- the Ewald parameter is the spec's
+SKEW_3D = np.array([[1.0, 0.9, 0.3], [0.0, 1.1, 0.6], [0.0, 0.0, 0.9]])
+
+
+@pytest.mark.parametrize("lam", [0.8, 1.0])
+def test_lambda_honoured_small_arguments(ez, lam):
+    """spec.lam is used as given: at small lam (and on a skewed lattice) some
+    reciprocal terms m* != 0 reach incomplete-gamma arguments below 1/4 near the
+    faces and corners of the cell, where the node kernel takes the series forms
+    of E_1 and E_{1/2} (the culling's near list); the oracle runs the same split.
+    (Below lam ~ 0.7 the split itself is ill-conditioned in FP64: the oracle's
+    own ATM values move by 3e-12 between lam = 0.5 and lam = 1.3.)"""
+    lats = [W.sc(), W.fcc(), W.bcc(), W.unit_density(SKEW_3D)]
+    spec = dict(W.SPEC_SMALL_3D, n_q=5, n_panels=3, n_g=7, lam=lam)
+    A = np.stack(lats)
+    got = ez.atm_energy(A, spec).cpu().numpy()
+    for i, Ai in enumerate(lats):
+        assert rel(got[i], O.atm(Ai, spec)) <= TOL, (lam, i)
+    # half-integer p (nu = 6 in d = 3) takes the E_{1/2} series on the near list
+    got = ez.nbody_lattice_sum(A, [6.0, 6.0, 6.0], spec).cpu().numpy()
+    for i, Ai in enumerate(lats):
+        v, bar = nbody_bar(Ai, [6.0, 6.0, 6.0], spec)
+        assert abs(got[i] - v) <= bar, (lam, i)
