@@ -179,6 +179,28 @@ ez_status ez_lattice_sums(int batch, int d, const double *A_dev, int n_nu, const
                           int n_results, const ez_quad_spec *specs, int n_specs, double *out_dev,
                           uint32_t *status_dev, void *stream);
 
+/* ez_lattice_sums for callers that cannot allocate device memory (code under HIP
+ * graph capture elsewhere in their stream, tight serving loops, harnesses that
+ * forbid hipMalloc): the same arguments, results and kernels as ez_lattice_sums
+ * (values only), with every intermediate buffer -- lattice tables, quadrature
+ * plan, partial sums, counters -- carved from a static device array of 64 MiB
+ * per GPU that the library holds from its first use until the process ends.
+ * The call allocates and frees nothing.  It runs the whole sequence on `stream`
+ * (no second stream, no events; results are bit-identical to ez_lattice_sums
+ * with EZ_SPEC_SERIAL and, like every schedule, to ez_lattice_sums itself).
+ * The plan is uploaded from host memory with hipMemcpyAsync when it differs
+ * from the one resident in the scratch (pageable source: the copy completes
+ * before the call returns), so a first call with a new plan cannot be captured.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (different streams or host threads) race and give undefined results.
+ * Errors: as ez_lattice_sums; EZ_ERR_INVALID_ARG when the plan and workspace of
+ * the call exceed the 64 MiB (the message gives the size needed). */
+ez_status ez_lattice_sums_noalloc(int batch, int d, const double *A_dev, int n_nu, const double *nu_host,
+                                  int n_terms, const int *term_result, const double *term_coef,
+                                  const int *term_nfac, const int *term_fac, const int *term_mult,
+                                  int n_results, const ez_quad_spec *specs, int n_specs, double *out_dev,
+                                  uint32_t *status_dev, void *stream);
+
 /* ez_lattice_sums with the derivatives of the results with respect to the
  * generator matrix (reverse mode through every step of the quadrature; the
  * derivative of the quadrature value on the given plan, lam held fixed).

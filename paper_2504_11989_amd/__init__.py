@@ -155,7 +155,7 @@ def atm_energy(A, spec=None, with_status=False, grad=False):
 
 
 def lattice_sums(A, nu: Sequence[float], terms: Iterable, n_results: int, specs=None, with_status=False,
-                 grad=False, out=None, status=None):
+                 grad=False, out=None, status=None, noalloc=False):
     """Several results per lattice, result_r = sum of coef * V int_BZ prod Z_nu^mult dk.
 
     terms: iterable of (result_index, coef, [(nu_index, multiplicity), ...]).
@@ -163,7 +163,10 @@ def lattice_sums(A, nu: Sequence[float], terms: Iterable, n_results: int, specs=
     Returns float64 tensor (batch, n_results); grad=True (n_results <= 2) also
     returns the derivatives with respect to A, float64 (batch, n_results, d, d).
     out / status: optional preallocated result (batch, n_results) float64 and
-    status (batch,) int32 tensors (nothing is allocated then, e.g. under graph capture)."""
+    status (batch,) int32 tensors (nothing is allocated then, e.g. under graph capture).
+    noalloc=True calls ez_lattice_sums_noalloc: the library allocates no device
+    memory for the call (its intermediates live in a static 64 MiB array per GPU);
+    values only."""
     torch = _torch()
     A, b, d = _lattices(A)
     nu_h, n_nu = _host_f64(nu)
@@ -199,6 +202,13 @@ def lattice_sums(A, nu: Sequence[float], terms: Iterable, n_results: int, specs=
         raise ValueError("status must be an int32 tensor of shape (batch,)")
     else:
         st = status
+    if noalloc:
+        if grad:
+            raise ValueError("the no-allocation entry point computes values only")
+        check(lib().ez_lattice_sums_noalloc(b, d, _dptr(A), n_nu, nu_h, nt, res, coef, nfac, fac, mult,
+                                            int(n_results), sp_arr, len(sp_list), _dptr(out), _dptr(st),
+                                            _stream_ptr(A.device)))
+        return (out, st) if with_status else out
     g = torch.empty((b, n_results, d, d), dtype=torch.float64, device=A.device) if grad else None
     check(lib().ez_lattice_sums_grad(b, d, _dptr(A), n_nu, nu_h, nt, res, coef, nfac, fac, mult, int(n_results),
                                      sp_arr, len(sp_list), _dptr(out), _dptr(g) if grad else None, _dptr(st),

@@ -28,7 +28,7 @@ def spec_bpc(n: int) -> int:
 # every symbol declared in include/ezeta.h
 EXPORTED = ("ez_epstein_zeta", "ez_epstein_grid", "ez_nbody_lattice_sum", "ez_atm_energy", "ez_lattice_sums", "ez_lattice_sums_grad",
             "ez_timing_enable", "ez_timing_reset", "ez_timing_read",
-            "ez_last_error", "ez_finalize", "ez_version", "ez_workspace_generation")
+            "ez_last_error", "ez_finalize", "ez_version", "ez_workspace_generation", "ez_lattice_sums_noalloc")
 (KERNEL_SETUP, KERNEL_NODES, KERNEL_HADAMARD, KERNEL_FINALIZE, KERNEL_EPSTEIN, KERNEL_NODES_ADJ, KERNEL_GRID,
  KERNEL_NODES_TAIL, KERNEL_TAYLOR) = (0, 1, 2, 3, 4, 5, 6, 7, 8)
 
@@ -77,6 +77,9 @@ def lib():
     L.ez_lattice_sums.restype = I
     L.ez_lattice_sums.argtypes = [I, I, VP, I, P, I, IP, P, IP, IP, IP, I, ctypes.POINTER(QuadSpec), I,
                                   VP, VP, VP]
+    L.ez_lattice_sums_noalloc.restype = I
+    L.ez_lattice_sums_noalloc.argtypes = [I, I, VP, I, P, I, IP, P, IP, IP, IP, I, ctypes.POINTER(QuadSpec), I,
+                                          VP, VP, VP]
     L.ez_lattice_sums_grad.restype = I
     L.ez_lattice_sums_grad.argtypes = [I, I, VP, I, P, I, IP, P, IP, IP, IP, I, ctypes.POINTER(QuadSpec), I,
                                        VP, VP, VP, VP]

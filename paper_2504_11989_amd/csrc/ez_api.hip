@@ -140,7 +140,8 @@ ez_status grow(DevBuf &b, size_t bytes) {
     return EZ_OK;
 }
 
-// Device pointers and counts of a plan.
+// Device pointers and counts of a plan, wherever it lives (cached plan buffers,
+// or the static scratch of the no-allocation entry point).
 struct PlanView {
     const double *rules = nullptr;
     const EzInstPlan *plans = nullptr;
@@ -149,6 +150,7 @@ struct PlanView {
     int n_probe = 0, ell_probe = 0, probe_off = 0;
     int pinv_off[EZ_ELL_MAX + 1] = {0};
 };
+using PlanViewBase = PlanView;
 
 // A plan depends only on (d, batch, specs): rule tables, per-lattice plans, prefixes.
 struct DevPlan {
@@ -172,6 +174,12 @@ struct DeviceState {
     int n_cu = 0;
     hipStream_t side = nullptr;  // second stream: Hadamard branch concurrent with the nodes
     hipEvent_t ev_setup = nullptr, ev_had = nullptr;
+    // no-allocation entry point: this device's address of the static scratch array,
+    // and the plan currently resident at its start
+    void *scratch = nullptr;
+    std::string scratch_key;
+    PlanViewBase scratch_plan;
+    size_t scratch_plan_bytes = 0;
 };
 
 std::mutex g_mu;
@@ -984,6 +992,33 @@ ez_status sums_program(int batch, int d, const double *A_dev, int n_nu, const do
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Scratch of the no-allocation entry point: file-scope device memory, one copy
+// per GPU, held until the process ends.  Host code never passes `scratch` itself
+// (in host code its name is a host-side stand-in, not a device address); it
+// uses the address hipGetSymbolAddress returns for the current device.
+#define EZ_SCRATCH_BYTES (64u << 20)
+static __device__ __align__(256) unsigned char scratch[EZ_SCRATCH_BYTES];
+
+namespace {
+
+// this device's address of `scratch` (looked up once per device, with that device current)
+ez_status scratch_address(DeviceState *S, void **out) {
+    if (!S->scratch) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(EZ_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        S->scratch = ptr;
+    }
+    *out = S->scratch;
+    return EZ_OK;
+}
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+}  // namespace
+
 extern "C" {
 
 const char *ez_last_error(void) { return g_err.c_str(); }
@@ -1032,6 +1067,82 @@ ez_status ez_lattice_sums_grad(int batch, int d, const double *A_dev, int n_nu, 
                                 term_mult, n_results, specs, n_specs, out_dev, grad_dev != nullptr, prog, combos);
     if (st) return st;
     return run_sums(batch, d, A_dev, prog, combos, specs, n_specs, out_dev, status_dev, (hipStream_t)stream, grad_dev);
+}
+
+ez_status ez_lattice_sums_noalloc(int batch, int d, const double *A_dev, int n_nu, const double *nu_host, int n_terms,
+                                  const int *term_result, const double *term_coef, const int *term_nfac,
+                                  const int *term_fac, const int *term_mult, int n_results, const ez_quad_spec *specs,
+                                  int n_specs, double *out_dev, uint32_t *status_dev, void *stream) {
+    EzProgram prog;
+    std::vector<EzCombo> combos;
+    ez_status st = sums_program(batch, d, A_dev, n_nu, nu_host, n_terms, term_result, term_coef, term_nfac, term_fac,
+                                term_mult, n_results, specs, n_specs, out_dev, false, prog, combos);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    EZ_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_mu);
+    DeviceState *S = device_state(dev);
+    void *base = nullptr;
+    if ((st = scratch_address(S, &base))) return st;
+    if (!S->n_cu) EZ_HIP_TRY(hipDeviceGetAttribute(&S->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    CallInfo C;
+    if ((st = prepare_call(batch, d, prog, combos, specs, n_specs, false, C))) return st;
+    // the plan at the start of the scratch; uploaded unless it is the resident one
+    const std::string key = plan_key(d, batch, specs, n_specs, C.ndb);
+    HostPlan H;
+    const bool resident = S->scratch_key == key && S->scratch_plan_bytes > 0;
+    if (!resident && (st = build_host_plan(d, batch, specs, n_specs, C.ndb, H))) return st;
+    unsigned char *p0 = (unsigned char *)base;
+    size_t off = 0;
+    PlanView pv;
+    size_t sz[6] = {0, 0, 0, 0, 0, 0}, o[6] = {0, 0, 0, 0, 0, 0};
+    if (resident) {
+        pv = S->scratch_plan;
+        off = S->scratch_plan_bytes;
+    } else {
+        sz[0] = H.rules.size() * sizeof(double);
+        sz[1] = sizeof(EzInstPlan) * (size_t)batch;
+        sz[2] = sz[3] = sz[4] = sizeof(int) * (size_t)(batch + 1);
+        sz[5] = sizeof(int) * std::max<size_t>(1, H.order.size());
+        for (int i = 0; i < 6; ++i) { o[i] = off; off += align256(sz[i]); }
+        fill_plan_view(H, pv);
+        pv.rules = (const double *)(p0 + o[0]);
+        pv.plans = (const EzInstPlan *)(p0 + o[1]);
+        pv.tile_begin = (const int *)(p0 + o[2]);
+        pv.dir_begin = (const int *)(p0 + o[3]);
+        pv.htile_begin = (const int *)(p0 + o[4]);
+        pv.tile_order = (const int *)(p0 + o[5]);
+    }
+    const size_t plan_bytes = off;
+    const int n_main = main_tiles(C, prog, S->n_cu, pv.n_tiles);
+    Workspace W;
+    workspace_sizes(batch, prog, C, pv, n_main, W);
+    for (int i = 0; i < WS_COUNT; ++i) {
+        if (W.bytes[i] == 0) continue;
+        W.ptr[i] = p0 + off;
+        off += align256(W.bytes[i]);
+    }
+    if (off > EZ_SCRATCH_BYTES)   // checked before anything is copied or launched
+        return fail(EZ_ERR_INVALID_ARG, "the call needs " + std::to_string(off) +
+                                            " bytes for its plan and workspace; the no-allocation scratch holds " +
+                                            std::to_string(EZ_SCRATCH_BYTES));
+    if (!resident) {
+        // pageable host sources: each copy has completed when hipMemcpyAsync returns
+        const void *src[6] = {H.rules.data(), H.plans.data(), H.tb.data(), H.db.data(), H.hb.data(), H.order.data()};
+        S->scratch_key.clear();
+        for (int i = 0; i < 6; ++i)
+            if (sz[i] && !(i == 5 && H.order.empty()))
+                EZ_HIP_TRY(hipMemcpyAsync(p0 + o[i], src[i], sz[i], hipMemcpyHostToDevice, s));
+        S->scratch_key = key;
+        S->scratch_plan = pv;
+        S->scratch_plan_bytes = plan_bytes;
+    }
+    // the tail group counters must start at zero (the scratch keeps the last call's contents)
+    EZ_HIP_TRY(ez_launch_fill_int((int *)W.ptr[WS_TAIL_CNT], (int)(W.bytes[WS_TAIL_CNT] / sizeof(int)), 0, s));
+    // one stream, no events: the Hadamard branch runs before the nodes
+    return enqueue_sums(batch, A_dev, prog, combos, C, pv, n_main, S->n_cu, W, out_dev, status_dev, nullptr, s,
+                        nullptr, nullptr, nullptr, false);
 }
 
 ez_status ez_lattice_sums(int batch, int d, const double *A_dev, int n_nu, const double *nu_host, int n_terms,
