@@ -437,13 +437,34 @@ ez_status build_host_plan(int d, int batch, const ez_quad_spec *specs, int n_spe
         long long nd = (long long)d * (1ll << (d - 1));
         for (int i = 0; i < d - 1; ++i) nd *= s.n_q;
         ip.n_dir = (int)nd;
-        long long nn = nd * n_u;
+        // wave blocks of 64 nodes: ub consecutive u-nodes (one u-panel when n_g = 16)
+        // across db = 64/ub neighbouring directions, so that each wave's k lie in a
+        // small box; the shape with the fewest empty lanes, 16 x 4 on ties
+        {
+            const int cand[4] = {4, 3, 5, 6};     // log2 ub: 16, 8, 32, 64
+            long long best = -1;
+            for (int ci = 0; ci < 4; ++ci) {
+                const int lg = (d == 1) ? 6 : cand[ci];
+                const long long ub = 1ll << lg, dbk = 64 / ub;
+                const long long slots = ((n_u + ub - 1) / ub) * ub * ((nd + dbk - 1) / dbk) * dbk;
+                if (best < 0 || slots < best) {
+                    best = slots;
+                    ip.ub_log2 = lg;
+                    ip.db = (int)dbk;
+                }
+                if (d == 1) break;
+            }
+            ip.n_ublk = (n_u + (1 << ip.ub_log2) - 1) >> ip.ub_log2;
+            const long long nblk = (long long)ip.n_ublk * ((nd + ip.db - 1) / ip.db);
+            if (nblk > (1ll << 30)) return fail(EZ_ERR_INVALID_ARG, "quadrature too large for one call");
+            ip.n_wblk = (int)nblk;
+        }
         ip.tile_begin = (int)tiles;
         ip.dir_begin = (int)dirs;
         tb[b] = (int)tiles;
         db[b] = (int)dirs;
         hb[b] = (int)htiles;
-        tiles += (nn + EZ_TILE - 1) / EZ_TILE;
+        tiles += (ip.n_wblk + EZ_TILE / 64 - 1) / (EZ_TILE / 64);
         dirs += nd;
         htiles += (nd + ndb - 1) / ndb;
         if (tiles > (1ll << 30) || dirs > (1ll << 30)) return fail(EZ_ERR_INVALID_ARG, "quadrature too large for one call");
@@ -460,12 +481,11 @@ ez_status build_host_plan(int d, int batch, const ez_quad_spec *specs, int n_spe
         for (int b = 0; b < batch; ++b) {
             const ez_quad_spec &s = specs[n_specs == 1 ? 0 : b];
             const EzInstPlan &ip = H.plans[b];
-            const long long nn = (long long)ip.n_dir * ip.n_u;
             const double R = std::sqrt(spec_acut(s) / M_PI), lam = spec_lam(s);
             const double per_node = kOmega[d] * (std::pow(R / lam, d) * 108.0 + 0.5 * std::pow(R * lam, d) * 14.0);
             for (int t = tb[b]; t < tb[b + 1]; ++t) {
-                const long long first = (long long)(t - tb[b]) * EZ_TILE;
-                cost[t] = (double)std::min<long long>(EZ_TILE, nn - first) * per_node;
+                const long long first = (long long)(t - tb[b]) * (EZ_TILE / 64);
+                cost[t] = (double)std::min<long long>(EZ_TILE / 64, ip.n_wblk - first) * 64.0 * per_node;
             }
         }
         for (size_t t = 0; t < order.size(); ++t) order[t] = (int)t;

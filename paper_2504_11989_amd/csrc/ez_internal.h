@@ -67,12 +67,18 @@ struct EzLatMeta {
 };
 
 // Per-lattice quadrature plan (host-built).
+// The nodes (direction, u-node) of a lattice are grouped into wave blocks of 64:
+// db directions x ub consecutive u-nodes (ub = 2^ub_log2, db ub = 64), blocks
+// numbered direction group first, u-chunk fastest; a node tile (one workgroup
+// of the node kernel) is four consecutive blocks.
 struct EzInstPlan {
     int n_q, n_u, n_dir, ell;
     int tile_begin;         // first node tile of this lattice
     int dir_begin;          // first direction of this lattice (Hadamard output)
     int vrule;              // offset of the n_q-point Gauss rule on [0,1] (nodes, then weights)
     int urule;              // offset of the n_u u-nodes on (eps,1/2] (nodes, then weights)
+    int ub_log2, db;        // wave block: 2^ub_log2 u-nodes x db directions
+    int n_ublk, n_wblk;     // u-chunks per direction group, wave blocks of the lattice
     double eps;
     double lam_rel;         // Ewald parameter in units of V^{1/d}
 };

@@ -12,11 +12,15 @@
 #include "e1_rational.h"
 #include "ez_internal.h"
 
-// a*b + c as one three-operand v_fma_f64: the addend (a table constant) is read in
-// place instead of being copied into the destination register first
+// a*b + c as one three-operand v_fma_f64 whose addend c, a compile-time constant of
+// a polynomial or rational table, is read from a scalar register pair: the
+// constants of the exponential and of the E_1 / E_{1/2} rationals (about 40
+// doubles) then live in SGPRs instead of VGPRs, which the compiler would otherwise
+// hoist out of the reciprocal loop (the d = 3 ATM node kernel: 66 VGPRs and seven
+// waves per SIMD instead of 124 and four).  c must be uniform over the wave.
 __device__ __forceinline__ double ez_fma3(double a, double b, double c) {
     double r;
-    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
     return r;
 }
 

@@ -27,13 +27,11 @@ __device__ __attribute__((noinline, const)) double ez_ehalf_ool(double a) {
     return ez_expm(a) * inv * ez_ehw_scaled(inv);
 }
 
-// Geometry of node nd: k = u w, theta = u w_hat (so that k.z = theta.n for z = A n)
-// and the quadrature weight W (Duffy Jacobian u^{d-1}, Gauss weights, factor 2).
+// Geometry of node (dir, iu): k = u w, theta = u w_hat (so that k.z = theta.n for
+// z = A n) and the quadrature weight W (Duffy Jacobian u^{d-1}, Gauss weights, factor 2).
 template <int D>
-__device__ __forceinline__ void node_geometry(const EzInstPlan &P, const double *rules, const EzLatMeta *M, int nd,
-                                              double *k, double *th, double *W) {
-    const int dir = nd / P.n_u;
-    const int iu = nd - dir * P.n_u;
+__device__ __forceinline__ void node_geometry(const EzInstPlan &P, const double *rules, const EzLatMeta *M, int dir,
+                                              int iu, double *k, double *th, double *W) {
     double B[D * D];
 #pragma unroll
     for (int i = 0; i < D * D; ++i) B[i] = M->B[i];
@@ -173,6 +171,132 @@ __device__ __forceinline__ void rec_list(const EzQuadArgs &args, const double *k
     }
 }
 
+// Reciprocal sum of one wave of the tile kernel over the whole table, culled per
+// wave: the table is read in chunks of 64 entries (one per lane); the entries
+// within sqrt(a_cut/alpha)
+// + r_w of the centre of the wave's bounding box (half-diagonal r_w) are summed
+// in table order, taken one by one from the chunk's ballot mask and loaded
+// through the scalar cache.  Entries that may reach a < 1/4 at some node of the
+// wave (|m* + c| <= r_w + 1/(2 sqrt alpha)) go to the wave's near list and are
+// added last with the series forms (out of line); a near list longer than
+// EZ_NEAR_MAX makes the sums NaN.  Order: m* = 0, the main entries, the near list.
+#define EZ_NEAR_MAX 128
+
+// a value equal on all lanes of the wave, moved to scalar registers
+__device__ __forceinline__ double wave_uniform(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int D, int NNU, int SET>
+__device__ __forceinline__ void rec_wave(const EzQuadArgs &args, const double *kt, int n_rec, const double *k,
+                                         bool valid, double alpha, double acut, unsigned short *nearl,
+                                         double *acck) {
+    const bool need_e1 = pset_need_e1<SET, NNU>(args.prog), need_half = pset_need_half<SET, NNU>(args.prog);
+    const int lane = (int)threadIdx.x & 63;
+    double c[3] = {0.0, 0.0, 0.0}, rt2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        double lo = k[i], hi = k[i];
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            lo = fmin(lo, __shfl_xor(lo, m, 64));
+            hi = fmax(hi, __shfl_xor(hi, m, 64));
+        }
+        c[i] = wave_uniform(0.5 * (lo + hi));
+        rt2 += 0.25 * (hi - lo) * (hi - lo);
+    }
+    const double rt = sqrt(rt2);
+    const double rmax = (sqrt(acut / alpha) + rt) * (1.0 + 1e-9) + 1e-12;
+    const double rnear = (0.5 / sqrt(alpha) + rt) * (1.0 + 1e-9) + 1e-12;
+    const double rmax2 = wave_uniform(rmax * rmax), rnear2 = wave_uniform(rnear * rnear);
+    // m* = 0
+    if (valid) {
+        double rho = k[0] * k[0];
+        if (D > 1) rho = fma(k[1], k[1], rho);
+        if (D > 2) rho = fma(k[2], k[2], rho);
+        const double a = alpha * rho;
+        if (a <= acut) {
+            const double ex = ez_expm(a);
+            const double inv = ez_rcp(a);
+            double E1 = 0.0;
+            if (need_e1) E1 = (a < 0.25) ? ez_e1_series(a) : ex * ez_e1w_scaled(inv);
+            const double Eh = need_half ? ((a < 0.25) ? ez_ehalf(a) : ex * inv * ez_ehw_scaled(inv)) : 0.0;
+#pragma unroll
+            for (int i = 0; i < NNU; ++i)
+                acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
+        }
+    }
+    int n_near = 0;
+    for (int base = 1; base < n_rec; base += 64) {
+        // the chunk's entries, one per lane (a prefetch of the next chunk held 14 more
+        // registers and cost the fourth wave per SIMD)
+        const int q = base + lane;
+        const bool in = q < n_rec;
+        double d2 = 0.0;
+        {
+            const double *e = kt + (size_t)(in ? q : base) * 4;
+            const double t0 = e[0] + c[0];
+            d2 = t0 * t0;
+            if (D > 1) { const double t1 = e[1] + c[1]; d2 = fma(t1, t1, d2); }
+            if (D > 2) { const double t2 = e[2] + c[2]; d2 = fma(t2, t2, d2); }
+        }
+        const bool near = in && d2 <= rnear2;
+        const bool keep = in && !near && d2 <= rmax2;
+        const unsigned long long baln = __ballot(near);
+        if (baln) {
+            const int slot = n_near + __popcll(baln & ((1ull << lane) - 1ull));
+            if (near && slot < EZ_NEAR_MAX) nearl[slot] = (unsigned short)q;
+            n_near += __popcll(baln);
+        }
+        unsigned long long bal = __ballot(keep);
+        while (bal) {
+            const int j = __builtin_ctzll(bal);
+            bal &= bal - 1ull;
+            const double *e = kt + (size_t)(base + j) * 4;
+            double qx = e[0] + k[0];
+            double rho = qx * qx;
+            if (D > 1) { const double qy = e[1] + k[1]; rho = fma(qy, qy, rho); }
+            if (D > 2) { const double qz = e[2] + k[2]; rho = fma(qz, qz, rho); }
+            const double a = alpha * rho;
+            if (a <= acut) {
+                const double ex = ez_expm(a);
+                const double inv = ez_rcp(a);
+                const double E1 = need_e1 ? ex * ez_e1w_scaled(inv) : 0.0;
+                const double Eh = need_half ? ex * inv * ez_ehw_scaled(inv) : 0.0;
+#pragma unroll
+                for (int i = 0; i < NNU; ++i)
+                    acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
+            }
+        }
+    }
+    if (n_near > EZ_NEAR_MAX) {
+#pragma unroll
+        for (int i = 0; i < NNU; ++i) acck[i] = __longlong_as_double(0x7ff8000000000000ll);
+        return;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int j = 0; j < n_near; ++j) {
+        const double *e = kt + (size_t)__builtin_amdgcn_readfirstlane((int)nearl[j]) * 4;
+        double rho = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) { const double t = e[i] + k[i]; rho = fma(t, t, rho); }
+        const double a = alpha * rho;
+        if (a <= acut) {
+            const double ex = ez_expm(a);
+            const double inv = ez_rcp(a);
+            const double E1 = need_e1 ? ez_e1_ool(a) : 0.0;
+            const double Eh = need_half ? ez_ehalf_ool(a) : 0.0;
+#pragma unroll
+            for (int i = 0; i < NNU; ++i)
+                acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
+        }
+    }
+}
+
 // Z_nu = real part + K_nu (reciprocal part) - self term, then the weighted
 // products of the program's terms added to res
 template <int NNU>
@@ -199,8 +323,8 @@ __device__ __forceinline__ void node_products(const EzQuadArgs &args, const EzLa
     for (int r = 0; r < EZ_RES_MAX; ++r) res[r] *= W;
 }
 
-// LDS of the node kernels.  kpool holds the culled reciprocal list (unsigned
-// short); the split path reuses it for its partial sums once the list is done.
+// LDS of the split kernel.  kpool holds the culled reciprocal list (unsigned
+// short) and, once the list is done, the partial sums.
 template <int NW>
 struct NodeLds {
     double kpool[EZ_KCULL / 4];
@@ -209,49 +333,45 @@ struct NodeLds {
     int kwave[NW];
     int kcount;
 };
-using TileLds = NodeLds<EZ_TILE / 64>;
 using TailLds = NodeLds<EZ_TAIL_WAVES>;
 
+// LDS of the tile kernel: each wave's near list, the tile reduction
+struct TileLds {
+    unsigned short nearl[EZ_TILE / 64][EZ_NEAR_MAX];
+    double red[EZ_RES_MAX][EZ_TILE / 64][2];
+};
+
+// One node tile: four wave blocks of the lattice, each wave culls and sums on its own
 template <int D, int NNU, int SET>
 __device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile, TileLds &L) {
     const int inst = find_segment(args.tile_begin, args.batch, tile);
     const EzInstPlan P = args.plans[inst];
     const EzLatMeta *M = args.meta + inst;
     const int n_res = args.prog.n_res;
-    const int node = (tile - args.tile_begin[inst]) * EZ_TILE + threadIdx.x;
-    const int n_nodes = P.n_dir * P.n_u;
-    unsigned short *klist = reinterpret_cast<unsigned short *>(L.kpool);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wb = (tile - args.tile_begin[inst]) * (EZ_TILE / 64) + wave;
 
     double res[EZ_RES_MAX];
 #pragma unroll
     for (int r = 0; r < EZ_RES_MAX; ++r) res[r] = 0.0;
 
-    if (M->status == 0) {                         // uniform over the workgroup
-        const bool valid = node < n_nodes;
-        // threads past the last node take the tile's first node (geometry only)
-        const int nd = valid ? node : (tile - args.tile_begin[inst]) * EZ_TILE;
+    if (M->status == 0 && wb < P.n_wblk) {        // uniform over the wave
+        int dir, iu;
+        const bool valid = block_node(P, wb, lane, &dir, &iu);
         double k[3], th[3], W;
-        node_geometry<D>(P, args.rules, M, nd, k, th, &W);
+        node_geometry<D>(P, args.rules, M, dir, iu, k, th, &W);
 
         double accr[NNU], acck[NNU];
 #pragma unroll
         for (int i = 0; i < NNU; ++i) { accr[i] = 0.0; acck[i] = 0.0; }
 
         const double *kt = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
-        const double alpha = M->alpha, acut = M->a_cut;
-        int n_near = 0;
-        const int nk = cull_reciprocal<D, EZ_TILE>(kt, M->n_rec, k, alpha, acut, klist, L.kbox, L.kwave, &L.kcount,
-                                                   &n_near);
-        if (valid) {
-            real_rows<D, NNU>(args, inst, th, 0, M->n_rows, accr);
-            rec_origin<D, NNU, SET>(args, kt, klist, n_near, k, alpha, acut, acck);
-            rec_list<D, NNU, SET>(args, kt, klist, 0, nk, k, alpha, acut, acck);
-            node_products<NNU>(args, M, accr, acck, W, res);
-        }
+        if (valid) real_rows<D, NNU>(args, inst, th, 0, M->n_rows, accr);
+        rec_wave<D, NNU, SET>(args, kt, M->n_rec, k, valid, M->alpha, M->a_cut, L.nearl[wave], acck);
+        if (valid) node_products<NNU>(args, M, accr, acck, W, res);
     }
 
     // tile reduction: wave butterflies, then the four waves in fixed order
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int r = 0; r < EZ_RES_MAX; ++r) {
         if (r < n_res) {
@@ -297,19 +417,19 @@ __device__ __forceinline__ void node_group_split(const EzQuadArgs &args, const i
     const EzInstPlan P = args.plans[inst];
     const EzLatMeta *M = args.meta + inst;
     const int n_res = args.prog.n_res;
-    const int tile0 = (tile - args.tile_begin[inst]) * EZ_TILE;
-    const int node = tile0 + quarter * 64 + lane;
-    const int n_nodes = P.n_dir * P.n_u;
+    const int wb = (tile - args.tile_begin[inst]) * GPT + quarter;   // the group is this wave block
     unsigned short *klist = reinterpret_cast<unsigned short *>(L.kpool);
 
-    const bool ok = M->status == 0;               // uniform over the workgroup
-    const bool valid = node < n_nodes;
+    // uniform over the workgroup: lattice flags, a block past the lattice's last
+    const bool ok = M->status == 0 && wb < P.n_wblk;
+    int dir, iu;
+    const bool valid = block_node(P, wb, lane, &dir, &iu);
     double accr[NNU], acck[NNU], W = 0.0;
 #pragma unroll
     for (int i = 0; i < NNU; ++i) { accr[i] = 0.0; acck[i] = 0.0; }
     if (ok) {
         double k[3], th[3];
-        node_geometry<D>(P, args.rules, M, valid ? node : tile0, k, th, &W);
+        node_geometry<D>(P, args.rules, M, dir, iu, k, th, &W);
         const double *kt = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
         const double alpha = M->alpha, acut = M->a_cut;
         int n_near = 0;

@@ -68,6 +68,21 @@ __device__ __forceinline__ void ez_direction(const EzInstPlan &P, const double *
     *wv = weight;
 }
 
+// Node of lane `lane` in wave block wb of a lattice (see EzInstPlan): the block's
+// db directions x ub consecutive u-nodes.  Returns false for lanes past the last
+// direction or u-node, and for blocks past the lattice's last one; invalid lanes
+// of a valid block take the block's first node (geometry only).
+__device__ __forceinline__ bool block_node(const EzInstPlan &P, int wb, int lane, int *dir, int *iu) {
+    if (wb >= P.n_wblk) { *dir = 0; *iu = 0; return false; }
+    const int dg = wb / P.n_ublk, uc = wb - dg * P.n_ublk;
+    const int dd = lane >> P.ub_log2, uu = lane & ((1 << P.ub_log2) - 1);
+    const int d0 = dg * P.db, u0 = uc << P.ub_log2;
+    const bool ok = d0 + dd < P.n_dir && u0 + uu < P.n_u;
+    *dir = ok ? d0 + dd : d0;
+    *iu = ok ? u0 + uu : u0;
+    return ok;
+}
+
 // complex multiply (a r + i a i)(b r + i b i)
 __device__ __forceinline__ void cmul(double &ar, double &ai, double br, double bi) {
     const double r = fma(ar, br, -ai * bi);

@@ -229,3 +229,26 @@ def test_enthalpy_gradient_finite_coupling_and_pressure(ez):
         assert relnorm(g, fd) <= 1e-7, (seed, relnorm(g, fd))
         assert relnorm(g, O.grad_fd(h_oracle, A, h=5e-4)) <= 1e-8, seed
 
+
+
+def test_phase_scan_small_grid(ez):
+    """the (c, p) scan on a 2 x 2 grid: the minimisation of H over the scale of
+    the fcc and bcc lattices converges everywhere, pure LJ (c = p = 0) gives the
+    fcc cohesive energy -8.6102 at R slightly below 1 and picks fcc, the final H
+    equals the oracle's H at the final matrix, pressure compresses, and the
+    general-matrix minimisation from the perturbed pure-LJ winner returns to fcc"""
+    from paper_2504_11989_amd import enthalpy as H
+    spec = W.SPEC_SMALL_3D
+    cs, ps = [0.0, 1.5], [0.0, 0.8]
+    res = H.phase_scan(cs, ps, spec, stability=True, stability_iter=150)
+    assert res["converged"].all(), res["H"]
+    assert res["phase"][0, 0] == "fcc" and abs(res["H"][0, 0, 0] + 8.6102) < 1e-3, res["H"][0, 0]
+    assert 0.95 < res["R"][0, 0, 0] < 1.0
+    assert res["general"][0, 0] == "fcc", res["general"]
+    i, j = 1, 1
+    Af = res["A"][i, j]
+    elj = 0.5 * O.nbody(Af, [5, 7], spec) - O.nbody(Af, [3, 3], spec)
+    ref = elj + cs[i] * O.atm(Af, spec) + ps[j] * abs(np.linalg.det(Af))
+    k = 0 if res["phase"][i, j] == "fcc" else 1
+    assert abs(res["H"][i, j, k] - ref) <= 1e-12 * abs(ref)
+    assert res["V"][0, 1] < res["V"][0, 0] and res["V"][1, 1] < res["V"][1, 0]
