@@ -26,7 +26,8 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_VALU_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 METRIC = "ATM lattice sums/s and Epstein-zeta evals/s at 1e-12 rel err, FP64 vs mixed"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nodes_c2.json")
-KERNEL_SOURCES = ["ez_nodes.hip", "ez_quad_common.h", "ez_math.h", "ez_internal.h", "ez_kernels.h", "e1_rational.h"]
+KERNEL_SOURCES = ["ez_nodes.hip", "ez_quad_common.h", "ez_math.h", "ez_internal.h", "ez_kernels.h", "e1_rational.h",
+                  "exp2_table.h"]
 
 
 def node_kernel_flops_per_node(lam_rel: float, a_cut: float, n_nu: int, d: int = 3) -> float:

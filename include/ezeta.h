@@ -81,13 +81,13 @@ typedef struct ez_quad_spec {
  *                       before the nodes instead of concurrently on a second
  *                       stream
  *  EZ_SPEC_BPC(n)     : persistent workgroups per CU (0: as many as fit)
- *  EZ_SPEC_NO_SPLIT   : value calls hand the last node tiles, when they would
- *                       fill at most a quarter of a round of workgroups over the
- *                       device, to a kernel that shares each node's terms among
- *                       16 waves on four CUs; this flag keeps every tile in the
- *                       tile kernel (the split changes the order in which a
- *                       node's terms are added, so the two agree to rounding,
- *                       not bit for bit) */
+ *  EZ_SPEC_NO_SPLIT   : value calls hand the last node tiles, when they pass a
+ *                       multiple of a round of workgroups over the device by a
+ *                       few tiles (at most one per 16 CUs), to a kernel that
+ *                       shares each node's terms among 16 waves on four CUs;
+ *                       this flag keeps every tile in the tile kernel (the split
+ *                       changes the order in which a node's terms are added, so
+ *                       the two agree to rounding, not bit for bit) */
 #define EZ_SPEC_PERSISTENT 0x1
 #define EZ_SPEC_SERIAL 0x2
 #define EZ_SPEC_NO_SPLIT 0x4

@@ -699,8 +699,11 @@ int probe_slices(int batch, int n_probe) {
     return std::max(1, std::min(EZ_SLICE_MAX, 512 / std::max(1, batch * n_pblk)));
 }
 
-// tiles [n_main, n_tiles) go to the split kernel when they would fill at most a
-// quarter of a round of tile-kernel workgroups (value calls without EZ_SPEC_NO_SPLIT)
+// tiles [n_main, n_tiles) go to the split kernel when they pass a multiple of a round
+// of tile-kernel workgroups by a few tiles only: the split kernel shares each 64-node
+// group among 16 waves of four workgroups and runs one workgroup per CU, so it pays
+// only while its workgroups (16 per tail tile) fit one per CU (value calls without
+// EZ_SPEC_NO_SPLIT); a larger tail stays in the tile kernel
 int main_tiles(const CallInfo &C, const EzProgram &prog, int n_cu, int n_tiles) {
     int round = 0;                     // tile-kernel workgroups resident on the device at once
     {
@@ -712,7 +715,8 @@ int main_tiles(const CallInfo &C, const EzProgram &prog, int n_cu, int n_tiles) 
     int n_main = n_tiles;
     if (!C.grad && !(C.flags & EZ_SPEC_NO_SPLIT)) {
         const int tail = round > 0 ? n_tiles % round : 0;
-        if (n_tiles > round && tail > 0 && tail <= round / 4) n_main = n_tiles - tail;
+        const int per_tile = (EZ_TILE / 64) * EZ_TAIL_PARTS;     // split-kernel workgroups per tail tile
+        if (n_tiles > round && tail > 0 && tail * per_tile <= n_cu) n_main = n_tiles - tail;
     }
     return n_main;
 }

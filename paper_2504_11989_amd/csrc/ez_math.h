@@ -10,6 +10,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include "e1_rational.h"
+#include "exp2_table.h"
 #include "ez_internal.h"
 
 // a*b + c as one three-operand v_fma_f64 whose addend c, a compile-time constant of
@@ -48,6 +49,28 @@ __device__ __forceinline__ double ez_expm(double a) {
     p = fma(p, x, 1.0);
     p = fma(p, x, 1.0);
     return ldexp(p, -(int)n);
+}
+
+// e^{-a} for 0 <= a <= 700 with a table of 2^{-j/64} in LDS (ez_exp2_tab copied to
+// `tab`): a = (n/64) ln2 + r, n = rint(64 a / ln2), |r| <= ln2/128, with ln2/64 split
+// as the Cody-Waite pair of ez_expm divided by 64 (n LN2_HI/64 exact for n < 2^21);
+// e^{-a} = 2^{-floor(n/64)} 2^{-(n mod 64)/64} e^{-r}, e^{-r} by its Taylor series
+// through r^6 (truncation < 3e-20).
+__device__ __forceinline__ double ez_expm_tab(double a, const double *tab) {
+    const double n = rint(a * 92.33248261689366);                 // 64 / ln 2
+    double r = fma(-n, 0.6931471803691238 / 64.0, a);
+    r = fma(-n, 1.9082149292705877e-10 / 64.0, r);
+    const int ni = (int)n;
+    const double t = tab[ni & 63];
+    const double x = -r;
+    double p = 1.0 / 720.0;
+    p = ez_fma3(p, x, 1.0 / 120.0);
+    p = ez_fma3(p, x, 1.0 / 24.0);
+    p = ez_fma3(p, x, 1.0 / 6.0);
+    p = fma(p, x, 0.5);
+    p = fma(p, x, 1.0);
+    p = fma(p, x, 1.0);
+    return ldexp(p * t, -(ni >> 6));
 }
 
 // 1/x: hardware reciprocal estimate refined by two Newton steps (x normal, finite)
@@ -95,6 +118,28 @@ __device__ __forceinline__ double ez_e1w_scaled(double t) {
         Q = ez_fma3(Q, t, ez_e1w_q[j]);
     }
     return t * P * ez_rcp(Q);
+}
+
+// e^a E1(a) for a >= 4 from the (7,7) rational fit, given t = 1/a
+__device__ __forceinline__ double ez_e1f_scaled(double t) {
+    double P = ez_e1f_p[EZ_E1F_DEG], Q = ez_e1f_q[EZ_E1F_DEG];
+#pragma unroll
+    for (int j = EZ_E1F_DEG - 1; j >= 0; --j) {
+        P = ez_fma3(P, t, ez_e1f_p[j]);
+        Q = ez_fma3(Q, t, ez_e1f_q[j]);
+    }
+    return t * P * ez_rcp(Q);
+}
+
+// sqrt(pi a) e^a erfc(sqrt a) for a >= 4 from the (7,7) rational fit, given t = 1/a
+__device__ __forceinline__ double ez_ehf_scaled(double t) {
+    double P = ez_ehf_p[EZ_E1F_DEG], Q = ez_ehf_q[EZ_E1F_DEG];
+#pragma unroll
+    for (int j = EZ_E1F_DEG - 1; j >= 0; --j) {
+        P = ez_fma3(P, t, ez_ehf_p[j]);
+        Q = ez_fma3(Q, t, ez_ehf_q[j]);
+    }
+    return P * ez_rcp(Q);
 }
 
 // E1(a) for 0 < a < 1/4 by the series; kept out of line so that its constants

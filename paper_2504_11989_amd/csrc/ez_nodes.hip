@@ -172,15 +172,21 @@ __device__ __forceinline__ void rec_list(const EzQuadArgs &args, const double *k
 }
 
 // Reciprocal sum of one wave of the tile kernel over the whole table, culled per
-// wave: the table is read in chunks of 64 entries (one per lane); the entries
-// within sqrt(a_cut/alpha)
-// + r_w of the centre of the wave's bounding box (half-diagonal r_w) are summed
-// in table order, taken one by one from the chunk's ballot mask and loaded
-// through the scalar cache.  Entries that may reach a < 1/4 at some node of the
-// wave (|m* + c| <= r_w + 1/(2 sqrt alpha)) go to the wave's near list and are
-// added last with the series forms (out of line); a near list longer than
-// EZ_NEAR_MAX makes the sums NaN.  Order: m* = 0, the main entries, the near list.
+// wave.  The table is read in chunks of 64 entries (one per lane); with c and r_w
+// the centre and half-diagonal of the bounding box of the wave's k, an entry is
+//   beyond the cutoff for every node   if |m* + c| > sqrt(a_cut/alpha) + r_w,
+//   near  (a may be < 1/4 at a node)   if |m* + c| <= 1/(2 sqrt alpha) + r_w,
+//   mid   (a may be < 4, never < 1/4)  if |m* + c| <= 2/sqrt(alpha) + r_w,
+//   far   (a >= 4 at every node)       otherwise.
+// Far entries (most of them) are summed as the chunk is read, taken one by one
+// from the chunk's ballot mask and loaded through the scalar cache, with E_1 and
+// E_{1/2} from the (7,7) rationals for a >= 4.  Mid and near entries go to the
+// wave's lists in LDS and are summed afterwards, mid ones with the (12,12)
+// rationals for a >= 1/4, near ones with the series forms below 1/4 (out of
+// line); a list longer than its capacity makes the sums NaN.
+// Order of the terms: m* = 0, far entries, mid list, near list (table order in each).
 #define EZ_NEAR_MAX 128
+#define EZ_MID_MAX 256
 
 // a value equal on all lanes of the wave, moved to scalar registers
 __device__ __forceinline__ double wave_uniform(double v) {
@@ -189,10 +195,22 @@ __device__ __forceinline__ double wave_uniform(double v) {
     const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+
+// appends the lanes with `sel` to a wave's index list at position *n (in lane order)
+__device__ __forceinline__ void wave_append(bool sel, int q, unsigned short *list, int cap, int *n) {
+    const unsigned long long bal = __ballot(sel);
+    if (bal) {
+        const int lane = (int)threadIdx.x & 63;
+        const int slot = *n + __popcll(bal & ((1ull << lane) - 1ull));
+        if (sel && slot < cap) list[slot] = (unsigned short)q;
+        *n += __popcll(bal);
+    }
+}
+
 template <int D, int NNU, int SET>
 __device__ __forceinline__ void rec_wave(const EzQuadArgs &args, const double *kt, int n_rec, const double *k,
                                          bool valid, double alpha, double acut, unsigned short *nearl,
-                                         double *acck) {
+                                         unsigned short *midl, const double *exptab, double *acck) {
     const bool need_e1 = pset_need_e1<SET, NNU>(args.prog), need_half = pset_need_half<SET, NNU>(args.prog);
     const int lane = (int)threadIdx.x & 63;
     double c[3] = {0.0, 0.0, 0.0}, rt2 = 0.0;
@@ -207,10 +225,12 @@ __device__ __forceinline__ void rec_wave(const EzQuadArgs &args, const double *k
         c[i] = wave_uniform(0.5 * (lo + hi));
         rt2 += 0.25 * (hi - lo) * (hi - lo);
     }
-    const double rt = sqrt(rt2);
+    const double rt = sqrt(rt2), ra = 1.0 / sqrt(alpha);
     const double rmax = (sqrt(acut / alpha) + rt) * (1.0 + 1e-9) + 1e-12;
-    const double rnear = (0.5 / sqrt(alpha) + rt) * (1.0 + 1e-9) + 1e-12;
+    const double rnear = (0.5 * ra + rt) * (1.0 + 1e-9) + 1e-12;
+    const double rmid = (2.0 * ra + rt) * (1.0 + 1e-9) + 1e-12;
     const double rmax2 = wave_uniform(rmax * rmax), rnear2 = wave_uniform(rnear * rnear);
+    const double rmid2 = wave_uniform(rmid * rmid);
     // m* = 0
     if (valid) {
         double rho = k[0] * k[0];
@@ -228,10 +248,10 @@ __device__ __forceinline__ void rec_wave(const EzQuadArgs &args, const double *k
                 acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
         }
     }
-    int n_near = 0;
+    int n_near = 0, n_mid = 0;
     for (int base = 1; base < n_rec; base += 64) {
         // the chunk's entries, one per lane (a prefetch of the next chunk held 14 more
-        // registers and cost the fourth wave per SIMD)
+        // registers)
         const int q = base + lane;
         const bool in = q < n_rec;
         double d2 = 0.0;
@@ -243,13 +263,10 @@ __device__ __forceinline__ void rec_wave(const EzQuadArgs &args, const double *k
             if (D > 2) { const double t2 = e[2] + c[2]; d2 = fma(t2, t2, d2); }
         }
         const bool near = in && d2 <= rnear2;
-        const bool keep = in && !near && d2 <= rmax2;
-        const unsigned long long baln = __ballot(near);
-        if (baln) {
-            const int slot = n_near + __popcll(baln & ((1ull << lane) - 1ull));
-            if (near && slot < EZ_NEAR_MAX) nearl[slot] = (unsigned short)q;
-            n_near += __popcll(baln);
-        }
+        const bool mid = in && !near && d2 <= rmid2;
+        const bool keep = in && !near && !mid && d2 <= rmax2;
+        wave_append(near, q, nearl, EZ_NEAR_MAX, &n_near);
+        wave_append(mid, q, midl, EZ_MID_MAX, &n_mid);
         unsigned long long bal = __ballot(keep);
         while (bal) {
             const int j = __builtin_ctzll(bal);
@@ -261,17 +278,17 @@ __device__ __forceinline__ void rec_wave(const EzQuadArgs &args, const double *k
             if (D > 2) { const double qz = e[2] + k[2]; rho = fma(qz, qz, rho); }
             const double a = alpha * rho;
             if (a <= acut) {
-                const double ex = ez_expm(a);
+                const double ex = ez_expm_tab(a, exptab);
                 const double inv = ez_rcp(a);
-                const double E1 = need_e1 ? ex * ez_e1w_scaled(inv) : 0.0;
-                const double Eh = need_half ? ex * inv * ez_ehw_scaled(inv) : 0.0;
+                const double E1 = need_e1 ? ex * ez_e1f_scaled(inv) : 0.0;
+                const double Eh = need_half ? ex * inv * ez_ehf_scaled(inv) : 0.0;
 #pragma unroll
                 for (int i = 0; i < NNU; ++i)
                     acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
             }
         }
     }
-    if (n_near > EZ_NEAR_MAX) {
+    if (n_near > EZ_NEAR_MAX || n_mid > EZ_MID_MAX) {
 #pragma unroll
         for (int i = 0; i < NNU; ++i) acck[i] = __longlong_as_double(0x7ff8000000000000ll);
         return;
@@ -279,6 +296,22 @@ __device__ __forceinline__ void rec_wave(const EzQuadArgs &args, const double *k
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int j = 0; j < n_mid; ++j) {
+        const double *e = kt + (size_t)__builtin_amdgcn_readfirstlane((int)midl[j]) * 4;
+        double rho = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) { const double t = e[i] + k[i]; rho = fma(t, t, rho); }
+        const double a = alpha * rho;
+        if (a <= acut) {
+            const double ex = ez_expm(a);
+            const double inv = ez_rcp(a);
+            const double E1 = need_e1 ? ex * ez_e1w_scaled(inv) : 0.0;
+            const double Eh = need_half ? ex * inv * ez_ehw_scaled(inv) : 0.0;
+#pragma unroll
+            for (int i = 0; i < NNU; ++i)
+                acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
+        }
+    }
     for (int j = 0; j < n_near; ++j) {
         const double *e = kt + (size_t)__builtin_amdgcn_readfirstlane((int)nearl[j]) * 4;
         double rho = 0.0;
@@ -335,9 +368,11 @@ struct NodeLds {
 };
 using TailLds = NodeLds<EZ_TAIL_WAVES>;
 
-// LDS of the tile kernel: each wave's near list, the tile reduction
+// LDS of the tile kernel: each wave's near and mid lists, the tile reduction
 struct TileLds {
+    double exptab[64];
     unsigned short nearl[EZ_TILE / 64][EZ_NEAR_MAX];
+    unsigned short midl[EZ_TILE / 64][EZ_MID_MAX];
     double red[EZ_RES_MAX][EZ_TILE / 64][2];
 };
 
@@ -354,6 +389,8 @@ __device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile
     double res[EZ_RES_MAX];
 #pragma unroll
     for (int r = 0; r < EZ_RES_MAX; ++r) res[r] = 0.0;
+    if (threadIdx.x < 64) L.exptab[threadIdx.x] = ez_exp2_tab[threadIdx.x];
+    __syncthreads();
 
     if (M->status == 0 && wb < P.n_wblk) {        // uniform over the wave
         int dir, iu;
@@ -367,7 +404,8 @@ __device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile
 
         const double *kt = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
         if (valid) real_rows<D, NNU>(args, inst, th, 0, M->n_rows, accr);
-        rec_wave<D, NNU, SET>(args, kt, M->n_rec, k, valid, M->alpha, M->a_cut, L.nearl[wave], acck);
+        rec_wave<D, NNU, SET>(args, kt, M->n_rec, k, valid, M->alpha, M->a_cut, L.nearl[wave], L.midl[wave],
+                              L.exptab, acck);
         if (valid) node_products<NNU>(args, M, accr, acck, W, res);
     }
 
