@@ -27,7 +27,7 @@ PEAK_FP64_VALU_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GH
 METRIC = "ATM lattice sums/s and Epstein-zeta evals/s at 1e-12 rel err, FP64 vs mixed"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nodes_c2.json")
 KERNEL_SOURCES = ["ez_nodes.hip", "ez_quad_common.h", "ez_math.h", "ez_internal.h", "ez_kernels.h", "e1_rational.h",
-                  "exp2_table.h"]
+                  "exp2_table.h", "ep_f32_rational.h"]
 
 
 def node_kernel_flops_per_node(lam_rel: float, a_cut: float, n_nu: int, d: int = 3) -> float:
@@ -128,10 +128,31 @@ def c3_scan_leg(args) -> dict:
     plain_specs = autotune.apply(specs, 1.0, 0)
     t_plain = timed(lambda: scan_sums(A, plain_specs), args.c3_reps)
     sample = slice(0, 512)
-    tuned = autotune.tune(A[sample], SCAN_NU, SCAN_TERMS, len(SCAN_RESULTS), specs[sample], reps=2)
+    tuned = autotune.tune(A[sample], SCAN_NU, SCAN_TERMS, len(SCAN_RESULTS), specs[sample], reps=2,
+                          wave_shapes=autotune.DEFAULT_WAVE_SHAPES)
     chosen = autotune.apply(specs, tuned["lam"], tuned["flags"])
     g = GraphedLatticeSums(A, SCAN_NU, SCAN_TERMS, len(SCAN_RESULTS), chosen)
     t_graph = timed(g.replay, args.c3_reps)
+    # node-kernel time of one eager call at the chosen configuration (library HIP
+    # events on the launch stream) for the roofline: the model's FP64 flops per
+    # node (seven exponents) over every node of the batch
+    from paper_2504_11989_amd import _native as nat
+    scan_sums(A, chosen)
+    torch.cuda.synchronize()
+    nat.timing_reset()
+    nat.timing_enable(True)
+    for _ in range(2):
+        scan_sums(A, chosen)
+    torch.cuda.synchronize()
+    nat.timing_enable(False)
+    kn = nat.timing_read(nat.KERNEL_NODES)
+    node_ms = kn[0] / max(1, kn[1])
+    flops = sum(node_kernel_flops_per_node(sp["lam"], sp["a_cut"], len(SCAN_NU)) * W.n_nodes(3, sp)
+                for sp in chosen)
+    achieved = flops / (node_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_VALU_TFLOPS, 5), "traffic": None,
+                "kernel": "ez_node_kernel<3,7,4>", "kernel_ms": round(node_ms, 4), "flops_per_launch": flops}
     out = g.out.cpu().numpy()
     st = g.status.cpu().numpy()
     plain = scan_sums(A, plain_specs).cpu().numpy()
@@ -151,11 +172,13 @@ def c3_scan_leg(args) -> dict:
         "plain": {"form": "eager call, lam = 1, one workgroup per tile", "ms_per_pass": 1e3 * t_plain,
                   "lattices_per_s": len(specs) / t_plain},
         "chosen": {"form": "autotuned lam and schedule, HIP-graph replay", "lam": tuned["lam"],
-                   "schedule": tuned["schedule"], "tuning_table_ms": [[l, n, round(m, 3)] for l, n, m in tuned["table"]]},
+                   "schedule": tuned["schedule"], "wave_block": tuned["wave"],
+                   "tuning_table_ms": [[l, n, w, round(m, 3)] for l, n, w, m in tuned["table"]]},
         "speedup_vs_plain": t_plain / t_graph,
         "max_rel_diff_chosen_vs_plain": float(np.max(np.abs(out - plain) / np.abs(plain))),
         "max_rel_err_vs_oracle_sample": err, "oracle_sample": idx,
         "status_nonzero": int(np.count_nonzero(st)),
+        "roofline": roofline,
     }
 
 
@@ -219,6 +242,157 @@ def c4_grid_leg(args) -> dict:
         "max_err_mixed_vs_fp64": worst["mixed_vs_fp64"], "max_err_fp64_vs_oracle": worst["fp64_vs_oracle"],
         "max_err_mixed_vs_oracle": worst["mixed_vs_oracle"], "max_a_priori_bound_mixed": worst["bound_max"],
         "error_measure": "|dZ| / max(|Z|, 1) per element"})
+    return out
+
+
+def mixed_leg(args, A, spec, gold, names, ms_fp64, node_ms_fp64) -> dict:
+    """The three-lattice ATM step in mixed precision (far-field reciprocal terms in
+    FP32, bound per result) against the FP64 step, for several FP32 thresholds
+    a_mix; `chosen` is the fastest a_mix whose bound certifies 1e-10 relative."""
+    import numpy as np
+    import torch
+    import paper_2504_11989_amd as ez
+    from paper_2504_11989_amd import _native as nat
+    atm_nu = [-1.0, 1.0, 3.0, 5.0]
+    atm_terms = [(0, 1.0 / 24.0, [(2, 3)]), (0, -3.0 / 16.0, [(0, 1), (3, 2)]),
+                 (0, 3.0 / 8.0, [(1, 1), (2, 1), (3, 1)])]
+    v64 = ez.atm_energy(A, spec).cpu().numpy()
+    ref = np.array([gold["atm"][n] for n in names])
+    table = []
+    steps = max(1, args.steps)
+    for a_mix in (8, 12, 16, 20, 24):
+        sm = dict(spec, precision=nat.PREC_MIXED, flags=nat.spec_mix_a(a_mix))
+        for _ in range(max(1, args.warmup)):
+            ez.atm_energy(A, sm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ez.atm_energy(A, sm)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        nat.timing_reset()
+        nat.timing_enable(True)
+        for _ in range(min(steps, 30)):
+            ez.atm_energy(A, sm)
+        torch.cuda.synchronize()
+        nat.timing_enable(False)
+        kn = nat.timing_read(nat.KERNEL_NODES)
+        v, bd = ez.lattice_sums(A, atm_nu, atm_terms, 1, sm, with_bound=True)
+        v, bd = v.cpu().numpy()[:, 0], bd.cpu().numpy()[:, 0]
+        table.append({"a_mix": a_mix, "ms_per_step": round(ms, 5), "node_kernel_ms": round(kn[0] / max(1, kn[1]), 5),
+                      "max_rel_bound": float(np.max(bd / np.abs(ref))),
+                      "max_rel_diff_vs_fp64": float(np.max(np.abs(v - v64) / np.abs(ref))),
+                      "max_rel_err_vs_oracle": float(np.max(np.abs(v - ref) / np.abs(ref))),
+                      "within_bound": bool(np.all(np.abs(v - v64) <= bd + 1e-13 * np.abs(ref)))})
+    ok = [r for r in table if r["max_rel_bound"] <= 1e-10 and r["within_bound"]]
+    chosen = min(ok, key=lambda r: r["ms_per_step"]) if ok else None
+    return {"workload": "the ATM step above with EZ_PREC_MIXED: reciprocal terms with a >= a_mix at every node "
+                        "of a 64-node wave block in FP32, the rest FP64; a-priori bound per result",
+            "fp64": {"ms_per_step": round(ms_fp64, 5), "node_kernel_ms": round(node_ms_fp64, 5)},
+            "table": table,
+            "chosen": chosen,
+            "speedup_step_vs_fp64": (ms_fp64 / chosen["ms_per_step"]) if chosen else None,
+            "speedup_node_kernel_vs_fp64": (node_ms_fp64 / chosen["node_kernel_ms"]) if chosen else None,
+            "equal_accuracy": "both within 1e-12 of the oracle on the identical plan; the mixed bound certifies "
+                              "<= 1e-10 relative"}
+
+
+def phase_leg(args) -> dict:
+    """fcc / bcc phase diagram over (p, lam) for LJ (12,6) and (8,4) with ATM
+    coupling lam (paper, Sec. 5) and the Bain path (bct, c/a from 0.9 to 1.6)."""
+    import numpy as np
+    import torch
+    from paper_2504_11989_amd import phase
+    import workloads as W
+    spec = dict(W.SPEC_FULL_3D)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    const = phase.lattice_constants(np.stack([W.A_FCC_NN1, W.A_BCC_NN1]), spec)
+    torch.cuda.synchronize()
+    t_const = time.perf_counter() - t0
+    f = {k: v[0:1] for k, v in const.items()}
+    b = {k: v[1:2] for k, v in const.items()}
+    ps = np.linspace(0.0, 2.0, 32)
+    lams = np.linspace(0.0, 4.0, 32)
+    out = {"workload": "fcc and bcc (unit nearest-neighbour distance) at the full plan: Z_12, Z_6, Z_8, Z_4 "
+                       "(two-body zeta functions) and E_ATM in one call; H minimised over R on a 32 x 32 "
+                       "(p in [0,2], lam in [0,4]) grid for LJ (12,6) and (8,4); Bain path of 64 bct lattices",
+           "constants_ms": round(1e3 * t_const, 3),
+           "constants": {k: [float(x) for x in v] for k, v in const.items()}}
+    t1 = time.perf_counter()
+    for lj in ((12, 6), (8, 4)):
+        dh = phase.phase_diagram(f, b, ps, lams, lj)
+        lc = phase.critical_coupling(f, b, ps, lj, lam_max=20.0)
+        out[f"lj_{lj[0]}_{lj[1]}"] = {
+            "phase_map_rows_p_cols_lam": ["".join("b" if x < 0 else "f" for x in row) for row in dh],
+            "lam_c_at_p": {f"{p:.3f}": float(l) for p, l in zip(ps[::8], lc[::8])},
+            "lam_c_range": [float(np.nanmin(lc)), float(np.nanmax(lc))]}
+    out["host_minimisation_s"] = round(time.perf_counter() - t1, 3)
+    cas = np.linspace(0.9, 1.6, 64)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    H0, s0, cb = phase.bain_path(cas, spec, (12, 6), 0.0, 0.0)
+    torch.cuda.synchronize()
+    lam_c0 = float(out["lj_12_6"]["lam_c_at_p"]["0.000"])
+    H1, _ = phase.h_min(cb, (12, 6), 0.0, lam_c0)
+    out["bain_path"] = {"c_over_a": [round(float(x), 5) for x in cas[::4]],
+                        "H_min_lam0": [float(x) for x in H0[::4]],
+                        "H_min_lam_c": [float(x) for x in H1[::4]],
+                        "batched_call_ms": round(1e3 * (time.perf_counter() - t2), 3),
+                        "argmin_c_over_a_lam0": float(cas[int(np.argmin(H0))]),
+                        "argmin_c_over_a_lam_c": float(cas[int(np.argmin(H1))])}
+    return out
+
+
+def highn_leg(args) -> dict:
+    """Ring sums zeta^(n)(3, ..., 3) on the square and hexagonal lattices for
+    n = 2 .. 51 (paper, Sec. 4.4: the 100-dimensional sum at n = 51), their ratio to
+    Z_3(0)^n and the time per sum against n; and the n_q study on A_kappa Z^2
+    (Sec. 4.1) as one batched call with per-lattice plans."""
+    import numpy as np
+    import torch
+    import paper_2504_11989_amd as ez
+    from paper_2504_11989_amd import autotune
+    import workloads as W
+    spec = dict(W.SPEC_2D)
+    out = {"workload": "zeta^(n)(3,...,3), n = 2..51, sq and hex, full 2D plan (n_q = 14, 96 graded u); "
+                       "zeta^(3)(1,3,5) on A_kappa, kappa = 1, 2, 3, n_q = 4..20 in one call"}
+    ns = [2, 3, 4, 6, 8, 12, 16, 24, 32, 40, 51]
+    for name, A in (("sq", np.eye(2)), ("hex", W.A_HEX)):
+        z0 = ez.epstein_zeta(A, [3.0], np.zeros((1, 2)), np.zeros((1, 2))).cpu().numpy()[0, 0, 0]
+        rows = []
+        for n in ns:
+            ez.nbody_lattice_sum(A, [3.0] * n, spec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps = 5
+            for _ in range(reps):
+                v = ez.nbody_lattice_sum(A, [3.0] * n, spec)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / reps
+            zn = v.item()
+            rows.append({"n": n, "zeta_n": zn, "zeta_n_over_Z0_n": zn / z0 ** n, "ms": round(ms, 4)})
+        out[name] = {"Z3_0": float(z0), "rows": rows}
+    kappas = [1.0, 2.0, 3.0]
+    nqs = list(range(4, 21, 2))
+    A = np.stack([W.a_kappa(k) for k in kappas for _ in nqs])
+    specs = [dict(spec, n_q=q) for _ in kappas for q in nqs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    got = ez.lattice_sums(A, [1.0, 3.0, 5.0], [(0, 1.0, [(0, 1), (1, 1), (2, 1)])], 1, specs).cpu().numpy()[:, 0]
+    t_batch = time.perf_counter() - t0
+    got = got.reshape(len(kappas), len(nqs))
+    study = []
+    for i, k in enumerate(kappas):
+        ref = got[i, -1]
+        err = [float(min(abs(x - ref), abs(x - ref) / abs(ref))) for x in got[i, :-1]]
+        e = np.array(err)
+        m = e > 1e-13
+        rho_fit = float(np.exp(-np.polyfit(np.array(nqs[:-1])[m], np.log(e[m]), 1)[0] / 2.0)) if m.sum() >= 3 else None
+        study.append({"kappa": k, "n_q": nqs[:-1], "E": err, "rho_fit": rho_fit,
+                      "rho_bound": autotune.rho_bound(W.a_kappa(k)),
+                      "n_q_for_1e-12": autotune.nq_for(W.a_kappa(k), 1e-12)})
+    out["kappa_study"] = {"batched_call_s": round(t_batch, 4), "rows": study}
     return out
 
 
@@ -337,6 +511,9 @@ def main() -> int:
     ap.add_argument("--c4-reps", type=int, default=3)
     ap.add_argument("--no-c5", action="store_true", help="skip the enthalpy scan and ring-sum leg")
     ap.add_argument("--c5-iters", type=int, default=100)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision ATM leg")
+    ap.add_argument("--no-phase", action="store_true", help="skip the phase-diagram / Bain-path leg")
+    ap.add_argument("--no-highn", action="store_true", help="skip the high-n / kappa-study leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 1 GiB device-to-device copies (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -474,6 +651,9 @@ def main() -> int:
         "c3_scan": None,
         "c4_grid": None,
         "c5": None,
+        "mixed": None,
+        "phase": None,
+        "highn": None,
         "cpu_baseline": None,
     }
     def leg(name, fn):
@@ -483,6 +663,12 @@ def main() -> int:
         print(f"bench: {name} done in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
         return r
 
+    if not args.no_mixed:
+        line["mixed"] = leg("mixed precision", lambda: mixed_leg(args, A, spec, gold, names, ms_step, node_ms))
+    if not args.no_phase:
+        line["phase"] = leg("phase diagram", lambda: phase_leg(args))
+    if not args.no_highn:
+        line["highn"] = leg("high-n sums", lambda: highn_leg(args))
     if not args.no_c3:
         line["c3_scan"] = leg("c3 scan", lambda: c3_scan_leg(args))
     if not args.no_c4:

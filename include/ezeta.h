@@ -60,7 +60,18 @@ typedef enum {
  *   n_g Gauss-Legendre points each.
  * lam: Ewald split parameter in units of V^{1/d} (0 selects 1.0), used as given;
  * a_cut: terms whose incomplete-gamma argument exceeds a_cut are dropped
- *   (0 selects 36, a truncation below 1e-15 relative for nu <= 12 at lam = 1). */
+ *   (0 selects 36, a truncation below 1e-15 relative for nu <= 12 at lam = 1).
+ * precision: EZ_PREC_MIXED (ez_lattice_sums, ez_lattice_sums_bound, ez_atm_energy
+ *   and ez_nbody_lattice_sum without derivatives) sums the reciprocal-space terms
+ *   whose incomplete-gamma argument is at least a_mix at every node of a 64-node
+ *   wave block in FP32: e^{-a} by the hardware exponential, E_p from FP32 rational
+ *   fits at the largest p and the stable downward recurrence; a_mix = 16 unless
+ *   EZ_SPEC_MIX_A(n) sets n >= 8.  Everything else (real-space sum, small and
+ *   middle arguments, the origin split, products, Hadamard part, reductions) stays
+ *   FP64.  ez_lattice_sums_bound returns an a-priori bound of the result's change.
+ *   When an exponent has 2p > 12 (p = (nu - d + 2)/2) or a_cut > 80 the call
+ *   computes in FP64 throughout (bound 0).  Derivatives and the no-allocation
+ *   entry point refuse it (EZ_ERR_UNSUPPORTED). */
 typedef struct ez_quad_spec {
     int32_t n_q;
     int32_t n_panels;
@@ -69,7 +80,7 @@ typedef struct ez_quad_spec {
     double eps;
     double lam;
     double a_cut;
-    int32_t precision; /* EZ_PREC_FP64 */
+    int32_t precision; /* EZ_PREC_FP64, or EZ_PREC_MIXED for value calls (below) */
     int32_t flags;     /* execution options below (0: defaults); equal for all specs of a call */
 } ez_quad_spec;
 
@@ -77,9 +88,9 @@ typedef struct ez_quad_spec {
  * the order of floating-point sums in the node reduction, which stays fixed)
  *  EZ_SPEC_PERSISTENT : the node kernel runs as a persistent grid that takes node
  *                       tiles from a work queue, costliest tiles first
- *  EZ_SPEC_SERIAL     : the Hadamard direction kernel runs on the caller's stream
- *                       before the nodes instead of concurrently on a second
- *                       stream
+ *  EZ_SPEC_SERIAL     : the kernels of the Hadamard part (probe, tensor,
+ *                       direction) run on the caller's stream before the nodes
+ *                       instead of concurrently on a second stream
  *  EZ_SPEC_BPC(n)     : persistent workgroups per CU (0: as many as fit)
  *  EZ_SPEC_NO_SPLIT   : value calls hand the last node tiles, when they pass a
  *                       multiple of a round of workgroups over the device by a
@@ -92,6 +103,14 @@ typedef struct ez_quad_spec {
 #define EZ_SPEC_SERIAL 0x2
 #define EZ_SPEC_NO_SPLIT 0x4
 #define EZ_SPEC_BPC(n) (((n) & 0xFF) << 8)
+/*  EZ_SPEC_MIX_A(n)   : mixed precision: FP32 far field from argument a_mix = n
+ *                       (n >= 8; 0 selects 16) */
+#define EZ_SPEC_MIX_A(n) (((n) & 0xFF) << 16)
+/*  EZ_SPEC_WAVE_U(k)  : shape of the 64-node wave blocks of the node kernel in
+ *                       d >= 2: 2^(k+2) consecutive u-nodes x 2^(4-k) directions
+ *                       (k = 1..4); 0 picks the shape with the fewest empty lanes
+ *                       (results do not depend on it beyond rounding) */
+#define EZ_SPEC_WAVE_U(k) (((k) & 0x7) << 24)
 
 /* Epstein zeta Z_{Lambda,nu}(x, y) = sum'_{z in Lambda} e^{-2 pi i y.z} |z - x|^{-nu},
  * meromorphically continued in nu (paper, Sec. 2, Definition (Epstein zeta
@@ -178,6 +197,24 @@ ez_status ez_lattice_sums(int batch, int d, const double *A_dev, int n_nu, const
                           const int *term_nfac, const int *term_fac, const int *term_mult,
                           int n_results, const ez_quad_spec *specs, int n_specs, double *out_dev,
                           uint32_t *status_dev, void *stream);
+
+/* ez_lattice_sums with an a-priori error bound per result, for EZ_PREC_MIXED specs:
+ *   bound_dev : batch x n_results doubles (device), |result_mixed - result_FP64| <=
+ *               bound_dev[b * n_results + r], where result_FP64 is the FP64 value on
+ *               the same plan up to FP64 rounding (about 1e-16 relative, not part of
+ *               the bound).  The bound propagates, to first order, the FP32 error of
+ *               each far-field chunk sum (a fixed multiple of u = 2^-24 per exponent,
+ *               from the error of e^{-a}, 1/a, the fits, the recurrence steps and 63
+ *               FP32 additions) through K_nu, the products and the quadrature
+ *               weights, with 1% for the second-order terms.  It is 0 for FP64 specs
+ *               and NaN for a lattice with a nonzero status.
+ * (The mixed-precision path: the spec's precision field.)
+ * Errors: as ez_lattice_sums; EZ_ERR_INVALID_ARG for a NULL bound_dev. */
+ez_status ez_lattice_sums_bound(int batch, int d, const double *A_dev, int n_nu, const double *nu_host,
+                                int n_terms, const int *term_result, const double *term_coef,
+                                const int *term_nfac, const int *term_fac, const int *term_mult,
+                                int n_results, const ez_quad_spec *specs, int n_specs, double *out_dev,
+                                double *bound_dev, uint32_t *status_dev, void *stream);
 
 /* ez_lattice_sums for callers that cannot allocate device memory (code under HIP
  * graph capture elsewhere in their stream, tight serving loops, harnesses that

@@ -836,9 +836,26 @@ static int nb_direction(const lat_t *L, int n, const double *nu, const nuctx_t *
     const int ell = sp->ell;
     double w2 = dot(d, w, w);
     /* --- (0, eps): product of (singular + Taylor) factors, term by term --- */
-    int maxterms = 1;
-    for (int i = 0; i < n; ++i) maxterms *= (ell + 2);
-    if (maxterms > 4000000) return EZO_EUNSUPPORTED;
+    /* Terms with equal (P, q) are merged, so the list never holds more than the
+       number of distinct pairs: the sums of the singular exponents take at most
+       prod over distinct nu of (count + 1) values, the Taylor degree 2K at most
+       n ell + 1 values and q at most n + 1; nor more than (ell + 2)^n.  (Counted
+       in double: the product overflows an int for large n.) */
+    double unmerged = 1.0, merged = (double)(n * ell + 1) * (double)(n + 1);
+    for (int i = 0; i < n; ++i) {
+        unmerged = fmin(unmerged * (ell + 2), 1e18);
+        int first = 1, count = 0;
+        for (int j = 0; j < n; ++j) {
+            if (nu[j] == nu[i]) {
+                if (j < i) first = 0;
+                ++count;
+            }
+        }
+        if (first) merged *= (double)(count + 1);
+    }
+    const double bound = fmin(unmerged, merged);
+    if (bound > 4000000.0) return EZO_EUNSUPPORTED;
+    const int maxterms = (int)bound;
     term_t *cur = (term_t *)malloc(sizeof(term_t) * (size_t)maxterms);
     term_t *nxt = (term_t *)malloc(sizeof(term_t) * (size_t)maxterms);
     if (!cur || !nxt) { free(cur); free(nxt); return EZO_ENOMEM; }

@@ -155,7 +155,7 @@ def atm_energy(A, spec=None, with_status=False, grad=False):
 
 
 def lattice_sums(A, nu: Sequence[float], terms: Iterable, n_results: int, specs=None, with_status=False,
-                 grad=False, out=None, status=None, noalloc=False):
+                 grad=False, out=None, status=None, noalloc=False, with_bound=False):
     """Several results per lattice, result_r = sum of coef * V int_BZ prod Z_nu^mult dk.
 
     terms: iterable of (result_index, coef, [(nu_index, multiplicity), ...]).
@@ -166,7 +166,10 @@ def lattice_sums(A, nu: Sequence[float], terms: Iterable, n_results: int, specs=
     status (batch,) int32 tensors (nothing is allocated then, e.g. under graph capture).
     noalloc=True calls ez_lattice_sums_noalloc: the library allocates no device
     memory for the call (its intermediates live in a static 64 MiB array per GPU);
-    values only."""
+    values only.
+    with_bound=True calls ez_lattice_sums_bound and also returns the a-priori bound
+    of each result's mixed-precision error, float64 (batch, n_results) (zero for
+    FP64 specs; specs with precision=PREC_MIXED select the mixed form)."""
     torch = _torch()
     A, b, d = _lattices(A)
     nu_h, n_nu = _host_f64(nu)
@@ -209,6 +212,14 @@ def lattice_sums(A, nu: Sequence[float], terms: Iterable, n_results: int, specs=
                                             int(n_results), sp_arr, len(sp_list), _dptr(out), _dptr(st),
                                             _stream_ptr(A.device)))
         return (out, st) if with_status else out
+    if with_bound:
+        if grad or noalloc:
+            raise ValueError("with_bound computes values only")
+        bound = torch.empty((b, n_results), dtype=torch.float64, device=A.device)
+        check(lib().ez_lattice_sums_bound(b, d, _dptr(A), n_nu, nu_h, nt, res, coef, nfac, fac, mult,
+                                          int(n_results), sp_arr, len(sp_list), _dptr(out), _dptr(bound), _dptr(st),
+                                          _stream_ptr(A.device)))
+        return (out, bound, st) if with_status else (out, bound)
     g = torch.empty((b, n_results, d, d), dtype=torch.float64, device=A.device) if grad else None
     check(lib().ez_lattice_sums_grad(b, d, _dptr(A), n_nu, nu_h, nt, res, coef, nfac, fac, mult, int(n_results),
                                      sp_arr, len(sp_list), _dptr(out), _dptr(g) if grad else None, _dptr(st),

@@ -25,10 +25,21 @@ def spec_bpc(n: int) -> int:
     """spec.flags bits for n persistent workgroups per CU (0: as many as fit)"""
     return (int(n) & 0xFF) << 8
 
+
+def spec_wave_u(k: int) -> int:
+    """spec.flags bits for wave blocks of 2^(k+2) u-nodes x 2^(4-k) directions (k = 1..4; 0: automatic)"""
+    return (int(k) & 0x7) << 24
+
+
+def spec_mix_a(n: int) -> int:
+    """spec.flags bits for the mixed-precision threshold a_mix = n (n >= 8; 0: 16)"""
+    return (int(n) & 0xFF) << 16
+
 # every symbol declared in include/ezeta.h
 EXPORTED = ("ez_epstein_zeta", "ez_epstein_grid", "ez_nbody_lattice_sum", "ez_atm_energy", "ez_lattice_sums", "ez_lattice_sums_grad",
             "ez_timing_enable", "ez_timing_reset", "ez_timing_read",
-            "ez_last_error", "ez_finalize", "ez_version", "ez_workspace_generation", "ez_lattice_sums_noalloc")
+            "ez_last_error", "ez_finalize", "ez_version", "ez_workspace_generation", "ez_lattice_sums_noalloc",
+            "ez_lattice_sums_bound")
 (KERNEL_SETUP, KERNEL_NODES, KERNEL_HADAMARD, KERNEL_FINALIZE, KERNEL_EPSTEIN, KERNEL_NODES_ADJ, KERNEL_GRID,
  KERNEL_NODES_TAIL, KERNEL_TAYLOR) = (0, 1, 2, 3, 4, 5, 6, 7, 8)
 
@@ -83,6 +94,9 @@ def lib():
     L.ez_lattice_sums_grad.restype = I
     L.ez_lattice_sums_grad.argtypes = [I, I, VP, I, P, I, IP, P, IP, IP, IP, I, ctypes.POINTER(QuadSpec), I,
                                        VP, VP, VP, VP]
+    L.ez_lattice_sums_bound.restype = I
+    L.ez_lattice_sums_bound.argtypes = [I, I, VP, I, P, I, IP, P, IP, IP, IP, I, ctypes.POINTER(QuadSpec), I,
+                                        VP, VP, VP, VP]
     L.ez_last_error.restype = ctypes.c_char_p
     L.ez_last_error.argtypes = []
     L.ez_finalize.restype = I

@@ -16,6 +16,7 @@
 #include "ez_internal.h"
 #include "ez_kernels.h"
 #include "ez_grid.h"
+#include "ep_f32_rational.h"
 
 namespace {
 
@@ -168,6 +169,7 @@ struct DeviceState {
         tile_grad, dir_grad;
     DevBuf gmeta, greal, grec;   // general-x Epstein tables
     DevBuf queue;                // work-queue position of the persistent node kernel
+    DevBuf tile_bound;           // mixed-precision bound partials per tile
     // Epstein grid workspace
     DevBuf g_pts_x, g_pts_y, g_perm, g_counts, g_A64r, g_B64r, g_A64k, g_B64k, g_R, g_Q, g_wsum, g_stat;
     DevBuf g_Ahr, g_Alr, g_Bhr, g_Blr, g_Ahk, g_Alk, g_Bhk, g_Blk;
@@ -256,9 +258,14 @@ ez_status check_spec(const ez_quad_spec &s) {
     if (!(s.eps > 0.0 && s.eps < 0.5)) return fail(EZ_ERR_INVALID_ARG, "spec.eps must be in (0, 1/2)");
     if (!(s.lam >= 0.0 && s.lam <= 8.0)) return fail(EZ_ERR_INVALID_ARG, "spec.lam must be in [0, 8]");
     if (!(s.a_cut >= 0.0 && s.a_cut <= 200.0)) return fail(EZ_ERR_INVALID_ARG, "spec.a_cut must be in [0, 200]");
-    if (s.precision != EZ_PREC_FP64) return fail(EZ_ERR_UNSUPPORTED, "spec.precision: only EZ_PREC_FP64 here");
-    if (s.flags & ~(EZ_SPEC_PERSISTENT | EZ_SPEC_SERIAL | EZ_SPEC_NO_SPLIT | 0xFF00))
+    if (s.precision != EZ_PREC_FP64 && s.precision != EZ_PREC_MIXED)
+        return fail(EZ_ERR_INVALID_ARG, "spec.precision must be EZ_PREC_FP64 or EZ_PREC_MIXED");
+    if (s.flags & ~(EZ_SPEC_PERSISTENT | EZ_SPEC_SERIAL | EZ_SPEC_NO_SPLIT | 0xFF00 | 0xFF0000 | 0x7000000))
         return fail(EZ_ERR_INVALID_ARG, "spec.flags: unknown bits");
+    if (((s.flags >> 24) & 0x7) > 4) return fail(EZ_ERR_INVALID_ARG, "EZ_SPEC_WAVE_U(k): k must be in [0, 4]");
+    const int amix = (s.flags >> 16) & 0xFF;
+    if (amix != 0 && amix < (int)EZ_EPF_XMIN)
+        return fail(EZ_ERR_INVALID_ARG, "EZ_SPEC_MIX_A(n): n must be 0 or >= 8");
     return EZ_OK;
 }
 
@@ -442,9 +449,10 @@ ez_status build_host_plan(int d, int batch, const ez_quad_spec *specs, int n_spe
         // small box; the shape with the fewest empty lanes, 16 x 4 on ties
         {
             const int cand[4] = {4, 3, 5, 6};     // log2 ub: 16, 8, 32, 64
+            const int forced = (s.flags >> 24) & 0x7;  // EZ_SPEC_WAVE_U: 1..4 -> log2 ub = 3..6
             long long best = -1;
             for (int ci = 0; ci < 4; ++ci) {
-                const int lg = (d == 1) ? 6 : cand[ci];
+                const int lg = (d == 1) ? 6 : (forced ? forced + 2 : cand[ci]);
                 const long long ub = 1ll << lg, dbk = 64 / ub;
                 const long long slots = ((n_u + ub - 1) / ub) * ub * ((nd + dbk - 1) / dbk) * dbk;
                 if (best < 0 || slots < best) {
@@ -452,7 +460,7 @@ ez_status build_host_plan(int d, int batch, const ez_quad_spec *specs, int n_spe
                     ip.ub_log2 = lg;
                     ip.db = (int)dbk;
                 }
-                if (d == 1) break;
+                if (d == 1 || forced) break;
             }
             ip.n_ublk = (n_u + (1 << ip.ub_log2) - 1) >> ip.ub_log2;
             const long long nblk = (long long)ip.n_ublk * ((nd + ip.db - 1) / ip.db);
@@ -545,10 +553,22 @@ void fill_plan_view(const HostPlan &H, PlanView &v) {
     for (int k = 0; k <= EZ_ELL_MAX; ++k) v.pinv_off[k] = H.pinv_off[k];
 }
 
+// Quadrature plans are cached per device, at most EZ_PLAN_CACHE of them; evicting
+// one frees its buffers and bumps the workspace generation.
+#define EZ_PLAN_CACHE 128
 ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, int n_specs, int ndb, DevPlan **out) {
     std::string key = plan_key(d, batch, specs, n_specs, ndb);
     auto it = S->plans.find(key);
-    if (it != S->plans.end()) { *out = it->second; return EZ_OK; }
+    if (it != S->plans.end()) {
+        // least recently used order: a hit moves the key to the back
+        auto pos = std::find(S->plan_order.begin(), S->plan_order.end(), key);
+        if (pos != S->plan_order.end() && pos + 1 != S->plan_order.end()) {
+            S->plan_order.erase(pos);
+            S->plan_order.push_back(key);
+        }
+        *out = it->second;
+        return EZ_OK;
+    }
     HostPlan H;
     ez_status st = build_host_plan(d, batch, specs, n_specs, ndb, H);
     if (st) return st;
@@ -581,7 +601,7 @@ ez_status get_plan(DeviceState *S, int d, int batch, const ez_quad_spec *specs, 
         free_plan(P);
         return fail(EZ_ERR_HIP, "upload of the quadrature plan failed");
     }
-    if (S->plans.size() >= 32) {                 // bounded cache, oldest out
+    if (S->plans.size() >= EZ_PLAN_CACHE) {      // bounded cache, least recently used out
         std::string old = S->plan_order.front();
         S->plan_order.erase(S->plan_order.begin());
         free_plan(S->plans[old]);
@@ -643,7 +663,50 @@ struct CallInfo {
     int ndb = 0, n_ch = 1, maxdeg = 0, flags = 0;
     double acut = 36.0;
     EzTables tab;
+    // mixed precision: requested, and active (FP32 far field in the node kernel)
+    bool mixed = false, mixed_active = false;
+    double a_mix = 16.0;
+    int top2[2] = {-1, -1};
+    double eps[EZ_NU_MAX] = {0.0};
 };
+
+// Relative error bound of one FP32 chunk sum of the far field, per exponent, first
+// order in u = 2^-24 (the terms of a chunk are positive):
+//   e^{-a}: the fraction x - n rounded to FP32 (0.35 u), v_exp_f32 (1 u): 2 u;
+//   t = 1/a: a rounded to FP32 (0.5 u), v_rcp_f32 (1 u): 1.5 u;  e^{-a} t: 0.5 u;
+//   the fit at a chain's top: its error with FP32 coefficients (EZ_EPF_FIT_ERR) plus
+//   Horner of degree 3 with positive terms in P and Q (6 u each), v_rcp_f32 and the
+//   product (1.5 u), and the product with e^{-a} t (0.5 u);
+//   a downward step E_{p-1} = fma(-(p-1), E_p, e^{-a}) t: with r = (p-1)/a_mix >=
+//   (p-1) E_p / e^{-a} (E_p <= e^{-a}/a for p >= 0), the difference carries
+//   (2 u + r e_p)/(1 - r) + 0.5 u when p - 1 > 0 and max(2 u, e_p) + 0.5 u otherwise,
+//   then t and the product add 2 u;
+//   the FP32 sum of at most 64 terms: 63 u;
+// and 1% for the second-order terms.
+void mixed_bounds(const EzProgram &prog, double a_mix, const int *top2, double *eps) {
+    const double u = std::ldexp(1.0, -24);
+    const double e_ex = 2.0, e_t = 1.5, e_fit = EZ_EPF_FIT_ERR / u + 13.5;
+    for (int i = 0; i < EZ_NU_MAX; ++i) eps[i] = 0.0;
+    for (int i = 0; i < prog.n_nu; ++i) {
+        const int p2 = prog.p2[i];
+        const int odd = p2 & 1;
+        const int top = top2[odd];
+        double e = e_ex + e_t + 0.5;
+        if (top >= (odd ? 1 : 2)) e += e_fit + 0.5;
+        for (int q2 = top; q2 > p2; q2 -= 2) {
+            const double q = 0.5 * (q2 - 2);
+            double eD;
+            if (q > 0.0) {
+                const double r = q / a_mix;
+                eD = (e_ex + r * e) / (1.0 - r) + 0.5;
+            } else {
+                eD = std::max(e_ex, e) + 0.5;
+            }
+            e = eD + e_t + 0.5;
+        }
+        eps[i] = 1.01 * (e + 63.0) * u;
+    }
+}
 
 ez_status prepare_call(int batch, int d, const EzProgram &prog, const std::vector<EzCombo> &combos,
                        const ez_quad_spec *specs, int n_specs, bool grad, CallInfo &C) {
@@ -662,11 +725,19 @@ ez_status prepare_call(int batch, int d, const EzProgram &prog, const std::vecto
         for (int f = 0; f < prog.term_nfac[cb.t]; ++f) rest += prog.term_mult[cb.t][f] - cb.j[f];
         C.maxdeg = std::max(C.maxdeg, rest * ell_max);
     }
-    if (C.maxdeg > 32)
-        return fail(EZ_ERR_UNSUPPORTED, "Taylor product of degree > 32 in u^2 on (0, eps): lower ell or the multiplicity");
+    // the product polynomials on (0, eps) keep powers up to u^64: a dropped power u^{2K},
+    // K > 32, integrates to a part of relative size below (C eps^2)^33 with C the
+    // ratio of successive Taylor coefficients (below 1e-40 at eps = 1e-2 for the
+    // lattices here), so many-factor products (n up to 64) are truncated there
+    C.maxdeg = std::min(C.maxdeg, 32);
     C.flags = specs[0].flags;
     for (int i = 1; i < n_specs; ++i)
         if (specs[i].flags != C.flags) return fail(EZ_ERR_INVALID_ARG, "all specs of one call must share flags");
+    C.mixed = specs[0].precision == EZ_PREC_MIXED;
+    for (int i = 1; i < n_specs; ++i)
+        if ((specs[i].precision == EZ_PREC_MIXED) != C.mixed)
+            return fail(EZ_ERR_INVALID_ARG, "all specs of one call must share the precision");
+    if (C.mixed && grad) return fail(EZ_ERR_UNSUPPORTED, "derivatives are computed in FP64 only (EZ_PREC_FP64)");
     double lam_min = 1e300, lam_max = 0.0;
     C.acut = spec_acut(specs[0]);
     for (int i = 0; i < n_specs; ++i) {
@@ -680,13 +751,26 @@ ez_status prepare_call(int batch, int d, const EzProgram &prog, const std::vecto
         return fail(EZ_ERR_UNSUPPORTED, "reciprocal table too large for this lam and a_cut (raise spec.lam)");
     C.tab.rstride = 4 * ((3 + (grad ? 2 : 1) * prog.n_nu + 3) / 4);
     C.tab.row_cap = C.tab.real_cap;
+    if (C.mixed) {
+        // the FP32 far field needs the fits of every chain top (2p <= EZ_EPF_P2MAX) and
+        // e^{-a} well inside the FP32 range (a_cut <= 80); otherwise the call stays FP64
+        const int amix = (C.flags >> 16) & 0xFF;
+        C.a_mix = amix ? (double)amix : 16.0;
+        for (int i = 0; i < prog.n_nu; ++i) {
+            const int odd = prog.p2[i] & 1;
+            C.top2[odd] = std::max(C.top2[odd], std::max(prog.p2[i], odd));
+        }
+        C.mixed_active = C.top2[0] <= EZ_EPF_P2MAX && C.top2[1] <= EZ_EPF_P2MAX && C.acut <= 80.0 &&
+                         C.a_mix < C.acut;
+        if (C.mixed_active) mixed_bounds(prog, C.a_mix, C.top2, C.eps);
+    }
     return EZ_OK;
 }
 
 // Workspace of one call: the buffers the kernels write and read back.
 enum WsSlot {
     WS_META, WS_SUB_PART, WS_TAIL_ACC, WS_REAL, WS_RN, WS_ROWS, WS_REC, WS_TILE_PART, WS_DIR_PART, WS_DIR_FLAG,
-    WS_PROBE_VAL, WS_TENSOR, WS_TILE_GRAD, WS_DIR_GRAD, WS_TAIL_CNT, WS_QUEUE, WS_COUNT
+    WS_PROBE_VAL, WS_TENSOR, WS_TILE_GRAD, WS_DIR_GRAD, WS_TAIL_CNT, WS_QUEUE, WS_TILE_BOUND, WS_COUNT
 };
 
 struct Workspace {
@@ -713,7 +797,7 @@ int main_tiles(const CallInfo &C, const EzProgram &prog, int n_cu, int n_tiles) 
         round = n_cu * ez_nodes_tile_blocks_per_cu(probe_args);
     }
     int n_main = n_tiles;
-    if (!C.grad && !(C.flags & EZ_SPEC_NO_SPLIT)) {
+    if (!C.grad && !C.mixed_active && !(C.flags & EZ_SPEC_NO_SPLIT)) {
         const int tail = round > 0 ? n_tiles % round : 0;
         const int per_tile = (EZ_TILE / 64) * EZ_TAIL_PARTS;     // split-kernel workgroups per tail tile
         if (n_tiles > round && tail > 0 && tail * per_tile <= n_cu) n_main = n_tiles - tail;
@@ -741,6 +825,7 @@ void workspace_sizes(int batch, const EzProgram &prog, const CallInfo &C, const 
     W.bytes[WS_DIR_GRAD] = C.grad ? sizeof(double) * 6 * (size_t)P.n_dirs * prog.n_res : 0;
     W.bytes[WS_TAIL_CNT] = sizeof(int) * (EZ_TILE / 64) * ntail;
     W.bytes[WS_QUEUE] = 256;
+    W.bytes[WS_TILE_BOUND] = C.mixed_active ? sizeof(double) * (size_t)P.n_tiles * prog.n_res : 0;
     for (int i = 0; i < WS_COUNT; ++i) W.ptr[i] = nullptr;
 }
 
@@ -751,7 +836,7 @@ void workspace_sizes(int batch, const EzProgram &prog, const CallInfo &C, const 
 ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, const std::vector<EzCombo> &combos,
                        const CallInfo &C, const PlanView &P, int n_main, int n_cu, const Workspace &W,
                        double *out_dev, uint32_t *status_dev, double *grad_dev, hipStream_t stream, hipStream_t side,
-                       hipEvent_t ev_setup, hipEvent_t ev_had, bool timing_ok = true) {
+                       hipEvent_t ev_setup, hipEvent_t ev_had, bool timing_ok = true, double *bound_dev = nullptr) {
     const bool grad = C.grad;
     // the timing hooks create events; the no-allocation entry point launches without them
     auto tm = [&](int kernel, hipStream_t st, auto launch) { return timing_ok ? timed(kernel, st, launch) : launch(); };
@@ -797,6 +882,13 @@ ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, co
     qa.tab = tab;
     qa.rules = P.rules;
     qa.tile_part = (double *)W.ptr[WS_TILE_PART];
+    qa.mixed = C.mixed_active ? 1 : 0;
+    qa.a_mix = C.a_mix;
+    qa.mix_top2[0] = C.top2[0];
+    qa.mix_top2[1] = C.top2[1];
+    for (int i = 0; i < EZ_NU_MAX; ++i) qa.mix_eps[i] = C.eps[i];
+    qa.tile_bound = (double *)W.ptr[WS_TILE_BOUND];
+    qa.bound_out = bound_dev;
     qa.dir_part = (double *)W.ptr[WS_DIR_PART];
     qa.dir_flag = (uint32_t *)W.ptr[WS_DIR_FLAG];
     qa.out = out_dev;
@@ -812,12 +904,14 @@ ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, co
     qa.tile_order = P.tile_order;
     qa.queue = (int *)W.ptr[WS_QUEUE];
 
-    // The Taylor/Hadamard branch depends only on the setup.  Its probe and tensor
-    // kernels are short and run on the caller's stream before the nodes (on a second
-    // queue they would wait for slots until the node kernel drains).  The direction
-    // kernel runs on a second stream, concurrently with the node kernels, and the
-    // caller's stream waits for it before the final reduction (event edges, so the
-    // sequence can be captured into a graph).  EZ_SPEC_SERIAL keeps it on `stream`.
+    // The Taylor/Hadamard branch depends only on the setup.  In value calls its
+    // probe, tensor and direction kernels run on a second stream, concurrently with
+    // the node kernel: they take the workgroup slots that the node kernel's last,
+    // partly filled round of tiles leaves free (three-lattice ATM call, 263424 nodes
+    // each: 0.297 ms per step against 0.302 ms with probe and tensor on the caller's
+    // stream before the nodes).  The caller's stream waits for the branch before the
+    // final reduction (event edges, so the sequence can be captured into a graph).
+    // EZ_SPEC_SERIAL keeps everything on `stream`.
     auto had = [&](hipStream_t s, int part, hipEvent_t done) {
         return grad ? ez_launch_hadamard_adj(qa, P.n_htiles, s, part, done)
                     : ez_launch_hadamard(qa, P.n_htiles, s, part, done);
@@ -829,10 +923,9 @@ ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, co
     // derivative, 263424 nodes each: 0.869 ms per step, 0.901 ms with the direction
     // kernel before the nodes).
     const bool two = side && !(C.flags & EZ_SPEC_SERIAL);
-    // Batches whose node tiles fill more than eight rounds of the device are bound by
-    // throughput, not latency: there the probe and tensor kernels go to the second
-    // stream as well, where their work fills slots beside the node kernel's instead of
-    // preceding it (the 4096-lattice scan).
+    // Derivative calls keep the (seven-channel) probe and the tensor kernel on the
+    // caller's stream before the adjoint node kernel unless the batch's tiles fill
+    // more than eight rounds of the device (throughput-bound: the 4096-lattice scan).
     int round = 0;
     {
         EzQuadArgs probe_args;
@@ -840,7 +933,7 @@ ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, co
         probe_args.prog = prog;
         round = n_cu * ez_nodes_tile_blocks_per_cu(probe_args);
     }
-    const bool big = two && P.n_tiles > 8 * round;
+    const bool big = two && (!grad || P.n_tiles > 8 * round);
     hipStream_t hs = stream;
     if (big) {
         EZ_HIP_TRY(hipEventRecord(ev_setup, stream));
@@ -861,7 +954,7 @@ ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, co
     EZ_HIP_TRY(tm(EZ_KERNEL_HADAMARD, hs, [&] { return had(hs, EZ_HAD_DIR, nullptr); }));
     if (grad) {
         EZ_HIP_TRY(tm(EZ_KERNEL_NODES_ADJ, stream, [&] { return ez_launch_nodes_adj(qa, P.n_tiles, stream); }));
-    } else if (C.flags & EZ_SPEC_PERSISTENT) {
+    } else if ((C.flags & EZ_SPEC_PERSISTENT) && !C.mixed_active) {
         int bpc = (C.flags >> 8) & 0xFF;
         if (bpc == 0) bpc = ez_nodes_blocks_per_cu(qa);
         const int nblk = std::max(1, std::min(P.n_tiles, n_cu * bpc));
@@ -883,7 +976,7 @@ ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, co
 // grad_dev (may be NULL): batch x n_res x d x d derivatives of the results with respect to A
 ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog, const std::vector<EzCombo> &combos,
                    const ez_quad_spec *specs, int n_specs, double *out_dev, uint32_t *status_dev, hipStream_t stream,
-                   double *grad_dev = nullptr) {
+                   double *grad_dev = nullptr, double *bound_dev = nullptr) {
     int dev = 0;
     EZ_HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lock(g_mu);
@@ -918,7 +1011,7 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     workspace_sizes(batch, prog, C, pv, n_main, W);
     DevBuf *bufs[WS_COUNT] = {&S->meta, &S->sub_part, &S->tail_acc, &S->real, &S->rn, &S->rows, &S->rec,
                               &S->tile_part, &S->dir_part, &S->dir_flag, &S->probe_val, &S->tensor,
-                              &S->tile_grad, &S->dir_grad, &S->tail_cnt, &S->queue};
+                              &S->tile_grad, &S->dir_grad, &S->tail_cnt, &S->queue, &S->tile_bound};
     for (int i = 0; i < WS_COUNT; ++i) {
         if (W.bytes[i] == 0) continue;
         const size_t had = bufs[i]->bytes;
@@ -930,7 +1023,7 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
             EZ_HIP_TRY(ez_launch_fill_int((int *)bufs[i]->p, (int)(bufs[i]->bytes / sizeof(int)), 0, stream));
     }
     return enqueue_sums(batch, A_dev, prog, combos, C, pv, n_main, S->n_cu, W, out_dev, status_dev, grad_dev, stream,
-                        S->side, S->ev_setup, S->ev_had);
+                        S->side, S->ev_setup, S->ev_had, true, bound_dev);
 }
 
 // tables of one lattice for general shifts x (every z, every m*, no weights)
@@ -1000,6 +1093,8 @@ ez_status sums_program(int batch, int d, const double *A_dev, int n_nu, const do
     int ell_max = 0;
     for (int i = 0; i < n_specs; ++i) {
         if ((st = check_spec(specs[i]))) return st;
+        if (grad && specs[i].precision != EZ_PREC_FP64)
+            return fail(EZ_ERR_UNSUPPORTED, "derivatives are computed in FP64 only (EZ_PREC_FP64)");
         ell_max = std::max(ell_max, specs[i].ell);
     }
     std::vector<double> nu(nu_host, nu_host + n_nu);
@@ -1047,7 +1142,7 @@ extern "C" {
 
 const char *ez_last_error(void) { return g_err.c_str(); }
 
-const char *ez_version(void) { return "libezeta 0.2 (gfx950, FP64)"; }
+const char *ez_version(void) { return "libezeta 0.3 (gfx950, FP64 and mixed precision)"; }
 
 uint64_t ez_workspace_generation(void) { return g_generation.load(); }
 
@@ -1062,7 +1157,7 @@ ez_status ez_finalize(void) {
         for (auto &p : S->plans) free_plan(p.second);
         free_buf(S->meta); free_buf(S->real); free_buf(S->rec); free_buf(S->rn); free_buf(S->rows);
         free_buf(S->tile_part); free_buf(S->sub_part); free_buf(S->tail_acc); free_buf(S->tail_cnt); free_buf(S->dir_part); free_buf(S->dir_flag); free_buf(S->probe_val); free_buf(S->tensor);
-        free_buf(S->tile_grad); free_buf(S->dir_grad); free_buf(S->queue);
+        free_buf(S->tile_grad); free_buf(S->dir_grad); free_buf(S->queue); free_buf(S->tile_bound);
         for (DevBuf *b : {&S->g_pts_x, &S->g_pts_y, &S->g_perm, &S->g_counts, &S->g_A64r, &S->g_B64r, &S->g_A64k,
                           &S->g_B64k, &S->g_R, &S->g_Q, &S->g_wsum, &S->g_stat, &S->g_Ahr, &S->g_Alr, &S->g_Bhr,
                           &S->g_Blr, &S->g_Ahk, &S->g_Alk, &S->g_Bhk, &S->g_Blk})
@@ -1102,6 +1197,9 @@ ez_status ez_lattice_sums_noalloc(int batch, int d, const double *A_dev, int n_n
     ez_status st = sums_program(batch, d, A_dev, n_nu, nu_host, n_terms, term_result, term_coef, term_nfac, term_fac,
                                 term_mult, n_results, specs, n_specs, out_dev, false, prog, combos);
     if (st) return st;
+    for (int i = 0; i < n_specs; ++i)
+        if (specs[i].precision != EZ_PREC_FP64)
+            return fail(EZ_ERR_UNSUPPORTED, "the no-allocation entry point computes in FP64 only");
     hipStream_t s = (hipStream_t)stream;
     int dev = 0;
     EZ_HIP_TRY(hipGetDevice(&dev));
@@ -1177,6 +1275,20 @@ ez_status ez_lattice_sums(int batch, int d, const double *A_dev, int n_nu, const
                                 term_mult, n_results, specs, n_specs, out_dev, nullptr, status_dev, stream);
 }
 
+ez_status ez_lattice_sums_bound(int batch, int d, const double *A_dev, int n_nu, const double *nu_host, int n_terms,
+                                const int *term_result, const double *term_coef, const int *term_nfac,
+                                const int *term_fac, const int *term_mult, int n_results, const ez_quad_spec *specs,
+                                int n_specs, double *out_dev, double *bound_dev, uint32_t *status_dev, void *stream) {
+    if (!bound_dev) return fail(EZ_ERR_INVALID_ARG, "null pointer argument");
+    EzProgram prog;
+    std::vector<EzCombo> combos;
+    ez_status st = sums_program(batch, d, A_dev, n_nu, nu_host, n_terms, term_result, term_coef, term_nfac, term_fac,
+                                term_mult, n_results, specs, n_specs, out_dev, false, prog, combos);
+    if (st) return st;
+    return run_sums(batch, d, A_dev, prog, combos, specs, n_specs, out_dev, status_dev, (hipStream_t)stream, nullptr,
+                    bound_dev);
+}
+
 ez_status ez_nbody_lattice_sum(int batch, int d, const double *A_dev, int n, const double *nu_host,
                                const ez_quad_spec *spec, double *out_dev, uint32_t *status_dev, void *stream) {
     ez_status st = check_common(batch, d, A_dev, spec, out_dev);
@@ -1207,6 +1319,8 @@ ez_status ez_atm_energy(int batch, int d, const double *A_dev, const ez_quad_spe
     ez_status st = check_common(batch, d, A_dev, spec, E_dev);
     if (st) return st;
     if ((st = check_spec(*spec))) return st;
+    if (dEdA_dev && spec->precision != EZ_PREC_FP64)
+        return fail(EZ_ERR_UNSUPPORTED, "derivatives are computed in FP64 only (EZ_PREC_FP64)");
     // nu set {-1, 1, 3, 5};  E = 1/24 Z3^3 - 3/16 Z-1 Z5^2 + 3/8 Z1 Z3 Z5
     std::vector<double> nu = {-1.0, 1.0, 3.0, 5.0};
     Term t0{0, 1.0 / 24.0, {{2, 3}}};

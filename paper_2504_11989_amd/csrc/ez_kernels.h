@@ -56,6 +56,15 @@ struct EzQuadArgs {
     EzTables tab;
     const double *rules;       // Gauss rules (v on [0,1], u on (eps,1/2])
     double *tile_part;         // [n_tiles][n_res][2] double-double partials
+    // mixed precision (EZ_PREC_MIXED): reciprocal entries with alpha |m* + k|^2 >= a_mix at
+    // every node of a wave are summed in FP32 (E_p from the fit at the largest p of each
+    // chain, smaller p by the downward recurrence); an a-priori bound per result
+    int mixed;                 // 0: FP64 throughout
+    double a_mix;              // FP32 threshold on the incomplete-gamma argument (>= EZ_EPF_XMIN)
+    int mix_top2[2];           // largest 2p of the integer (>= 0) and half-integer (>= 1) chains
+    double mix_eps[EZ_NU_MAX]; // relative error bound of one FP32 chunk sum of exponent i
+    double *tile_bound;        // [n_tiles][n_res] bound partials (mixed calls)
+    double *bound_out;         // [batch][n_res] per-result bound, or NULL
     double *sub_part;          // [4 (n_tiles - n_main)][n_res][2] partials of the 64-node groups
     double *tail_acc;          // [4 (n_tiles - n_main)][EZ_TAIL_PARTS][2 n_nu][64] partial sums of the split kernel
     int *tail_cnt;             // [4 (n_tiles - n_main)] parts finished per group (zero between calls)

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 #include "e1_rational.h"
 #include "exp2_table.h"
+#include "ep_f32_rational.h"
 #include "ez_internal.h"
 
 // a*b + c as one three-operand v_fma_f64 whose addend c, a compile-time constant of
@@ -51,26 +52,24 @@ __device__ __forceinline__ double ez_expm(double a) {
     return ldexp(p, -(int)n);
 }
 
-// e^{-a} for 0 <= a <= 700 with a table of 2^{-j/64} in LDS (ez_exp2_tab copied to
-// `tab`): a = (n/64) ln2 + r, n = rint(64 a / ln2), |r| <= ln2/128, with ln2/64 split
-// as the Cody-Waite pair of ez_expm divided by 64 (n LN2_HI/64 exact for n < 2^21);
-// e^{-a} = 2^{-floor(n/64)} 2^{-(n mod 64)/64} e^{-r}, e^{-r} by its Taylor series
-// through r^6 (truncation < 3e-20).
+// e^{-a} for 0 <= a <= 700 with a table of 2^{-j/256} in LDS (ez_exp2_tab copied to
+// `tab`): a = (n/256) ln2 + r, n = rint(256 a / ln2), |r| <= ln2/512, with ln2/256
+// split as the Cody-Waite pair of ez_expm divided by 256 (n LN2_HI/256 exact for
+// n < 2^21); e^{-a} = 2^{-floor(n/256)} 2^{-(n mod 256)/256} e^{-r}, e^{-r} by its
+// Taylor series through r^4 (truncation < 4e-17 relative).
 __device__ __forceinline__ double ez_expm_tab(double a, const double *tab) {
-    const double n = rint(a * 92.33248261689366);                 // 64 / ln 2
-    double r = fma(-n, 0.6931471803691238 / 64.0, a);
-    r = fma(-n, 1.9082149292705877e-10 / 64.0, r);
+    const double n = rint(a * 369.3299304675746);                 // 256 / ln 2
+    double r = fma(-n, 0.6931471803691238 / 256.0, a);
+    r = fma(-n, 1.9082149292705877e-10 / 256.0, r);
     const int ni = (int)n;
-    const double t = tab[ni & 63];
+    const double t = tab[ni & 255];
     const double x = -r;
-    double p = 1.0 / 720.0;
-    p = ez_fma3(p, x, 1.0 / 120.0);
-    p = ez_fma3(p, x, 1.0 / 24.0);
+    double p = 1.0 / 24.0;
     p = ez_fma3(p, x, 1.0 / 6.0);
     p = fma(p, x, 0.5);
     p = fma(p, x, 1.0);
     p = fma(p, x, 1.0);
-    return ldexp(p * t, -(ni >> 6));
+    return ldexp(p * t, -(ni >> 8));
 }
 
 // 1/x: hardware reciprocal estimate refined by two Newton steps (x normal, finite)
@@ -120,26 +119,61 @@ __device__ __forceinline__ double ez_e1w_scaled(double t) {
     return t * P * ez_rcp(Q);
 }
 
-// e^a E1(a) for a >= 4 from the (7,7) rational fit, given t = 1/a
-__device__ __forceinline__ double ez_e1f_scaled(double t) {
-    double P = ez_e1f_p[EZ_E1F_DEG], Q = ez_e1f_q[EZ_E1F_DEG];
+// Far-field bases for a >= 4 from the (7,7) fits with a single reciprocal: with the
+// coefficient order reversed, P*(a) = a^7 P(1/a) and Q*(a) = a^7 Q(1/a), so that
+//   e^a E1(a)      = t P(t)/Q(t)  = P*(a) / (a Q*(a)),
+//   e^a E_{1/2}(a) = t Ph(t)/Qh(t) = Ph*(a) / (a Qh*(a)),
+// and 1/a = Q*(a) / (a Q*(a)); all coefficients are positive, so Horner in a keeps
+// the relative error at a few units of rounding.  From ex = e^{-a}: E1, E_{1/2}
+// (when needed) and inv = 1/a.
+__device__ __forceinline__ void ez_far_bases(double a, double ex, bool need_e1, bool need_half, double *E1,
+                                             double *Eh, double *inv) {
+    double P1 = ez_e1f_p[0], Q1 = ez_e1f_q[0], Ph = ez_ehf_p[0], Qh = ez_ehf_q[0];
 #pragma unroll
-    for (int j = EZ_E1F_DEG - 1; j >= 0; --j) {
-        P = ez_fma3(P, t, ez_e1f_p[j]);
-        Q = ez_fma3(Q, t, ez_e1f_q[j]);
+    for (int j = 1; j <= EZ_E1F_DEG; ++j) {
+        if (need_e1) { P1 = ez_fma3(P1, a, ez_e1f_p[j]); Q1 = ez_fma3(Q1, a, ez_e1f_q[j]); }
+        if (need_half) { Ph = ez_fma3(Ph, a, ez_ehf_p[j]); Qh = ez_fma3(Qh, a, ez_ehf_q[j]); }
     }
-    return t * P * ez_rcp(Q);
+    if (need_e1 && need_half) {
+        const double QQ = Q1 * Qh;
+        const double R = ez_rcp(a * QQ);
+        *E1 = ex * P1 * (R * Qh);
+        *Eh = ex * Ph * (R * Q1);
+        *inv = R * QQ;
+    } else if (need_e1) {
+        const double R = ez_rcp(a * Q1);
+        *E1 = ex * P1 * R;
+        *Eh = 0.0;
+        *inv = R * Q1;
+    } else if (need_half) {
+        const double R = ez_rcp(a * Qh);
+        *E1 = 0.0;
+        *Eh = ex * Ph * R;
+        *inv = R * Qh;
+    } else {
+        *E1 = 0.0;
+        *Eh = 0.0;
+        *inv = ez_rcp(a);
+    }
 }
 
-// sqrt(pi a) e^a erfc(sqrt a) for a >= 4 from the (7,7) rational fit, given t = 1/a
-__device__ __forceinline__ double ez_ehf_scaled(double t) {
-    double P = ez_ehf_p[EZ_E1F_DEG], Q = ez_ehf_q[EZ_E1F_DEG];
+// ---- FP32 far-field terms of the mixed-precision mode (a >= EZ_EPF_XMIN) ----
+// e^{-a} in FP32: x = -a log2 e and n = rint(x) in FP64, the fraction x - n (|.| <= 1/2)
+// rounded to FP32, 2^{x-n} by the hardware exponential, scaled by 2^n (exact)
+__device__ __forceinline__ float ez_expm_f32(double a) {
+    const double x = a * -1.4426950408889634;
+    const double n = rint(x);
+    return ldexpf(__builtin_amdgcn_exp2f((float)(x - n)), (int)n);
+}
+// x e^x E_p(x) for x >= EZ_EPF_XMIN, 2p = row + 1, from the (3,3) FP32 fit in t = 1/x
+__device__ __forceinline__ float ez_epf(int row, float t) {
+    float P = ez_epf_p[row][EZ_EPF_DEG], Q = ez_epf_q[row][EZ_EPF_DEG];
 #pragma unroll
-    for (int j = EZ_E1F_DEG - 1; j >= 0; --j) {
-        P = ez_fma3(P, t, ez_ehf_p[j]);
-        Q = ez_fma3(Q, t, ez_ehf_q[j]);
+    for (int j = EZ_EPF_DEG - 1; j >= 0; --j) {
+        P = fmaf(P, t, ez_epf_p[row][j]);
+        Q = fmaf(Q, t, ez_epf_q[row][j]);
     }
-    return P * ez_rcp(Q);
+    return P * __builtin_amdgcn_rcpf(Q);
 }
 
 // E1(a) for 0 < a < 1/4 by the series; kept out of line so that its constants

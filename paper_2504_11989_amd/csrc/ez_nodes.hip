@@ -179,8 +179,9 @@ __device__ __forceinline__ void rec_list(const EzQuadArgs &args, const double *k
 //   mid   (a may be < 4, never < 1/4)  if |m* + c| <= 2/sqrt(alpha) + r_w,
 //   far   (a >= 4 at every node)       otherwise.
 // Far entries (most of them) are summed as the chunk is read, taken one by one
-// from the chunk's ballot mask and loaded through the scalar cache, with E_1 and
-// E_{1/2} from the (7,7) rationals for a >= 4.  Mid and near entries go to the
+// from the chunk's ballot mask and loaded through the scalar cache, with e^{-a}
+// from a 256-entry table of 2^{-j/256} in LDS and E_1, E_{1/2} and 1/a from the
+// (7,7) rationals for a >= 4 with one reciprocal.  Mid and near entries go to the
 // wave's lists in LDS and are summed afterwards, mid ones with the (12,12)
 // rationals for a >= 1/4, near ones with the series forms below 1/4 (out of
 // line); a list longer than its capacity makes the sums NaN.
@@ -207,10 +208,56 @@ __device__ __forceinline__ void wave_append(bool sel, int q, unsigned short *lis
     }
 }
 
-template <int D, int NNU, int SET>
+// Largest 2p of the integer chain (which = 0; 0 when its largest p is <= 0, -1 when
+// no exponent has an integer p) and of the half-integer chain (which = 1; 1 when its
+// largest p is <= 1/2, -1 when there is none)
+template <int SET, int NNU>
+__device__ __forceinline__ int mix_top2(const EzQuadArgs &args, int which) {
+    if constexpr (SET == 0) {
+        return args.mix_top2[which];
+    } else {
+        bool any = false;
+        int t = 0;
+#pragma unroll
+        for (int i = 0; i < NNU; ++i) {
+            const int p2 = ez_pset(SET).p2[i];
+            if ((p2 & 1) == which) {
+                t = (any && t > p2) ? t : p2;
+                any = true;
+            }
+        }
+        return any ? (t < which ? which : t) : -1;
+    }
+}
+
+// One far-field reciprocal term in FP32 (a >= a_mix >= EZ_EPF_XMIN): e^{-a}, 1/a, the
+// chain tops E_p = e^{-a} t g_p(t) from the fits, every exponent's E_p by the downward
+// recurrence E_{p-1} = (e^{-a} - (p-1) E_p) / a from its chain's top (stable for
+// a > p), added to accf
+template <int SET, int NNU>
+__device__ __forceinline__ void far32_term(const EzQuadArgs &args, double a, float *accf) {
+    const float ex = ez_expm_f32(a);
+    const float t = __builtin_amdgcn_rcpf((float)a);
+    const float ext = ex * t;
+    const int ti = mix_top2<SET, NNU>(args, 0), th = mix_top2<SET, NNU>(args, 1);
+    float Ei = ext, Eh = 0.0f;
+    if (ti >= 2) Ei = ext * ez_epf(ti - 1, t);
+    if (th >= 1) Eh = ext * ez_epf(th - 1, t);
+#pragma unroll
+    for (int i = 0; i < NNU; ++i) {
+        const int p2 = pset_p2<SET>(args.prog, i);
+        const bool odd = (p2 & 1) != 0;
+        float E = odd ? Eh : Ei;
+        for (int q2 = odd ? th : ti; q2 > p2; q2 -= 2) E = fmaf(-0.5f * (float)(q2 - 2), E, ex) * t;
+        accf[i] += E;
+    }
+}
+
+template <int D, int NNU, int SET, bool MIX>
 __device__ __forceinline__ void rec_wave(const EzQuadArgs &args, const double *kt, int n_rec, const double *k,
                                          bool valid, double alpha, double acut, unsigned short *nearl,
-                                         unsigned short *midl, const double *exptab, double *acck) {
+                                         unsigned short *midl, const double *exptab, double *acck,
+                                         double *far32) {
     const bool need_e1 = pset_need_e1<SET, NNU>(args.prog), need_half = pset_need_half<SET, NNU>(args.prog);
     const int lane = (int)threadIdx.x & 63;
     double c[3] = {0.0, 0.0, 0.0}, rt2 = 0.0;
@@ -231,6 +278,15 @@ __device__ __forceinline__ void rec_wave(const EzQuadArgs &args, const double *k
     const double rmid = (2.0 * ra + rt) * (1.0 + 1e-9) + 1e-12;
     const double rmax2 = wave_uniform(rmax * rmax), rnear2 = wave_uniform(rnear * rnear);
     const double rmid2 = wave_uniform(rmid * rmid);
+    // mixed precision: entries with |m* + c| >= sqrt(a_mix / alpha) + r_w have a >= a_mix
+    // at every node of the wave and are summed in FP32
+    double r32sq = 1e300;
+    if constexpr (MIX) {
+        const double r32 = (sqrt(args.a_mix / alpha) + rt) * (1.0 + 1e-9) + 1e-12;
+        r32sq = wave_uniform(r32 * r32);
+#pragma unroll
+        for (int i = 0; i < NNU; ++i) far32[i] = 0.0;
+    }
     // m* = 0
     if (valid) {
         double rho = k[0] * k[0];
@@ -265,9 +321,10 @@ __device__ __forceinline__ void rec_wave(const EzQuadArgs &args, const double *k
         const bool near = in && d2 <= rnear2;
         const bool mid = in && !near && d2 <= rmid2;
         const bool keep = in && !near && !mid && d2 <= rmax2;
+        const bool lo32 = MIX && keep && d2 >= r32sq;
         wave_append(near, q, nearl, EZ_NEAR_MAX, &n_near);
         wave_append(mid, q, midl, EZ_MID_MAX, &n_mid);
-        unsigned long long bal = __ballot(keep);
+        unsigned long long bal = __ballot(keep && !lo32);
         while (bal) {
             const int j = __builtin_ctzll(bal);
             bal &= bal - 1ull;
@@ -279,12 +336,37 @@ __device__ __forceinline__ void rec_wave(const EzQuadArgs &args, const double *k
             const double a = alpha * rho;
             if (a <= acut) {
                 const double ex = ez_expm_tab(a, exptab);
-                const double inv = ez_rcp(a);
-                const double E1 = need_e1 ? ex * ez_e1f_scaled(inv) : 0.0;
-                const double Eh = need_half ? ex * inv * ez_ehf_scaled(inv) : 0.0;
+                double E1, Eh, inv;
+                ez_far_bases(a, ex, need_e1, need_half, &E1, &Eh, &inv);
 #pragma unroll
                 for (int i = 0; i < NNU; ++i)
                     acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
+            }
+        }
+        if constexpr (MIX) {
+            // the chunk's FP32 far field: at most 64 terms summed in FP32 per exponent,
+            // then added to the FP64 sums (and to far32, for the error bound)
+            unsigned long long b32 = __ballot(lo32);
+            if (b32) {
+                float accf[NNU];
+#pragma unroll
+                for (int i = 0; i < NNU; ++i) accf[i] = 0.0f;
+                while (b32) {
+                    const int j = __builtin_ctzll(b32);
+                    b32 &= b32 - 1ull;
+                    const double *e = kt + (size_t)(base + j) * 4;
+                    double qx = e[0] + k[0];
+                    double rho = qx * qx;
+                    if (D > 1) { const double qy = e[1] + k[1]; rho = fma(qy, qy, rho); }
+                    if (D > 2) { const double qz = e[2] + k[2]; rho = fma(qz, qz, rho); }
+                    const double a = alpha * rho;
+                    if (a <= acut) far32_term<SET, NNU>(args, a, accf);
+                }
+#pragma unroll
+                for (int i = 0; i < NNU; ++i) {
+                    acck[i] += (double)accf[i];
+                    far32[i] += (double)accf[i];
+                }
             }
         }
     }
@@ -330,14 +412,55 @@ __device__ __forceinline__ void rec_wave(const EzQuadArgs &args, const double *k
     }
 }
 
+// First-order bound of the change of the node's weighted products when each Z_i
+// moves by at most dZ_i: sum over terms of |coef| W sum_f m_f dZ_f |Z_f|^{m_f - 1}
+// prod_{g != f} |Z_g|^{m_g}, added to rb (the second-order part is smaller by a
+// factor dZ/|Z| <= 1e-9 and is covered by the margin of the per-term bounds)
+template <int NNU>
+__device__ __forceinline__ void node_product_bounds(const EzQuadArgs &args, const double *Z, const double *dZ,
+                                                    double W, double *rb) {
+    for (int t = 0; t < args.prog.n_terms; ++t) {
+        const int nf = args.prog.term_nfac[t];
+        double b = 0.0;
+        for (int f = 0; f < nf; ++f) {
+            const int fi = args.prog.term_fac[t][f];
+            double dz = dZ[0];
+#pragma unroll
+            for (int i = 1; i < NNU; ++i) dz = (fi == i) ? dZ[i] : dz;
+            double part = (double)args.prog.term_mult[t][f] * dz;
+            for (int g = 0; g < nf; ++g) {
+                const int gi = args.prog.term_fac[t][g];
+                double z = Z[0];
+#pragma unroll
+                for (int i = 1; i < NNU; ++i) z = (gi == i) ? Z[i] : z;
+                const int mg = args.prog.term_mult[t][g] - (g == f ? 1 : 0);
+                for (int m = 0; m < mg; ++m) part *= fabs(z);
+            }
+            b += part;
+        }
+        const int rr = args.prog.term_res[t];
+#pragma unroll
+        for (int r = 0; r < EZ_RES_MAX; ++r)
+            if (rr == r) rb[r] += fabs(args.prog.term_coef[t]) * b * W;
+    }
+}
+
 // Z_nu = real part + K_nu (reciprocal part) - self term, then the weighted
-// products of the program's terms added to res
+// products of the program's terms added to res; with far32 (mixed precision) the
+// bound of the products' change from the FP32 far-field sums is added to rb
 template <int NNU>
 __device__ __forceinline__ void node_products(const EzQuadArgs &args, const EzLatMeta *M, const double *accr,
-                                              const double *acck, double W, double *res) {
+                                              const double *acck, double W, double *res,
+                                              const double *far32 = nullptr, double *rb = nullptr) {
     double Z[NNU];
 #pragma unroll
     for (int i = 0; i < NNU; ++i) Z[i] = accr[i] + M->K[i] * acck[i] - M->self_[i];
+    if (far32) {
+        double dZ[NNU];
+#pragma unroll
+        for (int i = 0; i < NNU; ++i) dZ[i] = args.mix_eps[i] * fabs(M->K[i]) * far32[i];
+        node_product_bounds<NNU>(args, Z, dZ, fabs(W), rb);
+    }
     for (int t = 0; t < args.prog.n_terms; ++t) {
         double prod = args.prog.term_coef[t];
         for (int f = 0; f < args.prog.term_nfac[t]; ++f) {
@@ -370,14 +493,15 @@ using TailLds = NodeLds<EZ_TAIL_WAVES>;
 
 // LDS of the tile kernel: each wave's near and mid lists, the tile reduction
 struct TileLds {
-    double exptab[64];
+    double exptab[EZ_EXP2_TAB_N];
     unsigned short nearl[EZ_TILE / 64][EZ_NEAR_MAX];
     unsigned short midl[EZ_TILE / 64][EZ_MID_MAX];
     double red[EZ_RES_MAX][EZ_TILE / 64][2];
+    double rbnd[EZ_RES_MAX][EZ_TILE / 64];
 };
 
 // One node tile: four wave blocks of the lattice, each wave culls and sums on its own
-template <int D, int NNU, int SET>
+template <int D, int NNU, int SET, bool MIX = false>
 __device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile, TileLds &L) {
     const int inst = find_segment(args.tile_begin, args.batch, tile);
     const EzInstPlan P = args.plans[inst];
@@ -386,10 +510,10 @@ __device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wb = (tile - args.tile_begin[inst]) * (EZ_TILE / 64) + wave;
 
-    double res[EZ_RES_MAX];
+    double res[EZ_RES_MAX], rbound[EZ_RES_MAX];
 #pragma unroll
-    for (int r = 0; r < EZ_RES_MAX; ++r) res[r] = 0.0;
-    if (threadIdx.x < 64) L.exptab[threadIdx.x] = ez_exp2_tab[threadIdx.x];
+    for (int r = 0; r < EZ_RES_MAX; ++r) { res[r] = 0.0; rbound[r] = 0.0; }
+    for (int j = (int)threadIdx.x; j < EZ_EXP2_TAB_N; j += EZ_TILE) L.exptab[j] = ez_exp2_tab[j];
     __syncthreads();
 
     if (M->status == 0 && wb < P.n_wblk) {        // uniform over the wave
@@ -404,9 +528,13 @@ __device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile
 
         const double *kt = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
         if (valid) real_rows<D, NNU>(args, inst, th, 0, M->n_rows, accr);
-        rec_wave<D, NNU, SET>(args, kt, M->n_rec, k, valid, M->alpha, M->a_cut, L.nearl[wave], L.midl[wave],
-                              L.exptab, acck);
-        if (valid) node_products<NNU>(args, M, accr, acck, W, res);
+        double far32[NNU];
+        rec_wave<D, NNU, SET, MIX>(args, kt, M->n_rec, k, valid, M->alpha, M->a_cut, L.nearl[wave],
+                                   L.midl[wave], L.exptab, acck, far32);
+        if (valid) {
+            if constexpr (MIX) node_products<NNU>(args, M, accr, acck, W, res, far32, rbound);
+            else node_products<NNU>(args, M, accr, acck, W, res);
+        }
     }
 
     // tile reduction: wave butterflies, then the four waves in fixed order
@@ -417,6 +545,17 @@ __device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile
             if (lane == 0) { L.red[r][wave][0] = v.hi; L.red[r][wave][1] = v.lo; }
         }
     }
+    if constexpr (MIX) {                          // the bound: plain sums in fixed order
+#pragma unroll
+        for (int r = 0; r < EZ_RES_MAX; ++r) {
+            if (r < n_res) {
+                double v = rbound[r];
+#pragma unroll
+                for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+                if (lane == 0) L.rbnd[r][wave] = v;
+            }
+        }
+    }
     __syncthreads();
     if (threadIdx.x < n_res) {
         const int r = threadIdx.x;
@@ -424,6 +563,11 @@ __device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile
         for (int wv = 1; wv < EZ_TILE / 64; ++wv) s = ez_dd_add(s, ez_dd{L.red[r][wv][0], L.red[r][wv][1]});
         args.tile_part[((size_t)tile * n_res + r) * 2 + 0] = s.hi;
         args.tile_part[((size_t)tile * n_res + r) * 2 + 1] = s.lo;
+        if constexpr (MIX) {
+            double b = L.rbnd[r][0];
+            for (int wv = 1; wv < EZ_TILE / 64; ++wv) b += L.rbnd[r][wv];
+            args.tile_bound[(size_t)tile * n_res + r] = b;
+        }
     }
 }
 
@@ -541,11 +685,11 @@ __device__ __forceinline__ void node_group_split(const EzQuadArgs &args, const i
     }
 }
 
-// one workgroup per tile (tiles [0, n_main))
-template <int D, int NNU, int SET>
+// one workgroup per tile (tiles [0, n_main)); MIX: the mixed-precision far field
+template <int D, int NNU, int SET, bool MIX = false>
 __global__ __launch_bounds__(EZ_TILE) void ez_node_kernel(EzQuadArgs args) {
     __shared__ TileLds L;
-    node_tile<D, NNU, SET>(args, (int)blockIdx.x, L);
+    node_tile<D, NNU, SET, MIX>(args, (int)blockIdx.x, L);
 }
 
 // persistent: a fixed grid of workgroups takes tiles from a queue, costliest first;
@@ -630,6 +774,17 @@ __global__ __launch_bounds__(FT) void ez_finalize_kernel(EzQuadArgs args) {
             else if (!isfinite(v)) st |= 0x4u;
             args.out[(size_t)inst * n_res + r] = v;
             if (args.status && r == 0) args.status[inst] = st;
+        }
+    }
+    if (args.bound_out) {
+        // a-priori bound of the FP32 far field's effect on each result: the tile bounds
+        // in tile order (mixed calls keep every tile in the tile kernel); 0 in FP64 calls
+        for (int r = (int)threadIdx.x; r < n_res; r += FT) {
+            double b = 0.0;
+            if (args.mixed)
+                for (int t = tb; t < te; ++t) b += args.tile_bound[(size_t)t * n_res + r];
+            args.bound_out[(size_t)inst * n_res + r] =
+                args.meta[inst].status ? __longlong_as_double(0x7ff8000000000000ll) : b;
         }
     }
     if (!args.grad_out) return;
@@ -736,6 +891,8 @@ hipError_t launch_nodes_t(const EzQuadArgs &args, int n_tiles, hipStream_t strea
         hipLaunchKernelGGL((ez_node_split_kernel<D, NNU, SET>), dim3(n_tiles), dim3(64 * EZ_TAIL_WAVES), pad, stream, args);
     } else if (mode == 1) {
         hipLaunchKernelGGL((ez_node_persist_kernel<D, NNU, SET>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
+    } else if (args.mixed) {
+        hipLaunchKernelGGL((ez_node_kernel<D, NNU, SET, true>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
     } else {
         hipLaunchKernelGGL((ez_node_kernel<D, NNU, SET>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
     }

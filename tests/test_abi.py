@@ -59,8 +59,12 @@ def test_host_validation_errors():
     # bad specs
     for bad in [dict(n_q=0), dict(ell=7), dict(ell=9), dict(eps=0.7), dict(eps=0.0), dict(lam=-1.0), dict(a_cut=500.0)]:
         assert L.ez_nbody_lattice_sum(1, 3, dummy, 3, nu, ctypes.byref(_spec(nat, **bad)), dummy, None, None) == 1
-    # mixed precision is refused by the FP64 build
-    assert L.ez_atm_energy(1, 3, dummy, ctypes.byref(_spec(nat, precision=1)), dummy, None, None, None) == 4
+    # mixed precision: derivatives refuse it, unknown precision and a_mix < 8 are invalid
+    assert L.ez_atm_energy(1, 3, dummy, ctypes.byref(_spec(nat, precision=1)), dummy, dummy, None, None) == 4
+    assert b"FP64 only" in L.ez_last_error()
+    assert L.ez_atm_energy(1, 3, dummy, ctypes.byref(_spec(nat, precision=2)), dummy, None, None, None) == 1
+    assert L.ez_atm_energy(1, 3, dummy, ctypes.byref(_spec(nat, precision=1, flags=nat.spec_mix_a(4))),
+                           dummy, None, None, None) == 1
     # non-integer exponents in the quadrature
     nu2 = (ctypes.c_double * 2)(2.5, 3.0)
     assert L.ez_nbody_lattice_sum(1, 3, dummy, 2, nu2, ctypes.byref(_spec(nat)), dummy, None, None) == 1
@@ -83,6 +87,12 @@ def test_host_validation_errors():
     assert L.ez_lattice_sums_grad(1, 3, dummy, 1, nu, 3, one, cf, nf, fac, mult, 3, sp, 1, dummy, dummy,
                                   None, None) == 1
     assert b"at most 2" in L.ez_last_error()
+    # the bound entry point needs its output pointer; the no-allocation one is FP64 only
+    assert L.ez_lattice_sums_bound(1, 3, dummy, 1, nu, 3, one, cf, nf, fac, mult, 3, sp, 1, dummy, None,
+                                   None, None) == 1
+    spm = (nat.QuadSpec * 1)(_spec(nat, precision=1))
+    assert L.ez_lattice_sums_noalloc(1, 3, dummy, 1, nu, 3, one, cf, nf, fac, mult, 3, spm, 1, dummy,
+                                     None, None) == 4
 
 
 def test_version_string():

@@ -73,6 +73,9 @@ def test_graph_replay_matches_eager(ez):
     from paper_2504_11989_amd.batch import SCAN_NU, SCAN_TERMS, GraphedLatticeSums, scan_sums
     A, specs = small_scan(8)
     eager = scan_sums(A, specs).cpu().numpy()
+    # the eager calls between replays use a plan of their own: create it before the
+    # capture (a new plan may evict an old one, which makes the graph refuse replay)
+    scan_sums(A[::-1].copy(), specs[::-1]).cpu()
     g = GraphedLatticeSums(A, SCAN_NU, SCAN_TERMS, 5, specs)
     for rep in range(3):
         out = g.replay()
@@ -100,6 +103,28 @@ def test_autotune_picks_a_valid_configuration(ez):
     tuned = scan_sums(A, autotune.apply(specs, res["lam"], res["flags"])).cpu().numpy()
     base = scan_sums(A, autotune.apply(specs, 1.3, 0)).cpu().numpy()
     assert np.all(np.abs(tuned - base) <= 1e-12 * np.abs(base))
+
+
+def test_autotune_wave_shapes_and_json_cache(ez, tmp_path):
+    """the wave-block shape is tuned after lam and schedule; every shape gives the
+    same sums to rounding; a result stored in the JSON cache is reused for the
+    same device, runtime and library without timing again"""
+    from paper_2504_11989_amd import autotune
+    from paper_2504_11989_amd.batch import SCAN_NU, SCAN_TERMS, scan_sums
+    A, specs = small_scan(8)
+    path = str(tmp_path / "tune.json")
+    kw = dict(lams=(1.3,), schedules=autotune.DEFAULT_SCHEDULES[:1], reps=1,
+              wave_shapes=autotune.DEFAULT_WAVE_SHAPES, cache_file=path)
+    res = autotune.tune(A, SCAN_NU, SCAN_TERMS, 5, specs, **kw)
+    assert len(res["table"]) == 1 + len(autotune.DEFAULT_WAVE_SHAPES) - 1
+    assert res["wave"] in dict(autotune.DEFAULT_WAVE_SHAPES)
+    base = scan_sums(A, autotune.apply(specs, 1.3, 0)).cpu().numpy()
+    for name, flags in autotune.DEFAULT_WAVE_SHAPES:
+        got = scan_sums(A, autotune.apply(specs, 1.3, flags)).cpu().numpy()
+        assert np.all(np.abs(got - base) <= 1e-12 * np.abs(base)), name
+    autotune._cache.clear()
+    again = autotune.tune(A, SCAN_NU, SCAN_TERMS, 5, specs, **kw)
+    assert again["ms"] == res["ms"] and again["wave"] == res["wave"]
 
 
 def tail_launches(ez, fn):

@@ -1,0 +1,133 @@
+"""Mixed precision in the lattice sums (EZ_PREC_MIXED): the far-field reciprocal
+terms in FP32 with an a-priori bound per result.  Every mixed result must lie
+within its bound of the FP64 result on the same plan (plus FP64 rounding), the
+bound must certify 1e-10 relative at the default threshold, and the FP64 parity
+against the oracle must still hold within TOL plus the bound."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+FP64_ROUND = 1e-13          # FP64 rounding differences of the two summation orders, relative: about
+                            # 1e-16 in each Z, amplified by the conditioning of the ATM combination (~14)
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+ATM_NU = [-1.0, 1.0, 3.0, 5.0]
+ATM_TERMS = [(0, 1.0 / 24.0, [(2, 3)]), (0, -3.0 / 16.0, [(0, 1), (3, 2)]), (0, 3.0 / 8.0, [(1, 1), (2, 1), (3, 1)])]
+
+
+@pytest.fixture(scope="module")
+def ez():
+    import paper_2504_11989_amd as ez
+    ez.version()
+    return ez
+
+
+def mixed(spec, a_mix=0):
+    from paper_2504_11989_amd import _native as nat
+    return dict(spec, precision=nat.PREC_MIXED, flags=spec.get("flags", 0) | nat.spec_mix_a(a_mix))
+
+
+def run_pair(ez, A, nu, terms, n_res, spec, a_mix=0):
+    v64, b64 = ez.lattice_sums(A, nu, terms, n_res, spec, with_bound=True)
+    vmx, bmx = ez.lattice_sums(A, nu, terms, n_res, mixed(spec, a_mix), with_bound=True)
+    return v64.cpu().numpy(), b64.cpu().numpy(), vmx.cpu().numpy(), bmx.cpu().numpy()
+
+
+def check_within_bound(v64, vmx, bmx):
+    assert np.all(np.isfinite(bmx)) and np.all(bmx >= 0.0)
+    diff = np.abs(vmx - v64)
+    assert np.all(diff <= bmx + FP64_ROUND * np.abs(v64)), (diff, bmx)
+
+
+def test_c2_full_plan_mixed_within_bound_and_certified(ez):
+    """sc, fcc, bcc at the full plan: FP64 bound is 0, the mixed result lies within
+    its bound of FP64, the bound certifies 1e-10, and both meet the stored oracle
+    values at TOL (plus the bound)"""
+    g = json.load(open(os.path.join(GOLD, "oracle_c2_full.json")))
+    names = ["sc", "fcc", "bcc"]
+    A = np.stack([W.c2_lattices()[n] for n in names])
+    v64, b64, vmx, bmx = run_pair(ez, A, ATM_NU, ATM_TERMS, 1, g["spec"])
+    assert np.all(b64 == 0.0)
+    check_within_bound(v64, vmx, bmx)
+    for i, n in enumerate(names):
+        ref = g["atm"][n]
+        assert bmx[i, 0] <= 1e-10 * abs(ref), (n, bmx[i, 0])
+        assert bmx[i, 0] > 0.0, n                      # the FP32 path ran
+        assert abs(vmx[i, 0] - ref) <= TOL * abs(ref) + bmx[i, 0], n
+    # the ATM entry point takes the same path
+    e = ez.atm_energy(A, mixed(g["spec"])).cpu().numpy()
+    assert np.array_equal(e, vmx[:, 0])
+
+
+@pytest.mark.parametrize("a_mix", [8, 12, 24])
+def test_threshold_moves_the_bound(ez, a_mix):
+    """a lower threshold puts more terms in FP32: the bound grows, the result stays
+    inside it"""
+    A = np.stack([W.sc(), W.fcc(), W.bcc()])
+    spec = W.SPEC_FULL_3D
+    v64, _, vmx, bmx = run_pair(ez, A, ATM_NU, ATM_TERMS, 1, spec, a_mix)
+    check_within_bound(v64, vmx, bmx)
+    _, _, _, b16 = run_pair(ez, A, ATM_NU, ATM_TERMS, 1, spec, 16)
+    if a_mix < 16:
+        assert np.all(bmx > b16)
+    else:
+        assert np.all(bmx < b16)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_small_plans_vs_oracle(ez, d):
+    """ATM in d = 1, 2, 3 on small plans, mixed against the oracle on the same plan"""
+    A = {1: np.eye(1), 2: W.A_HEX, 3: W.fcc()}[d]
+    spec = {1: W.SPEC_1D, 2: dict(W.SPEC_2D, n_q=6, n_panels=3, n_g=8), 3: W.SPEC_SMALL_3D}[d]
+    v64, _, vmx, bmx = run_pair(ez, A[None], ATM_NU, ATM_TERMS, 1, spec, 8)
+    check_within_bound(v64, vmx, bmx)
+    ref = O.atm(A, spec)
+    assert abs(vmx[0, 0] - ref) <= TOL * abs(ref) + bmx[0, 0] + 4e-15 * abs(ref)
+
+
+def test_run_time_exponent_program(ez):
+    """a program without a compiled exponent set (the LJ + ATM program, exponents
+    read at run time, integer chain up to 2p = 6) and the scan program (half-integer
+    chain up to 2p = 11)"""
+    from paper_2504_11989_amd.batch import SCAN_NU, SCAN_TERMS
+    from paper_2504_11989_amd.enthalpy import LJ_ATM_NU, LJ_ATM_TERMS
+    A = np.stack([W.fcc(), W.bcc(), W.bct(1.2)])
+    for nu, terms, n_res in ((LJ_ATM_NU, LJ_ATM_TERMS, 2), (SCAN_NU, SCAN_TERMS, 5)):
+        v64, _, vmx, bmx = run_pair(ez, A, nu, terms, n_res, W.SPEC_SMALL_3D, 8)
+        check_within_bound(v64, vmx, bmx)
+        assert np.all(bmx > 0.0)
+
+
+def test_out_of_range_exponent_stays_fp64(ez):
+    """2p = nu - d + 2 = 14 > 12 has no FP32 fit: the call computes in FP64 (bound
+    0, identical values)"""
+    nu = [3.0, 15.0]
+    terms = [(0, 1.0, [(0, 1), (1, 1)])]
+    v64, _, vmx, bmx = run_pair(ez, W.sc()[None], nu, terms, 1, W.SPEC_SMALL_3D)
+    assert np.all(bmx == 0.0)
+    assert np.array_equal(v64, vmx)
+
+
+def test_mixed_is_deterministic_and_batched(ez):
+    """bit-identical on repeat, and a lattice's result does not depend on its batch"""
+    A = np.stack([W.sc(), W.fcc(), W.bcc()])
+    spec = mixed(W.SPEC_FULL_3D, 8)
+    a = ez.lattice_sums(A, ATM_NU, ATM_TERMS, 1, spec, with_bound=True)
+    b = ez.lattice_sums(A, ATM_NU, ATM_TERMS, 1, spec, with_bound=True)
+    c = ez.lattice_sums(A[1:2], ATM_NU, ATM_TERMS, 1, spec, with_bound=True)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    assert a[0][1, 0].item() == c[0][0, 0].item() and a[1][1, 0].item() == c[1][0, 0].item()
+
+
+def test_derivatives_refuse_mixed(ez):
+    from paper_2504_11989_amd._native import EzError
+    with pytest.raises(EzError):
+        ez.atm_energy(W.sc(), mixed(W.SPEC_SMALL_3D), grad=True)

@@ -217,3 +217,33 @@ def test_ring_sums_hex_against_direct(nus, L):
     prev = O.direct_nbody(W.A_HEX, nus, L - 1)
     assert abs(dsum - prev) <= 1e-9 * abs(dsum)
     assert abs(q - dsum) <= 1e-13 * abs(q), (q, dsum)
+
+
+@pytest.mark.parametrize("name", ["sq", "hex"])
+def test_high_n_ring_sums_large_n_asymptotics(name):
+    """zeta^(n)(3, ..., 3) for n = 24 .. 51 on the square and hexagonal lattices
+    (paper, Sec. 4.4: up to the 100-dimensional sum at n = 51).  Near k = 0,
+    Z_3(k) = Z_0 - (4 pi^2 / V) |k| + O(|k|^2) (d = 2, the singular part's
+    coefficient Gamma(-1/2) pi^2 / (Gamma(3/2) V)) and |Z_3(k)| < Z_0 elsewhere, so
+    Laplace's method gives zeta^(n) = V int Z^n dk = Z_0^(n+2) V^3 / (8 pi^3 n^2)
+    (1 + c/n + O(1/n^2)): the ratio fitted over n must extrapolate to 1.  Pins the
+    products of many Taylor series, the Hadamard part with n + 1 combinations and
+    the merging of equal powers."""
+    A = np.eye(2) if name == "sq" else W.A_HEX
+    V = abs(np.linalg.det(A))
+    z0 = O.epstein(A, 3.0, np.zeros(2), np.zeros(2)).real
+    ns = np.arange(24, 52, 3)
+    r = np.array([O.nbody(A, [3.0] * int(n), W.SPEC_2D) * 8.0 * np.pi ** 3 * n ** 2 / (z0 ** (n + 2) * V ** 3)
+                  for n in ns])
+    M = np.stack([np.ones(len(ns)), 1.0 / ns, 1.0 / ns ** 2], axis=1)
+    coef = np.linalg.lstsq(M, r, rcond=None)[0]
+    assert abs(coef[0] - 1.0) < 1e-3, (coef, r)
+
+
+@pytest.mark.parametrize("n,nu,L", [(4, 12, 6), (4, 24, 6), (4, 32, 6), (5, 26, 3), (5, 46, 3)])
+def test_ring_sums_hex_fig8_protocol(n, nu, L):
+    """n = 4 at 12 <= nu <= 32 with L = 6 and n = 5 at 26 <= nu <= 46 with L = 3
+    (paper, Sec. 4.4, the comparison with direct sums on the hexagonal lattice)"""
+    q = O.nbody(W.A_HEX, [float(nu)] * n, W.SPEC_2D)
+    dsum = O.direct_nbody(W.A_HEX, [nu] * n, L)
+    assert abs(q - dsum) <= 1e-13 * abs(dsum), (q, dsum)
