@@ -359,7 +359,7 @@ def highn_leg(args) -> dict:
                        "zeta^(3)(1,3,5) on A_kappa, kappa = 1, 2, 3, n_q = 4..20 in one call"}
     ns = [2, 3, 4, 6, 8, 12, 16, 24, 32, 40, 51]
     for name, A in (("sq", np.eye(2)), ("hex", W.A_HEX)):
-        z0 = ez.epstein_zeta(A, [3.0], np.zeros((1, 2)), np.zeros((1, 2))).cpu().numpy()[0, 0, 0]
+        z0 = float(ez.epstein_zeta(A, [3.0], np.zeros((1, 2)), np.zeros((1, 2))).cpu().numpy()[0, 0].real)
         rows = []
         for n in ns:
             ez.nbody_lattice_sum(A, [3.0] * n, spec)

@@ -144,6 +144,38 @@ double ezo_gamma_upper(double s, double a) {
         double sgn = (m % 2) ? -1.0 : 1.0;
         return sgn / mfact * (ezo_e1(a) - exp(-a) * sum);
     }
+    /* Gamma(s, a) = Gamma(s) - gamma(s, a), gamma(s, a) = a^s sum_k (-a)^k / (k! (s + k))
+       (DLMF 8.7.1, the series without the factor e^{-a}).  Near a pole of Gamma(s),
+       s = -m + delta with m = round(-s) >= 0 and |delta| small, Gamma(s) and the k = m
+       term are both of size 1/delta and cancel.  They are taken together:
+         Gamma(-m + delta) = (-1)^m Gamma(1 + delta) / (m! delta prod_{j<=m} (1 - delta/j))
+       (DLMF 5.5.1 applied m + 1 times), so
+         Gamma(s) - a^s (-a)^m / (m! (s + m))
+           = (-1)^m / (m! delta) [ (R - 1) - (a^delta - 1) ],
+         R = Gamma(1 + delta) / prod_{j<=m} (1 - delta/j),
+       with R - 1 and a^delta - 1 from expm1 of their logarithms (lgamma, log1p). */
+    const double m_r = floor(-s + 0.5);
+    if (m_r >= 0.0 && fabs(s + m_r) < 0.25) {
+        const int m = (int)m_r;
+        const double delta = s + m_r;
+        double lr = lgamma(1.0 + delta), mfact = 1.0;
+        for (int j = 1; j <= m; ++j) {
+            lr -= log1p(-delta / (double)j);
+            mfact *= (double)j;
+        }
+        const double la = log(a);
+        double head = (expm1(lr) - expm1(delta * la)) / (mfact * delta);
+        if (m % 2) head = -head;
+        double rest = 0.0, term = 1.0;              /* term = (-a)^k / k! */
+        for (int k = 0; k < 100000; ++k) {
+            if (k > 0) term *= -a / (double)k;
+            if (k == m) continue;
+            const double t = term / (s + (double)k);
+            rest += t;
+            if (k > m && fabs(t) <= 1e-18 * fabs(rest)) break;
+        }
+        return head - exp(s * la) * rest;
+    }
     double term = 1.0 / s, sum = term;
     for (int k = 1; k < 100000; ++k) {
         term *= a / (s + (double)k);
