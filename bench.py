@@ -396,6 +396,40 @@ def highn_leg(args) -> dict:
     return out
 
 
+def meromorphic_leg(args) -> dict:
+    """The one-dimensional three-body zeta function zeta^(3)_Z(nu, nu, nu) along
+    -2 <= nu <= 3 in steps of 1/20 with the offset 1/50 (paper, Sec. 4.3, the scan of
+    the meromorphic continuation): 101 sums with non-integer exponents, GPU time
+    per sum and the largest deviation from the oracle on every 10th point."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_2504_11989_amd as ez
+    import workloads as W
+    spec = dict(W.SPEC_1D)
+    nus = [-2.0 + j / 20.0 + 1.0 / 50.0 for j in range(101)]
+    vals = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for nu in nus:
+        vals.append(ez.nbody_lattice_sum(np.eye(1), [nu] * 3, spec))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    vals = [v.item() for v in vals]
+    # relative deviation, and the deviation over the parity bar max(1e-12 |v|, 4e-15 (|H| + |N|))
+    # that allows for the cancellation of the Hadamard and node parts near the poles
+    err, over = 0.0, 0.0
+    for j in range(0, 101, 10):
+        ref, parts = oracle.nbody(np.eye(1), [nus[j]] * 3, spec, parts=True)
+        dev = abs(vals[j] - ref)
+        err = max(err, dev / max(abs(ref), 1e-300))
+        over = max(over, dev / max(1e-12 * abs(ref), 4e-15 * float(np.abs(parts).sum())))
+    return {"workload": "zeta^(3)_Z(nu,nu,nu), nu = -2 + j/20 + 1/50, j = 0..100, 1-D plan (1024 graded u-nodes)",
+            "sums": len(nus), "ms_per_sum": round(1e3 * dt / len(nus), 4),
+            "nu": [round(x, 4) for x in nus[::10]], "values": [vals[j] for j in range(0, 101, 10)],
+            "max_rel_err_vs_oracle_every_10th": err, "max_deviation_over_parity_bar": over}
+
+
 def c5_leg(args) -> dict:
     """Differentiation and n-body sums.  (1) dH/dA of H = E_LJ(12-6) + c E_ATM + p V
     from the adjoint kernels against central differences of the GPU value (h =
@@ -654,6 +688,7 @@ def main() -> int:
         "mixed": None,
         "phase": None,
         "highn": None,
+        "meromorphic_1d": None,
         "cpu_baseline": None,
     }
     def leg(name, fn):
@@ -669,6 +704,7 @@ def main() -> int:
         line["phase"] = leg("phase diagram", lambda: phase_leg(args))
     if not args.no_highn:
         line["highn"] = leg("high-n sums", lambda: highn_leg(args))
+        line["meromorphic_1d"] = leg("1-D continuation scan", lambda: meromorphic_leg(args))
     if not args.no_c3:
         line["c3_scan"] = leg("c3 scan", lambda: c3_scan_leg(args))
     if not args.no_c4:

@@ -290,19 +290,32 @@ ez_status build_program(int d, const std::vector<double> &nu, const std::vector<
     P.n_res = n_res;
     P.n_terms = (int)terms.size();
     for (int i = 0; i < P.n_nu; ++i) {
+        const double v = nu[i];
+        if (!std::isfinite(v) || std::fabs(v) > 64.0)
+            return fail(EZ_ERR_INVALID_ARG, "quadrature exponents must be finite with |nu| <= 64");
+        if (v != std::floor(v)) P.real_nu = 1;
+    }
+    for (int i = 0; i < P.n_nu; ++i) {
         double v = nu[i];
-        if (!std::isfinite(v) || v != std::floor(v) || std::fabs(v) > 64.0)
-            return fail(EZ_ERR_INVALID_ARG, "quadrature exponents must be integers with |nu| <= 64");
         P.nu[i] = v;
+        P.preal[i] = 0.5 * (v - d + 2.0);
+        P.e[i] = v - d;
+        if (P.real_nu) {                 // E_p of every exponent from its own incomplete gamma
+            P.p2[i] = 0;
+            P.logm[i] = -1;
+            if (v == std::floor(v) && (int)v - d >= 0 && ((int)v - d) % 2 == 0)
+                return fail(EZ_ERR_UNSUPPORTED, "an integer exponent nu = d + 2m (logarithmic singular part) "
+                                                "cannot share a call with non-integer exponents");
+            continue;
+        }
         P.p2[i] = (int)v - d + 2;
         int em = (int)v - d;
         P.logm[i] = (em >= 0 && em % 2 == 0) ? em / 2 : -1;
-        P.e[i] = v - d;
         if ((P.p2[i] & 1) == 0 && P.p2[i] / 2 >= 1) P.need_e1 = 1;
         if (P.p2[i] & 1) P.need_half = 1;
     }
     P.pset = 0;
-    for (int id = 1; id < EZ_NPSETS; ++id) {
+    for (int id = 1; id < EZ_NPSETS && !P.real_nu; ++id) {
         EzPSet ps = ez_pset(id);
         if (ps.n != P.n_nu) continue;
         bool same = true;
@@ -330,10 +343,11 @@ ez_status build_program(int d, const std::vector<double> &nu, const std::vector<
         // Hadamard exponents mu = d + sum_f j_f (nu_f - d) + 2J must avoid 0 (paper, Sec. 3)
         std::vector<int> jj(T.fac.size(), 0);
         while (true) {
-            int E = 0, rest = 0, Q = 0;
+            double E = 0.0;
+            int rest = 0, Q = 0;
             double coef = T.coef;
             for (size_t f = 0; f < T.fac.size(); ++f) {
-                E += jj[f] * ((int)P.nu[T.fac[f].first] - d);
+                E += jj[f] * (P.nu[T.fac[f].first] - d);
                 Q += jj[f] * (P.logm[T.fac[f].first] >= 0 ? 1 : 0);
                 rest += T.fac[f].second - jj[f];
                 double bn = 1.0;
@@ -353,7 +367,7 @@ ez_status build_program(int d, const std::vector<double> &nu, const std::vector<
             combos.push_back(cb);
             int Jmax = std::min(rest * ell_max, 32);
             for (int J = 0; J <= Jmax; ++J)
-                if (d + E + 2 * J == 0)
+                if (std::fabs(d + E + 2.0 * J) < 1e-12)
                     return fail(EZ_ERR_UNSUPPORTED, "Hadamard exponent mu + 2k = 0 (logarithmic correction not implemented)");
             size_t f = 0;
             while (f < T.fac.size()) {
@@ -760,8 +774,8 @@ ez_status prepare_call(int batch, int d, const EzProgram &prog, const std::vecto
             const int odd = prog.p2[i] & 1;
             C.top2[odd] = std::max(C.top2[odd], std::max(prog.p2[i], odd));
         }
-        C.mixed_active = C.top2[0] <= EZ_EPF_P2MAX && C.top2[1] <= EZ_EPF_P2MAX && C.acut <= 80.0 &&
-                         C.a_mix < C.acut;
+        C.mixed_active = !prog.real_nu && C.top2[0] <= EZ_EPF_P2MAX && C.top2[1] <= EZ_EPF_P2MAX &&
+                         C.acut <= 80.0 && C.a_mix < C.acut;
         if (C.mixed_active) mixed_bounds(prog, C.a_mix, C.top2, C.eps);
     }
     return EZ_OK;
@@ -797,7 +811,7 @@ int main_tiles(const CallInfo &C, const EzProgram &prog, int n_cu, int n_tiles) 
         round = n_cu * ez_nodes_tile_blocks_per_cu(probe_args);
     }
     int n_main = n_tiles;
-    if (!C.grad && !C.mixed_active && !(C.flags & EZ_SPEC_NO_SPLIT)) {
+    if (!C.grad && !C.mixed_active && !prog.real_nu && !(C.flags & EZ_SPEC_NO_SPLIT)) {
         const int tail = round > 0 ? n_tiles % round : 0;
         const int per_tile = (EZ_TILE / 64) * EZ_TAIL_PARTS;     // split-kernel workgroups per tail tile
         if (n_tiles > round && tail > 0 && tail * per_tile <= n_cu) n_main = n_tiles - tail;
@@ -954,7 +968,7 @@ ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, co
     EZ_HIP_TRY(tm(EZ_KERNEL_HADAMARD, hs, [&] { return had(hs, EZ_HAD_DIR, nullptr); }));
     if (grad) {
         EZ_HIP_TRY(tm(EZ_KERNEL_NODES_ADJ, stream, [&] { return ez_launch_nodes_adj(qa, P.n_tiles, stream); }));
-    } else if ((C.flags & EZ_SPEC_PERSISTENT) && !C.mixed_active) {
+    } else if ((C.flags & EZ_SPEC_PERSISTENT) && !C.mixed_active && !prog.real_nu) {
         int bpc = (C.flags >> 8) & 0xFF;
         if (bpc == 0) bpc = ez_nodes_blocks_per_cu(qa);
         const int nblk = std::max(1, std::min(P.n_tiles, n_cu * bpc));
@@ -1106,7 +1120,10 @@ ez_status sums_program(int batch, int d, const double *A_dev, int n_nu, const do
         for (int f = 0; f < term_nfac[t]; ++f)
             terms[t].fac.push_back({term_fac[EZ_FAC_MAX * t + f], term_mult[EZ_FAC_MAX * t + f]});
     }
-    return build_program(d, nu, terms, n_results, ell_max, prog, combos);
+    if ((st = build_program(d, nu, terms, n_results, ell_max, prog, combos))) return st;
+    if (grad && prog.real_nu)
+        return fail(EZ_ERR_UNSUPPORTED, "derivatives need integer exponents");
+    return EZ_OK;
 }
 
 }  // namespace

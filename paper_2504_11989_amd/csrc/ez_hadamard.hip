@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void ez_hadamard_kernel(EzQuadArgs args) {
         //   I_0 = eps^mu/mu,  I_q = (eps^mu L(eps)^q - 2q I_{q-1})/mu
         const double eps = P.eps, eps2 = eps * eps;
         const double Leps = dsh[myd][1];
-        double mu = (double)(D + cb.E);
+        double mu = (double)D + cb.E;
         double em = pow(eps, mu);
         double acc = 0.0;
 #pragma unroll

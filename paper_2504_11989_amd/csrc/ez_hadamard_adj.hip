@@ -39,10 +39,10 @@ __device__ __forceinline__ void poly_mul_trunc_d(double (&p)[PD], double (&dp)[P
 // sum_{J <= deg} p_J fp int_0^eps u^{mu_J - 1} L^Q du with mu_J = d + E + 2J (returned),
 // and the same with L^{Q-1} (in *s_qm1; 0 when Q = 0)
 template <int D, int PD>
-__device__ __forceinline__ double had_sum(const double (&p)[PD], int deg, int E, int Q, double eps, double Leps,
+__device__ __forceinline__ double had_sum(const double (&p)[PD], int deg, double E, int Q, double eps, double Leps,
                                           double *s_qm1, bool *bad) {
     const double eps2 = eps * eps;
-    double mu = (double)(D + E);
+    double mu = (double)D + E;
     double em = pow(eps, mu);
     double acc = 0.0, accm = 0.0;
 #pragma unroll

@@ -147,16 +147,23 @@ __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta 
                 if (q < hi) {
                     const double a0 = alpha * kt[(size_t)q * 4 + 3];
                     const double ex = exp(-a0), inv = ez_rcp(a0);
-                    const int p2 = prog.p2[i];
-                    const double E1 = ((p2 & 1) == 0) ? ez_e1(a0, ex, inv) : 0.0;
-                    const double Eh = (p2 & 1) ? ez_ehalf(a0) : 0.0;
-                    double E = ez_ep_from(p2, a0, ex, inv, E1, Eh);
+                    double E, pi_;
+                    if (prog.real_nu) {
+                        pi_ = prog.preal[i];
+                        E = ez_ep_real(pi_, a0);
+                    } else {
+                        const int p2 = prog.p2[i];
+                        pi_ = 0.5 * (double)p2;
+                        const double E1 = ((p2 & 1) == 0) ? ez_e1(a0, ex, inv) : 0.0;
+                        const double Eh = (p2 & 1) ? ez_ehalf(a0) : 0.0;
+                        E = ez_ep_from(p2, a0, ex, inv, E1, Eh);
+                    }
                     double sc = M->K[i];
 #pragma unroll
                     for (int n = 0; n < NF; ++n) {
                         if (n <= nfmax) {
                             fsh[te][i][n] = sc * E;
-                            const double pnm1 = 0.5 * (double)p2 - (double)n - 1.0;
+                            const double pnm1 = pi_ - (double)n - 1.0;
                             E = (ex - pnm1 * E) * inv;          // E_{p-n-1}
                             sc *= -alpha * (1.0 / (double)(n + 1));
                         }

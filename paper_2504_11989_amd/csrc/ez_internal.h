@@ -37,12 +37,15 @@ struct EzProgram {
     int need_e1;            // some p_i is an integer >= 1
     int need_half;          // some p_i is a half-integer
     int pset;               // id of a compile-time exponent set matching p2, or 0
+    int real_nu;            // some nu_i is not an integer: p2 unused, E_p from preal
+    double preal[EZ_NU_MAX];// p_i = (nu_i - d + 2)/2
 };
 
 // Exponent sets with kernels specialised at compile time (2 p_i = nu_i - d + 2);
 // set 0 reads the exponents at run time.
 struct EzPSet { int n; int p2[EZ_NU_MAX]; };
 #define EZ_NPSETS 5
+#define EZ_PSET_REAL 15     // kernels for real (non-integer) exponents: E_p per exponent
 __host__ __device__ constexpr EzPSet ez_pset(int id) {
     return id == 1 ? EzPSet{4, {-2, 0, 2, 4}}                 // d = 3, nu = -1, 1, 3, 5 (ATM)
          : id == 2 ? EzPSet{4, {-1, 1, 3, 5}}                 // d = 2, ATM

@@ -25,7 +25,8 @@ struct EzSetupArgs {
 #define EZ_COMBO_MAX 64
 struct EzCombo {
     double coef;
-    int E, Q;
+    double E;                  // sum_f j_f (nu_f - d): the u-exponent of the singular factors
+    int Q;                     // number of logarithmic singular factors
     signed char t, res, j[EZ_FAC_MAX];
     short pad_;
 };

@@ -234,9 +234,13 @@ __device__ __forceinline__ double ez_rgamma(double x) {
 
 // Upper incomplete gamma Gamma(s, a), a > 0, any real s (used off the hot path).
 //  2s integer: Gamma(s,a) = a^s E_{1-s}(a) through the E_p recurrences;
-//  otherwise:  a < max(2, s + 1): Gamma(s) - a^s e^{-a} sum_k a^k / (s)_{k+1} (DLMF 8.7.1),
-//              else the continued fraction of DLMF 8.9.2 (even part), Lentz's method,
-//              for s < 0 after the downward recurrence Gamma(s,a) = (Gamma(s+1,a) - a^s e^{-a})/s.
+//  otherwise, a >= 2 and a >= s + 1: the continued fraction of DLMF 8.9.2 (even
+//  part) by Lentz's method;
+//  otherwise the series Gamma(s) - a^s sum_k (-a)^k / (k! (s + k)) (DLMF 8.7.1).  Near
+//  a pole of Gamma, s = -m + delta (m = rint(-s) >= 0, |delta| < 1/4), Gamma(s) and the
+//  k = m term are both ~ 1/delta; with Gamma(-m + delta) = (-1)^m Gamma(1 + delta) /
+//  (m! delta prod_{j=1..m} (1 - delta/j)) (DLMF 5.5.1) they combine into
+//  (-1)^m [expm1(lgamma(1 + delta) - sum_j log1p(-delta/j)) - expm1(delta ln a)] / (m! delta).
 __device__ inline double ez_gamma_upper(double s, double a) {
     const double s2 = 2.0 * s;
     if (s2 == floor(s2) && fabs(s) <= 64.0) {
@@ -246,40 +250,55 @@ __device__ inline double ez_gamma_upper(double s, double a) {
         double Eh = (p2 & 1) ? ez_ehalf(a) : 0.0;
         return pow(a, s) * ez_ep_from(p2, a, e, inv, E1, Eh);
     }
-    if (a < 2.0 || a < s + 1.0) {
-        double term = 1.0 / s, sum = term;
-        for (int k = 1; k < 500; ++k) {
-            term *= a / (s + (double)k);
-            sum += term;
-            if (fabs(term) < 1e-17 * fabs(sum)) break;
-        }
-        return tgamma(s) - exp(s * log(a) - a) * sum;
-    }
-    // shift s up to s' > 0 if needed, then continued fraction at s'
-    int nshift = 0;
-    double sp = s;
-    while (sp <= 0.0) { sp += 1.0; ++nshift; }
-    double f;
-    {
+    const double la = log(a);
+    if (a >= 2.0 && a >= s + 1.0) {
         const double tiny = 1e-300;
         double F = tiny, C = F, D = 0.0;
-        for (int j = 1; j < 2000; ++j) {
-            double aj = (j == 1) ? 1.0 : -(double)(j - 1) * ((double)(j - 1) - sp);
-            double bj = a + 2.0 * j - 1.0 - sp;
+        for (int j = 1; j < 4000; ++j) {
+            const double aj = (j == 1) ? 1.0 : -(double)(j - 1) * ((double)(j - 1) - s);
+            const double bj = a + 2.0 * j - 1.0 - s;
             D = bj + aj * D; if (D == 0.0) D = tiny;
             C = bj + aj / C; if (C == 0.0) C = tiny;
             D = 1.0 / D;
-            double dl = C * D;
+            const double dl = C * D;
             F *= dl;
             if (fabs(dl - 1.0) < 1e-16) break;
         }
-        f = exp(sp * log(a) - a) * F;
+        return exp(s * la - a) * F;
     }
-    for (int i = 0; i < nshift; ++i) {
-        sp -= 1.0;
-        f = (f - exp(sp * log(a) - a)) / sp;
+    const double mr = rint(-s);
+    if (mr >= 0.0 && fabs(s + mr) < 0.25) {
+        const int m = (int)mr;
+        const double dlt = s + mr;
+        double lr = lgamma(1.0 + dlt), mf = 1.0;
+        for (int j = 1; j <= m; ++j) {
+            lr -= log1p(-dlt / (double)j);
+            mf *= (double)j;
+        }
+        const double hd = (expm1(lr) - expm1(dlt * la)) / (mf * dlt);
+        double tail = 0.0, pw = 1.0;                  // pw = (-a)^k / k!
+        for (int k = 0; k < 500; ++k) {
+            if (k > 0) pw *= -a / (double)k;
+            if (k == m) continue;
+            const double t = pw / (s + (double)k);
+            tail += t;
+            if (k > m && fabs(t) < 1e-18 * fabs(tail)) break;
+        }
+        return ((m & 1) ? -hd : hd) - exp(s * la) * tail;
     }
-    return f;
+    double term = 1.0 / s, sum = term;
+    for (int k = 1; k < 500; ++k) {
+        term *= a / (s + (double)k);
+        sum += term;
+        if (fabs(term) < 1e-17 * fabs(sum)) break;
+    }
+    return tgamma(s) - exp(s * la - a) * sum;
+}
+
+// E_p(a) = a^{p-1} Gamma(1 - p, a) for real p (non-integer exponents of the quadrature);
+// out of line, it is called per term and exponent
+__device__ __attribute__((noinline)) double ez_ep_real(double p, double a) {
+    return exp((p - 1.0) * log(a)) * ez_gamma_upper(1.0 - p, a);
 }
 
 // cos(2 pi t) with the argument reduced exactly modulo 1

@@ -113,7 +113,7 @@ __device__ __forceinline__ void rec_origin(const EzQuadArgs &args, const double 
             const double Eh = need_half ? ((a < 0.25) ? ez_ehalf(a) : ex * inv * ez_ehw_scaled(inv)) : 0.0;
 #pragma unroll
             for (int i = 0; i < NNU; ++i)
-                acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
+                acck[i] += pset_ep<SET>(args.prog, i, a, ex, inv, E1, Eh);
         }
     }
     for (int j = 1; j <= n_near; ++j) {
@@ -129,7 +129,7 @@ __device__ __forceinline__ void rec_origin(const EzQuadArgs &args, const double 
             const double Eh = need_half ? ez_ehalf_ool(a) : 0.0;
 #pragma unroll
             for (int i = 0; i < NNU; ++i)
-                acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
+                acck[i] += pset_ep<SET>(args.prog, i, a, ex, inv, E1, Eh);
         }
     }
 }
@@ -166,7 +166,7 @@ __device__ __forceinline__ void rec_list(const EzQuadArgs &args, const double *k
             const double Eh = need_half ? ex * inv * ez_ehw_scaled(inv) : 0.0;
 #pragma unroll
             for (int i = 0; i < NNU; ++i)
-                acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
+                acck[i] += pset_ep<SET>(args.prog, i, a, ex, inv, E1, Eh);
         }
     }
 }
@@ -301,7 +301,7 @@ __device__ __forceinline__ void rec_wave(const EzQuadArgs &args, const double *k
             const double Eh = need_half ? ((a < 0.25) ? ez_ehalf(a) : ex * inv * ez_ehw_scaled(inv)) : 0.0;
 #pragma unroll
             for (int i = 0; i < NNU; ++i)
-                acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
+                acck[i] += pset_ep<SET>(args.prog, i, a, ex, inv, E1, Eh);
         }
     }
     int n_near = 0, n_mid = 0;
@@ -340,7 +340,7 @@ __device__ __forceinline__ void rec_wave(const EzQuadArgs &args, const double *k
                 ez_far_bases(a, ex, need_e1, need_half, &E1, &Eh, &inv);
 #pragma unroll
                 for (int i = 0; i < NNU; ++i)
-                    acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
+                    acck[i] += pset_ep<SET>(args.prog, i, a, ex, inv, E1, Eh);
             }
         }
         if constexpr (MIX) {
@@ -391,7 +391,7 @@ __device__ __forceinline__ void rec_wave(const EzQuadArgs &args, const double *k
             const double Eh = need_half ? ex * inv * ez_ehw_scaled(inv) : 0.0;
 #pragma unroll
             for (int i = 0; i < NNU; ++i)
-                acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
+                acck[i] += pset_ep<SET>(args.prog, i, a, ex, inv, E1, Eh);
         }
     }
     for (int j = 0; j < n_near; ++j) {
@@ -407,7 +407,7 @@ __device__ __forceinline__ void rec_wave(const EzQuadArgs &args, const double *k
             const double Eh = need_half ? ez_ehalf_ool(a) : 0.0;
 #pragma unroll
             for (int i = 0; i < NNU; ++i)
-                acck[i] += ez_ep_from(pset_p2<SET>(args.prog, i), a, ex, inv, E1, Eh);
+                acck[i] += pset_ep<SET>(args.prog, i, a, ex, inv, E1, Eh);
         }
     }
 }
@@ -899,8 +899,42 @@ hipError_t launch_nodes_t(const EzQuadArgs &args, int n_tiles, hipStream_t strea
     return hipGetLastError();
 }
 
+// real (non-integer) exponents: the tile kernel only (mode 0) and its occupancy (mode 4);
+// such calls take no tail split, no persistent schedule and no mixed precision
+template <int D, int NNU>
+hipError_t launch_nodes_real(const EzQuadArgs &args, int n_tiles, hipStream_t stream, int mode, int *bpc) {
+    if (mode == 4) {
+        static int cached_r = 0;
+        if (!cached_r) {
+            int nb = 0;
+            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ez_node_kernel<D, NNU, EZ_PSET_REAL>,
+                                                                        EZ_TILE, 0);
+            if (e != hipSuccess) return e;
+            cached_r = nb > 0 ? nb : 1;
+        }
+        *bpc = cached_r;
+        return hipSuccess;
+    }
+    if (mode != 0 || args.mixed) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((ez_node_kernel<D, NNU, EZ_PSET_REAL>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
+    return hipGetLastError();
+}
+
 template <int D>
 hipError_t launch_nodes_d(const EzQuadArgs &args, int n_tiles, hipStream_t stream, int mode, int *bpc) {
+    if (args.prog.real_nu) {
+        switch (args.prog.n_nu) {
+            case 1: return launch_nodes_real<D, 1>(args, n_tiles, stream, mode, bpc);
+            case 2: return launch_nodes_real<D, 2>(args, n_tiles, stream, mode, bpc);
+            case 3: return launch_nodes_real<D, 3>(args, n_tiles, stream, mode, bpc);
+            case 4: return launch_nodes_real<D, 4>(args, n_tiles, stream, mode, bpc);
+            case 5: return launch_nodes_real<D, 5>(args, n_tiles, stream, mode, bpc);
+            case 6: return launch_nodes_real<D, 6>(args, n_tiles, stream, mode, bpc);
+            case 7: return launch_nodes_real<D, 7>(args, n_tiles, stream, mode, bpc);
+            case 8: return launch_nodes_real<D, 8>(args, n_tiles, stream, mode, bpc);
+            default: return hipErrorInvalidValue;
+        }
+    }
     if (D == 3 && args.prog.pset == 1) return launch_nodes_t<D, 4, 1>(args, n_tiles, stream, mode, bpc);
     if (D == 2 && args.prog.pset == 2) return launch_nodes_t<D, 4, 2>(args, n_tiles, stream, mode, bpc);
     if (D == 1 && args.prog.pset == 3) return launch_nodes_t<D, 4, 3>(args, n_tiles, stream, mode, bpc);

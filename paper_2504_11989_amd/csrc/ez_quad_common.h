@@ -98,6 +98,7 @@ __device__ __forceinline__ int pset_p2(const EzProgram &prog, int i) {
 }
 template <int SET, int NNU>
 __device__ __forceinline__ bool pset_need_e1(const EzProgram &prog) {
+    if constexpr (SET == EZ_PSET_REAL) return false;
     if constexpr (SET == 0) return prog.need_e1 != 0;
     bool r = false;
     for (int i = 0; i < NNU; ++i) r = r || ((ez_pset(SET).p2[i] & 1) == 0 && ez_pset(SET).p2[i] >= 2);
@@ -105,10 +106,20 @@ __device__ __forceinline__ bool pset_need_e1(const EzProgram &prog) {
 }
 template <int SET, int NNU>
 __device__ __forceinline__ bool pset_need_half(const EzProgram &prog) {
+    if constexpr (SET == EZ_PSET_REAL) return false;
     if constexpr (SET == 0) return prog.need_half != 0;
     bool r = false;
     for (int i = 0; i < NNU; ++i) r = r || (ez_pset(SET).p2[i] & 1);
     return r;
+}
+
+// E_{p_i}(a) of exponent i: from the bases E_1, E_{1/2} and the recurrences, or, for
+// real exponents, by the incomplete gamma of its own order
+template <int SET>
+__device__ __forceinline__ double pset_ep(const EzProgram &prog, int i, double a, double e, double inv, double E1,
+                                          double Eh) {
+    if constexpr (SET == EZ_PSET_REAL) return ez_ep_real(prog.preal[i], a);
+    else return ez_ep_from(pset_p2<SET>(prog, i), a, e, inv, E1, Eh);
 }
 
 // The reciprocal table covers every node of the cell; a workgroup needs only the

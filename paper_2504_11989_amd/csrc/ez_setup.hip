@@ -101,6 +101,9 @@ __device__ __attribute__((noinline)) double ep_half(int p2, double a) {
     return ez_ep_from(p2, a, e, inv, E1, Eh);
 }
 
+// E_p(a) for real p (non-integer quadrature exponents), out of line
+__device__ __attribute__((noinline)) double ep_any(double p, double a) { return ez_ep_real(p, a); }
+
 // Deterministic two-list compaction of one chunk.  Each list keeps a running
 // count that every thread carries in a register; the per-wave totals are double
 // buffered in LDS (chunk parity), so one barrier per chunk suffices: a buffer is
@@ -321,7 +324,8 @@ __global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
             // and a = (pi/lam^2) |z|^2: the powers of |z| cancel, 2 W_nu = 2 (pi/lam^2)^{nu/2}
             // E_{1-nu/2}(a) / Gamma(nu/2)
             const double pw = pow(pl, 0.5 * nu);
-            e[3 + i] = 2.0 * args.nuc[i][3] * pw * ep_half(2 - (int)nu, a);
+            e[3 + i] = 2.0 * args.nuc[i][3] * pw *
+                       (args.prog.real_nu ? ep_any(1.0 - 0.5 * nu, a) : ep_half(2 - (int)nu, a));
             int used = 3 + n_nu;
             if (args.grad) {
                 // strain weights: d(2 W_nu)/d|z|^2 times 2 (from d|z|^2 = 2 z^T G z), with

@@ -65,9 +65,23 @@ def test_host_validation_errors():
     assert L.ez_atm_energy(1, 3, dummy, ctypes.byref(_spec(nat, precision=2)), dummy, None, None, None) == 1
     assert L.ez_atm_energy(1, 3, dummy, ctypes.byref(_spec(nat, precision=1, flags=nat.spec_mix_a(4))),
                            dummy, None, None, None) == 1
-    # non-integer exponents in the quadrature
-    nu2 = (ctypes.c_double * 2)(2.5, 3.0)
+    # non-finite exponents in the quadrature; an exponent nu = d + 2m with its logarithmic
+    # singular part cannot share a call with non-integer exponents
+    nu2 = (ctypes.c_double * 2)(2.5, float("nan"))
     assert L.ez_nbody_lattice_sum(1, 3, dummy, 2, nu2, ctypes.byref(_spec(nat)), dummy, None, None) == 1
+    nu3 = (ctypes.c_double * 2)(2.5, 5.0)
+    assert L.ez_nbody_lattice_sum(1, 3, dummy, 2, nu3, ctypes.byref(_spec(nat)), dummy, None, None) == 4
+    assert b"logarithmic" in L.ez_last_error()
+    # derivatives need integer exponents
+    nu4 = (ctypes.c_double * 1)(2.5)
+    t1 = (ctypes.c_int * 1)(0)
+    c1 = (ctypes.c_double * 1)(1.0)
+    n1 = (ctypes.c_int * 1)(1)
+    f1 = (ctypes.c_int * 4)(0, 0, 0, 0)
+    m1 = (ctypes.c_int * 4)(2, 0, 0, 0)
+    sp1 = (nat.QuadSpec * 1)(_spec(nat))
+    assert L.ez_lattice_sums_grad(1, 3, dummy, 1, nu4, 1, t1, c1, n1, f1, m1, 1, sp1, 1, dummy, dummy,
+                                  None, None) == 4
     assert b"integer" in L.ez_last_error()
     # a Hadamard exponent mu = d + (nu - d) = 0: nu = 0 alone (paper, Sec. 3, mu + 2k = 0)
     nu0 = (ctypes.c_double * 1)(0.0)
