@@ -430,6 +430,45 @@ def meromorphic_leg(args) -> dict:
             "max_rel_err_vs_oracle_every_10th": err, "max_deviation_over_parity_bar": over}
 
 
+def direct_leg(args) -> dict:
+    """GPU direct sums of the ATM energy over boxes (ez_direct_atm): the paper's
+    printed direct sums (Lambda = Z at L = 5000, the square lattice at L = 250 and its
+    high-precision reference at L = 1600), the L^-4 Richardson extrapolation of the
+    square-lattice box sums against the Epstein zeta method on the full 2-D plan."""
+    import json as _json
+    import numpy as np
+    import torch
+    import paper_2504_11989_amd as ez
+    import workloads as W
+    paper = _json.load(open(os.path.join(ROOT, "tests", "golden", "paper_values.json")))
+    out = {"workload": "E_L = (1/6) sum over x, y in A{-L..L}^d of U_ATM(0, x, y); square lattice with the orbit "
+                       "reduction of the signed coordinate permutations"}
+    rows = []
+    for name, A, L, sym, key in (("Z", np.eye(1), 5000, False, "atm_1d_direct_L5000"),
+                                 ("sq", np.eye(2), 250, True, "atm_2d_sq_direct_L250"),
+                                 ("sq", np.eye(2), 1600, True, "atm_2d_sq_reference_L1600")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        v = ez.direct_atm(A, L, symmetry=sym)
+        dt = time.perf_counter() - t0
+        d = A.shape[0]
+        n = (2 * L + 1) ** d
+        p = paper[key]["value"]
+        # pairs: ordered pairs of the full box; terms_per_s: terms the kernel evaluates per
+        # second (about pairs / 8 under the orbit reduction of the square lattice)
+        rows.append({"lattice": name, "L": L, "value": v, "paper": p, "rel_diff_vs_paper": abs(v - p) / abs(p),
+                     "seconds": round(dt, 3), "pairs": float(n) * float(n - 2),
+                     "terms_per_s": float(n) * float(n - 2) / dt / (8.0 if sym and d == 2 else 1.0)})
+    out["sums"] = rows
+    e = ez.atm_energy(np.eye(2)[None], W.SPEC_2D).item()
+    v2, v4 = ez.direct_atm(np.eye(2), 200, symmetry=True), ez.direct_atm(np.eye(2), 400, symmetry=True)
+    ext = (16.0 * v4 - v2) / 15.0
+    out["square_epstein"] = e
+    out["square_richardson_L200_L400"] = ext
+    out["rel_diff_epstein_vs_richardson"] = abs(e - ext) / abs(ext)
+    return out
+
+
 def c5_leg(args) -> dict:
     """Differentiation and n-body sums.  (1) dH/dA of H = E_LJ(12-6) + c E_ATM + p V
     from the adjoint kernels against central differences of the GPU value (h =
@@ -548,6 +587,7 @@ def main() -> int:
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision ATM leg")
     ap.add_argument("--no-phase", action="store_true", help="skip the phase-diagram / Bain-path leg")
     ap.add_argument("--no-highn", action="store_true", help="skip the high-n / kappa-study leg")
+    ap.add_argument("--no-direct", action="store_true", help="skip the GPU direct-sum leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 1 GiB device-to-device copies (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -689,6 +729,7 @@ def main() -> int:
         "phase": None,
         "highn": None,
         "meromorphic_1d": None,
+        "direct_sums": None,
         "cpu_baseline": None,
     }
     def leg(name, fn):
@@ -705,6 +746,8 @@ def main() -> int:
     if not args.no_highn:
         line["highn"] = leg("high-n sums", lambda: highn_leg(args))
         line["meromorphic_1d"] = leg("1-D continuation scan", lambda: meromorphic_leg(args))
+    if not args.no_direct:
+        line["direct_sums"] = leg("direct sums", lambda: direct_leg(args))
     if not args.no_c3:
         line["c3_scan"] = leg("c3 scan", lambda: c3_scan_leg(args))
     if not args.no_c4:

@@ -198,6 +198,25 @@ ez_status ez_lattice_sums(int batch, int d, const double *A_dev, int n_nu, const
                           int n_results, const ez_quad_spec *specs, int n_specs, double *out_dev,
                           uint32_t *status_dev, void *stream);
 
+/* Direct summation of the Axilrod-Teller-Muto cohesive energy over the box
+ * A{-L..L}^d (paper, Sec. 2, Definition (ATM potential); Sec. 4.3 compares the
+ * Epstein zeta method with such sums on the square lattice):
+ *   E_L = (1/6) sum_{x, y in box, x, y, x - y != 0} U(x, y),
+ *   U = (1 + 3 cos g1 cos g2 cos g3) / (|x| |y| |x - y|)^3  (g_i the triangle's angles).
+ * An independent check of ez_atm_energy: the box sum converges to the lattice sum
+ * like L^{-d-2}.
+ *   A_host       : d*d doubles (host), row-major, columns the basis vectors
+ *   use_symmetry : 1 sums over one point per orbit of the signed coordinate
+ *                  permutations, with the orbit size as weight (needs A^T A = c I:
+ *                  square and cubic lattices; about 2^d d! times less work); 0 sums
+ *                  over every box point
+ *   out_dev      : 1 double (device), written on `stream`
+ * Deterministic (fixed-order double-double sums).  The outer-point list is copied
+ * from pageable host memory (the copy completes before the call returns).
+ * Errors: EZ_ERR_INVALID_ARG (d, L beyond 2^28 / 8192 / 512 for d = 1 / 2 / 3, null
+ * pointers, non-finite or singular A, use_symmetry without A^T A = c I). */
+ez_status ez_direct_atm(int d, const double *A_host, int L, int use_symmetry, double *out_dev, void *stream);
+
 /* ez_lattice_sums with an a-priori error bound per result, for EZ_PREC_MIXED specs:
  *   bound_dev : batch x n_results doubles (device), |result_mixed - result_FP64| <=
  *               bound_dev[b * n_results + r], where result_FP64 is the FP64 value on

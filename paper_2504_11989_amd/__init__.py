@@ -230,6 +230,21 @@ def lattice_sums(A, nu: Sequence[float], terms: Iterable, n_results: int, specs=
     return ret if len(ret) > 1 else ret[0]
 
 
+def direct_atm(A, L: int, symmetry: bool = False) -> float:
+    """ATM cohesive energy by direct summation over the box A{-L..L}^d on the GPU
+    (ez_direct_atm); symmetry=True for square / cubic lattices."""
+    import numpy as np
+    torch = _torch()
+    A_np = np.ascontiguousarray(np.asarray(A, dtype=np.float64))
+    d = A_np.shape[0]
+    if A_np.shape != (d, d):
+        raise ValueError("A must be d x d")
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    check(lib().ez_direct_atm(d, A_np.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(L), 1 if symmetry else 0,
+                              _dptr(out), _stream_ptr(out.device)))
+    return out.item()
+
+
 def version() -> str:
     return lib().ez_version().decode()
 

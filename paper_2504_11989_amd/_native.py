@@ -39,7 +39,7 @@ def spec_mix_a(n: int) -> int:
 EXPORTED = ("ez_epstein_zeta", "ez_epstein_grid", "ez_nbody_lattice_sum", "ez_atm_energy", "ez_lattice_sums", "ez_lattice_sums_grad",
             "ez_timing_enable", "ez_timing_reset", "ez_timing_read",
             "ez_last_error", "ez_finalize", "ez_version", "ez_workspace_generation", "ez_lattice_sums_noalloc",
-            "ez_lattice_sums_bound")
+            "ez_lattice_sums_bound", "ez_direct_atm")
 (KERNEL_SETUP, KERNEL_NODES, KERNEL_HADAMARD, KERNEL_FINALIZE, KERNEL_EPSTEIN, KERNEL_NODES_ADJ, KERNEL_GRID,
  KERNEL_NODES_TAIL, KERNEL_TAYLOR) = (0, 1, 2, 3, 4, 5, 6, 7, 8)
 
@@ -94,6 +94,8 @@ def lib():
     L.ez_lattice_sums_grad.restype = I
     L.ez_lattice_sums_grad.argtypes = [I, I, VP, I, P, I, IP, P, IP, IP, IP, I, ctypes.POINTER(QuadSpec), I,
                                        VP, VP, VP, VP]
+    L.ez_direct_atm.restype = I
+    L.ez_direct_atm.argtypes = [I, P, I, I, VP, VP]
     L.ez_lattice_sums_bound.restype = I
     L.ez_lattice_sums_bound.argtypes = [I, I, VP, I, P, I, IP, P, IP, IP, IP, I, ctypes.POINTER(QuadSpec), I,
                                         VP, VP, VP, VP]

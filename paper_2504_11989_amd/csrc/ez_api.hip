@@ -7,6 +7,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -170,6 +171,7 @@ struct DeviceState {
     DevBuf gmeta, greal, grec;   // general-x Epstein tables
     DevBuf queue;                // work-queue position of the persistent node kernel
     DevBuf tile_bound;           // mixed-precision bound partials per tile
+    DevBuf dxlist, dpart;        // direct ATM sum: outer points and partial sums
     // Epstein grid workspace
     DevBuf g_pts_x, g_pts_y, g_perm, g_counts, g_A64r, g_B64r, g_A64k, g_B64k, g_R, g_Q, g_wsum, g_stat;
     DevBuf g_Ahr, g_Alr, g_Bhr, g_Blr, g_Ahk, g_Alk, g_Bhk, g_Blk;
@@ -1175,6 +1177,7 @@ ez_status ez_finalize(void) {
         free_buf(S->meta); free_buf(S->real); free_buf(S->rec); free_buf(S->rn); free_buf(S->rows);
         free_buf(S->tile_part); free_buf(S->sub_part); free_buf(S->tail_acc); free_buf(S->tail_cnt); free_buf(S->dir_part); free_buf(S->dir_flag); free_buf(S->probe_val); free_buf(S->tensor);
         free_buf(S->tile_grad); free_buf(S->dir_grad); free_buf(S->queue); free_buf(S->tile_bound);
+        free_buf(S->dxlist); free_buf(S->dpart);
         for (DevBuf *b : {&S->g_pts_x, &S->g_pts_y, &S->g_perm, &S->g_counts, &S->g_A64r, &S->g_B64r, &S->g_A64k,
                           &S->g_B64k, &S->g_R, &S->g_Q, &S->g_wsum, &S->g_stat, &S->g_Ahr, &S->g_Alr, &S->g_Bhr,
                           &S->g_Blr, &S->g_Ahk, &S->g_Alk, &S->g_Bhk, &S->g_Blk})
@@ -1347,6 +1350,94 @@ ez_status ez_atm_energy(int batch, int d, const double *A_dev, const ez_quad_spe
     std::vector<EzCombo> combos;
     if ((st = build_program(d, nu, {t0, t1, t2}, 1, spec->ell, prog, combos))) return st;
     return run_sums(batch, d, A_dev, prog, combos, spec, 1, E_dev, status_dev, (hipStream_t)stream, dEdA_dev);
+}
+
+ez_status ez_direct_atm(int d, const double *A_host, int L, int use_symmetry, double *out_dev, void *stream) {
+    if (d < 1 || d > 3) return fail(EZ_ERR_INVALID_ARG, "d must be 1, 2 or 3");
+    if (!A_host || !out_dev) return fail(EZ_ERR_INVALID_ARG, "null pointer argument");
+    const long long Lmax = d == 1 ? (1ll << 28) : (d == 2 ? 8192 : 512);
+    if (L < 1 || L > Lmax) return fail(EZ_ERR_INVALID_ARG, "L out of range for this d");
+    double G[9] = {0}, tr = 0.0;
+    for (int i = 0; i < d * d; ++i)
+        if (!std::isfinite(A_host[i])) return fail(EZ_ERR_INVALID_ARG, "A not finite");
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            double g = 0.0;
+            for (int k = 0; k < d; ++k) g += A_host[k * d + i] * A_host[k * d + j];
+            G[i * 3 + j] = g;
+        }
+    for (int i = 0; i < d; ++i) tr += G[i * 3 + i];
+    if (!(tr > 0.0)) return fail(EZ_ERR_INVALID_ARG, "A is singular");
+    if (use_symmetry) {
+        // the metric must be c I so that the signed coordinate permutations are isometries
+        const double c = tr / d;
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j)
+                if (std::fabs(G[i * 3 + j] - (i == j ? c : 0.0)) > 1e-14 * c)
+                    return fail(EZ_ERR_INVALID_ARG, "use_symmetry needs A^T A = c I (square or cubic lattice)");
+    }
+    EzDirectArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.d = d;
+    g.L = L;
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) g.A[i * 3 + j] = A_host[i * d + j];
+    const long long M = 2ll * L + 1;
+    long long nbox = 1;
+    for (int i = 0; i < d; ++i) nbox *= M;
+    g.n_box = nbox;
+    // outer points with weights
+    std::vector<int> xl;
+    if (use_symmetry) {
+        // 0 <= n_1 <= ... <= n_d <= L, n != 0; weight 2^{#nonzero} d! / prod(multiplicities!)
+        int n[3] = {0, 0, 0};
+        std::function<void(int, int)> rec = [&](int j, int lo) {
+            if (j == d) {
+                int nz = 0;
+                for (int i = 0; i < d; ++i) nz += n[i] != 0;
+                if (nz == 0) return;
+                long long wgt = 1ll << nz, perm = 1, run = 1;
+                for (int i = 2; i <= d; ++i) perm *= i;
+                for (int i = 1; i < d; ++i) {
+                    if (n[i] == n[i - 1]) { ++run; perm /= run; } else run = 1;
+                }
+                xl.insert(xl.end(), {n[0], n[1], n[2], (int)(wgt * perm)});
+                return;
+            }
+            for (int v = lo; v <= L; ++v) { n[j] = v; rec(j + 1, v); }
+            n[j] = 0;
+        };
+        rec(0, 0);
+    } else {
+        for (long long k = 0; k < nbox; ++k) {
+            long long q = k;
+            int n[3] = {0, 0, 0};
+            bool zero = true;
+            for (int j = 0; j < d; ++j) { n[j] = (int)(q % M) - L; q /= M; zero = zero && n[j] == 0; }
+            if (!zero) xl.insert(xl.end(), {n[0], n[1], n[2], 1});
+        }
+    }
+    g.n_x = (long long)(xl.size() / 4);
+    const long long xblocks = (g.n_x + 255) / 256;
+    long long chunks = std::max<long long>(1, (nbox + 32767) / 32768);
+    chunks = std::max<long long>(chunks, (4096 + xblocks - 1) / xblocks);
+    chunks = std::min<long long>(chunks, std::min<long long>(65535, nbox));
+    g.per_chunk = (nbox + chunks - 1) / chunks;
+    int dev = 0;
+    EZ_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_mu);
+    DeviceState *S = device_state(dev);
+    ez_status st;
+    const long long nparts = ez_direct_parts(g.n_x, (int)chunks);
+    if ((st = grow(S->dxlist, sizeof(int) * xl.size())) || (st = grow(S->dpart, sizeof(double) * 2 * nparts)))
+        return st;
+    hipStream_t hs = (hipStream_t)stream;
+    // pageable host source: the copy has completed when the call returns
+    EZ_HIP_TRY(hipMemcpyAsync(S->dxlist.p, xl.data(), sizeof(int) * xl.size(), hipMemcpyHostToDevice, hs));
+    g.xlist = (const int *)S->dxlist.p;
+    g.part = (double *)S->dpart.p;
+    EZ_HIP_TRY(ez_launch_direct_atm(g, (int)chunks, out_dev, hs));
+    return EZ_OK;
 }
 
 ez_status ez_epstein_zeta(int d, const double *A_dev, int n_nu, const double *nu_host, int64_t n_pts,

@@ -112,3 +112,16 @@ hipError_t ez_launch_nodes_adj(const EzQuadArgs &args, int n_tiles, hipStream_t 
 hipError_t ez_launch_hadamard_adj(const EzQuadArgs &args, int n_htiles, hipStream_t stream, int part,
                                   hipEvent_t pre_done = nullptr);
 hipError_t ez_launch_epstein(const EzEpsteinArgs &args, hipStream_t stream);
+
+// direct ATM sum over the box A{-L..L}^d (ez_direct.hip)
+struct EzDirectArgs {
+    int d, L;
+    double A[9];               // row-major, padded to 3 x 3
+    const int *xlist;          // [n_x][4]: outer point n (3 ints) and its weight
+    long long n_x;
+    long long n_box;           // (2L + 1)^d inner points
+    long long per_chunk;       // inner points per workgroup column
+    double *part;              // [ez_direct_parts][2] double-double partials
+};
+long long ez_direct_parts(long long n_x, int n_chunks);
+hipError_t ez_launch_direct_atm(const EzDirectArgs &g, int n_chunks, double *out, hipStream_t stream);
