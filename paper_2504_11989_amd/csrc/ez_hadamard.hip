@@ -7,112 +7,154 @@
 
 namespace {
 
-template <int D, int NNU, int PD>
-__global__ __launch_bounds__(256) void ez_hadamard_kernel(EzQuadArgs args) {
-    __shared__ double Tsh[NNU * EZ_TDIM];
-    __shared__ double Csh[EZ_HDIR][NNU][EZ_ELL_MAX + 1];
-    __shared__ double ssh[EZ_HDIR][NNU];   // sigma_i |w|^{nu_i - d}
-    __shared__ double dsh[EZ_HDIR][3];     // 2 w_v, log(pi eps^2 |w|^2), validity
-    __shared__ double whsh[EZ_HDIR][3];    // w_hat
-    __shared__ double vsh[256];            // value of each (direction, combination)
-    __shared__ uint32_t fsh_bad[EZ_HDIR];  // a Hadamard exponent mu = 0 was met
+// C_k(w_hat), k = 0 .. ell, of one channel from its tensor row T (monomials of degree
+// 2k in the order a0 desc, a1 desc, orders one after the other): homogeneous Horner
+// in (x0, x1, x2); T is uniform over the wave
+template <int D, int LM>
+__device__ __forceinline__ void horner_orders(const double *T, int ell, double x0, double x1, double x2,
+                                              double (&C)[LM + 1]) {
+    int off = 0;
+#pragma unroll
+    for (int k = 0; k <= LM; ++k) {
+        C[k] = 0.0;
+        if (k > ell) continue;
+        const int g = 2 * k;
+        if (D == 1) {
+            double m = 1.0;
+            for (int q = 0; q < g; ++q) m *= x0;
+            C[k] = T[off] * m;
+            off += 1;
+        } else if (D == 2) {
+            // sum_a T[g - a] x0^a x1^(g - a), a descending
+            double acc = T[off], p1 = 1.0;
+            for (int a = g - 1; a >= 0; --a) {
+                p1 *= x1;
+                acc = fma(acc, x0, T[off + g - a] * p1);
+            }
+            C[k] = acc;
+            off += g + 1;
+        } else {
+            // sum_a x0^a S_a(x1, x2), S_a homogeneous of degree g - a in (x1, x2) with
+            // its coefficients in b = g - a .. 0 order
+            double acc = 0.0;
+            for (int a = g; a >= 0; --a) {
+                const int m = g - a;
+                double S = T[off], p2 = 1.0;
+                for (int b = m - 1; b >= 0; --b) {
+                    p2 *= x2;
+                    S = fma(S, x1, T[off + m - b] * p2);
+                }
+                off += m + 1;
+                acc = fma(acc, x0, S);
+            }
+            C[k] = acc;
+        }
+    }
+}
+
+// dynamic LDS of the direction kernel, in doubles: C_k per (channel, order, lane),
+// sigma_i |w|^{e_i} per (channel, lane), the waves' result sums per (wave, result,
+// lane), then one flag word per (wave, lane)
+template <int NNU, int LM>
+inline size_t had_lds_bytes(int n_res) {
+    return sizeof(double) * 64 * ((size_t)NNU * (LM + 2) + (size_t)EZ_HW * n_res) + sizeof(uint32_t) * 64 * EZ_HW;
+}
+
+template <int D, int NNU, int PD, int LM>
+__global__ __launch_bounds__(64 * EZ_HW) void ez_hadamard_kernel(EzQuadArgs args) {
+    extern __shared__ double lds[];                // had_lds_bytes<NNU, LM>(n_res)
+    const EzProgram &prog = args.prog;
+    const int n_res = prog.n_res, nc = args.n_combo;
+    double *Csh = lds;                             // [NNU][LM + 1][64]
+    double *ssh = Csh + NNU * (LM + 1) * 64;       // [NNU][64]
+    double *acc = ssh + NNU * 64;                  // [EZ_HW][n_res][64]
+    uint32_t *badsh = reinterpret_cast<uint32_t *>(acc + EZ_HW * n_res * 64);   // [EZ_HW][64]
     const int blk = blockIdx.x;
     const int inst = find_segment(args.htile_begin, args.batch, blk);
     const EzInstPlan P = args.plans[inst];
     const EzLatMeta *M = args.meta + inst;
-    const EzProgram &prog = args.prog;
-    const int n_res = prog.n_res, nc = args.n_combo;
     const int ndb = args.n_dir_blk;
     const int d0 = (blk - args.htile_begin[inst]) * ndb;
     const int ell = P.ell;
-    const int tid = (int)threadIdx.x;
-    if (M->status != 0) {                           // uniform over the workgroup
-        const int dl = d0 + tid;
-        if (tid < ndb && dl < P.n_dir) {
+    const int lane = (int)threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int dl = d0 + lane;
+    const bool valid = lane < ndb && dl < P.n_dir;
+    if (M->status != 0) {                          // uniform over the workgroup
+        if (wave == 0 && valid) {
             for (int r = 0; r < n_res; ++r) args.dir_part[(size_t)(P.dir_begin + dl) * n_res + r] = 0.0;
             args.dir_flag[P.dir_begin + dl] = 0;
         }
         return;
     }
-    int tdim = 0;
-    for (int k = 0; k <= ell; ++k) tdim += nmono(D, 2 * k);
-    if (tid < ndb) {
-        const int dl = d0 + tid;
-        const bool valid = dl < P.n_dir;
-        double B[D * D];
+    // the lane's direction (every wave computes it for itself)
+    double B[D * D];
 #pragma unroll
-        for (int i = 0; i < D * D; ++i) B[i] = M->B[i];
-        double w[3] = {0.0, 0.0, 0.0}, wh[3] = {0.0, 0.0, 0.0}, wv = 0.0;
-        ez_direction<D>(P, args.rules, B, valid ? dl : 0, w, &wv, wh);
-        double w2 = 0.0;
+    for (int i = 0; i < D * D; ++i) B[i] = M->B[i];
+    double w[3] = {0.0, 0.0, 0.0}, wh[3] = {0.0, 0.0, 0.0}, wv = 0.0;
+    ez_direction<D>(P, args.rules, B, valid ? dl : 0, w, &wv, wh);
+    double w2 = 0.0;
 #pragma unroll
-        for (int i = 0; i < D; ++i) w2 = fma(w[i], w[i], w2);
+    for (int i = 0; i < D; ++i) w2 = fma(w[i], w[i], w2);
+
+    // phase 1: channel i on wave i mod EZ_HW, lane = direction: C_k(w) from the tensor
+    // row and sigma_i |w|^{e_i}
+    for (int i = wave; i < NNU; i += EZ_HW) {
+        const double *T = args.tensor + ((size_t)inst * NNU + i) * EZ_TDIM;
+        double C[LM + 1];
+        horner_orders<D, LM>(T, ell, wh[0], wh[1], wh[2], C);
 #pragma unroll
-        for (int i = 0; i < NNU; ++i) ssh[tid][i] = M->sig[i] * pow(w2, 0.5 * prog.e[i]);
-        dsh[tid][0] = 2.0 * wv;
-        dsh[tid][1] = log(EZ_PI * P.eps * P.eps * w2);
-        dsh[tid][2] = valid ? 1.0 : 0.0;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) whsh[tid][i] = wh[i];
-        fsh_bad[tid] = 0u;
+        for (int k = 0; k <= LM; ++k) Csh[(i * (LM + 1) + k) * 64 + lane] = C[k];
+        ssh[i * 64 + lane] = M->sig[i] * pow(w2, 0.5 * prog.e[i]);
     }
-    // phase 1: C_k(w) from the tensors
-    contract_tensor<D, NNU>(args, inst, 0, NNU, ndb, ell, tdim, Tsh, whsh, &Csh[0][0][0], NNU * (EZ_ELL_MAX + 1),
-                            EZ_ELL_MAX + 1);
+    for (int r = 0; r < n_res; ++r) acc[(wave * n_res + r) * 64 + lane] = 0.0;
     __syncthreads();
 
-    // phase 2: one (direction, combination) per thread
-    const int myd = tid / nc, myc = tid - myd * nc;
-    bool bad = false;
-    if (myd < ndb) {
-        const EzCombo &cb = args.combo[myc];
+    // phase 2: combination c on wave c mod EZ_HW (uniform), lane = direction: the
+    // product polynomial (PD coefficients in registers) and its Hadamard integrals
+    //   fp int_0^eps u^{mu-1} L^Q du, mu = d + E + 2J:
+    //   I_0 = eps^mu/mu,  I_q = (eps^mu L(eps)^q - 2q I_{q-1})/mu
+    const double eps = P.eps, eps2 = eps * eps;
+    const double Leps = log(EZ_PI * eps2 * w2);
+    uint32_t bad = 0u;
+    for (int c = wave; c < nc; c += EZ_HW) {
+        const EzCombo &cb = args.combo[c];
         const int t = cb.t;
         const int nf = prog.term_nfac[t];
-        double c = cb.coef;
+        double cv = cb.coef;
         double poly[PD];
         poly[0] = 1.0;
 #pragma unroll
         for (int J = 1; J < PD; ++J) poly[J] = 0.0;
-        int deg = 0, rest = 0;
+        int deg = 0;
         for (int f = 0; f < nf; ++f) {
             const int i = prog.term_fac[t][f];
-            for (int q = 0; q < cb.j[f]; ++q) c *= ssh[myd][i];
-            for (int rep = 0; rep < prog.term_mult[t][f] - cb.j[f]; ++rep) deg = min(deg + ell, PD - 1);
-            rest += prog.term_mult[t][f] - cb.j[f];
-        }
-        // the Taylor factors in one loop of `rest` multiplications (factor f taken
-        // mult_f - j_f times in turn): the lanes of a wave hold different combinations
-        // and differ only in its trip count
-        int f = 0, left = nf > 0 ? prog.term_mult[t][0] - cb.j[0] : 0;
-        for (int m = 0; m < rest; ++m) {
-            while (left == 0) { ++f; left = prog.term_mult[t][f] - cb.j[f]; }
-            --left;
-            const int i = prog.term_fac[t][f];
-            double Ck[EZ_ELL_MAX + 1];
+            const int jf = cb.j[f];
+            for (int q = 0; q < jf; ++q) cv *= ssh[i * 64 + lane];
+            for (int rep = 0; rep < prog.term_mult[t][f] - jf; ++rep) {
+                deg = min(deg + ell, PD - 1);
+                // poly <- poly * sum_k C_k u^{2k}, truncated to PD coefficients
+                double Ck[LM + 1];
 #pragma unroll
-            for (int kk = 0; kk <= EZ_ELL_MAX; ++kk) Ck[kk] = (kk <= ell) ? Csh[myd][i][kk] : 0.0;
-            // poly <- poly * sum_k C_k u^{2k}, truncated to PD coefficients
+                for (int kk = 0; kk <= LM; ++kk) Ck[kk] = (kk <= ell) ? Csh[(i * (LM + 1) + kk) * 64 + lane] : 0.0;
 #pragma unroll
-            for (int J = PD - 1; J >= 0; --J) {
-                double sacc = 0.0;
+                for (int J = PD - 1; J >= 0; --J) {
+                    double sacc = 0.0;
 #pragma unroll
-                for (int kk = 0; kk <= EZ_ELL_MAX; ++kk)
-                    if (kk <= J) sacc = fma(poly[J - kk], Ck[kk], sacc);
-                poly[J] = sacc;
+                    for (int kk = 0; kk <= LM; ++kk)
+                        if (kk <= J) sacc = fma(poly[J - kk], Ck[kk], sacc);
+                    poly[J] = sacc;
+                }
             }
         }
-        // fp int_0^eps u^{mu-1} L^Q du, mu = d + E + 2J:
-        //   I_0 = eps^mu/mu,  I_q = (eps^mu L(eps)^q - 2q I_{q-1})/mu
-        const double eps = P.eps, eps2 = eps * eps;
-        const double Leps = dsh[myd][1];
         double mu = (double)D + cb.E;
         double em = pow(eps, mu);
-        double acc = 0.0;
+        double s = 0.0;
 #pragma unroll
         for (int J = 0; J < PD; ++J) {
             if (J <= deg) {
                 if (mu == 0.0) {
-                    bad = true;
+                    bad = 1u;
                 } else {
                     const double rmu = ez_rcp(mu);
                     double I = em * rmu, Lp = 1.0;
@@ -120,34 +162,33 @@ __global__ __launch_bounds__(256) void ez_hadamard_kernel(EzQuadArgs args) {
                         Lp *= Leps;
                         I = (em * Lp - 2.0 * (double)j * I) * rmu;
                     }
-                    acc = fma(poly[J], I, acc);
+                    s = fma(poly[J], I, s);
                 }
             }
             mu += 2.0;
             em *= eps2;
         }
-        vsh[tid] = c * acc;
-        if (bad) atomicOr(&fsh_bad[myd], 1u);
+        acc[(wave * n_res + cb.res) * 64 + lane] += cv * s;
     }
+    badsh[wave * 64 + lane] = bad;
     __syncthreads();
-    // phase 3: per direction, fixed-order sum over the combinations
-    if (tid < ndb) {
-        const int dl = d0 + tid;
-        if (dl < P.n_dir) {
-            const int gd = P.dir_begin + dl;
-            for (int r = 0; r < n_res; ++r) {
-                double h = 0.0;
-                for (int c = 0; c < nc; ++c)
-                    if (args.combo[c].res == r) h += vsh[tid * nc + c];
-                args.dir_part[(size_t)gd * n_res + r] = dsh[tid][0] * h;
-            }
-            // device-side guard for a Hadamard exponent mu = 0 (the host rejects such programs)
-            args.dir_flag[gd] = fsh_bad[tid];
+    // phase 3: per direction, the waves' sums in wave order
+    if (wave == 0 && valid) {
+        const int gd = P.dir_begin + dl;
+        for (int r = 0; r < n_res; ++r) {
+            double h = 0.0;
+#pragma unroll
+            for (int v = 0; v < EZ_HW; ++v) h += acc[(v * n_res + r) * 64 + lane];
+            args.dir_part[(size_t)gd * n_res + r] = 2.0 * wv * h;
         }
+        uint32_t b = 0u;
+#pragma unroll
+        for (int v = 0; v < EZ_HW; ++v) b |= badsh[v * 64 + lane];
+        // device-side guard for a Hadamard exponent mu = 0 (the host rejects such programs)
+        args.dir_flag[gd] = b;
     }
 }
 
-// poly <- poly * sum_k c_k u^{2k}, truncated to PD coefficients
 
 template <int D, int NNU, int PD>
 hipError_t launch_had_t(const EzQuadArgs &args, int n_htiles, hipStream_t stream, int part, hipEvent_t pre_done) {
@@ -155,8 +196,14 @@ hipError_t launch_had_t(const EzQuadArgs &args, int n_htiles, hipStream_t stream
     if (part & EZ_HAD_PRE) {            // probe values and Taylor tensors
         const int nblk = (args.n_probe + 63) / 64;
         const int nch = false ? args.n_ch : 1;
-        hipLaunchKernelGGL((ez_probe_kernel<D, NNU, false>), dim3(args.batch * nblk * args.n_slice * nch), dim3(64 * EZ_HW),
-                           (probe_lds_bytes<NNU, false>(args.ell_probe)), stream, args);
+        // Taylor orders up to 4 (the usual plans) keep 5 coefficients per exponent in
+        // registers, higher ones 9
+        if (args.ell_probe <= 4)
+            hipLaunchKernelGGL((ez_probe_kernel<D, NNU, false, 4>), dim3(args.batch * nblk * args.n_slice * nch),
+                               dim3(64 * EZ_HW), (probe_lds_bytes<NNU, false>(args.ell_probe)), stream, args);
+        else
+            hipLaunchKernelGGL((ez_probe_kernel<D, NNU, false>), dim3(args.batch * nblk * args.n_slice * nch),
+                               dim3(64 * EZ_HW), (probe_lds_bytes<NNU, false>(args.ell_probe)), stream, args);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         int tdim = 0;
@@ -172,7 +219,12 @@ hipError_t launch_had_t(const EzQuadArgs &args, int n_htiles, hipStream_t stream
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (!(part & EZ_HAD_DIR)) return hipSuccess;   // direction kernel
-    hipLaunchKernelGGL((ez_hadamard_kernel<D, NNU, PD>), dim3(n_htiles), dim3(256), 0, stream, args);
+    if (args.ell_probe <= 4)
+        hipLaunchKernelGGL((ez_hadamard_kernel<D, NNU, PD, 4>), dim3(n_htiles), dim3(64 * EZ_HW),
+                           (had_lds_bytes<NNU, 4>(args.prog.n_res)), stream, args);
+    else
+        hipLaunchKernelGGL((ez_hadamard_kernel<D, NNU, PD, EZ_ELL_MAX>), dim3(n_htiles), dim3(64 * EZ_HW),
+                           (had_lds_bytes<NNU, EZ_ELL_MAX>(args.prog.n_res)), stream, args);
     return hipGetLastError();
 }
 

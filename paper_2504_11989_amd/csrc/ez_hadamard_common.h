@@ -68,10 +68,10 @@ __host__ __device__ constexpr int ez_sb(int D, int s) { return s < D ? s : (s - 
 // d|w|^2 = -2 w w^T and dK = -K I.
 // Lane = direction, the slice's entries split over EZ_HW waves, summed in LDS in
 // fixed order; on return wave 0 holds the slice's coefficients.
-template <int D, int NNU, bool GR>
+template <int D, int NNU, bool GR, int LM = EZ_ELL_MAX>
 __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta *M, int ell, const double *w,
-                              double (&C)[NNU][EZ_ELL_MAX + 1], double *lds, int slice, int n_slice, int ch) {
-    constexpr int NF = GR ? EZ_NF + 1 : EZ_NF;
+                              double (&C)[NNU][LM + 1], double *lds, int slice, int n_slice, int ch) {
+    constexpr int NF = GR ? 2 * LM + 2 : 2 * LM + 1;
     double (*fsh)[NNU][NF] = reinterpret_cast<double (*)[NNU][NF]>(lds);
     const EzProgram &prog = args.prog;
     const int lane = (int)threadIdx.x & 63, part = (int)threadIdx.x >> 6;
@@ -83,14 +83,14 @@ __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta 
     for (int i = 0; i < D; ++i) w2 = fma(w[i], w[i], w2);
     const double ww = w[sa] * w[sb];
     const double alpha = M->alpha;
-    double pw2[EZ_ELL_MAX + 1];
+    double pw2[LM + 1];
     pw2[0] = 1.0;
 #pragma unroll
-    for (int j = 1; j <= EZ_ELL_MAX; ++j) pw2[j] = pw2[j - 1] * w2;
+    for (int j = 1; j <= LM; ++j) pw2[j] = pw2[j - 1] * w2;
 #pragma unroll
     for (int i = 0; i < NNU; ++i) {
 #pragma unroll
-        for (int k = 0; k <= EZ_ELL_MAX; ++k) C[i][k] = 0.0;
+        for (int k = 0; k <= LM; ++k) C[i][k] = 0.0;
         if (part == 0 && slice == 0 && !dch) C[i][0] = -M->self_[i];
     }
     // real space: 2 W cos(2 pi u w.z) = 2 W sum_k (-1)^k (2 pi w.z)^{2k} u^{2k} / (2k)!
@@ -116,7 +116,7 @@ __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta 
             double term0 = dch ? e0[sa] * e0[sb] : 1.0;
             double term1 = dch ? e1[sa] * e1[sb] : 1.0;
 #pragma unroll
-            for (int k = 0; k <= EZ_ELL_MAX; ++k) {
+            for (int k = 0; k <= LM; ++k) {
                 if (k <= ell) {
 #pragma unroll
                     for (int i = 0; i < NNU; ++i) C[i][k] = fma(ew1[i], term1, fma(ew0[i], term0, C[i][k]));
@@ -178,13 +178,13 @@ __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta 
 #pragma unroll
                 for (int i = 0; i < D; ++i) b = fma(w[i], e[i], b);
                 const double b4 = 4.0 * b * b;
-                double pb[EZ_ELL_MAX + 1];
+                double pb[LM + 1];
                 pb[0] = 1.0;
 #pragma unroll
-                for (int j = 1; j <= EZ_ELL_MAX; ++j) pb[j] = pb[j - 1] * b4;
+                for (int j = 1; j <= LM; ++j) pb[j] = pb[j - 1] * b4;
                 if (!dch) {
 #pragma unroll
-                    for (int k = 0; k <= EZ_ELL_MAX; ++k) {
+                    for (int k = 0; k <= LM; ++k) {
                         if (k <= ell) {
 #pragma unroll
                             for (int n = k; n <= 2 * k; ++n) {
@@ -198,7 +198,7 @@ __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta 
                     const double qq = e[sa] * e[sb];
                     const double wq = w[sa] * e[sb] + e[sa] * w[sb];
 #pragma unroll
-                    for (int k = 0; k <= EZ_ELL_MAX; ++k) {
+                    for (int k = 0; k <= LM; ++k) {
                         if (k <= ell) {
 #pragma unroll
                             for (int n = k; n <= 2 * k; ++n) {
@@ -233,7 +233,7 @@ __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta 
             if (m < 0) {
                 double awj = 1.0, jf = 1.0;
 #pragma unroll
-                for (int j = 0; j <= EZ_ELL_MAX; ++j) {
+                for (int j = 0; j <= LM; ++j) {
                     if (j <= ell) {
                         if (j > 0) { awj *= aw; jf *= (double)j; }
                         double v = -K * (((j & 1) ? -awj : awj) / (jf * (s + (double)j)));
@@ -250,7 +250,7 @@ __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta 
                 const double lnl2 = log(M->lam * M->lam);
                 double awj = 1.0;
 #pragma unroll
-                for (int J = 0; J <= EZ_ELL_MAX; ++J) {
+                for (int J = 0; J <= LM; ++J) {
                     if (J > ell) continue;
                     double c = 0.0;
                     if (J == m) c += -sm / mf * lnl2 + sm / mf * (-EZ_EULER);
@@ -288,7 +288,7 @@ __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta 
 #pragma unroll
         for (int i = 0; i < NNU; ++i)
 #pragma unroll
-            for (int k = 0; k <= EZ_ELL_MAX; ++k)
+            for (int k = 0; k <= LM; ++k)
                 if (k <= ell) R[(i * KL + k) * 64 + lane] = C[i][k];
     }
     __syncthreads();
@@ -298,7 +298,7 @@ __device__ void taylor_coeffs(const EzQuadArgs &args, int inst, const EzLatMeta 
 #pragma unroll
             for (int i = 0; i < NNU; ++i)
 #pragma unroll
-                for (int k = 0; k <= EZ_ELL_MAX; ++k)
+                for (int k = 0; k <= LM; ++k)
                     if (k <= ell) C[i][k] += R[(i * KL + k) * 64 + lane];
         }
     }
@@ -315,7 +315,7 @@ inline size_t probe_lds_bytes(int ell) {
 
 // Probe kernel: partial C_k(B w_hat_p) over one table slice for 64 probe directions,
 // one channel (value or strain component).  Grid: batch x probe blocks x slices x channels.
-template <int D, int NNU, bool GR>
+template <int D, int NNU, bool GR, int LM = EZ_ELL_MAX>
 __global__ __launch_bounds__(64 * EZ_HW) void ez_probe_kernel(EzQuadArgs args) {
     extern __shared__ double lds[];                 // probe_lds_bytes<NNU, GR>(args.ell_probe)
     const int nblk = (args.n_probe + 63) / 64;
@@ -344,13 +344,13 @@ __global__ __launch_bounds__(64 * EZ_HW) void ez_probe_kernel(EzQuadArgs args) {
         for (int c = 0; c < D; ++c) s = fma(M->B[i * D + c], wh[c], s);
         w[i] = s;
     }
-    double C[NNU][EZ_ELL_MAX + 1];
-    taylor_coeffs<D, NNU, GR>(args, inst, M, ell, w, C, lds, slice, S, ch);
+    double C[NNU][LM + 1];
+    taylor_coeffs<D, NNU, GR, LM>(args, inst, M, ell, w, C, lds, slice, S, ch);
     if (part != 0 || !valid) return;
 #pragma unroll
     for (int i = 0; i < NNU; ++i)
 #pragma unroll
-        for (int k = 0; k <= EZ_ELL_MAX; ++k)
+        for (int k = 0; k <= LM; ++k)
             if (k <= ell) out[i * (EZ_ELL_MAX + 1) + k] = C[i][k];
 }
 
@@ -470,10 +470,10 @@ __device__ __forceinline__ void contract_tensor(const EzQuadArgs &args, int inst
     }
 }
 
-// Direction kernel: a workgroup takes ndb = min(EZ_HDIR, 256 / n_combo) directions
-// of one lattice.  Phase 0: direction geometry and the tensors into LDS; phase 1:
-// one thread per (direction, order k) contracts the tensor with the monomials of
-// w_hat of degree 2k (C_k); phase 2: one thread per (direction, combination) builds
-// the product polynomial (PD coefficients, in registers) and its Hadamard
-// integrals; phase 3: per direction, the combinations are summed in fixed order.
+// Direction kernel (value calls): a workgroup takes EZ_HDIR = 64 directions of one
+// lattice, one per lane, and its EZ_HW waves share out the channels (phase 1: the
+// tensor contracted with the monomials of w_hat, C_k) and the combinations (phase 2:
+// the product polynomial, PD coefficients in registers, and its Hadamard integrals),
+// so that a wave's control flow is uniform; phase 3 adds the waves' per-result sums
+// in wave order.  The adjoint kernel keeps one thread per (direction, combination).
 }  // namespace
