@@ -140,13 +140,14 @@ ez_status ez_epstein_zeta(int d, const double *A_dev, int n_nu, const double *nu
  *   A_dev   : d*d doubles (one lattice)
  *   x_dev   : n_x x d shifts, y_dev : n_y x d points (Cartesian, row-major)
  *   precision : EZ_PREC_FP64 (FP64 products throughout) or EZ_PREC_MIXED (table
- *             entries whose weight exceeds e^{-18} for some x or y in FP64, the rest
+ *             entries whose weight exceeds e^{-21} for some x or y in FP64, the rest
  *             as split-BF16 products with FP32 accumulation per 32 entries and FP64
  *             accumulation across them)
  *   out_dev : n_nu x n_x x n_y x 2 doubles, (re, im) of Z(nu_k; x_j, y_m) at
  *             out_dev[2*((k*n_x + j)*n_y + m) + {0,1}]
- *   bound_dev : NULL or n_nu x n_x doubles: an a-priori bound of
- *             max_m |Z_mixed - Z_fp64| for each (nu_k, x_j) (zeros for FP64)
+ *   bound_dev : NULL or n_nu x (n_x + n_y) doubles, a shift term b[k][j] and a point
+ *             term b[k][n_x + m] per exponent: |Z_mixed - Z_fp64| at (nu_k, x_j, y_m) is
+ *             at most b[k][j] + b[k][n_x + m], a priori (zeros for FP64)
  *   status_dev : 1 uint32 (lattice flags, EZ_FLAG_POLE at nu = d, y in Lambda*), may be NULL
  * The call reads the lattice table sizes back once (it synchronises `stream`
  * after the setup kernel), so it cannot be captured into a graph.
@@ -283,10 +284,18 @@ ez_status ez_lattice_sums_grad(int batch, int d, const double *A_dev, int n_nu, 
 #define EZ_KERNEL_GRID 6       /* Z on a (shift x point) grid            */
 #define EZ_KERNEL_NODES_TAIL 7 /* last node tiles, terms split over waves */
 #define EZ_KERNEL_TAYLOR 8     /* probe values and Taylor tensors          */
-#define EZ_KERNEL_COUNT 9
+#define EZ_KERNEL_GRID_GEMM 9  /* the two matrix products of the grid (EZ_KERNEL_GRID: the rest) */
+#define EZ_KERNEL_COUNT 10
 ez_status ez_timing_enable(int enable);
 ez_status ez_timing_reset(void);
 ez_status ez_timing_read(int kernel, double *total_ms, int64_t *launches);
+
+/* Table sizes of the last ez_epstein_grid call on the current device (a tracing
+ * aid): n_real real-space and n_rec reciprocal entries, the inner dimensions of the
+ * real-space product ((n_nu n_x) x n_real times n_real x (2 n_y)) and of the
+ * reciprocal product ((2 n_x) x n_rec times n_rec x (n_nu n_y)); 0, 0 before the
+ * first call.  Errors: EZ_ERR_INVALID_ARG (null pointer). */
+ez_status ez_grid_last_tables(int64_t *n_real, int64_t *n_rec);
 
 /* Text of the last error on the calling host thread (never NULL). */
 const char *ez_last_error(void);
@@ -296,7 +305,7 @@ ez_status ez_finalize(void);
 
 /* A counter that changes whenever the library frees or moves device memory it
  * owns: a workspace buffer grown for a larger call, a cached plan evicted (the
- * cache keeps the 32 most recent plans per device), ez_finalize.  Work captured
+ * cache keeps the 128 most recently used plans per device), ez_finalize.  Work captured
  * into a HIP graph from calls of the library records the library's device
  * pointers; such a graph may be replayed only while this value is the one read
  * after the capture (the Python GraphedLatticeSums checks it). */

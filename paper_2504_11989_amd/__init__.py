@@ -100,8 +100,9 @@ def epstein_grid(A, nu: Sequence[float], x, y, lam: float = 0.0, a_cut: float = 
                  with_bound: bool = False, with_status: bool = False):
     """Z_{A Z^d, nu_k}(x_j, y_m) for every exponent, shift and point: complex128
     tensor (len(nu), n_x, n_y).  mixed=True: split-BF16 products for the far table
-    entries (see include/ezeta.h); with_bound also returns the a-priori bound of
-    max_m |Z_mixed - Z_fp64| per (nu_k, x_j), float64 (len(nu), n_x)."""
+    entries (see include/ezeta.h); with_bound also returns the a-priori bound as
+    float64 (len(nu), n_x + n_y): |Z_mixed - Z_fp64| at (nu_k, x_j, y_m) is at most
+    b[k, j] + b[k, n_x + m]."""
     torch = _torch()
     A, b, d = _lattices(A)
     if b != 1:
@@ -110,7 +111,7 @@ def epstein_grid(A, nu: Sequence[float], x, y, lam: float = 0.0, a_cut: float = 
     y = _dev_f64(y, A.device).reshape(-1, d).contiguous()
     nu_h, n_nu = _host_f64(nu)
     out = torch.empty((n_nu, x.shape[0], y.shape[0], 2), dtype=torch.float64, device=A.device)
-    bound = torch.empty((n_nu, x.shape[0]), dtype=torch.float64, device=A.device) if with_bound else None
+    bound = torch.empty((n_nu, x.shape[0] + y.shape[0]), dtype=torch.float64, device=A.device) if with_bound else None
     st = torch.zeros(1, dtype=torch.int32, device=A.device)
     check(lib().ez_epstein_grid(d, _dptr(A), n_nu, nu_h, x.shape[0], _dptr(x), y.shape[0], _dptr(y), float(lam),
                                 float(a_cut), PREC_MIXED if mixed else PREC_FP64, _dptr(out),

@@ -39,9 +39,9 @@ def spec_mix_a(n: int) -> int:
 EXPORTED = ("ez_epstein_zeta", "ez_epstein_grid", "ez_nbody_lattice_sum", "ez_atm_energy", "ez_lattice_sums", "ez_lattice_sums_grad",
             "ez_timing_enable", "ez_timing_reset", "ez_timing_read",
             "ez_last_error", "ez_finalize", "ez_version", "ez_workspace_generation", "ez_lattice_sums_noalloc",
-            "ez_lattice_sums_bound", "ez_direct_atm")
+            "ez_lattice_sums_bound", "ez_direct_atm", "ez_grid_last_tables")
 (KERNEL_SETUP, KERNEL_NODES, KERNEL_HADAMARD, KERNEL_FINALIZE, KERNEL_EPSTEIN, KERNEL_NODES_ADJ, KERNEL_GRID,
- KERNEL_NODES_TAIL, KERNEL_TAYLOR) = (0, 1, 2, 3, 4, 5, 6, 7, 8)
+ KERNEL_NODES_TAIL, KERNEL_TAYLOR, KERNEL_GRID_GEMM) = (0, 1, 2, 3, 4, 5, 6, 7, 8, 9)
 
 
 class EzError(RuntimeError):
@@ -113,6 +113,8 @@ def lib():
     L.ez_timing_reset.argtypes = []
     L.ez_timing_read.restype = I
     L.ez_timing_read.argtypes = [I, P, ctypes.POINTER(I64)]
+    L.ez_grid_last_tables.restype = I
+    L.ez_grid_last_tables.argtypes = [ctypes.POINTER(I64), ctypes.POINTER(I64)]
     _lib = L
     return L
 
@@ -136,6 +138,14 @@ def timing_read(kernel: int):
     n = ctypes.c_int64()
     check(lib().ez_timing_read(int(kernel), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def grid_last_tables():
+    """(n_real, n_rec): table sizes of the last grid call on the current device."""
+    a = ctypes.c_int64()
+    b = ctypes.c_int64()
+    check(lib().ez_grid_last_tables(ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def workspace_generation() -> int:

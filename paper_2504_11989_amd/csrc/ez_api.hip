@@ -174,6 +174,7 @@ struct DeviceState {
     DevBuf dxlist, dpart;        // direct ATM sum: outer points and partial sums
     // Epstein grid workspace
     DevBuf g_pts_x, g_pts_y, g_perm, g_counts, g_A64r, g_B64r, g_A64k, g_B64k, g_R, g_Q, g_wsum, g_stat;
+    long long grid_nr = 0, grid_nk = 0;          // table sizes of the last grid call
     DevBuf g_Ahr, g_Alr, g_Bhr, g_Blr, g_Ahk, g_Alk, g_Bhk, g_Blk;
     int n_cu = 0;
     hipStream_t side = nullptr;  // second stream: Hadamard branch concurrent with the nodes
@@ -1528,7 +1529,7 @@ ez_status ez_epstein_grid(int d, const double *A_dev, int n_nu, const double *nu
     g.Krn_pad = g.Krf_pad = g.Kr_pad;
     g.Kkn_pad = g.Kkf_pad = g.Kk_pad;
     g.mixed = precision == EZ_PREC_MIXED ? 1 : 0;
-    g.a_near = 18.0;
+    g.a_near = 21.0;
     g.ladder = 1;
     for (int i = 0; i < n_nu; ++i) {
         const double p2 = nu_host[i] - d + 2.0;
@@ -1550,7 +1551,7 @@ ez_status ez_epstein_grid(int d, const double *A_dev, int n_nu, const double *nu
         (st = grow(S->g_B64k, sizeof(double) * Kk * nn * Np)) ||
         (st = grow(S->g_R, sizeof(double) * nn * Mp * 2 * Np)) ||
         (st = grow(S->g_Q, sizeof(double) * 2 * Mp * nn * Np)) ||
-        (st = grow(S->g_wsum, sizeof(double) * 2 * (nn * Mp + nn * Kk))))
+        (st = grow(S->g_wsum, sizeof(double) * 2 * (nn * Mp + nn * Np))))
         return st;
     if (g.mixed &&
         ((st = grow(S->g_Ahr, 2 * nn * Mp * Kr)) || (st = grow(S->g_Alr, 2 * nn * Mp * Kr)) ||
@@ -1571,8 +1572,8 @@ ez_status ez_epstein_grid(int d, const double *A_dev, int n_nu, const double *nu
     g.R = (double *)S->g_R.p;
     g.Q = (double *)S->g_Q.p;
     g.wsum = (double *)S->g_wsum.p;
-    g.gmax = g.wsum + nn * Mp;
-    g.wall = g.gmax + nn * Kk;
+    g.gfar = g.wsum + nn * Mp;
+    g.wall = g.gfar + nn * Np;
     g.gall = g.wall + nn * Mp;
     if (g.mixed) {
         g.Ahr = (__bf16 *)S->g_Ahr.p; g.Alr = (__bf16 *)S->g_Alr.p;
@@ -1583,7 +1584,22 @@ ez_status ez_epstein_grid(int d, const double *A_dev, int n_nu, const double *nu
     g.out = out_dev;
     g.bound = bound_dev;
     g.status_acc = stat;
-    EZ_HIP_TRY(timed(EZ_KERNEL_GRID, s, [&] { return ez_grid_launch(g, s); }));
+    S->grid_nr = nr;
+    S->grid_nk = nk;
+    EZ_HIP_TRY(timed(EZ_KERNEL_GRID, s, [&] { return ez_grid_launch(g, s, EZ_GRID_PRE); }));
+    EZ_HIP_TRY(timed(EZ_KERNEL_GRID_GEMM, s, [&] { return ez_grid_launch(g, s, EZ_GRID_GEMM); }));
+    EZ_HIP_TRY(timed(EZ_KERNEL_GRID, s, [&] { return ez_grid_launch(g, s, EZ_GRID_POST); }));
+    return EZ_OK;
+}
+
+ez_status ez_grid_last_tables(int64_t *n_real, int64_t *n_rec) {
+    if (!n_real || !n_rec) return fail(EZ_ERR_INVALID_ARG, "null pointer argument");
+    int dev = 0;
+    EZ_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_mu);
+    DeviceState *S = device_state(dev);
+    *n_real = S->grid_nr;
+    *n_rec = S->grid_nk;
     return EZ_OK;
 }
 

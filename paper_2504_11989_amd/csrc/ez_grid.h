@@ -28,13 +28,18 @@ struct EzGridArgs {
     __bf16 *Ahk, *Alk, *Bhk, *Blk;   // (2 Mp) x Kkf_pad ; (n_nu Np) x Kkf_pad (transposed)
     double *R;                 // (n_nu Mp) x (2 Np)
     double *Q;                 // (2 Mp) x (n_nu Np)
-    double *wsum;              // [n_nu Mp] sum of |far real weights| per row (mixed)
-    double *gmax;              // [n_nu][Kk_pad] max |far G| per reciprocal column (mixed), follows wsum
-    double *wall;              // [n_nu Mp] sum of |weights| over every real column (mixed), follows gmax
-    double *gall;              // [n_nu][Kk_pad] max |G| per reciprocal column, every column (mixed), follows wall
+    double *wsum;              // [n_nu Mp] sum of |far real weights| per shift x_j (mixed)
+    double *gfar;              // [n_nu Np] sum of |far G| per point y_m (mixed), follows wsum
+    double *wall;              // [n_nu Mp] sum of |weights| over every real column (mixed), follows gfar
+    double *gall;              // [n_nu Np] sum of |G| over every reciprocal column (mixed), follows wall
     double *out;               // [n_nu][n_x][n_y][2]
-    double *bound;             // [n_nu][n_x] or NULL
+    double *bound;             // [n_nu][n_x + n_y] (shift terms, then point terms) or NULL
     uint32_t *status_acc;      // lattice status word (POLE bit)
 };
 
-hipError_t ez_grid_launch(const EzGridArgs &g, hipStream_t s);
+// the launch sequence in three parts: operands (points, classification, builds), the
+// two matrix products, and the combination with the bound
+#define EZ_GRID_PRE 1
+#define EZ_GRID_GEMM 2
+#define EZ_GRID_POST 4
+hipError_t ez_grid_launch(const EzGridArgs &g, hipStream_t s, int part);

@@ -49,8 +49,7 @@ __global__ __launch_bounds__(256) void grid_zero_kernel(double *p, long long n) 
     if (i < n) p[i] = 0.0;
 }
 
-
-// workgroup sum / max of one value per thread (256 threads), result valid in thread 0
+// workgroup sum of one value per thread (256 threads), result valid in thread 0
 __device__ __forceinline__ double block_sum(double v, double *sh) {
     for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -59,18 +58,7 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     __syncthreads();
     return sh[0] + sh[1] + sh[2] + sh[3];
 }
-__device__ __forceinline__ double block_max(double v, double *sh) {
-    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) sh[w] = v;
-    __syncthreads();
-    return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
-}
 
-__device__ __forceinline__ void atomic_max_pos(double *p, double v) {
-    atomicMax(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v));
-}
 
 // ---------------------------------------------------------------------------
 // points: t_j = A^{-1} x_j reduced to [-1/2,1/2) (n0_j the integer part, on-lattice
@@ -308,74 +296,87 @@ __global__ __launch_bounds__(256) void grid_build_b_kernel(EzGridArgs g) {
 // base (e^{-a} with E_1 or E_{1/2}) and the recurrences p E_{p+1} = e^{-a} - a E_p
 // when every 2p is an integer, else the incomplete gamma per exponent.
 // Grid: (Np / 256, Kk_pad).
+// B operands of the reciprocal product: G_nu(|m* + y_m|^2) for reciprocal column kr
+// and point m, FP64 for the near columns and split BF16 for the far ones.  A thread
+// takes one point and EZ_GRID_GCH consecutive columns; in mixed precision it adds up
+// |G| of its columns per exponent (far ones and all) for the error bound, one atomic
+// per (exponent, point) and workgroup.
+constexpr int EZ_GRID_GCH = 32;
 __global__ __launch_bounds__(256) void grid_build_g_kernel(EzGridArgs g) {
-    __shared__ double red[4];
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    const int kr = blockIdx.y;
     const EzLatMeta *M = g.meta;
     const int d = g.d;
     const int nnear = g.counts[2], nfar = g.counts[3];
-    double vals[EZ_NU_MAX];
-    for (int i = 0; i < EZ_NU_MAX; ++i) vals[i] = 0.0;
-    if (kr < nnear + nfar && m < g.n_y && M->status == 0) {
-        const double *e = g.tab.rec + (size_t)g.perm_rec[kr] * 4;
+    const int kr0 = blockIdx.y * EZ_GRID_GCH;
+    double sfar[EZ_NU_MAX], sall[EZ_NU_MAX];
+    for (int i = 0; i < EZ_NU_MAX; ++i) sfar[i] = sall[i] = 0.0;
+    double yr[3] = {0, 0, 0};
+    if (m < g.n_y) {
         const double *ps = g.pts_y + (size_t)m * 4;
-        double yr[3] = {0, 0, 0};
         for (int r = 0; r < d; ++r)
             for (int k = 0; k < d; ++k) yr[r] += M->B[r * d + k] * ps[k];
-        double r2 = 0.0;
-        for (int t = 0; t < d; ++t) { const double q = e[t] + yr[t]; r2 += q * q; }
-        const double a = M->alpha * r2;
-        if (r2 == 0.0) {                     // m* + y = 0: continuation in nu, -K_nu / s
-            for (int i = 0; i < g.n_nu; ++i) {
-                const double s = 0.5 * ((double)d - g.nu[i]);
-                if (s == 0.0) {
-                    atomicOr(g.status_acc, 0x10u);
-                    vals[i] = __longlong_as_double(0x7ff8000000000000ll);
-                } else {
-                    vals[i] = -g.kpref[i] / s;
-                }
-            }
-        } else if (a <= M->a_cut) {
-            if (g.ladder) {
-                const double ex = ez_expm(a), inv = ez_rcp(a);
-                bool ne1 = false, nh = false;
-                for (int i = 0; i < g.n_nu; ++i) {
-                    ne1 = ne1 || ((g.p2[i] & 1) == 0 && g.p2[i] >= 2);
-                    nh = nh || (g.p2[i] & 1);
-                }
-                double E1 = 0.0;
-                if (ne1) E1 = (a < 0.25) ? ez_e1_small(a) : ex * ez_e1w_scaled(inv);
-                const double Eh = nh ? ez_ehalf(a) : 0.0;
-                for (int i = 0; i < g.n_nu; ++i) vals[i] = g.kpref[i] * ez_ep_from(g.p2[i], a, ex, inv, E1, Eh);
-            } else {
+    }
+    for (int kr = kr0; kr < kr0 + EZ_GRID_GCH && kr < g.Kk_pad; ++kr) {
+        double vals[EZ_NU_MAX];
+        for (int i = 0; i < EZ_NU_MAX; ++i) vals[i] = 0.0;
+        if (kr < nnear + nfar && m < g.n_y && M->status == 0) {
+            const double *e = g.tab.rec + (size_t)g.perm_rec[kr] * 4;
+            double r2 = 0.0;
+            for (int t = 0; t < d; ++t) { const double q = e[t] + yr[t]; r2 += q * q; }
+            const double a = M->alpha * r2;
+            if (r2 == 0.0) {                     // m* + y = 0: continuation in nu, -K_nu / s
                 for (int i = 0; i < g.n_nu; ++i) {
                     const double s = 0.5 * ((double)d - g.nu[i]);
-                    vals[i] = g.kpref[i] * pow(a, -s) * ez_gamma_upper(s, a);
+                    if (s == 0.0) {
+                        atomicOr(g.status_acc, 0x10u);
+                        vals[i] = __longlong_as_double(0x7ff8000000000000ll);
+                    } else {
+                        vals[i] = -g.kpref[i] / s;
+                    }
                 }
+            } else if (a <= M->a_cut) {
+                if (g.ladder) {
+                    const double ex = ez_expm(a), inv = ez_rcp(a);
+                    bool ne1 = false, nh = false;
+                    for (int i = 0; i < g.n_nu; ++i) {
+                        ne1 = ne1 || ((g.p2[i] & 1) == 0 && g.p2[i] >= 2);
+                        nh = nh || (g.p2[i] & 1);
+                    }
+                    double E1 = 0.0;
+                    if (ne1) E1 = (a < 0.25) ? ez_e1_small(a) : ex * ez_e1w_scaled(inv);
+                    const double Eh = nh ? ez_ehalf(a) : 0.0;
+                    for (int i = 0; i < g.n_nu; ++i) vals[i] = g.kpref[i] * ez_ep_from(g.p2[i], a, ex, inv, E1, Eh);
+                } else {
+                    for (int i = 0; i < g.n_nu; ++i) {
+                        const double s = 0.5 * ((double)d - g.nu[i]);
+                        vals[i] = g.kpref[i] * pow(a, -s) * ez_gamma_upper(s, a);
+                    }
+                }
+            }
+        }
+        for (int i = 0; i < g.n_nu; ++i) {
+            const size_t col = (size_t)i * g.Np + m;
+            const double v = vals[i];
+            if (m < g.Np) {
+                if (kr < g.Kkn_pad) g.B64k[(size_t)kr * (g.n_nu * g.Np) + col] = (kr < nnear) ? v : 0.0;
+                const int kf = kr - nnear;
+                if (g.mixed && kf >= 0 && kf < g.Kkf_pad) {
+                    __bf16 h, l;
+                    split_bf16(kf < nfar ? v : 0.0, &h, &l);
+                    g.Bhk[col * g.Kkf_pad + kf] = h;
+                    g.Blk[col * g.Kkf_pad + kf] = l;
+                }
+            }
+            if (v == v) {
+                sall[i] += fabs(v);
+                if (kr >= nnear) sfar[i] += fabs(v);
             }
         }
     }
-    for (int i = 0; i < g.n_nu; ++i) {
-        const size_t col = (size_t)i * g.Np + m;
-        const double v = vals[i];
-        if (m < g.Np) {
-            if (kr < g.Kkn_pad) g.B64k[(size_t)kr * (g.n_nu * g.Np) + col] = (kr < nnear) ? v : 0.0;
-            const int kf = kr - nnear;
-            if (g.mixed && kf >= 0 && kf < g.Kkf_pad) {
-                __bf16 h, l;
-                split_bf16(kf < nfar ? v : 0.0, &h, &l);
-                g.Bhk[col * g.Kkf_pad + kf] = h;
-                g.Blk[col * g.Kkf_pad + kf] = l;
-            }
-        }
-        if (g.mixed && kr < nnear + nfar) {
-            // largest |G| per (exponent, reciprocal column) for the error bound
-            const double mx = block_max((m < g.n_y && v == v) ? fabs(v) : 0.0, red);
-            if (threadIdx.x == 0 && mx > 0.0) {
-                atomic_max_pos(&g.gall[(size_t)i * g.Kk_pad + kr], mx);
-                if (kr >= nnear) atomic_max_pos(&g.gmax[(size_t)i * g.Kkf_pad + (kr - nnear)], mx);
-            }
+    if (g.mixed && m < g.n_y) {
+        for (int i = 0; i < g.n_nu; ++i) {
+            if (sfar[i] != 0.0) atomicAdd(&g.gfar[(size_t)i * g.Np + m], sfar[i]);
+            if (sall[i] != 0.0) atomicAdd(&g.gall[(size_t)i * g.Np + m], sall[i]);
         }
     }
 }
@@ -385,10 +386,9 @@ __global__ __launch_bounds__(256) void grid_build_g_kernel(EzGridArgs g) {
 //         + sum_{k < Kf} (Ah + Al)[r][k] (Bh + Bl)[k][c]        (split BF16, far entries)
 // The FP64 part runs over the near table entries (zero-padded to multiples of 16),
 // the BF16 part over the far ones (padded to 32): per 32-wide step Ah Bh + Ah Bl +
-// Al Bh by v_mfma_f32_16x16x32_bf16, accumulated in FP32 over K (the far entries
-// total below e^{-a_near} of the sum, so the FP32 accumulation error K 2^-24 of
-// their part stays far below the FP64 rounding of the whole).  The two accumulators
-// are merged through LDS and C is written once.  A, A64 row-major; B64 row-major
+// Al Bh by v_mfma_f32_16x16x32_bf16 into a zeroed FP32 tile, which is then added to
+// the FP64 accumulators (the FP32 rounding covers 96 products at a time), and C is
+// written once.  A, A64 row-major; B64 row-major
 // (K x ldb); Bh, Bl stored transposed (columns x ldbh, K contiguous).  64 x 64 tile
 // per workgroup, each wave a 32 x 32 quarter.
 struct GemmF64Tiles {
@@ -401,16 +401,12 @@ struct alignas(16) GemmBf16Tiles {
     __bf16 Bsh[64][40];
     __bf16 Bsl[64][40];
 };
-// mixed: the FP32 merge tile reuses the FP64 tiles once both loops are done
 struct alignas(16) GemmLdsMixed {
-    union {
-        GemmF64Tiles f;
-        float Cf[64][65];
-    } u;
+    GemmF64Tiles f;
     GemmBf16Tiles b;
 };
 __device__ __forceinline__ GemmF64Tiles &f64_tiles(GemmF64Tiles &L) { return L; }
-__device__ __forceinline__ GemmF64Tiles &f64_tiles(GemmLdsMixed &L) { return L.u.f; }
+__device__ __forceinline__ GemmF64Tiles &f64_tiles(GemmLdsMixed &L) { return L.f; }
 
 template <bool MIXED>
 __global__ __launch_bounds__(256) void gemm_mixed_kernel(const double *A, int lda, const double *B, int ldb,
@@ -453,17 +449,10 @@ __global__ __launch_bounds__(256) void gemm_mixed_kernel(const double *A, int ld
         }
         __syncthreads();
     }
-    int nft = 0;
     if constexpr (MIXED) {
-        nft = (*Kf_dev + 31) / 32;
+        const int nft = (*Kf_dev + 31) / 32;
         __bf16 (*Ash)[40] = L.b.Ash, (*Asl)[40] = L.b.Asl, (*Bsh)[40] = L.b.Bsh, (*Bsl)[40] = L.b.Bsl;
-        float (*Cf)[65] = L.u.Cf;
-        if (nft > 0) {                                   // uniform over the workgroup
-            f32x4 accf[2][2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) accf[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        {
             for (int kt = 0; kt < nft; ++kt) {
                 {
                     const int r = tid >> 2, k8 = (tid & 3) * 8;
@@ -483,28 +472,27 @@ __global__ __launch_bounds__(256) void gemm_mixed_kernel(const double *A, int ld
                     bh[j] = *reinterpret_cast<const bf16x8 *>(&Bsh[32 * wc + 16 * j + (lane & 15)][8 * (lane >> 4)]);
                     bl[j] = *reinterpret_cast<const bf16x8 *>(&Bsl[32 * wc + 16 * j + (lane & 15)][8 * (lane >> 4)]);
                 }
+                // v_mfma_f32_16x16x32_bf16 leaves D[4 (l/16) + r][l % 16] in lane l, register
+                // r, and v_mfma_f64_16x16x4 D[l/16 + 4 r][l % 16]: the A rows are fed in the
+                // order pi(rho) = rho/4 + 4 (rho % 4), so that each lane's FP32 results are
+                // the rows of its FP64 accumulators
+                const int pr = ((lane & 15) >> 2) + 4 * (lane & 3);
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
-                    const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(&Ash[32 * wr + 16 * i + (lane & 15)][8 * (lane >> 4)]);
-                    const bf16x8 al = *reinterpret_cast<const bf16x8 *>(&Asl[32 * wr + 16 * i + (lane & 15)][8 * (lane >> 4)]);
+                    const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(&Ash[32 * wr + 16 * i + pr][8 * (lane >> 4)]);
+                    const bf16x8 al = *reinterpret_cast<const bf16x8 *>(&Asl[32 * wr + 16 * i + pr][8 * (lane >> 4)]);
 #pragma unroll
                     for (int j = 0; j < 2; ++j) {
-                        accf[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], accf[i][j], 0, 0, 0);
-                        accf[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], accf[i][j], 0, 0, 0);
-                        accf[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], accf[i][j], 0, 0, 0);
+                        f32x4 t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], f32x4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+                        t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], t, 0, 0, 0);
+                        t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], t, 0, 0, 0);
+                        // FP32 over the chunk's 3 x 32 products, FP64 across chunks
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)t[r];
                     }
                 }
                 __syncthreads();
             }
-            // v_mfma_f32_16x16x32_bf16: lane l, register r holds D[4 (l/16) + r][l % 16]
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        Cf[32 * wr + 16 * i + 4 * (lane >> 4) + r][32 * wc + 16 * j + (lane & 15)] = accf[i][j][r];
-            __syncthreads();
         }
     }
 #pragma unroll
@@ -515,11 +503,7 @@ __global__ __launch_bounds__(256) void gemm_mixed_kernel(const double *A, int ld
             for (int r = 0; r < 4; ++r) {
                 // v_mfma_f64_16x16x4: lane l, register r holds D[l/16 + 4 r][l % 16]
                 const int rl = 32 * wr + 16 * i + (lane >> 4) + 4 * r, cl = 32 * wc + 16 * j + (lane & 15);
-                double v = acc[i][j][r];
-                if constexpr (MIXED) {
-                    if (nft > 0) v += (double)L.u.Cf[rl][cl];
-                }
-                C[(size_t)(row0 + rl) * ldc + col0 + cl] = v;
+                C[(size_t)(row0 + rl) * ldc + col0 + cl] = acc[i][j][r];
             }
 }
 
@@ -559,64 +543,84 @@ __global__ __launch_bounds__(256) void grid_combine_kernel(EzGridArgs g) {
 }
 
 // a-priori bound of |Z_mixed - Z_fp64| per (nu, x_j), all phases having modulus <= 1:
-//  split-BF16 far products: (3 2^-17 + K_far 2^-24) (sum of |far weights| over the real
-//    columns + sum over reciprocal far columns of max_m |G|);
-//  FP64 products (both forms, their summation orders differ): 2 gamma_K with
+// at (x_j, y_m) the real-space sum over z has the weights of row j and the reciprocal
+// sum over m* those of point m, so the bound is a term per shift plus a term per point:
+//  split-BF16 far products: with a = a_hi + a_lo + da (a_hi = bf16(fp32(a)), a_lo =
+//    bf16(fp32(a - a_hi)), |da| <= (2^-8 + 2^-24)^2 |a|, |a_lo| <= 2^-8 (1 + 2^-7) |a|),
+//    ab - (a_hi b_hi + a_hi b_lo + a_lo b_hi) = a_lo b_lo + a_hi db + da b_hi + da db,
+//    at most 3.05 2^-16 |ab|; the products are exact in FP32 and each chunk adds 96 of
+//    them from zero in FP32, at most gamma_97 (1.01 sum |ab|), gamma_n = n 2^-24 /
+//    (1 - n 2^-24); so (3.05 2^-16 + 1.01 gamma_97) times (the sum of |far weights|
+//    of row j + the sum of |far G| of point m);
+//  FP64 products and sums (both forms, their summation orders differ): 2 gamma_K with
 //    gamma_K = K 2^-53 / (1 - K 2^-53), K the table size, times the same sums over
 //    every column;
 // each for the real and the imaginary part (factor 2)
 __global__ __launch_bounds__(256) void grid_bound_kernel(EzGridArgs g) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= g.n_nu * g.n_x) return;
-    const int nu_i = idx / g.n_x, j = idx - nu_i * g.n_x;
-    double sg = 0.0, sga = 0.0;
-    for (int k = 0; k < g.counts[3]; ++k) sg += g.gmax[(size_t)nu_i * g.Kkf_pad + k];
-    for (int k = 0; k < g.counts[2] + g.counts[3]; ++k) sga += g.gall[(size_t)nu_i * g.Kk_pad + k];
-    const double ubf = 3.0 * 0x1p-17 + (double)(g.counts[1] + g.counts[3] + 32) * 0x1p-24 + 0x1p-24;
+    const int nxy = g.n_x + g.n_y;
+    if (idx >= g.n_nu * nxy) return;
+    const int nu_i = idx / nxy, q = idx - nu_i * nxy;
+    const double g97 = 97.0 * 0x1p-24 / (1.0 - 97.0 * 0x1p-24);
+    const double ubf = 3.05 * 0x1p-16 + 1.01 * g97;
     const double K = (double)(g.counts[0] + g.counts[1] + g.counts[2] + g.counts[3]) + 4.0;
     const double g64 = 2.0 * K * 0x1p-53 / (1.0 - K * 0x1p-53);
-    g.bound[idx] = 2.0 * (ubf * (g.wsum[nu_i * g.Mp + j] + sg) + g64 * (g.wall[nu_i * g.Mp + j] + sga));
+    double far, all;
+    if (q < g.n_x) {                   // shift term: the real-space row sums
+        far = g.wsum[nu_i * g.Mp + q];
+        all = g.wall[nu_i * g.Mp + q];
+    } else {                           // point term: the reciprocal column sums
+        far = g.gfar[(size_t)nu_i * g.Np + (q - g.n_x)];
+        all = g.gall[(size_t)nu_i * g.Np + (q - g.n_x)];
+    }
+    g.bound[idx] = 2.0 * (ubf * far + g64 * all);
 }
 
 }  // namespace
 
-hipError_t ez_grid_launch(const EzGridArgs &g, hipStream_t s) {
-    const int mx = std::max(g.n_x, g.n_y);
-    if (g.mixed) {
-        const long long nz = 2 * ((long long)g.n_nu * g.Mp + (long long)g.n_nu * g.Kk_pad);   // wsum, gmax, wall, gall
-        hipLaunchKernelGGL(grid_zero_kernel, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, g.wsum, nz);
+hipError_t ez_grid_launch(const EzGridArgs &g, hipStream_t s, int part) {
+    hipError_t e = hipSuccess;
+    if (part & EZ_GRID_PRE) {
+        const int mx = std::max(g.n_x, g.n_y);
+        if (g.mixed) {
+            const long long nz = 2 * ((long long)g.n_nu * g.Mp + (long long)g.n_nu * g.Np);   // wsum, gfar, wall, gall
+            hipLaunchKernelGGL(grid_zero_kernel, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, g.wsum, nz);
+        }
+        hipLaunchKernelGGL(grid_points_kernel, dim3((mx + 255) / 256), dim3(256), 0, s, g);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(grid_classify_kernel, dim3(1), dim3(256), 0, s, g);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int kmax = std::max(g.Kr_pad, g.Kk_pad);
+        hipLaunchKernelGGL(grid_build_a_kernel, dim3((kmax + 255) / 256, g.n_nu * g.Mp + 2 * g.Mp), dim3(256), 0, s, g);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(grid_build_b_kernel, dim3((2 * g.Np + 255) / 256, g.Kr_pad), dim3(256), 0, s, g);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(grid_build_g_kernel, dim3((g.Np + 255) / 256, (g.Kk_pad + EZ_GRID_GCH - 1) / EZ_GRID_GCH),
+                           dim3(256), 0, s, g);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(grid_points_kernel, dim3((mx + 255) / 256), dim3(256), 0, s, g);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(grid_classify_kernel, dim3(1), dim3(256), 0, s, g);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int kmax = std::max(g.Kr_pad, g.Kk_pad);
-    hipLaunchKernelGGL(grid_build_a_kernel, dim3((kmax + 255) / 256, g.n_nu * g.Mp + 2 * g.Mp), dim3(256), 0, s, g);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(grid_build_b_kernel, dim3((2 * g.Np + 255) / 256, g.Kr_pad), dim3(256), 0, s, g);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(grid_build_g_kernel, dim3((g.Np + 255) / 256, g.Kk_pad), dim3(256), 0, s, g);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    // real space: (n_nu Mp) x (2 Np);  reciprocal: (2 Mp) x (n_nu Np)
-    auto gemm = g.mixed ? gemm_mixed_kernel<true> : gemm_mixed_kernel<false>;
-    hipLaunchKernelGGL(gemm, dim3(2 * g.Np / 64, g.n_nu * g.Mp / 64), dim3(256), 0, s, g.A64r, g.Krn_pad, g.B64r,
-                       2 * g.Np, g.counts + 0, g.Ahr, g.Alr, g.Krf_pad, g.Bhr, g.Blr, g.Krf_pad, g.counts + 1, g.R,
-                       2 * g.Np);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(gemm, dim3(g.n_nu * g.Np / 64, 2 * g.Mp / 64), dim3(256), 0, s, g.A64k, g.Kkn_pad, g.B64k,
-                       g.n_nu * g.Np, g.counts + 2, g.Ahk, g.Alk, g.Kkf_pad, g.Bhk, g.Blk, g.Kkf_pad, g.counts + 3, g.Q,
-                       g.n_nu * g.Np);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (part & EZ_GRID_GEMM) {
+        // real space: (n_nu Mp) x (2 Np);  reciprocal: (2 Mp) x (n_nu Np)
+        auto gemm = g.mixed ? gemm_mixed_kernel<true> : gemm_mixed_kernel<false>;
+        hipLaunchKernelGGL(gemm, dim3(2 * g.Np / 64, g.n_nu * g.Mp / 64), dim3(256), 0, s, g.A64r, g.Krn_pad, g.B64r,
+                           2 * g.Np, g.counts + 0, g.Ahr, g.Alr, g.Krf_pad, g.Bhr, g.Blr, g.Krf_pad, g.counts + 1, g.R,
+                           2 * g.Np);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(gemm, dim3(g.n_nu * g.Np / 64, 2 * g.Mp / 64), dim3(256), 0, s, g.A64k, g.Kkn_pad, g.B64k,
+                           g.n_nu * g.Np, g.counts + 2, g.Ahk, g.Alk, g.Kkf_pad, g.Bhk, g.Blk, g.Kkf_pad, g.counts + 3, g.Q,
+                           g.n_nu * g.Np);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (!(part & EZ_GRID_POST)) return hipSuccess;
     const long long total = (long long)g.n_nu * g.n_x * g.n_y;
     hipLaunchKernelGGL(grid_combine_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (g.bound) {
         if (g.mixed)   // FP64 products: no bound beyond rounding, zeros
-            hipLaunchKernelGGL(grid_bound_kernel, dim3((g.n_nu * g.n_x + 255) / 256), dim3(256), 0, s, g);
+            hipLaunchKernelGGL(grid_bound_kernel, dim3((g.n_nu * (g.n_x + g.n_y) + 255) / 256), dim3(256), 0, s, g);
         else
-            hipLaunchKernelGGL(grid_zero_kernel, dim3((g.n_nu * g.n_x + 255) / 256), dim3(256), 0, s, g.bound,
-                               (long long)g.n_nu * g.n_x);
+            hipLaunchKernelGGL(grid_zero_kernel, dim3((g.n_nu * (g.n_x + g.n_y) + 255) / 256), dim3(256), 0, s,
+                               g.bound, (long long)g.n_nu * (g.n_x + g.n_y));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
