@@ -279,8 +279,14 @@ hipError_t launch_had_t(const EzQuadArgs &args, int n_htiles, hipStream_t stream
     if (part & EZ_HAD_PRE) {            // probe values and Taylor tensors
         const int nblk = (args.n_probe + 63) / 64;
         const int nch = true ? args.n_ch : 1;
-        hipLaunchKernelGGL((ez_probe_kernel<D, NNU, true>), dim3(args.batch * nblk * args.n_slice * nch), dim3(64 * EZ_HW),
-                           (probe_lds_bytes<NNU, true>(args.ell_probe)), stream, args);
+        // Taylor orders up to 4 (the usual plans) keep 5 coefficients per exponent in
+        // registers, higher ones 9
+        if (args.ell_probe <= 4)
+            hipLaunchKernelGGL((ez_probe_kernel<D, NNU, true, 4>), dim3(args.batch * nblk * args.n_slice * nch),
+                               dim3(64 * EZ_HW), (probe_lds_bytes<NNU, true>(args.ell_probe)), stream, args);
+        else
+            hipLaunchKernelGGL((ez_probe_kernel<D, NNU, true>), dim3(args.batch * nblk * args.n_slice * nch),
+                               dim3(64 * EZ_HW), (probe_lds_bytes<NNU, true>(args.ell_probe)), stream, args);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         int tdim = 0;
