@@ -462,6 +462,39 @@ def meromorphic_leg(args) -> dict:
             "max_rel_err_vs_oracle_every_10th": err, "max_deviation_over_parity_bar": over}
 
 
+def batch_scan_leg(args) -> dict:
+    """The node stage of the three-lattice ATM call at several copies of the batch
+    (sc, fcc, bcc repeated), HIP events on the launch stream, 10 calls each: how far
+    the three-lattice call is from the device's throughput at large batches."""
+    import numpy as np
+    import torch
+    import paper_2504_11989_amd as ez
+    import workloads as W
+    from paper_2504_11989_amd import _native as nat
+    spec = dict(W.SPEC_FULL_3D)
+    lats = [W.sc(), W.fcc(), W.bcc()]
+    rows = []
+    for r in (1, 2, 4, 8, 16):
+        A = torch.tensor(np.stack(lats * r), dtype=torch.float64, device="cuda")
+        ez.atm_energy(A, spec)
+        torch.cuda.synchronize()
+        nat.timing_reset()
+        nat.timing_enable(True)
+        for _ in range(10):
+            ez.atm_energy(A, spec)
+        torch.cuda.synchronize()
+        nat.timing_enable(False)
+        ms, n = nat.timing_read(nat.KERNEL_NODES)
+        mt, _ = nat.timing_read(nat.KERNEL_NODES_TAIL)
+        per_call = (ms + mt) / 10
+        flops = node_kernel_flops_per_node(spec["lam"], spec["a_cut"], 4) * W.n_nodes(3, spec) * 3 * r
+        rows.append({"lattices": 3 * r, "node_ms_per_call": round(per_call, 4),
+                     "ms_per_lattice": round(per_call / (3 * r), 5),
+                     "frac_fp64_peak": round(flops / (per_call * 1e-3) / 1e12 / PEAK_FP64_VALU_TFLOPS, 4)})
+    return {"workload": "three-lattice ATM call (full plan) repeated 1, 2, 4, 8, 16 times in one batch",
+            "rows": rows}
+
+
 def direct_leg(args) -> dict:
     """GPU direct sums of the ATM energy over boxes (ez_direct_atm): the paper's
     printed direct sums (Lambda = Z at L = 5000, the square lattice at L = 250 and its
@@ -620,6 +653,8 @@ def main() -> int:
     ap.add_argument("--no-phase", action="store_true", help="skip the phase-diagram / Bain-path leg")
     ap.add_argument("--no-highn", action="store_true", help="skip the high-n / kappa-study leg")
     ap.add_argument("--no-direct", action="store_true", help="skip the GPU direct-sum leg")
+    ap.add_argument("--batch-scan", action="store_true",
+                    help="also time the node stage of the ATM call at 1-16 copies of the three lattices")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 1 GiB device-to-device copies (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -780,6 +815,8 @@ def main() -> int:
         line["meromorphic_1d"] = leg("1-D continuation scan", lambda: meromorphic_leg(args))
     if not args.no_direct:
         line["direct_sums"] = leg("direct sums", lambda: direct_leg(args))
+    if args.batch_scan:
+        line["c2_batch_scan"] = leg("batch scan", lambda: batch_scan_leg(args))
     if not args.no_c3:
         line["c3_scan"] = leg("c3 scan", lambda: c3_scan_leg(args))
     if not args.no_c4:
