@@ -877,7 +877,25 @@ ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, co
     sa.grad = grad ? 1 : 0;
     sa.status_out = nullptr;
     fill_nu_constants(prog, sa);
-    EZ_HIP_TRY(tm(EZ_KERNEL_SETUP, stream, [&] { return ez_launch_setup(sa, batch, stream); }));
+    const bool two = side && !(C.flags & EZ_SPEC_SERIAL);
+    // Derivative calls keep the (seven-channel) probe and the tensor kernel on the
+    // caller's stream before the adjoint node kernel unless the batch's tiles fill
+    // more than eight rounds of the device (throughput-bound: the 4096-lattice scan).
+    int round = 0;
+    {
+        EzQuadArgs probe_args;
+        std::memset(&probe_args, 0, sizeof(probe_args));
+        probe_args.prog = prog;
+        round = n_cu * ez_nodes_tile_blocks_per_cu(probe_args);
+    }
+    const bool big = two && (!grad || P.n_tiles > 8 * round);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    EZ_HIP_TRY(hipStreamIsCapturing(stream, &cap));
+    // the fork event after the setup is recorded by the setup launch itself (no marker
+    // packet between the setup and the node kernel), or by hipEventRecord under capture
+    const bool ext_setup = big && cap == hipStreamCaptureStatusNone;
+    EZ_HIP_TRY(tm(EZ_KERNEL_SETUP, stream,
+                  [&] { return ez_launch_setup(sa, batch, stream, ext_setup ? ev_setup : nullptr); }));
 
     EzQuadArgs qa;
     qa.prog = prog;
@@ -942,27 +960,13 @@ ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, co
     // drains, and runs beside its last, partly filled round of tiles (three-lattice ATM
     // derivative, 263424 nodes each: 0.869 ms per step, 0.901 ms with the direction
     // kernel before the nodes).
-    const bool two = side && !(C.flags & EZ_SPEC_SERIAL);
-    // Derivative calls keep the (seven-channel) probe and the tensor kernel on the
-    // caller's stream before the adjoint node kernel unless the batch's tiles fill
-    // more than eight rounds of the device (throughput-bound: the 4096-lattice scan).
-    int round = 0;
-    {
-        EzQuadArgs probe_args;
-        std::memset(&probe_args, 0, sizeof(probe_args));
-        probe_args.prog = prog;
-        round = n_cu * ez_nodes_tile_blocks_per_cu(probe_args);
-    }
-    const bool big = two && (!grad || P.n_tiles > 8 * round);
     hipStream_t hs = stream;
     if (big) {
-        EZ_HIP_TRY(hipEventRecord(ev_setup, stream));
+        if (!ext_setup) EZ_HIP_TRY(hipEventRecord(ev_setup, stream));
         EZ_HIP_TRY(hipStreamWaitEvent(side, ev_setup, 0));
         hs = side;
         EZ_HIP_TRY(tm(EZ_KERNEL_TAYLOR, hs, [&] { return had(hs, EZ_HAD_PRE, nullptr); }));
     } else {
-        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-        EZ_HIP_TRY(hipStreamIsCapturing(stream, &cap));
         const bool ext = two && cap == hipStreamCaptureStatusNone;
         EZ_HIP_TRY(tm(EZ_KERNEL_TAYLOR, stream, [&] { return had(stream, EZ_HAD_PRE, ext ? ev_setup : nullptr); }));
         if (two) {

@@ -89,7 +89,7 @@ struct EzEpsteinArgs {
     uint32_t *status;
 };
 
-hipError_t ez_launch_setup(const EzSetupArgs &args, int batch, hipStream_t stream);
+hipError_t ez_launch_setup(const EzSetupArgs &args, int batch, hipStream_t stream, hipEvent_t done = nullptr);
 hipError_t ez_launch_nodes(const EzQuadArgs &args, int n_tiles, hipStream_t stream);
 // tiles [n_main, n_tiles): EZ_TAIL_PARTS workgroups per 64-node group
 hipError_t ez_launch_nodes_split(const EzQuadArgs &args, hipStream_t stream);

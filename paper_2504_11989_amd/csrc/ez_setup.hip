@@ -18,6 +18,8 @@
 // per-exponent constants are computed in one parallel phase.  Point order is
 // the enumeration order of the integer box (n_1 fastest), made deterministic by
 // a ballot/prefix compaction with one barrier per chunk.
+#include <hip/hip_ext.h>
+
 #include "ez_internal.h"
 #include "ez_math.h"
 #include "ez_kernels.h"
@@ -342,11 +344,13 @@ __global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
 
 }  // namespace
 
-hipError_t ez_launch_setup(const EzSetupArgs &args, int batch, hipStream_t stream) {
+hipError_t ez_launch_setup(const EzSetupArgs &args, int batch, hipStream_t stream, hipEvent_t done) {
+    // `done` (if given) is recorded by the launch itself: no marker packet between
+    // the setup and the next kernel on `stream`
     switch (args.prog.d) {
-        case 1: hipLaunchKernelGGL(ez_setup_kernel<1>, dim3(batch), dim3(SB), 0, stream, args); break;
-        case 2: hipLaunchKernelGGL(ez_setup_kernel<2>, dim3(batch), dim3(SB), 0, stream, args); break;
-        case 3: hipLaunchKernelGGL(ez_setup_kernel<3>, dim3(batch), dim3(SB), 0, stream, args); break;
+        case 1: hipExtLaunchKernelGGL(ez_setup_kernel<1>, dim3(batch), dim3(SB), 0, stream, nullptr, done, 0, args); break;
+        case 2: hipExtLaunchKernelGGL(ez_setup_kernel<2>, dim3(batch), dim3(SB), 0, stream, nullptr, done, 0, args); break;
+        case 3: hipExtLaunchKernelGGL(ez_setup_kernel<3>, dim3(batch), dim3(SB), 0, stream, nullptr, done, 0, args); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
