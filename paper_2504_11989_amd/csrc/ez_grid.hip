@@ -291,92 +291,120 @@ __global__ __launch_bounds__(256) void grid_build_b_kernel(EzGridArgs g) {
     }
 }
 
-// reciprocal B operand G_nu(h, m) = K_nu E_{p_nu}(pi lam^2 |m*_h + y_m|^2), laid out
-// K x (n_nu Np): one thread per (entry, point) evaluates every exponent from one
-// base (e^{-a} with E_1 or E_{1/2}) and the recurrences p E_{p+1} = e^{-a} - a E_p
-// when every 2p is an integer, else the incomplete gamma per exponent.
-// Grid: (Np / 256, Kk_pad).
-// B operands of the reciprocal product: G_nu(|m* + y_m|^2) for reciprocal column kr
-// and point m, FP64 for the near columns and split BF16 for the far ones.  A thread
-// takes one point and EZ_GRID_GCH consecutive columns; in mixed precision it adds up
-// |G| of its columns per exponent (far ones and all) for the error bound, one atomic
-// per (exponent, point) and workgroup.
-constexpr int EZ_GRID_GCH = 32;
-__global__ __launch_bounds__(256) void grid_build_g_kernel(EzGridArgs g) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+// reciprocal B operand G_nu(h, m) = K_nu E_{p_nu}(pi lam^2 |m*_h + y_m|^2) of column
+// kr (near columns first) at the reduced point yr, every exponent: one base per
+// entry (e^{-a} with E_1 or E_{1/2}) and the recurrences p E_{p+1} = e^{-a} - a E_p
+// when every 2p is an integer, else the incomplete gamma per exponent; zero past the
+// table, for a failed lattice and beyond a_cut.
+__device__ __forceinline__ void grid_g_values(const EzGridArgs &g, int kr, bool pt, const double *yr,
+                                              double (&vals)[EZ_NU_MAX]) {
     const EzLatMeta *M = g.meta;
     const int d = g.d;
-    const int nnear = g.counts[2], nfar = g.counts[3];
-    const int kr0 = blockIdx.y * EZ_GRID_GCH;
-    double sfar[EZ_NU_MAX], sall[EZ_NU_MAX];
-    for (int i = 0; i < EZ_NU_MAX; ++i) sfar[i] = sall[i] = 0.0;
+    for (int i = 0; i < EZ_NU_MAX; ++i) vals[i] = 0.0;
+    if (!pt || kr >= g.counts[2] + g.counts[3] || M->status != 0) return;
+    const double *e = g.tab.rec + (size_t)g.perm_rec[kr] * 4;
+    double r2 = 0.0;
+    for (int t = 0; t < d; ++t) { const double q = e[t] + yr[t]; r2 += q * q; }
+    const double a = M->alpha * r2;
+    if (r2 == 0.0) {                     // m* + y = 0: continuation in nu, -K_nu / s
+        for (int i = 0; i < g.n_nu; ++i) {
+            const double s = 0.5 * ((double)d - g.nu[i]);
+            if (s == 0.0) {
+                atomicOr(g.status_acc, 0x10u);
+                vals[i] = __longlong_as_double(0x7ff8000000000000ll);
+            } else {
+                vals[i] = -g.kpref[i] / s;
+            }
+        }
+    } else if (a <= M->a_cut) {
+        if (g.ladder) {
+            const double ex = ez_expm(a), inv = ez_rcp(a);
+            bool ne1 = false, nh = false;
+            for (int i = 0; i < g.n_nu; ++i) {
+                ne1 = ne1 || ((g.p2[i] & 1) == 0 && g.p2[i] >= 2);
+                nh = nh || (g.p2[i] & 1);
+            }
+            double E1 = 0.0;
+            if (ne1) E1 = (a < 0.25) ? ez_e1_small(a) : ex * ez_e1w_scaled(inv);
+            const double Eh = nh ? ez_ehalf(a) : 0.0;
+            for (int i = 0; i < g.n_nu; ++i) vals[i] = g.kpref[i] * ez_ep_from(g.p2[i], a, ex, inv, E1, Eh);
+        } else {
+            for (int i = 0; i < g.n_nu; ++i) {
+                const double s = 0.5 * ((double)d - g.nu[i]);
+                vals[i] = g.kpref[i] * pow(a, -s) * ez_gamma_upper(s, a);
+            }
+        }
+    }
+}
+
+// B operands of the reciprocal product, near columns (every column in FP64
+// precision): G_nu(|m* + y_m|^2) as FP64 rows of B64k, one thread per (column,
+// point), stores coalesced over the points.  Grid: (Np / 256, Kkn_pad).
+__global__ __launch_bounds__(256) void grid_build_g_kernel(EzGridArgs g) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    const int kr = blockIdx.y;
+    const EzLatMeta *M = g.meta;
+    const int d = g.d;
+    const bool pt = m < g.n_y;
     double yr[3] = {0, 0, 0};
-    if (m < g.n_y) {
+    if (pt) {
         const double *ps = g.pts_y + (size_t)m * 4;
         for (int r = 0; r < d; ++r)
             for (int k = 0; k < d; ++k) yr[r] += M->B[r * d + k] * ps[k];
     }
-    for (int kr = kr0; kr < kr0 + EZ_GRID_GCH && kr < g.Kk_pad; ++kr) {
-        double vals[EZ_NU_MAX];
-        for (int i = 0; i < EZ_NU_MAX; ++i) vals[i] = 0.0;
-        if (kr < nnear + nfar && m < g.n_y && M->status == 0) {
-            const double *e = g.tab.rec + (size_t)g.perm_rec[kr] * 4;
-            double r2 = 0.0;
-            for (int t = 0; t < d; ++t) { const double q = e[t] + yr[t]; r2 += q * q; }
-            const double a = M->alpha * r2;
-            if (r2 == 0.0) {                     // m* + y = 0: continuation in nu, -K_nu / s
-                for (int i = 0; i < g.n_nu; ++i) {
-                    const double s = 0.5 * ((double)d - g.nu[i]);
-                    if (s == 0.0) {
-                        atomicOr(g.status_acc, 0x10u);
-                        vals[i] = __longlong_as_double(0x7ff8000000000000ll);
-                    } else {
-                        vals[i] = -g.kpref[i] / s;
-                    }
-                }
-            } else if (a <= M->a_cut) {
-                if (g.ladder) {
-                    const double ex = ez_expm(a), inv = ez_rcp(a);
-                    bool ne1 = false, nh = false;
-                    for (int i = 0; i < g.n_nu; ++i) {
-                        ne1 = ne1 || ((g.p2[i] & 1) == 0 && g.p2[i] >= 2);
-                        nh = nh || (g.p2[i] & 1);
-                    }
-                    double E1 = 0.0;
-                    if (ne1) E1 = (a < 0.25) ? ez_e1_small(a) : ex * ez_e1w_scaled(inv);
-                    const double Eh = nh ? ez_ehalf(a) : 0.0;
-                    for (int i = 0; i < g.n_nu; ++i) vals[i] = g.kpref[i] * ez_ep_from(g.p2[i], a, ex, inv, E1, Eh);
-                } else {
-                    for (int i = 0; i < g.n_nu; ++i) {
-                        const double s = 0.5 * ((double)d - g.nu[i]);
-                        vals[i] = g.kpref[i] * pow(a, -s) * ez_gamma_upper(s, a);
-                    }
-                }
-            }
-        }
-        for (int i = 0; i < g.n_nu; ++i) {
-            const size_t col = (size_t)i * g.Np + m;
-            const double v = vals[i];
-            if (m < g.Np) {
-                if (kr < g.Kkn_pad) g.B64k[(size_t)kr * (g.n_nu * g.Np) + col] = (kr < nnear) ? v : 0.0;
-                const int kf = kr - nnear;
-                if (g.mixed && kf >= 0 && kf < g.Kkf_pad) {
-                    __bf16 h, l;
-                    split_bf16(kf < nfar ? v : 0.0, &h, &l);
-                    g.Bhk[col * g.Kkf_pad + kf] = h;
-                    g.Blk[col * g.Kkf_pad + kf] = l;
-                }
-            }
-            if (v == v) {
-                sall[i] += fabs(v);
-                if (kr >= nnear) sfar[i] += fabs(v);
-            }
-        }
+    double vals[EZ_NU_MAX];
+    grid_g_values(g, kr < g.counts[2] ? kr : 1 << 30, pt, yr, vals);
+    if (m < g.Np)
+        for (int i = 0; i < g.n_nu; ++i) g.B64k[(size_t)kr * (g.n_nu * g.Np) + (size_t)i * g.Np + m] = vals[i];
+}
+
+// mixed precision, for the error bound: sum of |G| over the near columns per
+// (exponent, point) column of B64k, added to the far columns' sum (the kernels run
+// one after the other on one stream)
+__global__ __launch_bounds__(256) void grid_gsum_kernel(EzGridArgs g) {
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= g.n_nu * g.Np || col % g.Np >= g.n_y) return;
+    const size_t ld = (size_t)g.n_nu * g.Np;
+    double s = 0.0;
+    for (int kr = 0; kr < g.counts[2]; ++kr) {
+        const double v = g.B64k[(size_t)kr * ld + col];
+        if (v == v) s += fabs(v);
     }
-    if (g.mixed && m < g.n_y) {
-        for (int i = 0; i < g.n_nu; ++i) {
-            if (sfar[i] != 0.0) atomicAdd(&g.gfar[(size_t)i * g.Np + m], sfar[i]);
-            if (sall[i] != 0.0) atomicAdd(&g.gall[(size_t)i * g.Np + m], sall[i]);
+    g.gall[col] += s;
+}
+
+// Far columns (mixed precision): the split-BF16 pairs of G, K-contiguous per
+// (exponent, point) column.  A workgroup takes one point and 256 consecutive far
+// columns, one per thread, so the two-byte stores of a wave are contiguous; the
+// workgroup adds up |G| per exponent for the bound (one atomic per exponent).
+__global__ __launch_bounds__(256) void grid_build_gfar_kernel(EzGridArgs g) {
+    __shared__ double red[4];
+    const int kf = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    const EzLatMeta *M = g.meta;
+    const int d = g.d;
+    const bool pt = m < g.n_y;
+    double yr[3] = {0, 0, 0};
+    if (pt) {
+        const double *ps = g.pts_y + (size_t)m * 4;
+        for (int r = 0; r < d; ++r)
+            for (int k = 0; k < d; ++k) yr[r] += M->B[r * d + k] * ps[k];
+    }
+    double vals[EZ_NU_MAX];
+    grid_g_values(g, kf < g.counts[3] ? g.counts[2] + kf : 1 << 30, pt, yr, vals);
+    for (int i = 0; i < g.n_nu; ++i) {
+        const double v = vals[i];
+        if (kf < g.Kkf_pad) {
+            __bf16 h, l;
+            split_bf16(v, &h, &l);
+            const size_t col = (size_t)i * g.Np + m;
+            g.Bhk[col * g.Kkf_pad + kf] = h;
+            g.Blk[col * g.Kkf_pad + kf] = l;
+        }
+        const double s = block_sum((kf < g.Kkf_pad && v == v) ? fabs(v) : 0.0, red);
+        if (threadIdx.x == 0 && pt && s != 0.0) {
+            atomicAdd(&g.gfar[(size_t)i * g.Np + m], s);
+            atomicAdd(&g.gall[(size_t)i * g.Np + m], s);
         }
     }
 }
@@ -391,9 +419,9 @@ __global__ __launch_bounds__(256) void grid_build_g_kernel(EzGridArgs g) {
 // written once.  A, A64 row-major; B64 row-major
 // (K x ldb); Bh, Bl stored transposed (columns x ldbh, K contiguous).  64 x 64 tile
 // per workgroup, each wave a 32 x 32 quarter.
-struct GemmF64Tiles {
-    double As[64][17];
-    double Bs[16][65];
+struct GemmF64Tiles {                // two buffers: the next K step is stored while this one is read
+    double As[2][64][17];
+    double Bs[2][16][65];
 };
 struct alignas(16) GemmBf16Tiles {
     __bf16 Ash[64][40];
@@ -401,12 +429,15 @@ struct alignas(16) GemmBf16Tiles {
     __bf16 Bsh[64][40];
     __bf16 Bsl[64][40];
 };
+// mixed: the BF16 tiles reuse the FP64 tiles once the FP64 loop is done
 struct alignas(16) GemmLdsMixed {
-    GemmF64Tiles f;
-    GemmBf16Tiles b;
+    union {
+        GemmF64Tiles f;
+        GemmBf16Tiles b;
+    } u;
 };
 __device__ __forceinline__ GemmF64Tiles &f64_tiles(GemmF64Tiles &L) { return L; }
-__device__ __forceinline__ GemmF64Tiles &f64_tiles(GemmLdsMixed &L) { return L.f; }
+__device__ __forceinline__ GemmF64Tiles &f64_tiles(GemmLdsMixed &L) { return L.u.f; }
 
 template <bool MIXED>
 __global__ __launch_bounds__(256) void gemm_mixed_kernel(const double *A, int lda, const double *B, int ldb,
@@ -414,58 +445,82 @@ __global__ __launch_bounds__(256) void gemm_mixed_kernel(const double *A, int ld
                                                          int ldah, const __bf16 *Bh, const __bf16 *Bl, int ldbh,
                                                          const int *Kf_dev, double *C, int ldc) {
     __shared__ typename std::conditional<MIXED, GemmLdsMixed, GemmF64Tiles>::type L;
-    double (*As)[17] = f64_tiles(L).As;
-    double (*Bs)[65] = f64_tiles(L).Bs;
+    GemmF64Tiles &F = f64_tiles(L);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
-    const int row0 = blockIdx.y * 64, col0 = blockIdx.x * 64;
+    // workgroups go to the XCDs in turn (g mod 8): XCD x takes the x-th eighth of the
+    // tiles, column block by column block with the row blocks innermost, so that the
+    // workgroups an XCD runs one after another share their B columns in its L2 (the
+    // tile count is a multiple of 8: rows and columns are padded to multiples of 128)
+    const int T = (int)(gridDim.x * gridDim.y), Mt = (int)gridDim.y;
+    const int g = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    const int t = (g & 7) * (T >> 3) + (g >> 3);
+    const int row0 = (t % Mt) * 64, col0 = (t / Mt) * 64;
     f64x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
     const int nkt = (*Kn_dev + 15) / 16;
-    for (int kt = 0; kt < nkt; ++kt) {
+    // K steps of 16: the next step's A and B are loaded into registers while this
+    // step's MFMAs run, and stored to the other LDS buffer at the top of the next
+    // iteration (that buffer's last readers passed this iteration's barrier)
+    double ra[4], rb[4];
+    auto gload = [&](int kt) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int idx = tid + 256 * q;
-            const int r = idx >> 4, k = idx & 15;
-            As[r][k] = A[(size_t)(row0 + r) * lda + kt * 16 + k];
-            const int kb = idx >> 6, cb = idx & 63;
-            Bs[kb][cb] = B[(size_t)(kt * 16 + kb) * ldb + col0 + cb];
+            ra[q] = A[(size_t)(row0 + (idx >> 4)) * lda + kt * 16 + (idx & 15)];
+            rb[q] = B[(size_t)(kt * 16 + (idx >> 6)) * ldb + col0 + (idx & 63)];
+        }
+    };
+    if (nkt > 0) gload(0);
+    for (int kt = 0; kt < nkt; ++kt) {
+        const int buf = kt & 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = tid + 256 * q;
+            F.As[buf][idx >> 4][idx & 15] = ra[q];
+            F.Bs[buf][idx >> 6][idx & 63] = rb[q];
         }
         __syncthreads();
+        if (kt + 1 < nkt) gload(kt + 1);
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             double a[2], b[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) a[i] = As[32 * wr + 16 * i + (lane & 15)][4 * kk + (lane >> 4)];
+            for (int i = 0; i < 2; ++i) a[i] = F.As[buf][32 * wr + 16 * i + (lane & 15)][4 * kk + (lane >> 4)];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) b[j] = Bs[4 * kk + (lane >> 4)][32 * wc + 16 * j + (lane & 15)];
+            for (int j = 0; j < 2; ++j) b[j] = F.Bs[buf][4 * kk + (lane >> 4)][32 * wc + 16 * j + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
-        __syncthreads();
     }
     if constexpr (MIXED) {
         const int nft = (*Kf_dev + 31) / 32;
-        __bf16 (*Ash)[40] = L.b.Ash, (*Asl)[40] = L.b.Asl, (*Bsh)[40] = L.b.Bsh, (*Bsl)[40] = L.b.Bsl;
+        __syncthreads();                                 // the BF16 tiles reuse the FP64 ones
+        __bf16 (*Ash)[40] = L.u.b.Ash, (*Asl)[40] = L.u.b.Asl, (*Bsh)[40] = L.u.b.Bsh, (*Bsl)[40] = L.u.b.Bsl;
         {
+            // the next 32-wide step's operands are loaded into registers while this
+            // step's MFMAs run
+            const int lr = tid >> 2, k8 = (tid & 3) * 8;
+            bf16x8 pah, pal, pbh, pbl;
+            auto bload = [&](int kt) {
+                pah = *reinterpret_cast<const bf16x8 *>(Ah + (size_t)(row0 + lr) * ldah + kt * 32 + k8);
+                pal = *reinterpret_cast<const bf16x8 *>(Al + (size_t)(row0 + lr) * ldah + kt * 32 + k8);
+                pbh = *reinterpret_cast<const bf16x8 *>(Bh + (size_t)(col0 + lr) * ldbh + kt * 32 + k8);
+                pbl = *reinterpret_cast<const bf16x8 *>(Bl + (size_t)(col0 + lr) * ldbh + kt * 32 + k8);
+            };
+            if (nft > 0) bload(0);
             for (int kt = 0; kt < nft; ++kt) {
-                {
-                    const int r = tid >> 2, k8 = (tid & 3) * 8;
-                    *reinterpret_cast<bf16x8 *>(&Ash[r][k8]) =
-                        *reinterpret_cast<const bf16x8 *>(Ah + (size_t)(row0 + r) * ldah + kt * 32 + k8);
-                    *reinterpret_cast<bf16x8 *>(&Asl[r][k8]) =
-                        *reinterpret_cast<const bf16x8 *>(Al + (size_t)(row0 + r) * ldah + kt * 32 + k8);
-                    *reinterpret_cast<bf16x8 *>(&Bsh[r][k8]) =
-                        *reinterpret_cast<const bf16x8 *>(Bh + (size_t)(col0 + r) * ldbh + kt * 32 + k8);
-                    *reinterpret_cast<bf16x8 *>(&Bsl[r][k8]) =
-                        *reinterpret_cast<const bf16x8 *>(Bl + (size_t)(col0 + r) * ldbh + kt * 32 + k8);
-                }
+                *reinterpret_cast<bf16x8 *>(&Ash[lr][k8]) = pah;
+                *reinterpret_cast<bf16x8 *>(&Asl[lr][k8]) = pal;
+                *reinterpret_cast<bf16x8 *>(&Bsh[lr][k8]) = pbh;
+                *reinterpret_cast<bf16x8 *>(&Bsl[lr][k8]) = pbl;
                 __syncthreads();
+                if (kt + 1 < nft) bload(kt + 1);
                 bf16x8 bh[2], bl[2];
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
@@ -595,11 +650,19 @@ hipError_t ez_grid_launch(const EzGridArgs &g, hipStream_t s, int part) {
         if ((e = hipGetLastError()) != hipSuccess) return e;
         hipLaunchKernelGGL(grid_build_b_kernel, dim3((2 * g.Np + 255) / 256, g.Kr_pad), dim3(256), 0, s, g);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(grid_build_g_kernel, dim3((g.Np + 255) / 256, (g.Kk_pad + EZ_GRID_GCH - 1) / EZ_GRID_GCH),
-                           dim3(256), 0, s, g);
+        hipLaunchKernelGGL(grid_build_g_kernel, dim3((g.Np + 255) / 256, g.Kkn_pad), dim3(256), 0, s, g);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (g.mixed) {
+            hipLaunchKernelGGL(grid_build_gfar_kernel, dim3((g.Kkf_pad + 255) / 256, g.Np), dim3(256), 0, s, g);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL(grid_gsum_kernel, dim3((g.n_nu * g.Np + 255) / 256), dim3(256), 0, s, g);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (part & EZ_GRID_GEMM) {
+        // the products' tile remap takes the tile count to be a multiple of 8
+        if ((((2 * g.Np / 64) * (g.n_nu * g.Mp / 64)) & 7) || (((g.n_nu * g.Np / 64) * (2 * g.Mp / 64)) & 7))
+            return hipErrorInvalidValue;
         // real space: (n_nu Mp) x (2 Np);  reciprocal: (2 Mp) x (n_nu Np)
         auto gemm = g.mixed ? gemm_mixed_kernel<true> : gemm_mixed_kernel<false>;
         hipLaunchKernelGGL(gemm, dim3(2 * g.Np / 64, g.n_nu * g.Mp / 64), dim3(256), 0, s, g.A64r, g.Krn_pad, g.B64r,
