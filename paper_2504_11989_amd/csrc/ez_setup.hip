@@ -129,10 +129,18 @@ __device__ __forceinline__ void compact2(bool k0, bool k1, Compact &c, int (*wt)
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
     int o0 = c.cnt[0], o1 = c.cnt[1], t0 = 0, t1 = 0;
-    for (int w = 0; w < NW; ++w) {
-        const int a = wt[buf][0][w], b = wt[buf][1][w];
-        if (w < wave) { o0 += a; o1 += b; }
-        t0 += a; t1 += b;
+    // the NW totals of each list in four 16-byte reads
+    const int4 *w0 = reinterpret_cast<const int4 *>(wt[buf][0]), *w1 = reinterpret_cast<const int4 *>(wt[buf][1]);
+#pragma unroll
+    for (int q = 0; q < NW / 4; ++q) {
+        const int4 a4 = w0[q], b4 = w1[q];
+        const int a[4] = {a4.x, a4.y, a4.z, a4.w}, b[4] = {b4.x, b4.y, b4.z, b4.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int w = 4 * q + u;
+            if (w < wave) { o0 += a[u]; o1 += b[u]; }
+            t0 += a[u]; t1 += b[u];
+        }
     }
     *slot0 = k0 ? o0 + __popcll(b0 & lt) : -1;
     *slot1 = k1 ? o1 + __popcll(b1 & lt) : -1;
@@ -143,7 +151,7 @@ __device__ __forceinline__ void compact2(bool k0, bool k1, Compact &c, int (*wt)
 
 template <int D>
 __global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
-    __shared__ int wt[2][2][NW];
+    __shared__ alignas(16) int wt[2][2][NW];
     const int inst = blockIdx.x;
     const int tid = threadIdx.x;
     constexpr int d = D;
@@ -164,7 +172,7 @@ __global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
         mat_inverse<D>(A, Ai, &det);
         if (!(fabs(det) > 1e-300) || !isfinite(det)) st |= 0x1u;
     }
-    double V = 0.0, lam = 0.0, alpha = 0.0, Rr = 0.0, Rk = 0.0;
+    double V = 0.0, lam = 0.0, alpha = 0.0, Rr = 0.0, Rk = 0.0, lpl = 0.0;
     int hr[3] = {0, 0, 0}, hk[3] = {0, 0, 0}, nbox_r = 0, nbox_k = 0;
     if (!st) {
         for (int i = 0; i < d; ++i)
@@ -172,6 +180,7 @@ __global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
         V = fabs(det);
         lam = lam_rel * pow(V, 1.0 / d);
         alpha = EZ_PI * lam * lam;
+        lpl = log2(EZ_PI / (lam * lam));
         Rr = lam * sqrt(a_cut / EZ_PI);
         if (args.general_x) Rr += half_diag<D>(A);
         // real box for |A n| <= Rr: |n_i| <= Rr |row_i(A^{-1})|
@@ -324,8 +333,9 @@ __global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
             const double nu = args.prog.nu[i];
             // 2 W_nu = 2 Gamma(nu/2, a) |z|^{-nu} / Gamma(nu/2) with Gamma(s, a) = a^s E_{1-s}(a)
             // and a = (pi/lam^2) |z|^2: the powers of |z| cancel, 2 W_nu = 2 (pi/lam^2)^{nu/2}
-            // E_{1-nu/2}(a) / Gamma(nu/2)
-            const double pw = pow(pl, 0.5 * nu);
+            // E_{1-nu/2}(a) / Gamma(nu/2); (pi/lam^2)^{nu/2} from log2(pi/lam^2), taken once
+            // per thread (a relative error of a few ulps times |nu/2 log2(pi/lam^2)|)
+            const double pw = exp2(0.5 * nu * lpl);
             e[3 + i] = 2.0 * args.nuc[i][3] * pw *
                        (args.prog.real_nu ? ep_any(1.0 - 0.5 * nu, a) : ep_half(2 - (int)nu, a));
             int used = 3 + n_nu;
