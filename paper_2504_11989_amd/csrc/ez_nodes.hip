@@ -692,6 +692,13 @@ __global__ __launch_bounds__(EZ_TILE) void ez_node_kernel(EzQuadArgs args) {
     node_tile<D, NNU, SET, MIX>(args, (int)blockIdx.x, L);
 }
 
+// mixed precision held to the FP64 kernel's 7 waves per SIMD (72 registers)
+template <int D, int NNU, int SET>
+__global__ __launch_bounds__(EZ_TILE) __attribute__((amdgpu_waves_per_eu(7))) void ez_node_mix7_kernel(EzQuadArgs args) {
+    __shared__ TileLds L;
+    node_tile<D, NNU, SET, true>(args, (int)blockIdx.x, L);
+}
+
 // persistent: a fixed grid of workgroups takes tiles from a queue, costliest first;
 // every workgroup leaves once the queue position passes the last tile.  Tiles from
 // n_main on are left to the split kernel.
@@ -892,7 +899,7 @@ hipError_t launch_nodes_t(const EzQuadArgs &args, int n_tiles, hipStream_t strea
     } else if (mode == 1) {
         hipLaunchKernelGGL((ez_node_persist_kernel<D, NNU, SET>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
     } else if (args.mixed) {
-        hipLaunchKernelGGL((ez_node_kernel<D, NNU, SET, true>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
+        hipLaunchKernelGGL((ez_node_mix7_kernel<D, NNU, SET>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
     } else {
         hipLaunchKernelGGL((ez_node_kernel<D, NNU, SET>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
     }
