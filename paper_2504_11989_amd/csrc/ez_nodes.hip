@@ -686,15 +686,22 @@ __device__ __forceinline__ void node_group_split(const EzQuadArgs &args, const i
 }
 
 // one workgroup per tile (tiles [0, n_main)); MIX: the mixed-precision far field
+// waves per SIMD the compiler is held to: one more than the registers alone allow for
+// the ATM (4 exponents, 8) and scan (7 exponents, 6) sets, at the cost of a few
+// bytes of spill
+template <int NNU, int SET>
+constexpr int node_waves() { return (SET == 1) ? 8 : (SET == 4 ? 6 : 1); }
+
 template <int D, int NNU, int SET, bool MIX = false>
-__global__ __launch_bounds__(EZ_TILE) void ez_node_kernel(EzQuadArgs args) {
+__global__ __launch_bounds__(EZ_TILE) __attribute__((amdgpu_waves_per_eu(node_waves<NNU, SET>())))
+void ez_node_kernel(EzQuadArgs args) {
     __shared__ TileLds L;
     node_tile<D, NNU, SET, MIX>(args, (int)blockIdx.x, L);
 }
 
-// mixed precision held to the FP64 kernel's 7 waves per SIMD (72 registers)
+// mixed precision held to 8 waves per SIMD (64 registers, a few bytes of spill)
 template <int D, int NNU, int SET>
-__global__ __launch_bounds__(EZ_TILE) __attribute__((amdgpu_waves_per_eu(7))) void ez_node_mix7_kernel(EzQuadArgs args) {
+__global__ __launch_bounds__(EZ_TILE) __attribute__((amdgpu_waves_per_eu(8))) void ez_node_mix_kernel(EzQuadArgs args) {
     __shared__ TileLds L;
     node_tile<D, NNU, SET, true>(args, (int)blockIdx.x, L);
 }
@@ -899,7 +906,7 @@ hipError_t launch_nodes_t(const EzQuadArgs &args, int n_tiles, hipStream_t strea
     } else if (mode == 1) {
         hipLaunchKernelGGL((ez_node_persist_kernel<D, NNU, SET>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
     } else if (args.mixed) {
-        hipLaunchKernelGGL((ez_node_mix7_kernel<D, NNU, SET>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
+        hipLaunchKernelGGL((ez_node_mix_kernel<D, NNU, SET>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
     } else {
         hipLaunchKernelGGL((ez_node_kernel<D, NNU, SET>), dim3(n_tiles), dim3(EZ_TILE), 0, stream, args);
     }

@@ -32,7 +32,7 @@ __device__ __forceinline__ void sym_acc(double *S, double t, const double *v) {
 // SIMD, rounds of 768 tiles); held to four waves it spills 64 bytes per lane and
 // runs the three-lattice ATM derivative 5% faster (709 against 746 us).
 template <int D, int NNU, int SET, int NR>
-__global__ __launch_bounds__(EZ_TILE) __attribute__((amdgpu_waves_per_eu(SET == 1 ? 4 : 1)))
+__global__ __launch_bounds__(EZ_TILE) __attribute__((amdgpu_waves_per_eu(SET == 1 ? 5 : 1)))
 void ez_node_adj_kernel(EzQuadArgs args) {
     constexpr int NS = D * (D + 1) / 2;
     const int tile = blockIdx.x;
