@@ -732,10 +732,9 @@ ez_status prepare_call(int batch, int d, const EzProgram &prog, const std::vecto
     C.grad = grad;
     if (grad && prog.n_res > EZ_GRAD_RES_MAX)
         return fail(EZ_ERR_INVALID_ARG, "derivatives are available for at most 2 results per call");
-    // value calls: 64 directions per direction workgroup (one per lane, the combinations
-    // shared out over its waves); the adjoint kernel takes one thread per (direction,
-    // combination)
-    C.ndb = grad ? std::min(EZ_HDIR_GRAD, 256 / (int)combos.size()) : EZ_HDIR;
+    // 64 directions per direction workgroup (one per lane, the combinations shared out
+    // over its waves), values and derivatives alike
+    C.ndb = EZ_HDIR;
     C.n_ch = grad ? 1 + d * (d + 1) / 2 : 1;
     int ell_max = 0;
     for (int i = 0; i < n_specs; ++i) ell_max = std::max(ell_max, specs[i].ell);

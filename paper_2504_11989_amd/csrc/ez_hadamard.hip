@@ -7,51 +7,6 @@
 
 namespace {
 
-// C_k(w_hat), k = 0 .. ell, of one channel from its tensor row T (monomials of degree
-// 2k in the order a0 desc, a1 desc, orders one after the other): homogeneous Horner
-// in (x0, x1, x2); T is uniform over the wave
-template <int D, int LM>
-__device__ __forceinline__ void horner_orders(const double *T, int ell, double x0, double x1, double x2,
-                                              double (&C)[LM + 1]) {
-    int off = 0;
-#pragma unroll
-    for (int k = 0; k <= LM; ++k) {
-        C[k] = 0.0;
-        if (k > ell) continue;
-        const int g = 2 * k;
-        if (D == 1) {
-            double m = 1.0;
-            for (int q = 0; q < g; ++q) m *= x0;
-            C[k] = T[off] * m;
-            off += 1;
-        } else if (D == 2) {
-            // sum_a T[g - a] x0^a x1^(g - a), a descending
-            double acc = T[off], p1 = 1.0;
-            for (int a = g - 1; a >= 0; --a) {
-                p1 *= x1;
-                acc = fma(acc, x0, T[off + g - a] * p1);
-            }
-            C[k] = acc;
-            off += g + 1;
-        } else {
-            // sum_a x0^a S_a(x1, x2), S_a homogeneous of degree g - a in (x1, x2) with
-            // its coefficients in b = g - a .. 0 order
-            double acc = 0.0;
-            for (int a = g; a >= 0; --a) {
-                const int m = g - a;
-                double S = T[off], p2 = 1.0;
-                for (int b = m - 1; b >= 0; --b) {
-                    p2 *= x2;
-                    S = fma(S, x1, T[off + m - b] * p2);
-                }
-                off += m + 1;
-                acc = fma(acc, x0, S);
-            }
-            C[k] = acc;
-        }
-    }
-}
-
 // dynamic LDS of the direction kernel, in doubles: C_k per (channel, order, lane),
 // sigma_i |w|^{e_i} per (channel, lane), the waves' result sums per (wave, result,
 // lane), then one flag word per (wave, lane)

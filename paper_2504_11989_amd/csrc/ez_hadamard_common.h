@@ -407,68 +407,51 @@ __global__ __launch_bounds__(256) void ez_tensor_kernel(EzQuadArgs args) {
     }
 }
 
-// C_k(w) of NNU channels staged at Tsh (NNU rows of tdim coefficients) for one order
-// k: monomials of w_hat of degree 2k in the order a0 desc, a1 desc
-template <int D, int NNU>
-__device__ __forceinline__ void contract_order(const double *Tsh, int tdim, int k, double x0, double x1, double x2,
-                                               double (&acc)[NNU]) {
-    const int g = 2 * k;
+// C_k(w_hat), k = 0 .. ell, of one channel from its tensor row T (monomials of degree
+// 2k in the order a0 desc, a1 desc, orders one after the other): homogeneous Horner
+// in (x0, x1, x2); T is uniform over the wave
+template <int D, int LM>
+__device__ __forceinline__ void horner_orders(const double *T, int ell, double x0, double x1, double x2,
+                                              double (&C)[LM + 1]) {
     int off = 0;
-    for (int kk = 0; kk < k; ++kk) off += nmono(D, 2 * kk);
 #pragma unroll
-    for (int i = 0; i < NNU; ++i) acc[i] = 0.0;
-    if (D == 1) {
-        double mono = 1.0;
-        for (int q = 0; q < g; ++q) mono *= x0;
-#pragma unroll
-        for (int i = 0; i < NNU; ++i) acc[i] = Tsh[i * tdim + off] * mono;
-    } else if (D == 2) {
-        int a_idx = 0;
-        for (int a = g; a >= 0; --a, ++a_idx) {
-            double mono = 1.0;
-            for (int q = 0; q < a; ++q) mono *= x0;
-            for (int q = 0; q < g - a; ++q) mono *= x1;
-#pragma unroll
-            for (int i = 0; i < NNU; ++i) acc[i] = fma(Tsh[i * tdim + off + a_idx], mono, acc[i]);
-        }
-    } else {
-        int a_idx = 0;
-        for (int a = g; a >= 0; --a) {
-            double p0 = 1.0;
-            for (int q = 0; q < a; ++q) p0 *= x0;
-            for (int b = g - a; b >= 0; --b, ++a_idx) {
-                double mono = p0;
-                for (int q = 0; q < b; ++q) mono *= x1;
-                for (int q = 0; q < g - a - b; ++q) mono *= x2;
-#pragma unroll
-                for (int i = 0; i < NNU; ++i) acc[i] = fma(Tsh[i * tdim + off + a_idx], mono, acc[i]);
+    for (int k = 0; k <= LM; ++k) {
+        C[k] = 0.0;
+        if (k > ell) continue;
+        const int g = 2 * k;
+        if (D == 1) {
+            double m = 1.0;
+            for (int q = 0; q < g; ++q) m *= x0;
+            C[k] = T[off] * m;
+            off += 1;
+        } else if (D == 2) {
+            // sum_a T[g - a] x0^a x1^(g - a), a descending
+            double acc = T[off], p1 = 1.0;
+            for (int a = g - 1; a >= 0; --a) {
+                p1 *= x1;
+                acc = fma(acc, x0, T[off + g - a] * p1);
             }
+            C[k] = acc;
+            off += g + 1;
+        } else {
+            // sum_a x0^a S_a(x1, x2), S_a homogeneous of degree g - a in (x1, x2) with
+            // its coefficients in b = g - a .. 0 order
+            double acc = 0.0;
+            for (int a = g; a >= 0; --a) {
+                const int m = g - a;
+                double S = T[off], p2 = 1.0;
+                for (int b = m - 1; b >= 0; --b) {
+                    p2 *= x2;
+                    S = fma(S, x1, T[off + m - b] * p2);
+                }
+                off += m + 1;
+                acc = fma(acc, x0, S);
+            }
+            C[k] = acc;
         }
     }
 }
 
-// C_k(w) of the channels [c0, c0 + NNU) for the directions of a workgroup: the
-// tensors staged in LDS, one thread per (direction, order k)
-template <int D, int NNU>
-__device__ __forceinline__ void contract_tensor(const EzQuadArgs &args, int inst, int c0, int NC, int ndb, int ell,
-                                                int tdim, double *Tsh, const double (*wsh)[3],
-                                                double *Cout, int cstride_d, int cstride_c) {
-    const int tid = (int)threadIdx.x;
-    const double *T = args.tensor + ((size_t)inst * NC + c0) * EZ_TDIM;
-    __syncthreads();
-    for (int idx = tid; idx < NNU * tdim; idx += 256) {
-        const int i = idx / tdim;
-        Tsh[idx] = T[(size_t)i * EZ_TDIM + (idx - i * tdim)];
-    }
-    __syncthreads();
-    for (int idx = tid; idx < ndb * (ell + 1); idx += 256) {
-        const int dd = idx / (ell + 1), k = idx - dd * (ell + 1);
-        double acc[NNU];
-        contract_order<D, NNU>(Tsh, tdim, k, wsh[dd][0], wsh[dd][1], wsh[dd][2], acc);
-#pragma unroll
-        for (int i = 0; i < NNU; ++i) Cout[dd * cstride_d + i * cstride_c + k] = acc[i];
-    }
-}
 
 // Direction kernel (value calls): a workgroup takes EZ_HDIR = 64 directions of one
 // lattice, one per lane, and its EZ_HW waves share out the channels (phase 1: the

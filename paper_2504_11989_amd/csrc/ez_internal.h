@@ -15,8 +15,6 @@
 #define EZ_KCULL 8192    // reciprocal table capacity per lattice in the quadrature (node tiles list it in LDS)
 #define EZ_SLICE_MAX 8   // table slices of the probe kernel
 #define EZ_GRAD_RES_MAX 2  // results per call when strain derivatives are requested
-#define EZ_HDIR_GRAD 16  // directions per workgroup of the Hadamard adjoint kernel
-#define EZ_HADJ_TSTAGE 8192  // tensor coefficients staged at once in the LDS of the Hadamard adjoint kernel
 #define EZ_TAIL_WAVES 4  // waves per workgroup of the tail node kernel
 #define EZ_TAIL_PARTS 4  // workgroups sharing one 64-node group of the tail node tiles
 
