@@ -10,20 +10,22 @@ namespace {
 // dynamic LDS of the direction kernel, in doubles: C_k per (channel, order, lane),
 // sigma_i |w|^{e_i} per (channel, lane), the waves' result sums per (wave, result,
 // lane), then one flag word per (wave, lane)
-template <int NNU, int LM>
+template <int NNU, int LM, int HW>
 inline size_t had_lds_bytes(int n_res) {
-    return sizeof(double) * 64 * ((size_t)NNU * (LM + 2) + (size_t)EZ_HW * n_res) + sizeof(uint32_t) * 64 * EZ_HW;
+    return sizeof(double) * 64 * ((size_t)NNU * (LM + 2) + (size_t)HW * n_res) + sizeof(uint32_t) * 64 * HW;
 }
 
-template <int D, int NNU, int PD, int LM>
-__global__ __launch_bounds__(64 * EZ_HW) void ez_hadamard_kernel(EzQuadArgs args) {
+// HW waves per workgroup: 16 (about one combination each) when the call has few
+// direction blocks, so that each block ends sooner; 4 for a large batch
+template <int D, int NNU, int PD, int LM, int HW>
+__global__ __launch_bounds__(64 * HW) void ez_hadamard_kernel(EzQuadArgs args) {
     extern __shared__ double lds[];                // had_lds_bytes<NNU, LM>(n_res)
     const EzProgram &prog = args.prog;
     const int n_res = prog.n_res, nc = args.n_combo;
     double *Csh = lds;                             // [NNU][LM + 1][64]
     double *ssh = Csh + NNU * (LM + 1) * 64;       // [NNU][64]
-    double *acc = ssh + NNU * 64;                  // [EZ_HW][n_res][64]
-    uint32_t *badsh = reinterpret_cast<uint32_t *>(acc + EZ_HW * n_res * 64);   // [EZ_HW][64]
+    double *acc = ssh + NNU * 64;                  // [HW][n_res][64]
+    uint32_t *badsh = reinterpret_cast<uint32_t *>(acc + HW * n_res * 64);   // [HW][64]
     const int blk = blockIdx.x;
     const int inst = find_segment(args.htile_begin, args.batch, blk);
     const EzInstPlan P = args.plans[inst];
@@ -52,9 +54,9 @@ __global__ __launch_bounds__(64 * EZ_HW) void ez_hadamard_kernel(EzQuadArgs args
 #pragma unroll
     for (int i = 0; i < D; ++i) w2 = fma(w[i], w[i], w2);
 
-    // phase 1: channel i on wave i mod EZ_HW, lane = direction: C_k(w) from the tensor
+    // phase 1: channel i on wave i mod HW, lane = direction: C_k(w) from the tensor
     // row and sigma_i |w|^{e_i}
-    for (int i = wave; i < NNU; i += EZ_HW) {
+    for (int i = wave; i < NNU; i += HW) {
         const double *T = args.tensor + ((size_t)inst * NNU + i) * EZ_TDIM;
         double C[LM + 1];
         horner_orders<D, LM>(T, ell, wh[0], wh[1], wh[2], C);
@@ -65,14 +67,14 @@ __global__ __launch_bounds__(64 * EZ_HW) void ez_hadamard_kernel(EzQuadArgs args
     for (int r = 0; r < n_res; ++r) acc[(wave * n_res + r) * 64 + lane] = 0.0;
     __syncthreads();
 
-    // phase 2: combination c on wave c mod EZ_HW (uniform), lane = direction: the
+    // phase 2: combination c on wave c mod HW (uniform), lane = direction: the
     // product polynomial (PD coefficients in registers) and its Hadamard integrals
     //   fp int_0^eps u^{mu-1} L^Q du, mu = d + E + 2J:
     //   I_0 = eps^mu/mu,  I_q = (eps^mu L(eps)^q - 2q I_{q-1})/mu
     const double eps = P.eps, eps2 = eps * eps;
     const double Leps = log(EZ_PI * eps2 * w2);
     uint32_t bad = 0u;
-    for (int c = wave; c < nc; c += EZ_HW) {
+    for (int c = wave; c < nc; c += HW) {
         const EzCombo &cb = args.combo[c];
         const int t = cb.t;
         const int nf = prog.term_nfac[t];
@@ -133,12 +135,12 @@ __global__ __launch_bounds__(64 * EZ_HW) void ez_hadamard_kernel(EzQuadArgs args
         for (int r = 0; r < n_res; ++r) {
             double h = 0.0;
 #pragma unroll
-            for (int v = 0; v < EZ_HW; ++v) h += acc[(v * n_res + r) * 64 + lane];
+            for (int v = 0; v < HW; ++v) h += acc[(v * n_res + r) * 64 + lane];
             args.dir_part[(size_t)gd * n_res + r] = 2.0 * wv * h;
         }
         uint32_t b = 0u;
 #pragma unroll
-        for (int v = 0; v < EZ_HW; ++v) b |= badsh[v * 64 + lane];
+        for (int v = 0; v < HW; ++v) b |= badsh[v * 64 + lane];
         // device-side guard for a Hadamard exponent mu = 0 (the host rejects such programs)
         args.dir_flag[gd] = b;
     }
@@ -174,12 +176,24 @@ hipError_t launch_had_t(const EzQuadArgs &args, int n_htiles, hipStream_t stream
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (!(part & EZ_HAD_DIR)) return hipSuccess;   // direction kernel
-    if (args.ell_probe <= 4)
-        hipLaunchKernelGGL((ez_hadamard_kernel<D, NNU, PD, 4>), dim3(n_htiles), dim3(64 * EZ_HW),
-                           (had_lds_bytes<NNU, 4>(args.prog.n_res)), stream, args);
-    else
-        hipLaunchKernelGGL((ez_hadamard_kernel<D, NNU, PD, EZ_ELL_MAX>), dim3(n_htiles), dim3(64 * EZ_HW),
-                           (had_lds_bytes<NNU, EZ_ELL_MAX>(args.prog.n_res)), stream, args);
+    // up to 1024 direction blocks (a few rounds of the device at 4 waves): 16 waves each
+    const bool wide = n_htiles <= 1024;
+    const dim3 grid(n_htiles);
+    if (args.ell_probe <= 4) {
+        if (wide)
+            hipLaunchKernelGGL((ez_hadamard_kernel<D, NNU, PD, 4, 16>), grid, dim3(64 * 16),
+                               (had_lds_bytes<NNU, 4, 16>(args.prog.n_res)), stream, args);
+        else
+            hipLaunchKernelGGL((ez_hadamard_kernel<D, NNU, PD, 4, 4>), grid, dim3(64 * 4),
+                               (had_lds_bytes<NNU, 4, 4>(args.prog.n_res)), stream, args);
+    } else {
+        if (wide)
+            hipLaunchKernelGGL((ez_hadamard_kernel<D, NNU, PD, EZ_ELL_MAX, 16>), grid, dim3(64 * 16),
+                               (had_lds_bytes<NNU, EZ_ELL_MAX, 16>(args.prog.n_res)), stream, args);
+        else
+            hipLaunchKernelGGL((ez_hadamard_kernel<D, NNU, PD, EZ_ELL_MAX, 4>), grid, dim3(64 * 4),
+                               (had_lds_bytes<NNU, EZ_ELL_MAX, 4>(args.prog.n_res)), stream, args);
+    }
     return hipGetLastError();
 }
 

@@ -454,9 +454,10 @@ __device__ __forceinline__ void horner_orders(const double *T, int ell, double x
 
 
 // Direction kernel (value calls): a workgroup takes EZ_HDIR = 64 directions of one
-// lattice, one per lane, and its EZ_HW waves share out the channels (phase 1: the
-// tensor contracted with the monomials of w_hat, C_k) and the combinations (phase 2:
-// the product polynomial, PD coefficients in registers, and its Hadamard integrals),
-// so that a wave's control flow is uniform; phase 3 adds the waves' per-result sums
-// in wave order.  The adjoint kernel keeps one thread per (direction, combination).
+// lattice, one per lane, and its waves (16, or 4 for a large batch) share out the
+// channels (phase 1: the tensor contracted with the monomials of w_hat, C_k) and the
+// combinations (phase 2: the product polynomial, PD coefficients in registers, and
+// its Hadamard integrals), so that a wave's control flow is uniform; phase 3 adds the
+// waves' per-result sums in wave order.  The adjoint kernel has the same layout, one
+// workgroup per (direction block, strain component).
 }  // namespace
