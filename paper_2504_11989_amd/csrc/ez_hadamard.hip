@@ -169,10 +169,10 @@ hipError_t launch_had_t(const EzQuadArgs &args, int n_htiles, hipStream_t stream
         // pre_done (if given) is recorded by the tensor launch itself: no marker packet
         // on `stream` between the tensors and the node kernel
         if (pre_done)
-            hipExtLaunchKernelGGL((ez_tensor_kernel<D, NNU>), dim3(args.batch * NNU * nch * ngrp), dim3(256), 0, stream,
+            hipExtLaunchKernelGGL((ez_tensor_kernel<D, NNU>), dim3(args.batch * NNU * nch * ngrp), dim3(64 * EZ_TOUT), 0, stream,
                                   nullptr, pre_done, 0, args);
         else
-            hipLaunchKernelGGL((ez_tensor_kernel<D, NNU>), dim3(args.batch * NNU * nch * ngrp), dim3(256), 0, stream, args);
+            hipLaunchKernelGGL((ez_tensor_kernel<D, NNU>), dim3(args.batch * NNU * nch * ngrp), dim3(64 * EZ_TOUT), 0, stream, args);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (!(part & EZ_HAD_DIR)) return hipSuccess;   // direction kernel

@@ -357,15 +357,15 @@ __global__ __launch_bounds__(64 * EZ_HW) void ez_probe_kernel(EzQuadArgs args) {
 // number of monomials of degree g in D variables
 __host__ __device__ constexpr int nmono(int D, int g) { return D == 1 ? 1 : (D == 2 ? g + 1 : (g + 1) * (g + 2) / 2); }
 
-constexpr int EZ_TOUT = 16;                     // tensor coefficients per workgroup
+constexpr int EZ_TOUT = 4;                      // tensor coefficients per workgroup (one per wave)
 
 // Tensor kernel: T[c][off_k + a] = sum_p pinv_k[a][p] C_k(probe p) for each channel
 // c = ch * n_nu + i, the probe values first summed over the table slices in fixed
-// order.  Grid: batch x channels x groups of EZ_TOUT coefficients; thread =
-// (coefficient, probe residue mod 16).
+// order.  Grid: batch x channels x groups of EZ_TOUT coefficients; wave = coefficient,
+// lane = probe residue mod 64 (the slice loads of a probe issued eight at a time);
+// the lanes' sums are added by a fixed butterfly.
 template <int D, int NNU>
-__global__ __launch_bounds__(256) void ez_tensor_kernel(EzQuadArgs args) {
-    __shared__ double part[EZ_TOUT][17];
+__global__ __launch_bounds__(64 * EZ_TOUT) void ez_tensor_kernel(EzQuadArgs args) {
     const int lp = args.ell_probe, S = args.n_slice, np = args.n_probe;
     const int NC = NNU * args.n_ch;
     int tdim = 0;
@@ -375,36 +375,30 @@ __global__ __launch_bounds__(256) void ez_tensor_kernel(EzQuadArgs args) {
     const int rem = (int)blockIdx.x - inst * NC * ngrp;
     const int c = rem / ngrp, grp = rem - c * ngrp;
     if (args.meta[inst].status != 0) return;  // uniform over the workgroup
-    const int o = (int)threadIdx.x >> 4, pp = (int)threadIdx.x & 15;
-    const int aa = grp * EZ_TOUT + o;
+    const int lane = (int)threadIdx.x & 63;
+    const int aa = grp * EZ_TOUT + ((int)threadIdx.x >> 6);
+    if (aa >= tdim) return;                   // uniform over the wave
+    int a = aa, k = 0;
+    while (a >= nmono(D, 2 * k)) { a -= nmono(D, 2 * k); ++k; }
+    const double *pinv = args.rules + args.pinv_off[k] + (size_t)a * np;
+    const double *pv = args.probe_val + (size_t)inst * S * np * NC * (EZ_ELL_MAX + 1) + (size_t)c * (EZ_ELL_MAX + 1) + k;
     double s = 0.0;
-    if (aa < tdim) {
-        int a = aa, k = 0;
-        while (a >= nmono(D, 2 * k)) { a -= nmono(D, 2 * k); ++k; }
-        const double *pinv = args.rules + args.pinv_off[k] + (size_t)a * np;
-        const double *pv = args.probe_val + (size_t)inst * S * np * NC * (EZ_ELL_MAX + 1) +
-                           (size_t)c * (EZ_ELL_MAX + 1) + k;
-        for (int p = pp; p < np; p += 16) {
-            // the slices in fixed order, their loads issued eight at a time
-            double v = 0.0;
-            for (int sl0 = 0; sl0 < S; sl0 += 8) {
-                double t[8];
+    for (int p = lane; p < np; p += 64) {
+        // the slices in fixed order, their loads issued eight at a time
+        double v = 0.0;
+        for (int sl0 = 0; sl0 < S; sl0 += 8) {
+            double t[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    t[q] = (sl0 + q < S) ? pv[((size_t)(sl0 + q) * np + p) * NC * (EZ_ELL_MAX + 1)] : 0.0;
+            for (int q = 0; q < 8; ++q)
+                t[q] = (sl0 + q < S) ? pv[((size_t)(sl0 + q) * np + p) * NC * (EZ_ELL_MAX + 1)] : 0.0;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) v += t[q];
-            }
-            s = fma(pinv[p], v, s);
+            for (int q = 0; q < 8; ++q) v += t[q];
         }
+        s = fma(pinv[p], v, s);
     }
-    part[o][pp] = s;
-    __syncthreads();
-    if (pp == 0 && aa < tdim) {
-        double t = 0.0;
-        for (int q = 0; q < 16; ++q) t += part[o][q];
-        args.tensor[((size_t)inst * NC + c) * EZ_TDIM + aa] = t;
-    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
+    if (lane == 0) args.tensor[((size_t)inst * NC + c) * EZ_TDIM + aa] = s;
 }
 
 // C_k(w_hat), k = 0 .. ell, of one channel from its tensor row T (monomials of degree

@@ -214,6 +214,11 @@ def test_large_batch_second_stream_schedule(ez):
     got = scan_sums(A, specs).cpu().numpy()
     ser = scan_sums(A, [dict(s, flags=nat.SPEC_SERIAL) for s in specs]).cpu().numpy()
     assert np.array_equal(got, ser)
+    # the batch has more than 1024 direction blocks (direction kernel at 4 waves per
+    # workgroup); five of its lattices alone take the 16-wave form, which adds the
+    # combinations in another order
+    alone = scan_sums(A[:5], specs[:5]).cpu().numpy()
+    assert np.all(np.abs(alone - got[:5]) <= 1e-13 * np.abs(got[:5])), (alone, got[:5])
     for i in [int(j) for j in np.argsort(ns, kind="stable")[:3]]:
         ref = oracle_scan(A[i], specs[i])
         for r in range(5):
