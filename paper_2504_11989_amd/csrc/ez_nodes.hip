@@ -792,13 +792,23 @@ __global__ __launch_bounds__(FT) void ez_finalize_kernel(EzQuadArgs args) {
     }
     if (args.bound_out) {
         // a-priori bound of the FP32 far field's effect on each result: the tile bounds
-        // in tile order (mixed calls keep every tile in the tile kernel); 0 in FP64 calls
-        for (int r = (int)threadIdx.x; r < n_res; r += FT) {
+        // (mixed calls keep every tile in the tile kernel) added by a fixed tree, each
+        // thread a strided share, then the waves in order; 0 in FP64 calls
+        for (int r = 0; r < n_res; ++r) {
             double b = 0.0;
             if (args.mixed)
-                for (int t = tb; t < te; ++t) b += args.tile_bound[(size_t)t * n_res + r];
-            args.bound_out[(size_t)inst * n_res + r] =
-                args.meta[inst].status ? __longlong_as_double(0x7ff8000000000000ll) : b;
+                for (int t = tb + (int)threadIdx.x; t < te; t += FT) b += args.tile_bound[(size_t)t * n_res + r];
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) b += __shfl_xor(b, m, 64);
+            __syncthreads();
+            if (lane == 0) red[wave][0] = b;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double tot = red[0][0];
+                for (int w = 1; w < FT / 64; ++w) tot += red[w][0];
+                args.bound_out[(size_t)inst * n_res + r] =
+                    args.meta[inst].status ? __longlong_as_double(0x7ff8000000000000ll) : tot;
+            }
         }
     }
     if (!args.grad_out) return;
