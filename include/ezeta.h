@@ -297,6 +297,15 @@ ez_status ez_timing_read(int kernel, double *total_ms, int64_t *launches);
  * first call.  Errors: EZ_ERR_INVALID_ARG (null pointer). */
 ez_status ez_grid_last_tables(int64_t *n_real, int64_t *n_rec);
 
+/* Node tiles of the last lattice-sum call (ez_atm_energy, ez_nbody_lattice_sum,
+ * ez_lattice_sums and their variants) on the current device (a tracing aid): n_tiles
+ * tiles of 256 nodes, n_main of them taken whole by the tile kernel, and the tail
+ * [n_main, n_tiles): tail_mode 0 none, 1 the split kernel (a few tiles past a full
+ * round of workgroups), 2 two half-term workgroups per tile in the tile kernel (up to
+ * about half a round).  All 0 before the first call.  Errors: EZ_ERR_INVALID_ARG
+ * (null pointer). */
+ez_status ez_last_sum_tiles(int64_t *n_tiles, int64_t *n_main, int *tail_mode);
+
 /* Text of the last error on the calling host thread (never NULL). */
 const char *ez_last_error(void);
 

@@ -39,7 +39,8 @@ def spec_mix_a(n: int) -> int:
 EXPORTED = ("ez_epstein_zeta", "ez_epstein_grid", "ez_nbody_lattice_sum", "ez_atm_energy", "ez_lattice_sums", "ez_lattice_sums_grad",
             "ez_timing_enable", "ez_timing_reset", "ez_timing_read",
             "ez_last_error", "ez_finalize", "ez_version", "ez_workspace_generation", "ez_lattice_sums_noalloc",
-            "ez_lattice_sums_bound", "ez_direct_atm", "ez_grid_last_tables")
+            "ez_lattice_sums_bound", "ez_direct_atm", "ez_grid_last_tables",
+            "ez_last_sum_tiles")
 (KERNEL_SETUP, KERNEL_NODES, KERNEL_HADAMARD, KERNEL_FINALIZE, KERNEL_EPSTEIN, KERNEL_NODES_ADJ, KERNEL_GRID,
  KERNEL_NODES_TAIL, KERNEL_TAYLOR, KERNEL_GRID_GEMM) = (0, 1, 2, 3, 4, 5, 6, 7, 8, 9)
 
@@ -115,6 +116,8 @@ def lib():
     L.ez_timing_read.argtypes = [I, P, ctypes.POINTER(I64)]
     L.ez_grid_last_tables.restype = I
     L.ez_grid_last_tables.argtypes = [ctypes.POINTER(I64), ctypes.POINTER(I64)]
+    L.ez_last_sum_tiles.restype = I
+    L.ez_last_sum_tiles.argtypes = [ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I)]
     _lib = L
     return L
 
@@ -138,6 +141,16 @@ def timing_read(kernel: int):
     n = ctypes.c_int64()
     check(lib().ez_timing_read(int(kernel), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def last_sum_tiles():
+    """(n_tiles, n_main, tail_mode) of the last lattice-sum call on the current device:
+    tail_mode 0 none, 1 split kernel, 2 half-term workgroups in the tile kernel."""
+    a = ctypes.c_int64()
+    b = ctypes.c_int64()
+    m = ctypes.c_int()
+    check(lib().ez_last_sum_tiles(ctypes.byref(a), ctypes.byref(b), ctypes.byref(m)))
+    return a.value, b.value, m.value
 
 
 def grid_last_tables():

@@ -175,6 +175,8 @@ struct DeviceState {
     // Epstein grid workspace
     DevBuf g_pts_x, g_pts_y, g_perm, g_counts, g_A64r, g_B64r, g_A64k, g_B64k, g_R, g_Q, g_wsum, g_stat;
     long long grid_nr = 0, grid_nk = 0;          // table sizes of the last grid call
+    long long sum_tiles = 0, sum_main = 0;       // node tiles of the last lattice-sum call
+    int sum_tail = 0;                            // and its tail (0 none, 1 split kernel, 2 halves)
     DevBuf g_Ahr, g_Alr, g_Bhr, g_Blr, g_Ahk, g_Alk, g_Bhk, g_Blk;
     int n_cu = 0;
     hipStream_t side = nullptr;  // second stream: Hadamard branch concurrent with the nodes
@@ -685,6 +687,8 @@ struct CallInfo {
     double a_mix = 16.0;
     int top2[2] = {-1, -1};
     double eps[EZ_NU_MAX] = {0.0};
+    // tail tiles [n_main, n_tiles) taken as two half-tile workgroups each by the tile kernel
+    bool tail_halves = false;
 };
 
 // Relative error bound of one FP32 chunk sum of the far field, per exponent, first
@@ -802,12 +806,17 @@ int probe_slices(int batch, int n_probe) {
     return std::max(1, std::min(EZ_SLICE_MAX, 512 / std::max(1, batch * n_pblk)));
 }
 
-// tiles [n_main, n_tiles) go to the split kernel when they pass a multiple of a round
-// of tile-kernel workgroups by a few tiles only: the split kernel shares each 64-node
-// group among 16 waves of four workgroups and runs one workgroup per CU, so it pays
-// only while its workgroups (16 per tail tile) fit one per CU (value calls without
-// EZ_SPEC_NO_SPLIT); a larger tail stays in the tile kernel
-int main_tiles(const CallInfo &C, const EzProgram &prog, int n_cu, int n_tiles) {
+// The tail of the tile kernel: with round = the tile-kernel workgroups resident on the
+// device at once, the last n_tiles % round tiles form a partly filled last round.
+//  - A few tiles (16 split-kernel workgroups per tile fit one per CU): they go to the
+//    split kernel, launched after the tile kernel with one workgroup per CU; each
+//    64-node group is shared by 16 waves of four workgroups.
+//  - Up to about half a round: the tile kernel takes each of them as two workgroups of
+//    half the terms (C.tail_halves), so that the last round runs at the occupancy of
+//    the others (three-lattice ATM call, 3087 tiles over rounds of 2048).
+//  - More: the tile kernel as it is.
+// Value calls only, without EZ_SPEC_NO_SPLIT; the persistent schedule takes no halves.
+int main_tiles(CallInfo &C, const EzProgram &prog, int n_cu, int n_tiles) {
     int round = 0;                     // tile-kernel workgroups resident on the device at once
     {
         EzQuadArgs probe_args;
@@ -816,20 +825,37 @@ int main_tiles(const CallInfo &C, const EzProgram &prog, int n_cu, int n_tiles) 
         round = n_cu * ez_nodes_tile_blocks_per_cu(probe_args);
     }
     int n_main = n_tiles;
+    C.tail_halves = false;
     if (!C.grad && !C.mixed_active && !prog.real_nu && !(C.flags & EZ_SPEC_NO_SPLIT)) {
         const int tail = round > 0 ? n_tiles % round : 0;
         const int per_tile = (EZ_TILE / 64) * EZ_TAIL_PARTS;     // split-kernel workgroups per tail tile
-        if (n_tiles > round && tail > 0 && tail * per_tile <= n_cu) n_main = n_tiles - tail;
+        if (n_tiles > round && tail > 0) {
+            if (tail * per_tile <= n_cu) {
+                n_main = n_tiles - tail;
+            } else if (!(C.flags & EZ_SPEC_PERSISTENT) && 2 * tail <= round + round / 4) {
+                n_main = n_tiles - tail;
+                C.tail_halves = true;
+            }
+        }
     }
     return n_main;
 }
 
+// the node tiles of a lattice-sum call and its tail, for ez_last_sum_tiles
+void note_tiles(DeviceState *S, const CallInfo &C, int n_tiles, int n_main) {
+    S->sum_tiles = n_tiles;
+    S->sum_main = n_main;
+    S->sum_tail = n_main == n_tiles ? 0 : (C.tail_halves ? 2 : 1);
+}
+
 void workspace_sizes(int batch, const EzProgram &prog, const CallInfo &C, const PlanView &P, int n_main, Workspace &W) {
     const size_t ntail = (size_t)std::max(1, P.n_tiles - n_main);
+    // the split kernel's part sums and counters (half-tile tails combine in LDS)
+    const size_t nsplit = C.tail_halves ? 1 : ntail;
     const int n_slice = probe_slices(batch, P.n_probe);
     W.bytes[WS_META] = sizeof(EzLatMeta) * batch;
     W.bytes[WS_SUB_PART] = sizeof(double) * 2 * (EZ_TILE / 64) * ntail * prog.n_res;
-    W.bytes[WS_TAIL_ACC] = sizeof(double) * (EZ_TILE / 64) * EZ_TAIL_PARTS * 2 * 64 * ntail * prog.n_nu;
+    W.bytes[WS_TAIL_ACC] = sizeof(double) * (EZ_TILE / 64) * EZ_TAIL_PARTS * 2 * 64 * nsplit * prog.n_nu;
     W.bytes[WS_REAL] = sizeof(double) * (size_t)batch * C.tab.real_cap * C.tab.rstride;
     W.bytes[WS_RN] = sizeof(int) * 4 * (size_t)batch * C.tab.real_cap;
     W.bytes[WS_ROWS] = sizeof(int) * 8 * (size_t)batch * C.tab.row_cap;
@@ -842,7 +868,7 @@ void workspace_sizes(int batch, const EzProgram &prog, const CallInfo &C, const 
     W.bytes[WS_TENSOR] = sizeof(double) * (size_t)batch * C.n_ch * prog.n_nu * EZ_TDIM;
     W.bytes[WS_TILE_GRAD] = C.grad ? sizeof(double) * 12 * (size_t)P.n_tiles * prog.n_res : 0;
     W.bytes[WS_DIR_GRAD] = C.grad ? sizeof(double) * 6 * (size_t)P.n_dirs * prog.n_res : 0;
-    W.bytes[WS_TAIL_CNT] = sizeof(int) * (EZ_TILE / 64) * ntail;
+    W.bytes[WS_TAIL_CNT] = sizeof(int) * (EZ_TILE / 64) * nsplit;
     W.bytes[WS_QUEUE] = 256;
     W.bytes[WS_TILE_BOUND] = C.mixed_active ? sizeof(double) * (size_t)P.n_tiles * prog.n_res : 0;
     for (int i = 0; i < WS_COUNT; ++i) W.ptr[i] = nullptr;
@@ -935,6 +961,7 @@ ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, co
     qa.grad_out = grad_dev;
     qa.n_tiles = P.n_tiles;
     qa.n_main = n_main;
+    qa.tail_halves = C.tail_halves ? 1 : 0;
     qa.sub_part = (double *)W.ptr[WS_SUB_PART];
     qa.tail_acc = (double *)W.ptr[WS_TAIL_ACC];
     qa.tail_cnt = (int *)W.ptr[WS_TAIL_CNT];
@@ -984,9 +1011,10 @@ ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, co
         EZ_HIP_TRY(ez_launch_fill_int(qa.queue, 1, 0, stream));
         EZ_HIP_TRY(tm(EZ_KERNEL_NODES, stream, [&] { return ez_launch_nodes_persistent(qa, nblk, stream); }));
     } else {
-        EZ_HIP_TRY(tm(EZ_KERNEL_NODES, stream, [&] { return ez_launch_nodes(qa, n_main, stream); }));
+        const int n_wg = C.tail_halves ? n_main + 2 * (P.n_tiles - n_main) : n_main;
+        EZ_HIP_TRY(tm(EZ_KERNEL_NODES, stream, [&] { return ez_launch_nodes(qa, n_wg, stream); }));
     }
-    if (n_main < P.n_tiles)
+    if (n_main < P.n_tiles && !C.tail_halves)
         EZ_HIP_TRY(tm(EZ_KERNEL_NODES_TAIL, stream, [&] { return ez_launch_nodes_split(qa, stream); }));
     if (hs != stream) {
         EZ_HIP_TRY(hipEventRecord(ev_had, hs));
@@ -1030,6 +1058,7 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
     pv.probe_off = P->probe_off;
     for (int k = 0; k <= EZ_ELL_MAX; ++k) pv.pinv_off[k] = P->pinv_off[k];
     const int n_main = main_tiles(C, prog, S->n_cu, P->n_tiles);
+    note_tiles(S, C, P->n_tiles, n_main);
     Workspace W;
     workspace_sizes(batch, prog, C, pv, n_main, W);
     DevBuf *bufs[WS_COUNT] = {&S->meta, &S->sub_part, &S->tail_acc, &S->real, &S->rn, &S->rows, &S->rec,
@@ -1265,6 +1294,7 @@ ez_status ez_lattice_sums_noalloc(int batch, int d, const double *A_dev, int n_n
     }
     const size_t plan_bytes = off;
     const int n_main = main_tiles(C, prog, S->n_cu, pv.n_tiles);
+    note_tiles(S, C, pv.n_tiles, n_main);
     Workspace W;
     workspace_sizes(batch, prog, C, pv, n_main, W);
     for (int i = 0; i < WS_COUNT; ++i) {
@@ -1603,6 +1633,18 @@ ez_status ez_grid_last_tables(int64_t *n_real, int64_t *n_rec) {
     DeviceState *S = device_state(dev);
     *n_real = S->grid_nr;
     *n_rec = S->grid_nk;
+    return EZ_OK;
+}
+
+ez_status ez_last_sum_tiles(int64_t *n_tiles, int64_t *n_main, int *tail_mode) {
+    if (!n_tiles || !n_main || !tail_mode) return fail(EZ_ERR_INVALID_ARG, "null pointer argument");
+    int dev = 0;
+    EZ_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_mu);
+    DeviceState *S = device_state(dev);
+    *n_tiles = S->sum_tiles;
+    *n_main = S->sum_main;
+    *tail_mode = S->sum_tail;
     return EZ_OK;
 }
 

@@ -37,7 +37,9 @@ struct EzQuadArgs {
     const EzInstPlan *plans;
     const int *tile_begin;     // batch + 1 prefix of node tiles
     int n_tiles;               // node tiles of the whole batch
-    int n_main;                // tiles [0, n_main) whole, [n_main, n_tiles) split into 64-node groups
+    int n_main;                // tiles [0, n_main) whole, [n_main, n_tiles) the tail (below)
+    int tail_halves;           // 0: the tail goes to the split kernel (64-node groups); 1: the
+                               // tile kernel takes each tail tile as two workgroups of half its terms
     const int *tile_order;     // persistent node kernel: tiles in the order they are taken (costliest first)
     int *queue;                // persistent node kernel: next position in tile_order (reset before launch)
     const int *dir_begin;      // batch + 1 prefix of directions
@@ -67,6 +69,7 @@ struct EzQuadArgs {
     double *tile_bound;        // [n_tiles][n_res] bound partials (mixed calls)
     double *bound_out;         // [batch][n_res] per-result bound, or NULL
     double *sub_part;          // [4 (n_tiles - n_main)][n_res][2] partials of the 64-node groups
+                               // (tail_halves: slot 4t + h of workgroup h of tail tile t, 4t + 2 + h zero)
     double *tail_acc;          // [4 (n_tiles - n_main)][EZ_TAIL_PARTS][2 n_nu][64] partial sums of the split kernel
     int *tail_cnt;             // [4 (n_tiles - n_main)] parts finished per group (zero between calls)
     double *dir_part;          // [n_dirs][n_res] Hadamard part per direction (times 2 w_v)

@@ -171,8 +171,8 @@ __device__ __forceinline__ void rec_list(const EzQuadArgs &args, const double *k
     }
 }
 
-// Reciprocal sum of one wave of the tile kernel over the whole table, culled per
-// wave.  The table is read in chunks of 64 entries (one per lane); with c and r_w
+// Reciprocal sum of one wave of the tile kernel over the table entries [q0, q1) (and
+// m* = 0 if `origin`), culled per wave.  The table is read in chunks of 64 entries (one per lane); with c and r_w
 // the centre and half-diagonal of the bounding box of the wave's k, an entry is
 //   beyond the cutoff for every node   if |m* + c| > sqrt(a_cut/alpha) + r_w,
 //   near  (a may be < 1/4 at a node)   if |m* + c| <= 1/(2 sqrt alpha) + r_w,
@@ -254,10 +254,10 @@ __device__ __forceinline__ void far32_term(const EzQuadArgs &args, double a, flo
 }
 
 template <int D, int NNU, int SET, bool MIX>
-__device__ __forceinline__ void rec_wave(const EzQuadArgs &args, const double *kt, int n_rec, const double *k,
-                                         bool valid, double alpha, double acut, unsigned short *nearl,
-                                         unsigned short *midl, const double *exptab, double *acck,
-                                         double *far32) {
+__device__ __forceinline__ void rec_wave(const EzQuadArgs &args, const double *kt, int q0, int q1, bool origin,
+                                         const double *k, bool valid, double alpha, double acut,
+                                         unsigned short *nearl, unsigned short *midl, const double *exptab,
+                                         double *acck, double *far32) {
     const bool need_e1 = pset_need_e1<SET, NNU>(args.prog), need_half = pset_need_half<SET, NNU>(args.prog);
     const int lane = (int)threadIdx.x & 63;
     double c[3] = {0.0, 0.0, 0.0}, rt2 = 0.0;
@@ -288,7 +288,7 @@ __device__ __forceinline__ void rec_wave(const EzQuadArgs &args, const double *k
         for (int i = 0; i < NNU; ++i) far32[i] = 0.0;
     }
     // m* = 0
-    if (valid) {
+    if (valid && origin) {
         double rho = k[0] * k[0];
         if (D > 1) rho = fma(k[1], k[1], rho);
         if (D > 2) rho = fma(k[2], k[2], rho);
@@ -305,11 +305,11 @@ __device__ __forceinline__ void rec_wave(const EzQuadArgs &args, const double *k
         }
     }
     int n_near = 0, n_mid = 0;
-    for (int base = 1; base < n_rec; base += 64) {
+    for (int base = q0; base < q1; base += 64) {
         // the chunk's entries, one per lane (a prefetch of the next chunk held 14 more
         // registers)
         const int q = base + lane;
-        const bool in = q < n_rec;
+        const bool in = q < q1;
         double d2 = 0.0;
         {
             const double *e = kt + (size_t)(in ? q : base) * 4;
@@ -491,50 +491,103 @@ struct NodeLds {
 };
 using TailLds = NodeLds<EZ_TAIL_WAVES>;
 
-// LDS of the tile kernel: each wave's near and mid lists, the tile reduction
-struct TileLds {
+// LDS of the tile kernel: each wave's near and mid lists, the tile reduction.  A
+// half-tile workgroup passes its odd waves' sums to the even waves through `xch`,
+// which takes the place of the table and the lists once every wave has summed.
+struct TileTables {
     double exptab[EZ_EXP2_TAB_N];
     unsigned short nearl[EZ_TILE / 64][EZ_NEAR_MAX];
     unsigned short midl[EZ_TILE / 64][EZ_MID_MAX];
+};
+struct TileLds {
+    union {
+        TileTables t;
+        double xch[EZ_TILE / 128][4][64];
+    } u;
     double red[EZ_RES_MAX][EZ_TILE / 64][2];
     double rbnd[EZ_RES_MAX][EZ_TILE / 64];
 };
 
-// One node tile: four wave blocks of the lattice, each wave culls and sums on its own
+// One node tile: four wave blocks of the lattice, each wave culls and sums on its own.
+//
+// half = 0 or 1: a tile of the tail of a call whose tiles pass a multiple of a round
+// of workgroups by a large part of a round.  Its last round would run at about half
+// the occupancy of the others, and waves alone on a SIMD are latency-bound, so each
+// tail tile goes to two workgroups: workgroup `half` takes wave blocks 2 half and
+// 2 half + 1, wave 2j + p of it takes block 2 half + j with part p of the terms:
+// real-space rows [p n_rows/2, (p+1) n_rows/2), reciprocal entries [1, q_m) with
+// m* = 0 (p = 0) or [q_m, n_rec) (p = 1), q_m on a 64-entry chunk boundary.  The
+// even wave adds the odd wave's sums to its own (part 0 + part 1, in that order),
+// forms the products, and the workgroup's partial goes to sub_part.
 template <int D, int NNU, int SET, bool MIX = false>
-__device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile, TileLds &L) {
+__device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile, TileLds &L, const int half = -1) {
     const int inst = find_segment(args.tile_begin, args.batch, tile);
     const EzInstPlan P = args.plans[inst];
     const EzLatMeta *M = args.meta + inst;
     const int n_res = args.prog.n_res;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wb = (tile - args.tile_begin[inst]) * (EZ_TILE / 64) + wave;
+    const bool split = !MIX && half >= 0;           // uniform over the workgroup
+    // uniform over the wave: kept in scalar registers, so that the entry loops below
+    // keep their table reads on the scalar path
+    const int part = __builtin_amdgcn_readfirstlane(split ? (wave & 1) : 0);
+    const int wb = (tile - args.tile_begin[inst]) * (EZ_TILE / 64) + (split ? 2 * half + (wave >> 1) : wave);
 
     double res[EZ_RES_MAX], rbound[EZ_RES_MAX];
 #pragma unroll
     for (int r = 0; r < EZ_RES_MAX; ++r) { res[r] = 0.0; rbound[r] = 0.0; }
-    for (int j = (int)threadIdx.x; j < EZ_EXP2_TAB_N; j += EZ_TILE) L.exptab[j] = ez_exp2_tab[j];
+    for (int j = (int)threadIdx.x; j < EZ_EXP2_TAB_N; j += EZ_TILE) L.u.t.exptab[j] = ez_exp2_tab[j];
     __syncthreads();
 
-    if (M->status == 0 && wb < P.n_wblk) {        // uniform over the wave
+    const bool ok = M->status == 0 && wb < P.n_wblk;   // uniform over the wave
+    bool valid = false;
+    double W = 0.0;
+    double accr[NNU], acck[NNU], far32[NNU];
+#pragma unroll
+    for (int i = 0; i < NNU; ++i) { accr[i] = 0.0; acck[i] = 0.0; }
+    if (ok) {
         int dir, iu;
-        const bool valid = block_node(P, wb, lane, &dir, &iu);
-        double k[3], th[3], W;
+        valid = block_node(P, wb, lane, &dir, &iu);
+        double k[3], th[3];
         node_geometry<D>(P, args.rules, M, dir, iu, k, th, &W);
 
-        double accr[NNU], acck[NNU];
-#pragma unroll
-        for (int i = 0; i < NNU; ++i) { accr[i] = 0.0; acck[i] = 0.0; }
-
         const double *kt = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
-        if (valid) real_rows<D, NNU>(args, inst, th, 0, M->n_rows, accr);
-        double far32[NNU];
-        rec_wave<D, NNU, SET, MIX>(args, kt, M->n_rec, k, valid, M->alpha, M->a_cut, L.nearl[wave],
-                                   L.midl[wave], L.exptab, acck, far32);
-        if (valid) {
-            if constexpr (MIX) node_products<NNU>(args, M, accr, acck, W, res, far32, rbound);
-            else node_products<NNU>(args, M, accr, acck, W, res);
+        const int n_rec = M->n_rec, n_rows = M->n_rows;
+        int q0 = 1, q1 = n_rec, r0 = 0, r1 = n_rows;
+        if (split) {
+            const int qm = min(n_rec, 1 + 64 * (((n_rec - 1) / 2 + 63) / 64));
+            q0 = __builtin_amdgcn_readfirstlane(part ? qm : 1);
+            q1 = __builtin_amdgcn_readfirstlane(part ? n_rec : qm);
+            r0 = __builtin_amdgcn_readfirstlane(part ? n_rows / 2 : 0);
+            r1 = __builtin_amdgcn_readfirstlane(part ? n_rows : n_rows / 2);
         }
+        if (valid) real_rows<D, NNU>(args, inst, th, r0, r1, accr);
+        rec_wave<D, NNU, SET, MIX>(args, kt, q0, q1, part == 0, k, valid, M->alpha, M->a_cut, L.u.t.nearl[wave],
+                                   L.u.t.midl[wave], L.u.t.exptab, acck, far32);
+    }
+    if (split) {
+        // the odd waves' sums to the even waves, four values per pass
+        constexpr int NV = 2 * NNU;
+#pragma unroll
+        for (int c0 = 0; c0 < NV; c0 += 4) {
+            __syncthreads();                        // the table, lists or last pass are read
+            if (part == 1) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (c0 + u < NV) L.u.xch[wave >> 1][u][lane] = (c0 + u < NNU) ? accr[c0 + u] : acck[c0 + u - NNU];
+            }
+            __syncthreads();
+            if (part == 0) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (c0 + u < NNU) accr[c0 + u] += L.u.xch[wave >> 1][u][lane];
+                    else if (c0 + u < NV) acck[c0 + u - NNU] += L.u.xch[wave >> 1][u][lane];
+                }
+            }
+        }
+    }
+    if (ok && valid && part == 0) {
+        if constexpr (MIX) node_products<NNU>(args, M, accr, acck, W, res, far32, rbound);
+        else node_products<NNU>(args, M, accr, acck, W, res);
     }
 
     // tile reduction: wave butterflies, then the four waves in fixed order
@@ -561,8 +614,16 @@ __device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile
         const int r = threadIdx.x;
         ez_dd s{L.red[r][0][0], L.red[r][0][1]};
         for (int wv = 1; wv < EZ_TILE / 64; ++wv) s = ez_dd_add(s, ez_dd{L.red[r][wv][0], L.red[r][wv][1]});
-        args.tile_part[((size_t)tile * n_res + r) * 2 + 0] = s.hi;
-        args.tile_part[((size_t)tile * n_res + r) * 2 + 1] = s.lo;
+        if (split) {
+            const size_t g = (size_t)(tile - args.n_main) * (EZ_TILE / 64) + half;
+            args.sub_part[(g * n_res + r) * 2 + 0] = s.hi;
+            args.sub_part[(g * n_res + r) * 2 + 1] = s.lo;
+            args.sub_part[((g + 2) * n_res + r) * 2 + 0] = 0.0;
+            args.sub_part[((g + 2) * n_res + r) * 2 + 1] = 0.0;
+        } else {
+            args.tile_part[((size_t)tile * n_res + r) * 2 + 0] = s.hi;
+            args.tile_part[((size_t)tile * n_res + r) * 2 + 1] = s.lo;
+        }
         if constexpr (MIX) {
             double b = L.rbnd[r][0];
             for (int wv = 1; wv < EZ_TILE / 64; ++wv) b += L.rbnd[r][wv];
@@ -696,7 +757,15 @@ template <int D, int NNU, int SET, bool MIX = false>
 __global__ __launch_bounds__(EZ_TILE) __attribute__((amdgpu_waves_per_eu(node_waves<NNU, SET>())))
 void ez_node_kernel(EzQuadArgs args) {
     __shared__ TileLds L;
-    node_tile<D, NNU, SET, MIX>(args, (int)blockIdx.x, L);
+    // workgroups [0, n_main) take whole tiles; with tail_halves, workgroup n_main + 2 t + h
+    // takes half h of tail tile n_main + t
+    const int b = (int)blockIdx.x;
+    int tile = b, half = -1;
+    if (args.tail_halves && b >= args.n_main) {
+        tile = args.n_main + ((b - args.n_main) >> 1);
+        half = (b - args.n_main) & 1;
+    }
+    node_tile<D, NNU, SET, MIX>(args, tile, L, half);
 }
 
 // mixed precision held to 8 waves per SIMD (64 registers, a few bytes of spill)

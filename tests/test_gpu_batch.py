@@ -138,19 +138,58 @@ def tail_launches(ez, fn):
 
 
 def test_tail_split_full_c2_plan(ez):
-    """the three-lattice ATM workload on the full plan: with or without the split
-    kernel for the last tiles (used when the tiles pass a multiple of a round of
-    workgroups by at most a quarter round) the sums agree up to the order of each
-    node's terms, and the persistent schedule gives the default's bits"""
+    """the three-lattice ATM workload on the full plan (3087 tiles): on 256 CUs at 8
+    workgroups each the last 1039 tiles form a second round, which the tile kernel
+    takes as two workgroups of half the terms per tile; the sums agree with whole
+    tiles (EZ_SPEC_NO_SPLIT) up to the order of each node's terms, and the
+    persistent schedule (whole tiles) gives the bits of EZ_SPEC_NO_SPLIT"""
     from paper_2504_11989_amd import _native as nat
     lat = np.stack([W.sc(), W.fcc(), W.bcc()])
     spec = dict(W.SPEC_FULL_3D)
-    split, _ = tail_launches(ez, lambda: ez.atm_energy(lat, spec).cpu().numpy())
+    halves, n_tail = tail_launches(ez, lambda: ez.atm_energy(lat, spec).cpu().numpy())
+    n_tiles, n_main, mode = nat.last_sum_tiles()
+    assert n_tiles == 3087 and n_tail == 0
+    if n_main < n_tiles:
+        assert mode == 2, (n_tiles, n_main, mode)
     whole, n0 = tail_launches(ez, lambda: ez.atm_energy(lat, dict(spec, flags=nat.SPEC_NO_SPLIT)).cpu().numpy())
-    assert n0 == 0
-    assert np.all(np.abs(split - whole) <= 1e-13 * np.abs(whole)), (split, whole)
+    assert n0 == 0 and nat.last_sum_tiles()[1:] == (3087, 0)
+    assert np.all(np.abs(halves - whole) <= 1e-13 * np.abs(whole)), (halves, whole)
     pers = ez.atm_energy(lat, dict(spec, flags=nat.SPEC_PERSISTENT)).cpu().numpy()
-    assert np.array_equal(pers, split)
+    assert np.array_equal(pers, whole)
+    again = ez.atm_energy(lat, spec).cpu().numpy()
+    assert np.array_equal(again, halves)
+
+
+def test_tail_halves_batch_agrees_with_oracle(ez):
+    """a batch of small plans whose tiles pass a multiple of a round of tile-kernel
+    workgroups by about a third of a round: the tail tiles go to half-term
+    workgroups (each tile's four 64-node blocks as two workgroups, the terms of a
+    block shared by two waves); the sums agree with whole tiles and, for lattices
+    of the tail, with the oracle"""
+    from paper_2504_11989_amd import _native as nat
+    spec = W.SPEC_SMALL_3D
+    per = (W.n_nodes(3, spec) + 255) // 256
+    ca, nside, A = W.c3_scan()
+    ez.atm_energy(A[:1], spec)
+    n_tiles1, _, _ = nat.last_sum_tiles()
+    assert n_tiles1 == per
+    seen = 0
+    for round_ in (1024, 1536, 1792, 2048):
+        nb = (round_ + round_ // 3) // per + 1
+        if nb > len(A):
+            continue
+        Ab = A[:nb]
+        got = ez.atm_energy(Ab, spec).cpu().numpy()
+        n_tiles, n_main, mode = nat.last_sum_tiles()
+        whole = ez.atm_energy(Ab, dict(spec, flags=nat.SPEC_NO_SPLIT)).cpu().numpy()
+        assert np.all(np.abs(got - whole) <= TOL * np.abs(whole)), round_
+        if mode == 2:
+            seen += 1
+            first = n_main // per            # first lattice with tiles in the tail
+            for i in sorted({first, (first + nb - 1) // 2, nb - 1}):
+                ref = O.atm(Ab[i], spec)
+                assert abs(got[i] - ref) <= TOL * abs(ref), (round_, i, got[i], ref)
+    assert seen >= 1
 
 
 def test_tail_split_kernel_runs_and_agrees(ez):

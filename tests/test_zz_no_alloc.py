@@ -30,7 +30,7 @@ def both(ez, A, nu, terms, n_res, specs):
 
 def test_noalloc_matches_lattice_sums_two_calls(ez):
     from paper_2504_11989_amd.batch import SCAN_NU, SCAN_TERMS
-    # 1: the three-lattice ATM workload on the full plan (split tail kernel included)
+    # 1: the three-lattice ATM workload on the full plan (half-term tail workgroups included)
     lat = np.stack([W.sc(), W.fcc(), W.bcc()])
     got, ref, st, st_ref = both(ez, lat, ATM_NU, ATM_TERMS, 1, W.SPEC_FULL_3D)
     assert np.array_equal(st, np.zeros(3, np.int32)) and np.array_equal(st_ref, st)
