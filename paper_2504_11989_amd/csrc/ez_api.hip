@@ -815,7 +815,8 @@ int probe_slices(int batch, int n_probe) {
 //    half the terms (C.tail_halves), so that the last round runs at the occupancy of
 //    the others (three-lattice ATM call, 3087 tiles over rounds of 2048).
 //  - More: the tile kernel as it is.
-// Value calls only, without EZ_SPEC_NO_SPLIT; the persistent schedule takes no halves.
+// Value calls only, without EZ_SPEC_NO_SPLIT; the persistent schedule takes no halves,
+// mixed-precision calls no split kernel.
 int main_tiles(CallInfo &C, const EzProgram &prog, int n_cu, int n_tiles) {
     int round = 0;                     // tile-kernel workgroups resident on the device at once
     {
@@ -826,12 +827,12 @@ int main_tiles(CallInfo &C, const EzProgram &prog, int n_cu, int n_tiles) {
     }
     int n_main = n_tiles;
     C.tail_halves = false;
-    if (!C.grad && !C.mixed_active && !prog.real_nu && !(C.flags & EZ_SPEC_NO_SPLIT)) {
+    if (!C.grad && !prog.real_nu && !(C.flags & EZ_SPEC_NO_SPLIT)) {
         const int tail = round > 0 ? n_tiles % round : 0;
         const int per_tile = (EZ_TILE / 64) * EZ_TAIL_PARTS;     // split-kernel workgroups per tail tile
         if (n_tiles > round && tail > 0) {
             if (tail * per_tile <= n_cu) {
-                n_main = n_tiles - tail;
+                if (!C.mixed_active) n_main = n_tiles - tail;     // the split kernel is FP64 only
             } else if (!(C.flags & EZ_SPEC_PERSISTENT) && 2 * tail <= round + round / 4) {
                 n_main = n_tiles - tail;
                 C.tail_halves = true;
@@ -870,7 +871,9 @@ void workspace_sizes(int batch, const EzProgram &prog, const CallInfo &C, const 
     W.bytes[WS_DIR_GRAD] = C.grad ? sizeof(double) * 6 * (size_t)P.n_dirs * prog.n_res : 0;
     W.bytes[WS_TAIL_CNT] = sizeof(int) * (EZ_TILE / 64) * nsplit;
     W.bytes[WS_QUEUE] = 256;
-    W.bytes[WS_TILE_BOUND] = C.mixed_active ? sizeof(double) * (size_t)P.n_tiles * prog.n_res : 0;
+    // mixed calls: one bound per tile, and one more per tail tile taken in halves
+    W.bytes[WS_TILE_BOUND] =
+        C.mixed_active ? sizeof(double) * ((size_t)P.n_tiles + (C.tail_halves ? ntail : 0)) * prog.n_res : 0;
     for (int i = 0; i < WS_COUNT; ++i) W.ptr[i] = nullptr;
 }
 

@@ -66,7 +66,8 @@ struct EzQuadArgs {
     double a_mix;              // FP32 threshold on the incomplete-gamma argument (>= EZ_EPF_XMIN)
     int mix_top2[2];           // largest 2p of the integer (>= 0) and half-integer (>= 1) chains
     double mix_eps[EZ_NU_MAX]; // relative error bound of one FP32 chunk sum of exponent i
-    double *tile_bound;        // [n_tiles][n_res] bound partials (mixed calls)
+    double *tile_bound;        // [n_tiles (+ n_tiles - n_main with tail_halves)][n_res] bound
+                               // partials (mixed calls; half 1 of tail tile t at n_tiles + t - n_main)
     double *bound_out;         // [batch][n_res] per-result bound, or NULL
     double *sub_part;          // [4 (n_tiles - n_main)][n_res][2] partials of the 64-node groups
                                // (tail_halves: slot 4t + h of workgroup h of tail tile t, 4t + 2 + h zero)

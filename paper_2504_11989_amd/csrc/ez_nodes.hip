@@ -526,7 +526,7 @@ __device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile
     const EzLatMeta *M = args.meta + inst;
     const int n_res = args.prog.n_res;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const bool split = !MIX && half >= 0;           // uniform over the workgroup
+    const bool split = half >= 0;                   // uniform over the workgroup
     // uniform over the wave: kept in scalar registers, so that the entry loops below
     // keep their table reads on the scalar path
     const int part = __builtin_amdgcn_readfirstlane(split ? (wave & 1) : 0);
@@ -543,7 +543,7 @@ __device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile
     double W = 0.0;
     double accr[NNU], acck[NNU], far32[NNU];
 #pragma unroll
-    for (int i = 0; i < NNU; ++i) { accr[i] = 0.0; acck[i] = 0.0; }
+    for (int i = 0; i < NNU; ++i) { accr[i] = 0.0; acck[i] = 0.0; far32[i] = 0.0; }
     if (ok) {
         int dir, iu;
         valid = block_node(P, wb, lane, &dir, &iu);
@@ -565,22 +565,28 @@ __device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile
                                    L.u.t.midl[wave], L.u.t.exptab, acck, far32);
     }
     if (split) {
-        // the odd waves' sums to the even waves, four values per pass
-        constexpr int NV = 2 * NNU;
+        // the odd waves' sums (and FP32 far-field sums of mixed calls) to the even
+        // waves, four values per pass
+        constexpr int NV = (MIX ? 3 : 2) * NNU;
 #pragma unroll
         for (int c0 = 0; c0 < NV; c0 += 4) {
             __syncthreads();                        // the table, lists or last pass are read
             if (part == 1) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (c0 + u < NV) L.u.xch[wave >> 1][u][lane] = (c0 + u < NNU) ? accr[c0 + u] : acck[c0 + u - NNU];
+                for (int u = 0; u < 4; ++u) {
+                    const int c = c0 + u;
+                    if (c < NV)
+                        L.u.xch[wave >> 1][u][lane] = c < NNU ? accr[c] : (c < 2 * NNU ? acck[c - NNU] : far32[c - 2 * NNU]);
+                }
             }
             __syncthreads();
             if (part == 0) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    if (c0 + u < NNU) accr[c0 + u] += L.u.xch[wave >> 1][u][lane];
-                    else if (c0 + u < NV) acck[c0 + u - NNU] += L.u.xch[wave >> 1][u][lane];
+                    const int c = c0 + u;
+                    if (c < NNU) accr[c] += L.u.xch[wave >> 1][u][lane];
+                    else if (c < 2 * NNU) acck[c - NNU] += L.u.xch[wave >> 1][u][lane];
+                    else if (c < NV) far32[c - 2 * NNU] += L.u.xch[wave >> 1][u][lane];
                 }
             }
         }
@@ -625,9 +631,11 @@ __device__ __forceinline__ void node_tile(const EzQuadArgs &args, const int tile
             args.tile_part[((size_t)tile * n_res + r) * 2 + 1] = s.lo;
         }
         if constexpr (MIX) {
+            // half 1 of a tail tile: the slot n_tiles + (tile - n_main)
             double b = L.rbnd[r][0];
             for (int wv = 1; wv < EZ_TILE / 64; ++wv) b += L.rbnd[r][wv];
-            args.tile_bound[(size_t)tile * n_res + r] = b;
+            const size_t slot = half == 1 ? (size_t)args.n_tiles + (tile - args.n_main) : (size_t)tile;
+            args.tile_bound[slot * n_res + r] = b;
         }
     }
 }
@@ -772,7 +780,13 @@ void ez_node_kernel(EzQuadArgs args) {
 template <int D, int NNU, int SET>
 __global__ __launch_bounds__(EZ_TILE) __attribute__((amdgpu_waves_per_eu(8))) void ez_node_mix_kernel(EzQuadArgs args) {
     __shared__ TileLds L;
-    node_tile<D, NNU, SET, true>(args, (int)blockIdx.x, L);
+    const int b = (int)blockIdx.x;
+    int tile = b, half = -1;
+    if (args.tail_halves && b >= args.n_main) {
+        tile = args.n_main + ((b - args.n_main) >> 1);
+        half = (b - args.n_main) & 1;
+    }
+    node_tile<D, NNU, SET, true>(args, tile, L, half);
 }
 
 // persistent: a fixed grid of workgroups takes tiles from a queue, costliest first;
@@ -865,8 +879,13 @@ __global__ __launch_bounds__(FT) void ez_finalize_kernel(EzQuadArgs args) {
         // thread a strided share, then the waves in order; 0 in FP64 calls
         for (int r = 0; r < n_res; ++r) {
             double b = 0.0;
-            if (args.mixed)
+            if (args.mixed) {
                 for (int t = tb + (int)threadIdx.x; t < te; t += FT) b += args.tile_bound[(size_t)t * n_res + r];
+                // second halves of the lattice's tail tiles
+                if (args.tail_halves)
+                    for (int t = max(tb, args.n_main) + (int)threadIdx.x; t < te; t += FT)
+                        b += args.tile_bound[((size_t)args.n_tiles + (t - args.n_main)) * n_res + r];
+            }
 #pragma unroll
             for (int m = 32; m >= 1; m >>= 1) b += __shfl_xor(b, m, 64);
             __syncthreads();
