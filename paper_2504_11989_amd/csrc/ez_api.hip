@@ -916,12 +916,17 @@ ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, co
         probe_args.prog = prog;
         round = n_cu * ez_nodes_tile_blocks_per_cu(probe_args);
     }
-    const bool big = two && (!grad || P.n_tiles > 8 * round);
+    // Value calls whose tiles fill at most eight rounds swap the streams: the Hadamard
+    // branch on the caller's stream right behind the setup, so that its probe kernel is
+    // dispatched before the node kernel fills the device, and the node kernels on the
+    // second stream (three-lattice ATM call: the branch no longer ends after the nodes)
+    const bool swap = two && !grad && P.n_tiles <= 8 * round;
+    const bool big = two && !swap && (!grad || P.n_tiles > 8 * round);
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     EZ_HIP_TRY(hipStreamIsCapturing(stream, &cap));
     // the fork event after the setup is recorded by the setup launch itself (no marker
     // packet between the setup and the node kernel), or by hipEventRecord under capture
-    const bool ext_setup = big && cap == hipStreamCaptureStatusNone;
+    const bool ext_setup = (big || swap) && cap == hipStreamCaptureStatusNone;
     EZ_HIP_TRY(tm(EZ_KERNEL_SETUP, stream,
                   [&] { return ez_launch_setup(sa, batch, stream, ext_setup ? ev_setup : nullptr); }));
 
@@ -971,14 +976,18 @@ ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, co
     qa.tile_order = P.tile_order;
     qa.queue = (int *)W.ptr[WS_QUEUE];
 
-    // The Taylor/Hadamard branch depends only on the setup.  In value calls its
-    // probe, tensor and direction kernels run on a second stream, concurrently with
-    // the node kernel: they take the workgroup slots that the node kernel's last,
-    // partly filled round of tiles leaves free (three-lattice ATM call, 263424 nodes
-    // each: 0.297 ms per step against 0.302 ms with probe and tensor on the caller's
-    // stream before the nodes).  The caller's stream waits for the branch before the
-    // final reduction (event edges, so the sequence can be captured into a graph).
-    // EZ_SPEC_SERIAL keeps everything on `stream`.
+    // The Taylor/Hadamard branch depends only on the setup.  Its probe, tensor and
+    // direction kernels run concurrently with the node kernel on the other stream:
+    // they take the workgroup slots that the node kernel leaves free.  Small value
+    // calls (`swap`) keep the branch on the caller's stream and put the nodes on the
+    // second one; the probe, queued right behind the setup, then starts before the
+    // node kernel fills the device (three-lattice ATM call, 263424 nodes each: 0.2458
+    // ms per step against 0.2489 ms with the nodes on the caller's stream, where the
+    // probe waited for the node kernel's drain and the branch ended after the nodes).
+    // Large scans and derivative calls keep the nodes on the caller's stream.  The
+    // caller's stream joins the other before the final reduction (event edges, so the
+    // sequence can be captured into a graph).  EZ_SPEC_SERIAL keeps everything on
+    // `stream`.
     auto had = [&](hipStream_t s, int part, hipEvent_t done) {
         return grad ? ez_launch_hadamard_adj(qa, P.n_htiles, s, part, done)
                     : ez_launch_hadamard(qa, P.n_htiles, s, part, done);
@@ -989,8 +998,14 @@ ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, co
     // drains, and runs beside its last, partly filled round of tiles (three-lattice ATM
     // derivative, 263424 nodes each: 0.869 ms per step, 0.901 ms with the direction
     // kernel before the nodes).
-    hipStream_t hs = stream;
-    if (big) {
+    hipStream_t hs = stream;                      // the Hadamard branch
+    hipStream_t ns = stream;                      // the node kernels
+    if (swap) {
+        if (!ext_setup) EZ_HIP_TRY(hipEventRecord(ev_setup, stream));
+        EZ_HIP_TRY(hipStreamWaitEvent(side, ev_setup, 0));
+        ns = side;
+        EZ_HIP_TRY(tm(EZ_KERNEL_TAYLOR, stream, [&] { return had(stream, EZ_HAD_PRE, nullptr); }));
+    } else if (big) {
         if (!ext_setup) EZ_HIP_TRY(hipEventRecord(ev_setup, stream));
         EZ_HIP_TRY(hipStreamWaitEvent(side, ev_setup, 0));
         hs = side;
@@ -1006,21 +1021,22 @@ ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, co
     }
     EZ_HIP_TRY(tm(EZ_KERNEL_HADAMARD, hs, [&] { return had(hs, EZ_HAD_DIR, nullptr); }));
     if (grad) {
-        EZ_HIP_TRY(tm(EZ_KERNEL_NODES_ADJ, stream, [&] { return ez_launch_nodes_adj(qa, P.n_tiles, stream); }));
+        EZ_HIP_TRY(tm(EZ_KERNEL_NODES_ADJ, ns, [&] { return ez_launch_nodes_adj(qa, P.n_tiles, ns); }));
     } else if ((C.flags & EZ_SPEC_PERSISTENT) && !C.mixed_active && !prog.real_nu) {
         int bpc = (C.flags >> 8) & 0xFF;
         if (bpc == 0) bpc = ez_nodes_blocks_per_cu(qa);
         const int nblk = std::max(1, std::min(P.n_tiles, n_cu * bpc));
-        EZ_HIP_TRY(ez_launch_fill_int(qa.queue, 1, 0, stream));
-        EZ_HIP_TRY(tm(EZ_KERNEL_NODES, stream, [&] { return ez_launch_nodes_persistent(qa, nblk, stream); }));
+        EZ_HIP_TRY(ez_launch_fill_int(qa.queue, 1, 0, ns));
+        EZ_HIP_TRY(tm(EZ_KERNEL_NODES, ns, [&] { return ez_launch_nodes_persistent(qa, nblk, ns); }));
     } else {
         const int n_wg = C.tail_halves ? n_main + 2 * (P.n_tiles - n_main) : n_main;
-        EZ_HIP_TRY(tm(EZ_KERNEL_NODES, stream, [&] { return ez_launch_nodes(qa, n_wg, stream); }));
+        EZ_HIP_TRY(tm(EZ_KERNEL_NODES, ns, [&] { return ez_launch_nodes(qa, n_wg, ns); }));
     }
     if (n_main < P.n_tiles && !C.tail_halves)
-        EZ_HIP_TRY(tm(EZ_KERNEL_NODES_TAIL, stream, [&] { return ez_launch_nodes_split(qa, stream); }));
-    if (hs != stream) {
-        EZ_HIP_TRY(hipEventRecord(ev_had, hs));
+        EZ_HIP_TRY(tm(EZ_KERNEL_NODES_TAIL, ns, [&] { return ez_launch_nodes_split(qa, ns); }));
+    // join the second stream before the final reduction
+    if (hs != stream || ns != stream) {
+        EZ_HIP_TRY(hipEventRecord(ev_had, hs != stream ? hs : ns));
         EZ_HIP_TRY(hipStreamWaitEvent(stream, ev_had, 0));
     }
     EZ_HIP_TRY(tm(EZ_KERNEL_FINALIZE, stream, [&] { return ez_launch_finalize(qa, stream); }));
