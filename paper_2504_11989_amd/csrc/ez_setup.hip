@@ -81,14 +81,19 @@ __device__ __forceinline__ bool make_box(double R, const double *norm2, int *h, 
     return true;
 }
 
-// box index -> integer point, n_1 fastest
+// box index -> integer point, n_1 fastest: n_i = lo_i + (digit i of idx in base w_i).
+// winv[i] = 1/w_i in FP64: idx <= 2^26 converts exactly, the product's rounding moves
+// the truncated quotient by at most one, and the remainder's sign corrects it (a few
+// instructions against the integer division's few dozen)
 template <int d>
-__device__ __forceinline__ void box_point(int idx, const int *h, int *n) {
+__device__ __forceinline__ void box_point(int idx, const int *w, const int *lo, const double *winv, int *n) {
     n[0] = n[1] = n[2] = 0;
     for (int i = 0; i < d; ++i) {
-        const int w = 2 * h[i] + 1;
-        const int q = idx / w;
-        n[i] = idx - q * w - h[i];
+        int q = (int)((double)idx * winv[i]);
+        int r = idx - q * w[i];
+        if (r < 0) { q -= 1; r += w[i]; }
+        if (r >= w[i]) { q += 1; r -= w[i]; }
+        n[i] = r + lo[i];
         idx = q;
     }
 }
@@ -205,6 +210,21 @@ __global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
     double *ktab = args.tab.rec + (size_t)inst * args.tab.rec_cap * 4;
     int *rn = args.general_x ? nullptr : args.tab.rn + (size_t)inst * args.tab.real_cap * 4;
     const double Rr2 = Rr * Rr, Rk2 = Rk * Rk;
+    // box digits: widths, lowest values, reciprocal widths.  Pairs mode keeps the points
+    // whose last nonzero coordinate is positive, so the real box starts its last
+    // coordinate at 0: the kept points, and their order, are those of the full box
+    int bwr[3] = {1, 1, 1}, blr[3] = {0, 0, 0}, bwk[3] = {1, 1, 1}, blk[3] = {0, 0, 0};
+    double wr[3] = {1.0, 1.0, 1.0}, wk[3] = {1.0, 1.0, 1.0};
+    for (int i = 0; i < d; ++i) {
+        const bool halfdim = !args.general_x && i == d - 1;
+        bwr[i] = halfdim ? hr[i] + 1 : 2 * hr[i] + 1;
+        blr[i] = halfdim ? 0 : -hr[i];
+        bwk[i] = 2 * hk[i] + 1;
+        blk[i] = -hk[i];
+        wr[i] = 1.0 / (double)bwr[i];
+        wk[i] = 1.0 / (double)bwk[i];
+    }
+    if (!args.general_x) nbox_r = nbox_r / (2 * hr[d - 1] + 1) * (hr[d - 1] + 1);
     if (tid == 0) { ktab[0] = 0.0; ktab[1] = 0.0; ktab[2] = 0.0; ktab[3] = 0.0; }   // m* = 0 first
     Compact cp;
     cp.cnt[0] = 0; cp.cnt[1] = 1; cp.chunk = 0;
@@ -215,7 +235,7 @@ __global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
         double v[3] = {0.0, 0.0, 0.0};
         int n[3] = {0, 0, 0};
         if (idx < nbox_r) {
-            box_point<D>(idx, hr, n);
+            box_point<D>(idx, bwr, blr, wr, n);
             const bool nonzero = (n[0] | n[1] | n[2]) != 0;
             // pairs mode: keep the representative whose last nonzero coordinate is > 0
             bool half = true;
@@ -232,7 +252,7 @@ __global__ __launch_bounds__(SB) void ez_setup_kernel(EzSetupArgs args) {
             const double r2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
             keep_r = (args.general_x ? true : nonzero) && half && r2 <= Rr2;
         } else if (idx < n_all) {
-            box_point<D>(idx - nbox_r, hk, n);
+            box_point<D>(idx - nbox_r, bwk, blk, wk, n);
             for (int i = 0; i < d; ++i) {
                 double s = 0.0;
                 for (int j = 0; j < d; ++j) s += B[i * d + j] * (double)n[j];
