@@ -163,6 +163,17 @@ struct DevPlan {
     std::vector<EzInstPlan> host_plans;
 };
 
+// Two 8-byte signal words for stream-ordered edges between the caller's stream and
+// the second stream: a stream writes the next value of a word after its prior work, the
+// other waits until the word reaches it.  A value wait resumes sooner than an event
+// wait (about 5 against 8.5 µs per edge between two streams, measured with 100 µs
+// kernels on the MI355X).  64-bit values only grow.
+struct StreamSignals {
+    uint64_t *p[2] = {nullptr, nullptr};
+    uint64_t seq[2] = {0, 0};
+    bool ok = false;
+};
+
 struct DeviceState {
     std::map<std::string, DevPlan *> plans;
     std::vector<std::string> plan_order;
@@ -181,6 +192,7 @@ struct DeviceState {
     int n_cu = 0;
     hipStream_t side = nullptr;  // second stream: Hadamard branch concurrent with the nodes
     hipEvent_t ev_setup = nullptr, ev_had = nullptr;
+    StreamSignals sig;           // value-wait edges between the two streams (small value calls)
     // no-allocation entry point: this device's address of the static scratch array,
     // and the plan currently resident at its start
     void *scratch = nullptr;
@@ -884,7 +896,8 @@ void workspace_sizes(int batch, const EzProgram &prog, const CallInfo &C, const 
 ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, const std::vector<EzCombo> &combos,
                        const CallInfo &C, const PlanView &P, int n_main, int n_cu, const Workspace &W,
                        double *out_dev, uint32_t *status_dev, double *grad_dev, hipStream_t stream, hipStream_t side,
-                       hipEvent_t ev_setup, hipEvent_t ev_had, bool timing_ok = true, double *bound_dev = nullptr) {
+                       hipEvent_t ev_setup, hipEvent_t ev_had, bool timing_ok = true, double *bound_dev = nullptr,
+                       StreamSignals *sig = nullptr) {
     const bool grad = C.grad;
     // the timing hooks create events; the no-allocation entry point launches without them
     auto tm = [&](int kernel, hipStream_t st, auto launch) { return timing_ok ? timed(kernel, st, launch) : launch(); };
@@ -926,7 +939,9 @@ ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, co
     EZ_HIP_TRY(hipStreamIsCapturing(stream, &cap));
     // the fork event after the setup is recorded by the setup launch itself (no marker
     // packet between the setup and the node kernel), or by hipEventRecord under capture
-    const bool ext_setup = (big || swap) && cap == hipStreamCaptureStatusNone;
+    // small value calls outside capture take their two edges as value waits
+    const bool use_sig = swap && sig && sig->ok && cap == hipStreamCaptureStatusNone;
+    const bool ext_setup = (big || (swap && !use_sig)) && cap == hipStreamCaptureStatusNone;
     EZ_HIP_TRY(tm(EZ_KERNEL_SETUP, stream,
                   [&] { return ez_launch_setup(sa, batch, stream, ext_setup ? ev_setup : nullptr); }));
 
@@ -1001,8 +1016,16 @@ ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, co
     hipStream_t hs = stream;                      // the Hadamard branch
     hipStream_t ns = stream;                      // the node kernels
     if (swap) {
-        if (!ext_setup) EZ_HIP_TRY(hipEventRecord(ev_setup, stream));
-        EZ_HIP_TRY(hipStreamWaitEvent(side, ev_setup, 0));
+        if (use_sig) {
+            // the wait is enqueued only once the write it waits for is
+            const uint64_t v = sig->seq[0] + 1;
+            EZ_HIP_TRY(hipStreamWriteValue64(stream, sig->p[0], v, 0));
+            sig->seq[0] = v;
+            EZ_HIP_TRY(hipStreamWaitValue64(side, sig->p[0], v, hipStreamWaitValueGte, ~0ull));
+        } else {
+            if (!ext_setup) EZ_HIP_TRY(hipEventRecord(ev_setup, stream));
+            EZ_HIP_TRY(hipStreamWaitEvent(side, ev_setup, 0));
+        }
         ns = side;
         EZ_HIP_TRY(tm(EZ_KERNEL_TAYLOR, stream, [&] { return had(stream, EZ_HAD_PRE, nullptr); }));
     } else if (big) {
@@ -1035,7 +1058,12 @@ ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, co
     if (n_main < P.n_tiles && !C.tail_halves)
         EZ_HIP_TRY(tm(EZ_KERNEL_NODES_TAIL, ns, [&] { return ez_launch_nodes_split(qa, ns); }));
     // join the second stream before the final reduction
-    if (hs != stream || ns != stream) {
+    if (use_sig) {
+        const uint64_t v = sig->seq[1] + 1;
+        EZ_HIP_TRY(hipStreamWriteValue64(ns, sig->p[1], v, 0));
+        sig->seq[1] = v;
+        EZ_HIP_TRY(hipStreamWaitValue64(stream, sig->p[1], v, hipStreamWaitValueGte, ~0ull));
+    } else if (hs != stream || ns != stream) {
         EZ_HIP_TRY(hipEventRecord(ev_had, hs != stream ? hs : ns));
         EZ_HIP_TRY(hipStreamWaitEvent(stream, ev_had, 0));
     }
@@ -1061,6 +1089,24 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
         EZ_HIP_TRY(hipEventCreate(&S->ev_setup));     // recorded by a kernel launch (needs timing)
         EZ_HIP_TRY(hipEventCreateWithFlags(&S->ev_had, hipEventDisableTiming));
         EZ_HIP_TRY(hipDeviceGetAttribute(&S->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+        // the signal words, zeroed once (outside capture only: otherwise the calls keep events)
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        int can = 0;
+        if (hipStreamIsCapturing((hipStream_t)stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone &&
+            hipDeviceGetAttribute(&can, hipDeviceAttributeCanUseStreamWaitValue, dev) == hipSuccess && can) {
+            bool good = true;
+            for (int i = 0; i < 2 && good; ++i) {
+                void *w = nullptr;
+                good = hipExtMallocWithFlags(&w, 8, hipMallocSignalMemory) == hipSuccess;
+                if (good) {
+                    S->sig.p[i] = (uint64_t *)w;
+                    good = hipMemset(w, 0, 8) == hipSuccess;
+                }
+            }
+            if (good) good = hipDeviceSynchronize() == hipSuccess;
+            S->sig.ok = good;
+            if (!good) (void)hipGetLastError();
+        }
     }
     PlanView pv;
     pv.rules = (const double *)P->rules.p;
@@ -1094,7 +1140,7 @@ ez_status run_sums(int batch, int d, const double *A_dev, const EzProgram &prog,
             EZ_HIP_TRY(ez_launch_fill_int((int *)bufs[i]->p, (int)(bufs[i]->bytes / sizeof(int)), 0, stream));
     }
     return enqueue_sums(batch, A_dev, prog, combos, C, pv, n_main, S->n_cu, W, out_dev, status_dev, grad_dev, stream,
-                        S->side, S->ev_setup, S->ev_had, true, bound_dev);
+                        S->side, S->ev_setup, S->ev_had, true, bound_dev, &S->sig);
 }
 
 // tables of one lattice for general shifts x (every z, every m*, no weights)
@@ -1243,6 +1289,8 @@ ez_status ez_finalize(void) {
             (void)hipEventDestroy(S->ev_setup);
             (void)hipEventDestroy(S->ev_had);
         }
+        for (int i = 0; i < 2; ++i)
+            if (S->sig.p[i]) (void)hipFree(S->sig.p[i]);
         free_buf(S->gmeta); free_buf(S->greal); free_buf(S->grec);
         delete S;
     }
