@@ -163,11 +163,12 @@ struct DevPlan {
     std::vector<EzInstPlan> host_plans;
 };
 
-// Two 8-byte signal words for stream-ordered edges between the caller's stream and
-// the second stream: a stream writes the next value of a word after its prior work, the
-// other waits until the word reaches it.  A value wait resumes sooner than an event
-// wait (about 5 against 8.5 µs per edge between two streams, measured with 100 µs
-// kernels on the MI355X).  64-bit values only grow.
+// Signal words for stream-ordered edges between the caller's stream and the second
+// stream: a stream writes the next value of a word after its prior work, the other
+// waits until the word reaches it.  A value wait resumes sooner than an event wait
+// (about 5 against 8.5 µs per edge between two streams, measured with 100 µs kernels
+// on the MI355X).  64-bit values only grow.  Word 1 joins the node kernels' stream
+// into the caller's; word 0 is allocated but unused.
 struct StreamSignals {
     uint64_t *p[2] = {nullptr, nullptr};
     uint64_t seq[2] = {0, 0};
@@ -939,9 +940,11 @@ ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, co
     EZ_HIP_TRY(hipStreamIsCapturing(stream, &cap));
     // the fork event after the setup is recorded by the setup launch itself (no marker
     // packet between the setup and the node kernel), or by hipEventRecord under capture
-    // small value calls outside capture take their two edges as value waits
+    // small value calls outside capture join the streams at the end with a value wait
+    // (the setup edge stays an event recorded by the setup launch: a value write there
+    // is a runtime kernel that would hold the probe back behind the setup)
     const bool use_sig = swap && sig && sig->ok && cap == hipStreamCaptureStatusNone;
-    const bool ext_setup = (big || (swap && !use_sig)) && cap == hipStreamCaptureStatusNone;
+    const bool ext_setup = (big || swap) && cap == hipStreamCaptureStatusNone;
     EZ_HIP_TRY(tm(EZ_KERNEL_SETUP, stream,
                   [&] { return ez_launch_setup(sa, batch, stream, ext_setup ? ev_setup : nullptr); }));
 
@@ -1016,16 +1019,8 @@ ez_status enqueue_sums(int batch, const double *A_dev, const EzProgram &prog, co
     hipStream_t hs = stream;                      // the Hadamard branch
     hipStream_t ns = stream;                      // the node kernels
     if (swap) {
-        if (use_sig) {
-            // the wait is enqueued only once the write it waits for is
-            const uint64_t v = sig->seq[0] + 1;
-            EZ_HIP_TRY(hipStreamWriteValue64(stream, sig->p[0], v, 0));
-            sig->seq[0] = v;
-            EZ_HIP_TRY(hipStreamWaitValue64(side, sig->p[0], v, hipStreamWaitValueGte, ~0ull));
-        } else {
-            if (!ext_setup) EZ_HIP_TRY(hipEventRecord(ev_setup, stream));
-            EZ_HIP_TRY(hipStreamWaitEvent(side, ev_setup, 0));
-        }
+        if (!ext_setup) EZ_HIP_TRY(hipEventRecord(ev_setup, stream));
+        EZ_HIP_TRY(hipStreamWaitEvent(side, ev_setup, 0));
         ns = side;
         EZ_HIP_TRY(tm(EZ_KERNEL_TAYLOR, stream, [&] { return had(stream, EZ_HAD_PRE, nullptr); }));
     } else if (big) {
